@@ -1,0 +1,318 @@
+"""Seeded synthetic inputs for the SNMPBB workloads.
+
+This module builds inputs only: the symmetric nonnegative matrix A (dense, CSR or
+low-rank U diag(lam) U^T), the graph Laplacian L, cluster labels and the starting
+factor W0.  It contains none of the solver's arithmetic, so both the HIP path and the
+CPU reference consume identical bytes from it without sharing any solver code.
+
+Recipes (all seeds go through numpy's PCG64 ``default_rng``):
+
+* planted dense problem -- a random nonnegative ``W*`` gives ``W* W*^T``; symmetric
+  Gaussian noise with standard deviation ``noise * mean(W* W*^T)`` is added to the upper
+  triangle (diagonal included) and mirrored; the sum is clipped at zero.  This follows
+  the synthetic experiment of the paper's Section 4 (there ``V = W W^T`` without noise).
+* stochastic block model graphs with equal clusters, normalised as
+  ``D^{-1/2} Adj D^{-1/2}`` (isolated nodes get a zero scale).
+* a normalised Laplacian ``I - D^{-1/2} K D^{-1/2}`` of the symmetrised, unweighted
+  K-nearest-neighbour graph over Gaussian node features with cluster-shifted means
+  (the Laplacian of eq. (2.3) built over a feature graph).
+* a power-law CSR matrix (Chung-Lu-like sampling of row degrees with exponent 2.1).
+* the randomized range finder of Section 2.3 (sketch, thin QR, small symmetric
+  eigendecomposition) that turns a CSR matrix into the low-rank input ``U diag(lam) U^T``.
+* ``W0 = U[0,1] * sqrt(mean(A) / r)`` (Section 4.1 item (4) uses ``2*sqrt(mean/r)``;
+  the workloads here use the factor 1).
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+
+SEED_BASE = 1000
+
+
+# --------------------------------------------------------------------------- dense
+def planted_dense(n: int, r: int, seed: int, noise: float = 0.01):
+    """Planted dense problem ``A = max(W* W*^T + E, 0)`` in float64.
+
+    Returns a dict with ``A`` (n x n, float64, C order), ``Wstar`` (n x r) and
+    ``W0`` (n x r).
+    """
+    rng = np.random.default_rng(seed)
+    wstar = rng.random((n, r))
+    a = wstar @ wstar.T
+    if noise > 0.0:
+        sigma = noise * float(a.mean())
+        e = rng.standard_normal((n, n))
+        e = np.triu(e)
+        e += np.triu(e, 1).T
+        e *= sigma
+        a += e
+        del e
+    np.maximum(a, 0.0, out=a)
+    a = 0.5 * (a + a.T)          # exact symmetry of the stored bytes
+    w0 = start_factor(rng, n, r, float(a.mean()))
+    return {"A": np.ascontiguousarray(a), "Wstar": wstar, "W0": w0}
+
+
+def start_factor(rng, n: int, r: int, mean_a: float, scale: float = 1.0):
+    """``W0 = U[0,1] * scale * sqrt(mean(A)/r)`` (random start of Section 4.1)."""
+    return rng.random((n, r)) * (scale * np.sqrt(max(mean_a, 0.0) / r))
+
+
+def mean_of_sparse(a: sp.csr_matrix) -> float:
+    """Mean over all n*n entries of a sparse matrix (zeros included)."""
+    n = a.shape[0]
+    return float(a.data.sum()) / float(n) / float(n)
+
+
+# --------------------------------------------------------------------------- graphs
+def _tri_unrank(idx: np.ndarray, m: int):
+    """Map ranks of pairs (i<j) of an m-set, enumerated row by row, to (i, j)."""
+    idx = idx.astype(np.int64)
+    b = 2 * m - 1
+    i = np.floor((b - np.sqrt(np.maximum(b * b - 8.0 * idx, 0.0))) / 2.0).astype(np.int64)
+    i = np.clip(i, 0, m - 2)
+    start = i * (2 * m - i - 1) // 2
+    over = start > idx
+    while np.any(over):
+        i[over] -= 1
+        start = i * (2 * m - i - 1) // 2
+        over = start > idx
+    nxt = (i + 1) * (2 * m - i - 2) // 2
+    under = nxt <= idx
+    while np.any(under):
+        i[under] += 1
+        start = i * (2 * m - i - 1) // 2
+        nxt = (i + 1) * (2 * m - i - 2) // 2
+        under = nxt <= idx
+    j = idx - start + i + 1
+    return i, j
+
+
+def sbm_adjacency(n: int, k: int, p_in: float, p_out: float, rng):
+    """Unweighted SBM adjacency (CSR, symmetric, no self loops) and labels.
+
+    Clusters are as equal as possible (sizes differ by at most one); every pair in a
+    block is an independent Bernoulli draw, sampled as a binomial count followed by a
+    uniform choice of distinct pairs.
+    """
+    sizes = np.full(k, n // k, dtype=np.int64)
+    sizes[: n % k] += 1
+    starts = np.concatenate([[0], np.cumsum(sizes)])
+    labels = np.repeat(np.arange(k), sizes)
+    rows, cols = [], []
+    for a in range(k):
+        na = int(sizes[a])
+        for b in range(a, k):
+            nb = int(sizes[b])
+            if a == b:
+                m = na * (na - 1) // 2
+                if m == 0:
+                    continue
+                cnt = int(rng.binomial(m, p_in))
+                if cnt == 0:
+                    continue
+                idx = rng.choice(m, size=cnt, replace=False)
+                i, j = _tri_unrank(idx, na)
+            else:
+                m = na * nb
+                cnt = int(rng.binomial(m, p_out))
+                if cnt == 0:
+                    continue
+                idx = rng.choice(m, size=cnt, replace=False).astype(np.int64)
+                i, j = idx // nb, idx % nb
+            rows.append(i + starts[a])
+            cols.append(j + starts[b])
+    if rows:
+        r_ = np.concatenate(rows)
+        c_ = np.concatenate(cols)
+    else:
+        r_ = np.zeros(0, np.int64)
+        c_ = np.zeros(0, np.int64)
+    data = np.ones(2 * r_.size)
+    adj = sp.coo_matrix((data, (np.concatenate([r_, c_]), np.concatenate([c_, r_]))),
+                        shape=(n, n)).tocsr()
+    adj.sum_duplicates()
+    adj.data[:] = 1.0
+    return adj, labels
+
+
+def normalized_adjacency(adj: sp.csr_matrix) -> sp.csr_matrix:
+    """``D^{-1/2} Adj D^{-1/2}`` with ``d^{-1/2} := 0`` for isolated nodes."""
+    d = np.asarray(adj.sum(axis=1)).ravel()
+    s = np.zeros_like(d)
+    nz = d > 0
+    s[nz] = 1.0 / np.sqrt(d[nz])
+    out = sp.diags(s) @ adj @ sp.diags(s)
+    out = sp.csr_matrix(out)
+    out.sort_indices()
+    return out
+
+
+def knn_laplacian(x: np.ndarray, knn: int) -> sp.csr_matrix:
+    """Normalised Laplacian ``I - D^{-1/2} K D^{-1/2}`` of the symmetrised (union),
+    unweighted ``knn``-nearest-neighbour graph over the rows of ``x`` (Euclidean)."""
+    from scipy.spatial import cKDTree
+
+    n = x.shape[0]
+    tree = cKDTree(x)
+    _, nb = tree.query(x, k=knn + 1)
+    rows = np.repeat(np.arange(n), knn)
+    cols = nb[:, 1:].reshape(-1)
+    keep = rows != cols
+    rows, cols = rows[keep], cols[keep]
+    k = sp.coo_matrix((np.ones(rows.size), (rows, cols)), shape=(n, n)).tocsr()
+    k = k + k.T
+    k.data[:] = 1.0
+    d = np.asarray(k.sum(axis=1)).ravel()
+    s = np.zeros_like(d)
+    s[d > 0] = 1.0 / np.sqrt(d[d > 0])
+    lap = sp.identity(n, format="csr") - sp.diags(s) @ k @ sp.diags(s)
+    lap = sp.csr_matrix(lap)
+    lap.sum_duplicates()
+    lap.sort_indices()
+    return lap
+
+
+def cluster_features(labels: np.ndarray, k: int, dim: int, rng, spread: float = 2.0):
+    """Gaussian node features ``x_i ~ N(mu_{c(i)}, I)`` with ``mu_c ~ N(0, spread^2 I)``."""
+    mu = rng.standard_normal((k, dim)) * spread
+    return mu[labels] + rng.standard_normal((labels.size, dim))
+
+
+def sbm_problem(n: int = 20000, k: int = 20, r: int = 20, p_in: float = 0.02,
+                p_out: float = 0.0005, seed: int = SEED_BASE + 2, knn: int = 10,
+                feat_dim: int = 16, with_laplacian: bool = True):
+    """Graph workload: normalised SBM adjacency, optional kNN-feature Laplacian, W0."""
+    rng = np.random.default_rng(seed)
+    adj, labels = sbm_adjacency(n, k, p_in, p_out, rng)
+    a = normalized_adjacency(adj)
+    lap = None
+    if with_laplacian:
+        x = cluster_features(labels, k, feat_dim, rng)
+        lap = knn_laplacian(x, knn)
+    w0 = start_factor(rng, n, r, mean_of_sparse(a))
+    return {"A": a, "L": lap, "labels": labels, "W0": w0, "k": k}
+
+
+# --------------------------------------------------------------------------- power law
+def _powerlaw_sample(n, xmin, exponent, cap, rng_seed):
+    rng = np.random.default_rng(rng_seed)
+    u = 1.0 - rng.random(n)                          # (0, 1]
+    tail = exponent - 1.0
+    deg = np.floor(xmin * u ** (-1.0 / tail)).astype(np.int64)
+    deg = np.clip(deg, 1, cap)
+    w = deg.astype(np.float64)
+    p = w / w.sum()
+    total = int(deg.sum())
+    rows = np.repeat(np.arange(n, dtype=np.int64), deg)
+    cols = rng.choice(n, size=total, p=p)
+    keep = rows != cols
+    rows, cols = rows[keep], cols[keep]
+    vals = 1.0 - rng.random(rows.size)               # U(0, 1]
+    a = sp.coo_matrix((vals, (rows, cols)), shape=(n, n)).tocsr()
+    a.sum_duplicates()                               # repeated draws of one pair: keep one value
+    a.data = np.minimum(a.data, 1.0)
+    a = a.maximum(a.T).tocsr()
+    a.sort_indices()
+    return a
+
+
+def powerlaw_csr(n: int = 200000, exponent: float = 2.1, mean_degree: float = 10.0,
+                 seed: int = SEED_BASE + 3, tol: float = 0.02):
+    """Symmetric nonnegative power-law CSR matrix with mean nnz per row ~= mean_degree.
+
+    Target degrees are ``floor(xmin * u^{-1/(exponent-1)})`` capped at ``sqrt(n*mean)``;
+    each row draws that many columns with probability proportional to the target
+    degrees, values are U(0,1], and ``A <- max(A, A^T)`` symmetrises.  ``xmin`` is
+    found by bisection so that the mean nnz per row after symmetrisation is within
+    ``tol`` of ``mean_degree``.
+    """
+    cap = int(np.sqrt(n * mean_degree))
+    lo, hi = 0.3, 8.0
+    best = None
+    for _ in range(30):
+        mid = 0.5 * (lo + hi)
+        a = _powerlaw_sample(n, mid, exponent, cap, seed)
+        m = a.nnz / n
+        best = a
+        if abs(m - mean_degree) <= tol * mean_degree:
+            break
+        if m > mean_degree:
+            hi = mid
+        else:
+            lo = mid
+    return best
+
+
+def range_finder(a, rank: int, oversample: int, power_iters: int, seed: int):
+    """Randomized eigen-sketch of a symmetric matrix (Section 2.3 of the paper).
+
+    ``Y = A Omega`` with Gaussian ``Omega`` (n x (rank+oversample)), orthonormalised
+    by thin QR; each power iteration multiplies by A twice with a QR after every
+    product; then the small matrix ``Q^T A Q`` is diagonalised and the ``rank``
+    eigenpairs of largest magnitude are kept: ``U = Q P``, ``lam = E``.
+    Returns ``U`` (n x rank, float64, orthonormal columns) and ``lam`` (rank,).
+    """
+    rng = np.random.default_rng(seed)
+    n = a.shape[0]
+    ell = rank + oversample
+    omega = rng.standard_normal((n, ell))
+    q, _ = np.linalg.qr(a @ omega)
+    for _ in range(power_iters):
+        q, _ = np.linalg.qr(a @ q)
+        q, _ = np.linalg.qr(a @ q)
+    t = q.T @ (a @ q)
+    t = 0.5 * (t + t.T)
+    ev, p = np.linalg.eigh(t)
+    order = np.argsort(-np.abs(ev), kind="stable")[:rank]
+    u = q @ p[:, order]
+    return np.ascontiguousarray(u), ev[order].copy()
+
+
+def lai_problem(n: int = 200000, rank: int = 64, oversample: int = 10, power_iters: int = 2,
+                r: int = 32, seed: int = SEED_BASE + 3):
+    """Low-rank input workload: power-law CSR A, its sketch (U, lam) and W0."""
+    a = powerlaw_csr(n=n, seed=seed)
+    u, lam = range_finder(a, rank, oversample, power_iters, seed + 17)
+    rng = np.random.default_rng(seed + 29)
+    w0 = start_factor(rng, n, r, mean_of_sparse(a))
+    return {"A": a, "U": u, "lam": lam, "W0": w0}
+
+
+# --------------------------------------------------------------------------- batches
+def batched_sbm(num_graphs: int = 256, n_lo: int = 500, n_hi: int = 5000,
+                ranks=(8, 16, 32), restarts: int = 8, p_in: float = 0.02,
+                p_out: float = 0.0005, seed: int = SEED_BASE + 4):
+    """A batch of independent SBM graphs of uneven size (k = r clusters each).
+
+    Graph g uses seed ``seed + g``.  Each graph carries ``restarts`` random starts.
+    """
+    graphs = []
+    for g in range(num_graphs):
+        rng = np.random.default_rng(seed + g)
+        n = int(rng.integers(n_lo, n_hi + 1))
+        r = int(ranks[int(rng.integers(0, len(ranks)))])
+        adj, labels = sbm_adjacency(n, r, p_in, p_out, rng)
+        a = normalized_adjacency(adj)
+        mean_a = mean_of_sparse(a)
+        w0s = [start_factor(rng, n, r, mean_a) for _ in range(restarts)]
+        graphs.append({"A": a, "labels": labels, "r": r, "n": n, "W0": w0s})
+    return graphs
+
+
+# --------------------------------------------------------------------------- named configs
+def config(c: int, **over):
+    """The five named workloads (c = 0..4) with their fixed seeds."""
+    seed = SEED_BASE + c
+    if c == 0:
+        return planted_dense(over.get("n", 500), over.get("r", 10), seed)
+    if c == 1:
+        return planted_dense(over.get("n", 8192), over.get("r", 64), seed)
+    if c == 2:
+        return sbm_problem(seed=seed, **over)
+    if c == 3:
+        return lai_problem(seed=seed, **over)
+    if c == 4:
+        return batched_sbm(seed=seed, **over)
+    raise ValueError(f"unknown workload {c}")

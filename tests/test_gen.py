@@ -1,0 +1,73 @@
+"""Checks of the seeded workload generators (input recipes, not solver arithmetic)."""
+import numpy as np
+import scipy.sparse as sp
+
+from paper_2606_02887_amd import gen
+
+
+def test_planted_dense_is_symmetric_nonnegative_and_seeded():
+    p = gen.planted_dense(64, 4, 123)
+    q = gen.planted_dense(64, 4, 123)
+    A = p["A"]
+    assert (A == A.T).all() and (A >= 0).all()
+    assert np.array_equal(A, q["A"]) and np.array_equal(p["W0"], q["W0"])
+    # noise is 1% of the mean: the planted product explains ~99% of A
+    res = np.linalg.norm(A - p["Wstar"] @ p["Wstar"].T) / np.linalg.norm(A)
+    assert 1e-3 < res < 2e-2
+
+
+def test_sbm_structure():
+    rng = np.random.default_rng(0)
+    adj, labels = gen.sbm_adjacency(600, 6, 0.1, 0.005, rng)
+    assert (adj != adj.T).nnz == 0 and adj.diagonal().sum() == 0
+    rows, cols = adj.nonzero()
+    same = labels[rows] == labels[cols]
+    n_in = same.sum() / 2
+    n_out = (~same).sum() / 2
+    pairs_in = 6 * (100 * 99 / 2)
+    pairs_out = 600 * 599 / 2 - pairs_in
+    assert abs(n_in / pairs_in - 0.1) < 0.01
+    assert abs(n_out / pairs_out - 0.005) < 0.001
+    a = gen.normalized_adjacency(adj)
+    d = np.asarray(adj.sum(1)).ravel()
+    i, j = rows[0], cols[0]
+    assert abs(a[i, j] - 1 / np.sqrt(d[i] * d[j])) < 1e-15
+
+
+def test_tri_unrank_enumerates_all_pairs():
+    m = 37
+    i, j = gen._tri_unrank(np.arange(m * (m - 1) // 2), m)
+    ref = [(a, b) for a in range(m) for b in range(a + 1, m)]
+    assert list(zip(i.tolist(), j.tolist())) == ref
+
+
+def test_knn_laplacian_is_normalised_laplacian():
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal((200, 3))
+    L = gen.knn_laplacian(x, 5)
+    Ld = L.toarray()
+    assert np.allclose(Ld, Ld.T) and np.allclose(np.diag(Ld), 1.0)
+    ev = np.linalg.eigvalsh(Ld)
+    assert ev.min() > -1e-12 and ev.max() < 2 + 1e-12
+
+
+def test_powerlaw_mean_degree_and_symmetry():
+    a = gen.powerlaw_csr(n=20000, seed=5)
+    assert abs(a.nnz / a.shape[0] - 10) <= 0.2 + 1e-9
+    assert abs(a - a.T).max() == 0
+    assert a.data.min() > 0 and a.data.max() <= 1
+    assert a.diagonal().sum() == 0
+
+
+def test_range_finder_orthonormal_and_near_optimal():
+    rng = np.random.default_rng(2)
+    n, k = 400, 10
+    w = rng.random((n, k))
+    A = sp.csr_matrix(w @ w.T + 0.01 * (lambda e: e + e.T)(rng.standard_normal((n, n))))
+    U, lam = gen.range_finder(A, k, 10, 2, 7)
+    assert np.abs(U.T @ U - np.eye(k)).max() < 1e-12
+    Ad = A.toarray()
+    ev = np.linalg.eigvalsh(Ad)
+    best = np.sqrt(np.sort(ev ** 2)[:-k].sum())
+    err = np.linalg.norm(Ad - (U * lam) @ U.T)
+    assert best <= err <= 1.05 * best
