@@ -1,0 +1,188 @@
+/*
+ * snmf.h -- C ABI of the MI355X (gfx950) SNMPBB library.
+ *
+ * SNMPBB computes a symmetric nonnegative factorisation A ~= W H with W, H^T >= 0 and a
+ * penalty that couples W and H^T (Swart & Brust, "A Nonmonotone Gradient-Based Algorithm
+ * for Symmetric Nonnegative Matrix Factorization and Graph Clustering"):
+ *
+ *   minimise  f(W, H) = 1/2 ||A - W H||_F^2 + lam/2 ||W - H^T||_F^2 + gam/2 tr(H L H^T)
+ *
+ * (eq. (1.3); the last term is the Graph-SNMPBB regulariser of eq. (2.3) with a graph
+ * Laplacian L).  The solver alternates a W-step and an H-step (Section 2.1); each is a run
+ * of Algorithm 1 (nonmonotone projected Barzilai-Borwein, Section 2.4).  A may be dense,
+ * CSR, or the low-rank surrogate U diag(lam) U^T of LAI-SNMPBB (Section 2.3).
+ *
+ * Conventions shared by every entry point
+ *  - All matrices are row-major.  The factor H is exchanged transposed, Ht = H^T (n x r),
+ *    so W and Ht have the same shape.
+ *  - Array arguments are DEVICE pointers (memory of the current HIP device) unless the
+ *    comment says "host".  Struct arguments (snmf_matrix, snmf_params, snmf_info) are host
+ *    pointers.  The caller owns every buffer; the library keeps no pointer after a call
+ *    returns.  Scratch memory is allocated inside a call (or inside a plan) and freed
+ *    before it returns (or when the plan is destroyed).
+ *  - `stream` is a hipStream_t (NULL = default stream).  Work is stream-ordered; calls
+ *    that return results in host structs synchronise the stream first.
+ *  - Errors: argument checks run first and leave every output untouched.  Nothing is
+ *    printed, no exception crosses the ABI.  snmf_last_error() returns a thread-local
+ *    message describing the last non-OK status.
+ *  - Limits: 1 <= r <= 64; sketch rank ell <= 128; n < 2^31 for CSR column indices.
+ */
+#ifndef SNMF_H
+#define SNMF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SNMF_ABI_VERSION 1
+#define SNMF_TRACE_FIELDS 10
+
+typedef enum snmf_status {
+  SNMF_OK = 0,
+  SNMF_E_ARG = 1,           /* invalid argument (null pointer, bad parameter value) */
+  SNMF_E_SHAPE = 2,         /* inconsistent sizes (r > n, r > 64, bad leading dimension) */
+  SNMF_E_NOT_SYMMETRIC = 3, /* CSR pattern/values not symmetric */
+  SNMF_E_NEGATIVE = 4,      /* negative entry in A or W0 (A >= 0 and W0 >= 0 are required) */
+  SNMF_E_NONFINITE = 5,     /* NaN or Inf in A or W0 */
+  SNMF_E_OOM = 6,           /* device allocation failed */
+  SNMF_E_DEVICE = 7,        /* a HIP call failed */
+  SNMF_E_UNSUPPORTED = 8,   /* valid but unsupported combination (e.g. BF16X3 with CSR) */
+  SNMF_E_BREAKDOWN = 9      /* numeric breakdown (rho = 0 or a non-finite scalar); the last
+                               finite iterate is written */
+} snmf_status;
+
+typedef enum snmf_format { SNMF_DENSE = 0, SNMF_CSR = 1, SNMF_LOWRANK = 2 } snmf_format;
+
+/* Arithmetic of the solve.  F64: every array is double.  F32: every array is float,
+ * reductions and line-search scalars are FP64.  BF16X3: as F32, but the dense A-pass
+ * multiplies round-to-nearest-even BF16 hi/lo splits of A and of the partner factor on
+ * MFMA (A P ~= Ahi Phi + Ahi Plo + Alo Phi, FP32 accumulation); A is given in FP32 and
+ * split once per plan. */
+typedef enum snmf_precision { SNMF_F64 = 0, SNMF_F32 = 1, SNMF_BF16X3 = 2 } snmf_precision;
+
+/* The symmetric nonnegative input A (n x n), or a graph Laplacian L.  Element type of
+ * `dense`, `val` and `U` follows the solve precision (double for F64, float otherwise).
+ *  DENSE:   dense[i*ld + j], ld >= n; symmetry is the caller's promise (not checked).
+ *  CSR:     rowptr[n+1] (int64, device), col[nnz] (int32, device), val[nnz]; both
+ *           triangles stored; rows need not be sorted.
+ *  LOWRANK: U[i*ell + a] (n x ell, orthonormal columns) and lam[ell] (double, device):
+ *           A ~= U diag(lam) U^T.  Products A P are formed as U (lam .* (U^T P)). */
+typedef struct snmf_matrix {
+  int32_t fmt;
+  int32_t reserved;
+  int64_t n;
+  const void* dense;
+  int64_t ld;
+  const int64_t* rowptr;
+  const int32_t* col;
+  const void* val;
+  int64_t nnz;
+  const void* U;
+  int64_t ell;
+  const double* lam;
+} snmf_matrix;
+
+/* Solver parameters.  snmf_params_default() fills the values in brackets. */
+typedef struct snmf_params {
+  double lambda;       /* symmetric penalty lam >= 0 (eq. (1.3))                         [0] */
+  double gamma;        /* Laplacian weight gam >= 0 (eq. (2.3)), used when L != NULL     [0] */
+  const snmf_matrix* L;/* CSR Laplacian (n x n) or NULL                                [NULL] */
+  double eta;          /* nonmonotone memory, 0 <= eta < 1                            [0.85] */
+  double theta;        /* Armijo parameter, 0 < theta < 1                             [1e-3] */
+  double phi;          /* relaxation factor of W_{k+1} = Z_k + phi beta D_k, phi > 0   [1.7] */
+  double alpha_min;    /* BB step clip, 0 < alpha_min < alpha_max                    [1e-10] */
+  double alpha_max;    /*                                                             [1e10] */
+  double beta_shrink;  /* backtracking factor, 0 < beta_shrink < 1                     [0.5] */
+  int32_t max_ls;      /* backtracking reductions per inner iteration, >= 0             [20] */
+  int32_t inner_iters; /* inner iterations per half-step, >= 1                           [5] */
+  int32_t max_outer;   /* outer (W-step + H-step) iterations, >= 1                      [100] */
+  int32_t check_every; /* host checks the stop flag every this many outer iterations     [8] */
+  double target_res;   /* stop at the first outer iteration with ||A - W H||/||A|| <= this
+                          (0 disables)                                                   [0] */
+  int32_t prec;        /* snmf_precision                                          [SNMF_F32] */
+  int32_t accept_at_relaxed; /* 0: test f(Z + beta D) (Algorithm 1); 1: test f(Z + phi beta D)
+                                (requires project_update = 0)                            [0] */
+  int32_t project_update;    /* 1: W_{k+1} = max(0, Z + phi beta D); 0: no projection     [1] */
+  int32_t validate;    /* 1: check A >= 0, finite, W0 >= 0 finite, CSR structure        [1] */
+  int32_t use_graph;   /* 1: replay one outer iteration as a captured hipGraph           [1] */
+  int32_t reserved;
+} snmf_params;
+
+/* Per-solve results (host struct written on return). */
+typedef struct snmf_info {
+  int32_t status;        /* snmf_status of the solve */
+  int32_t outer;         /* completed outer iterations */
+  int32_t converged_at;  /* first outer iteration meeting target_res (1-based), 0 if none */
+  int32_t reserved;
+  int64_t inner_total;   /* inner iterations run (all half-steps) */
+  int64_t ls_evals;      /* line-search trials */
+  int64_t ls_exhausted;  /* inner iterations whose backtracking hit max_ls */
+  double res_WH;         /* ||A - W Ht^T||_F / ||A||_F at the returned factors */
+  double res_WWt;        /* ||A - W W^T||_F / ||A||_F */
+  double sym_gap;        /* ||W - Ht||_F / ||W||_F */
+  double pg_norm;        /* ||min(W, grad_W f)||^2 + ||min(Ht, grad_Ht f)||^2, square root:
+                            zero exactly at first-order stationary points (Section 3.1) */
+  double objective;      /* f(W, H) */
+  double seconds;        /* device time from solve start to the last completed outer
+                            iteration */
+  double seconds_to_target; /* device time to converged_at, or -1 */
+  double normA2;         /* ||A||_F^2 (surrogate norm sum(lam^2) for LOWRANK) */
+} snmf_info;
+
+snmf_status snmf_params_default(snmf_params* p);
+
+/* Solve SNMPBB.  W0 (n x r) is the start of both factors (W = Ht = W0, as H0 = W0^T in
+ * Section 4.1).  W_out, Ht_out: n x r outputs (may alias W0 only if W_out == W0).
+ * trace: optional host array of max_outer * SNMF_TRACE_FIELDS doubles; record i holds
+ * {res_WH, res_WWt, sym_gap, pg_norm, objective, device_ticks, ls_evals, ls_exhausted,
+ *  alpha, inner_total} after outer iteration i+1 (device_ticks at the clock rate returned
+ * by snmf_clock_rate_hz()). */
+snmf_status snmf_solve(const snmf_matrix* A, int32_t r, const void* W0, const snmf_params* p,
+                       void* W_out, void* Ht_out, snmf_info* info, void* stream, double* trace);
+
+/* Plans: the same solve with scratch memory and input preprocessing (||A||^2, validation,
+ * the BF16 split) kept across calls, for repeated timed solves.  A plan keeps the
+ * pointers of A and L given at creation; they must stay valid until destroy. */
+typedef struct snmf_plan snmf_plan;
+snmf_status snmf_plan_create(const snmf_matrix* A, int32_t r, const snmf_params* p,
+                             void* stream, snmf_plan** out);
+snmf_status snmf_plan_solve(snmf_plan* plan, const void* W0, void* W_out, void* Ht_out,
+                            snmf_info* info, void* stream, double* trace);
+snmf_status snmf_plan_destroy(snmf_plan* plan);
+
+/* One half-step of SNMPBB (Algorithm 1 run for inner_iters iterations) with the partner
+ * block P fixed: X (n x r, in/out) is W (is_hstep = 0, P = Ht) or Ht (is_hstep = 1,
+ * P = W, the Laplacian term applies).  Used to check the method step by step.
+ * scalars (host, optional, 8 doubles): {rho, alpha_next, beta_last, e, ss, sy, ls_evals,
+ * inner_done}. */
+snmf_status snmf_plan_half_step(snmf_plan* plan, void* X, const void* P, int32_t is_hstep,
+                                void* stream, double* scalars);
+
+/* Primitives of the hot path, for per-kernel checks.  All arrays are device arrays of the
+ * plan's precision type unless stated.
+ *  apass:   B = A P (n x r).  For BF16X3 plans the split product above, B in float.
+ *  gram:    G = P^T P (r x r, double), accumulated in FP64.
+ *  rho:     ||G||_2 of a symmetric PSD r x r double matrix G (device), returned in *rho
+ *           (host).
+ *  spmm:    Y = M X for a CSR matrix M of the plan's type (e.g. the Laplacian). */
+snmf_status snmf_plan_apass(snmf_plan* plan, const void* P, void* B, void* stream);
+snmf_status snmf_plan_gram(snmf_plan* plan, const void* P, double* G, void* stream);
+snmf_status snmf_rho(const double* G, int32_t r, double* rho, void* stream);
+snmf_status snmf_spmm(const snmf_matrix* M, int32_t prec, const void* X, int32_t r, void* Y,
+                      void* stream);
+/* BF16 round-to-nearest-even split of n*ld floats: hi = bf16(x), lo = bf16(x - hi);
+ * hi and lo are uint16 device arrays of n*ld elements. */
+snmf_status snmf_split_bf16(const float* x, int64_t count, uint16_t* hi, uint16_t* lo,
+                            void* stream);
+
+/* Device clock rate (Hz) of the trace ticks and info.seconds. */
+double snmf_clock_rate_hz(void);
+const char* snmf_last_error(void);
+int32_t snmf_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SNMF_H */

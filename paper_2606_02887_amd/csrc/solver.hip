@@ -1,0 +1,764 @@
+// Host orchestration and C ABI of the SNMPBB library (see include/snmf.h).
+//
+// One outer iteration = W-step then H-step (Section 2.1).  A half-step with variable X
+// and partner P launches, in stream order:
+//   gram(P) -> rho(G) -> A-pass(P) -> [L X] -> init -> inner_iters x (step1, step2)
+// with the Laplacian path (H-step of Graph-SNMPBB) splitting step1/step2 around the
+// sparse products L(Z-X), <D, L D> and L S.  All iteration scalars stay on the device;
+// every kernel returns at once when the device "done" flag is set, so an outer
+// iteration can be captured once as a hipGraph and replayed.  The host only reads the
+// flag every check_every outer iterations.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/snmf.h"
+#include "common.hpp"
+#include "kernels.hpp"
+
+using namespace snmf;
+
+namespace {
+
+thread_local std::string g_err;
+
+snmf_status fail(snmf_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define HIP_TRY(call)                                                                  \
+  do {                                                                                 \
+    hipError_t _e = (call);                                                            \
+    if (_e != hipSuccess)                                                              \
+      return fail(_e == hipErrorOutOfMemory ? SNMF_E_OOM : SNMF_E_DEVICE,              \
+                  std::string(#call) + ": " + hipGetErrorString(_e));                  \
+  } while (0)
+
+#define SNMF_TRY(call)                  \
+  do {                                  \
+    snmf_status _s = (call);            \
+    if (_s != SNMF_OK) return _s;       \
+  } while (0)
+
+size_t elt_size(int prec) { return prec == SNMF_F64 ? 8 : 4; }
+
+struct DevBuf {
+  void* p = nullptr;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+}  // namespace
+
+struct snmf_plan {
+  snmf_matrix A{};
+  snmf_matrix L{};
+  snmf_params p{};
+  bool lap = false;
+  int r = 0;
+  int64_t n = 0;
+  int prec = SNMF_F32;
+  size_t esz = 4;
+  hipStream_t s = nullptr;  // private stream of the plan (default priority)
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  // device memory (one allocation, carved)
+  void* pool = nullptr;
+  void *Wb = nullptr, *Hb = nullptr, *C = nullptr, *g = nullptr, *Z = nullptr, *D = nullptr;
+  void *Bpart = nullptr, *LT = nullptr, *LX = nullptr, *GT[2] = {nullptr, nullptr}, *TT = nullptr;
+  double* G64[2] = {nullptr, nullptr};
+  double *part = nullptr, *gram_part = nullptr, *lai_part = nullptr, *dots = nullptr;
+  double* trace = nullptr;
+  uint16_t *Ahi = nullptr, *Alo = nullptr, *Pthi = nullptr, *Ptlo = nullptr;
+  int64_t ldb = 0;
+  State* st = nullptr;
+  unsigned* counters = nullptr;
+  unsigned* flags = nullptr;
+  DenseSplit ds{};
+  int gram_blocks = 1;
+  double normA2 = 0.0;
+  KParams kp{};
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+
+  ~snmf_plan() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (pool) (void)hipFree(pool);
+    if (ev_in) (void)hipEventDestroy(ev_in);
+    if (ev_out) (void)hipEventDestroy(ev_out);
+    if (s) (void)hipStreamDestroy(s);
+  }
+};
+
+namespace {
+
+snmf_status check_params(const snmf_params* p) {
+  if (!p) return fail(SNMF_E_ARG, "params is NULL");
+  if (!(p->lambda >= 0.0) || !std::isfinite(p->lambda)) return fail(SNMF_E_ARG, "lambda must be >= 0");
+  if (!(p->gamma >= 0.0) || !std::isfinite(p->gamma)) return fail(SNMF_E_ARG, "gamma must be >= 0");
+  if (!(p->eta >= 0.0 && p->eta < 1.0)) return fail(SNMF_E_ARG, "eta must lie in [0, 1)");
+  if (!(p->theta > 0.0 && p->theta < 1.0)) return fail(SNMF_E_ARG, "theta must lie in (0, 1)");
+  if (!(p->phi > 0.0) || !std::isfinite(p->phi)) return fail(SNMF_E_ARG, "phi must be > 0");
+  if (!(p->alpha_min > 0.0 && p->alpha_min < p->alpha_max) || !std::isfinite(p->alpha_max))
+    return fail(SNMF_E_ARG, "need 0 < alpha_min < alpha_max < inf");
+  if (!(p->beta_shrink > 0.0 && p->beta_shrink < 1.0))
+    return fail(SNMF_E_ARG, "beta_shrink must lie in (0, 1)");
+  if (p->max_ls < 0) return fail(SNMF_E_ARG, "max_ls must be >= 0");
+  if (p->inner_iters < 1) return fail(SNMF_E_ARG, "inner_iters must be >= 1");
+  if (p->max_outer < 1) return fail(SNMF_E_ARG, "max_outer must be >= 1");
+  if (!(p->target_res >= 0.0)) return fail(SNMF_E_ARG, "target_res must be >= 0");
+  if (p->prec < SNMF_F64 || p->prec > SNMF_BF16X3) return fail(SNMF_E_ARG, "unknown precision");
+  if (p->accept_at_relaxed && p->project_update)
+    return fail(SNMF_E_UNSUPPORTED,
+                "accept_at_relaxed needs project_update = 0 (the projected relaxed point has "
+                "no closed-form objective)");
+  return SNMF_OK;
+}
+
+snmf_status check_matrix(const snmf_matrix* A, const char* what) {
+  if (!A) return fail(SNMF_E_ARG, std::string(what) + " is NULL");
+  if (A->n < 1) return fail(SNMF_E_SHAPE, std::string(what) + ": n must be >= 1");
+  switch (A->fmt) {
+    case SNMF_DENSE:
+      if (!A->dense) return fail(SNMF_E_ARG, std::string(what) + ": dense pointer is NULL");
+      if (A->ld < A->n) return fail(SNMF_E_SHAPE, std::string(what) + ": ld < n");
+      break;
+    case SNMF_CSR:
+      if (!A->rowptr || (A->nnz > 0 && (!A->col || !A->val)))
+        return fail(SNMF_E_ARG, std::string(what) + ": CSR pointer is NULL");
+      if (A->nnz < 0) return fail(SNMF_E_SHAPE, std::string(what) + ": nnz < 0");
+      if (A->n >= (int64_t)1 << 31) return fail(SNMF_E_SHAPE, std::string(what) + ": n >= 2^31");
+      break;
+    case SNMF_LOWRANK:
+      if (!A->U || !A->lam) return fail(SNMF_E_ARG, std::string(what) + ": U or lam is NULL");
+      if (A->ell < 1 || A->ell > kMaxEll)
+        return fail(SNMF_E_SHAPE, std::string(what) + ": ell must lie in [1, 128]");
+      break;
+    default:
+      return fail(SNMF_E_ARG, std::string(what) + ": unknown format");
+  }
+  return SNMF_OK;
+}
+
+template <typename T>
+snmf_status stats(snmf_plan* pl, const T* x, int64_t rows, int64_t cols, int64_t ld, double* out3) {
+  launch_stats2d<T>(x, rows, cols, ld, pl->part, pl->dots, pl->counters + C_NORM, pl->s);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(out3, pl->dots, 3 * sizeof(double), hipMemcpyDeviceToHost, pl->s));
+  HIP_TRY(hipStreamSynchronize(pl->s));
+  return SNMF_OK;
+}
+
+snmf_status stats_any(snmf_plan* pl, const void* x, int64_t rows, int64_t cols, int64_t ld,
+                      double* out3) {
+  if (pl->prec == SNMF_F64) return stats<double>(pl, (const double*)x, rows, cols, ld, out3);
+  return stats<float>(pl, (const float*)x, rows, cols, ld, out3);
+}
+
+snmf_status check_values(const double* st3, const char* what) {
+  if (st3[2] > 0) return fail(SNMF_E_NONFINITE, std::string(what) + " has NaN/Inf entries");
+  if (st3[1] > 0) return fail(SNMF_E_NEGATIVE, std::string(what) + " has negative entries");
+  return SNMF_OK;
+}
+
+snmf_status check_csr(snmf_plan* pl, const snmf_matrix* M, const char* what, bool need_nonneg,
+                      double* sumsq) {
+  HIP_TRY(hipMemsetAsync(pl->flags, 0, 4 * sizeof(unsigned), pl->s));
+  launch_csr_structure(M->rowptr, M->col, M->n, M->nnz, pl->flags, pl->s);
+  HIP_TRY(hipGetLastError());
+  unsigned f[4];
+  HIP_TRY(hipMemcpyAsync(f, pl->flags, sizeof(f), hipMemcpyDeviceToHost, pl->s));
+  HIP_TRY(hipStreamSynchronize(pl->s));
+  if (f[0] || f[1]) return fail(SNMF_E_SHAPE, std::string(what) + ": malformed CSR structure");
+  if (pl->p.validate && f[2] == 0) {
+    if (pl->prec == SNMF_F64)
+      launch_csr_symmetry<double>(M->rowptr, M->col, (const double*)M->val, M->n, pl->flags, pl->s);
+    else
+      launch_csr_symmetry<float>(M->rowptr, M->col, (const float*)M->val, M->n, pl->flags, pl->s);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(f, pl->flags, sizeof(f), hipMemcpyDeviceToHost, pl->s));
+    HIP_TRY(hipStreamSynchronize(pl->s));
+    if (f[3]) return fail(SNMF_E_NOT_SYMMETRIC, std::string(what) + " is not symmetric");
+  }
+  double st3[3] = {0, 0, 0};
+  if (M->nnz > 0) SNMF_TRY(stats_any(pl, M->val, 1, M->nnz, M->nnz, st3));
+  if (st3[2] > 0) return fail(SNMF_E_NONFINITE, std::string(what) + " has NaN/Inf entries");
+  if (need_nonneg && st3[1] > 0) return fail(SNMF_E_NEGATIVE, std::string(what) + " has negative entries");
+  if (sumsq) *sumsq = st3[0];
+  return SNMF_OK;
+}
+
+// ------------------------------------------------------------------ one half-step
+template <typename T>
+snmf_status apass(snmf_plan* pl, const T* P, hipStream_t s) {
+  const int64_t n = pl->n;
+  const int r = pl->r;
+  const int32_t* gate = &pl->st->done;
+  switch (pl->A.fmt) {
+    case SNMF_DENSE:
+      if (pl->prec == SNMF_F64) {
+        launch_apass_f64((const double*)pl->A.dense, pl->A.ld, (const double*)P, n, r,
+                         (double*)pl->Bpart, pl->st, s);
+      } else if (pl->prec == SNMF_F32) {
+        launch_apass_f32((const float*)pl->A.dense, pl->A.ld, (const float*)P, n, r, pl->ds,
+                         (float*)pl->Bpart, n * r, pl->st, s);
+      } else {
+        launch_split_pt((const float*)P, n, r, pl->ldb, pl->Pthi, pl->Ptlo, pl->st, s);
+        launch_apass_bf16x3(pl->Ahi, pl->Alo, pl->ldb, pl->Pthi, pl->Ptlo, pl->ldb, n, r, pl->ds,
+                            (float*)pl->Bpart, n * r, pl->st, s);
+      }
+      break;
+    case SNMF_CSR:
+      launch_spmm<T>(pl->A.rowptr, pl->A.col, (const T*)pl->A.val, P, n, r, (T*)pl->Bpart, nullptr,
+                     nullptr, nullptr, nullptr, gate, nullptr, s);
+      break;
+    default:
+      launch_lai<T>((const T*)pl->A.U, (int)pl->A.ell, pl->A.lam, P, n, r, pl->lai_part,
+                    (T*)pl->TT, (T*)pl->Bpart, gate, s);
+      break;
+  }
+  HIP_TRY(hipGetLastError());
+  return SNMF_OK;
+}
+
+int ksplit_of(const snmf_plan* pl) {
+  return (pl->A.fmt == SNMF_DENSE && pl->prec != SNMF_F64) ? pl->ds.ksplit : 1;
+}
+
+// Start of a half-step up to and including init: G, rho, the A-pass and the gradient.
+template <typename T>
+snmf_status half_start(snmf_plan* pl, T* X, const T* P, int is_hstep, bool with_rho,
+                       hipStream_t s) {
+  const int64_t n = pl->n;
+  const int r = pl->r;
+  const int gi = is_hstep ? 1 : 0;
+  launch_gram<T>(P, n, r, pl->gram_part, pl->gram_blocks, pl->G64[gi], (T*)pl->GT[gi],
+                 pl->counters + C_GRAM, pl->st, s);
+  if (with_rho) launch_rho(pl->G64[gi], r, pl->st, s);
+  HIP_TRY(hipGetLastError());
+  SNMF_TRY(apass<T>(pl, P, s));
+  const bool lap = pl->lap && is_hstep;
+  if (lap) {
+    launch_spmm<T>(pl->L.rowptr, pl->L.col, (const T*)pl->L.val, X, n, r, (T*)pl->LX, nullptr,
+                   nullptr, nullptr, nullptr, &pl->st->done, nullptr, s);
+  }
+  launch_init<T>(X, P, (const T*)pl->Bpart, ksplit_of(pl), n * r, (T*)pl->C, (T*)pl->g,
+                 lap ? (const T*)pl->LX : nullptr, (const T*)pl->GT[gi], pl->G64[0], pl->G64[1], n,
+                 r, is_hstep, pl->kp, pl->st, pl->part, pl->counters + C_INIT, pl->trace, s);
+  HIP_TRY(hipGetLastError());
+  return SNMF_OK;
+}
+
+template <typename T>
+snmf_status inner_steps(snmf_plan* pl, T* X, const T* P, int is_hstep, hipStream_t s) {
+  const int64_t n = pl->n;
+  const int r = pl->r;
+  const int gi = is_hstep ? 1 : 0;
+  const T* GT = (const T*)pl->GT[gi];
+  T* Z = (T*)pl->Z;
+  T* D = (T*)pl->D;
+  T* g = (T*)pl->g;
+  const bool lap = pl->lap && is_hstep;
+  const int32_t* g1 = &pl->st->hs_done;
+  const int32_t* g2 = &pl->st->done;
+  for (int k = 0; k < pl->p.inner_iters; ++k) {
+    if (!lap) {
+      launch_step1<T>(X, g, Z, D, nullptr, nullptr, GT, n, r, 0, 0, pl->kp, pl->st, pl->part,
+                      pl->counters + C_STEP1, s);
+      launch_step2<T>(X, g, Z, D, nullptr, (const T*)pl->C, P, nullptr, GT, n, r, 0, is_hstep,
+                      pl->kp, pl->st, pl->part, pl->counters + C_STEP2, s);
+    } else {
+      const int64_t* rp = pl->L.rowptr;
+      const int32_t* ci = pl->L.col;
+      const T* lv = (const T*)pl->L.val;
+      T* LT = (T*)pl->LT;
+      launch_step1<T>(X, g, Z, D, nullptr, D, GT, n, r, 1, 1, pl->kp, pl->st, pl->part,
+                      pl->counters + C_STEP1, s);
+      launch_spmm<T>(rp, ci, lv, D, n, r, LT, nullptr, nullptr, nullptr, nullptr, g1, g2, s);
+      launch_step1<T>(X, g, Z, D, LT, nullptr, GT, n, r, 2, 1, pl->kp, pl->st, pl->part,
+                      pl->counters + C_STEP1, s);
+      launch_spmm<T>(rp, ci, lv, D, n, r, nullptr, D, pl->part + kMaxGrid * kNumPart, pl->dots,
+                     pl->counters + C_LAPRED, g1, g2, s);
+      launch_line_search(pl->st, pl->kp, pl->dots, s);
+      launch_step2<T>(X, g, Z, D, nullptr, (const T*)pl->C, P, nullptr, GT, n, r, 1, is_hstep,
+                      pl->kp, pl->st, pl->part, pl->counters + C_STEP2, s);
+      launch_spmm<T>(rp, ci, lv, D, n, r, LT, nullptr, nullptr, nullptr, nullptr, g1, g2, s);
+      launch_step2<T>(X, g, Z, D, LT, (const T*)pl->C, P, (T*)pl->LX, GT, n, r, 2, is_hstep,
+                      pl->kp, pl->st, pl->part, pl->counters + C_STEP2, s);
+    }
+  }
+  HIP_TRY(hipGetLastError());
+  return SNMF_OK;
+}
+
+template <typename T>
+snmf_status outer_iteration(snmf_plan* pl, hipStream_t s) {
+  T* W = (T*)pl->Wb;
+  T* H = (T*)pl->Hb;
+  SNMF_TRY(half_start<T>(pl, W, H, 0, true, s));
+  SNMF_TRY(inner_steps<T>(pl, W, H, 0, s));
+  SNMF_TRY(half_start<T>(pl, H, W, 1, true, s));
+  SNMF_TRY(inner_steps<T>(pl, H, W, 1, s));
+  return SNMF_OK;
+}
+
+snmf_status outer_any(snmf_plan* pl, hipStream_t s) {
+  return pl->prec == SNMF_F64 ? outer_iteration<double>(pl, s) : outer_iteration<float>(pl, s);
+}
+
+// Monitor record of the last outer iteration: the first half of a W-step.
+snmf_status finalize_any(snmf_plan* pl, hipStream_t s) {
+  if (pl->prec == SNMF_F64)
+    return half_start<double>(pl, (double*)pl->Wb, (const double*)pl->Hb, 0, false, s);
+  return half_start<float>(pl, (float*)pl->Wb, (const float*)pl->Hb, 0, false, s);
+}
+
+snmf_status build_kparams(snmf_plan* pl) {
+  KParams& k = pl->kp;
+  const snmf_params& p = pl->p;
+  k.lam = p.lambda;
+  k.gamma = pl->lap ? p.gamma : 0.0;
+  k.eta = p.eta;
+  k.theta = p.theta;
+  k.phi = p.phi;
+  k.amin = p.alpha_min;
+  k.amax = p.alpha_max;
+  k.shrink = p.beta_shrink;
+  k.target = p.target_res;
+  k.max_ls = p.max_ls;
+  k.relaxed = p.accept_at_relaxed;
+  k.project = p.project_update;
+  k.max_outer = p.max_outer;
+  return SNMF_OK;
+}
+
+snmf_status plan_create(const snmf_matrix* A, int32_t r, const snmf_params* p, hipStream_t user,
+                        snmf_plan** out) {
+  if (!out) return fail(SNMF_E_ARG, "out is NULL");
+  *out = nullptr;
+  SNMF_TRY(check_params(p));
+  SNMF_TRY(check_matrix(A, "A"));
+  if (r < 1 || r > kMaxRank) return fail(SNMF_E_SHAPE, "r must lie in [1, 64]");
+  if (r > A->n) return fail(SNMF_E_SHAPE, "r must not exceed n");
+  const bool lap = p->L != nullptr && p->gamma > 0.0;
+  if (lap) {
+    SNMF_TRY(check_matrix(p->L, "L"));
+    if (p->L->fmt != SNMF_CSR) return fail(SNMF_E_UNSUPPORTED, "L must be CSR");
+    if (p->L->n != A->n) return fail(SNMF_E_SHAPE, "L must be n x n");
+  }
+  if (p->prec == SNMF_BF16X3 && A->fmt != SNMF_DENSE)
+    return fail(SNMF_E_UNSUPPORTED, "BF16X3 applies to dense A only");
+  auto pl = new (std::nothrow) snmf_plan();
+  if (!pl) return fail(SNMF_E_OOM, "host allocation failed");
+  std::unique_ptr<snmf_plan> guard(pl);
+  pl->A = *A;
+  if (lap) pl->L = *p->L;
+  pl->p = *p;
+  pl->lap = lap;
+  pl->r = r;
+  pl->n = A->n;
+  pl->prec = p->prec;
+  pl->esz = elt_size(p->prec);
+  HIP_TRY(hipStreamCreateWithFlags(&pl->s, hipStreamNonBlocking));
+  HIP_TRY(hipEventCreateWithFlags(&pl->ev_in, hipEventDisableTiming));
+  HIP_TRY(hipEventCreateWithFlags(&pl->ev_out, hipEventDisableTiming));
+  if (user) {
+    HIP_TRY(hipEventRecord(pl->ev_in, user));
+    HIP_TRY(hipStreamWaitEvent(pl->s, pl->ev_in, 0));
+  }
+  const int64_t n = pl->n;
+  const size_t nr = (size_t)n * r * pl->esz;
+  int ksplit = 1;
+  if (A->fmt == SNMF_DENSE && pl->prec == SNMF_F32) pl->ds = plan_dense_f32(n);
+  if (A->fmt == SNMF_DENSE && pl->prec == SNMF_BF16X3) {
+    pl->ds = plan_dense_bf16(n);
+    pl->ldb = (n + 63) / 64 * 64;
+  }
+  if (A->fmt == SNMF_DENSE && pl->prec != SNMF_F64) ksplit = pl->ds.ksplit;
+  pl->gram_blocks = (int)std::min<int64_t>(64, std::max<int64_t>(1, (n + 127) / 128));
+  const int lai_nb = lai_blocks(n);
+  // carve one allocation
+  std::vector<std::pair<void**, size_t>> req;
+  auto add = [&](void** dst, size_t bytes) { req.push_back({dst, (bytes + 255) / 256 * 256}); };
+  add(&pl->Wb, nr);
+  add(&pl->Hb, nr);
+  add(&pl->C, nr);
+  add(&pl->g, nr);
+  add(&pl->Z, nr);
+  add(&pl->D, nr);
+  add(&pl->Bpart, nr * ksplit);
+  if (lap) {
+    add(&pl->LT, nr);
+    add(&pl->LX, nr);
+  }
+  add(&pl->GT[0], (size_t)r * r * pl->esz);
+  add(&pl->GT[1], (size_t)r * r * pl->esz);
+  add((void**)&pl->G64[0], (size_t)r * r * 8);
+  add((void**)&pl->G64[1], (size_t)r * r * 8);
+  add((void**)&pl->part, (size_t)2 * kMaxGrid * kNumPart * 8);
+  add((void**)&pl->gram_part, (size_t)pl->gram_blocks * r * r * 8);
+  add((void**)&pl->dots, 64 * 8);
+  add((void**)&pl->trace, (size_t)p->max_outer * kTraceFields * 8);
+  add((void**)&pl->st, sizeof(State));
+  add((void**)&pl->counters, C_COUNT * sizeof(unsigned));
+  add((void**)&pl->flags, 4 * sizeof(unsigned));
+  if (A->fmt == SNMF_LOWRANK) {
+    add((void**)&pl->lai_part, (size_t)lai_nb * A->ell * r * 8);
+    add(&pl->TT, (size_t)A->ell * r * pl->esz);
+  }
+  if (pl->prec == SNMF_BF16X3) {
+    add((void**)&pl->Ahi, (size_t)n * pl->ldb * 2);
+    add((void**)&pl->Alo, (size_t)n * pl->ldb * 2);
+    add((void**)&pl->Pthi, (size_t)r * pl->ldb * 2);
+    add((void**)&pl->Ptlo, (size_t)r * pl->ldb * 2);
+  }
+  size_t total = 0;
+  for (auto& q : req) total += q.second;
+  HIP_TRY(hipMalloc(&pl->pool, total));
+  size_t off = 0;
+  for (auto& q : req) {
+    *q.first = (char*)pl->pool + off;
+    off += q.second;
+  }
+  HIP_TRY(hipMemsetAsync(pl->counters, 0, C_COUNT * sizeof(unsigned), pl->s));
+  HIP_TRY(hipMemsetAsync(pl->st, 0, sizeof(State), pl->s));
+  // input checks and ||A||^2
+  double st3[3] = {0, 0, 0};
+  if (A->fmt == SNMF_DENSE) {
+    SNMF_TRY(stats_any(pl, A->dense, n, n, A->ld, st3));
+    if (p->validate) SNMF_TRY(check_values(st3, "A"));
+    pl->normA2 = st3[0];
+  } else if (A->fmt == SNMF_CSR) {
+    SNMF_TRY(check_csr(pl, A, "A", p->validate != 0, &pl->normA2));
+  } else {
+    std::vector<double> lam(A->ell);
+    HIP_TRY(hipMemcpyAsync(lam.data(), A->lam, A->ell * 8, hipMemcpyDeviceToHost, pl->s));
+    HIP_TRY(hipStreamSynchronize(pl->s));
+    double s2 = 0.0;
+    for (double v : lam) {
+      if (!std::isfinite(v)) return fail(SNMF_E_NONFINITE, "lam has NaN/Inf entries");
+      s2 += v * v;
+    }
+    pl->normA2 = s2;
+    if (p->validate) {
+      SNMF_TRY(stats_any(pl, A->U, n, A->ell, A->ell, st3));
+      if (st3[2] > 0) return fail(SNMF_E_NONFINITE, "U has NaN/Inf entries");
+    }
+  }
+  if (lap) SNMF_TRY(check_csr(pl, &pl->L, "L", false, nullptr));
+  if (!(pl->normA2 > 0.0)) return fail(SNMF_E_ARG, "A is zero");
+  if (pl->prec == SNMF_BF16X3) {
+    launch_split_rows((const float*)A->dense, n, A->ld, pl->ldb, pl->Ahi, pl->Alo, pl->s);
+    HIP_TRY(hipGetLastError());
+  }
+  SNMF_TRY(build_kparams(pl));
+  HIP_TRY(hipStreamSynchronize(pl->s));
+  *out = guard.release();
+  return SNMF_OK;
+}
+
+snmf_status read_info(snmf_plan* pl, snmf_info* info, double* trace) {
+  State hs;
+  HIP_TRY(hipMemcpyAsync(&hs, pl->st, sizeof(State), hipMemcpyDeviceToHost, pl->s));
+  HIP_TRY(hipStreamSynchronize(pl->s));
+  const double hz = snmf_clock_rate_hz();
+  std::vector<double> tr;
+  if (hs.trace_len > 0) {
+    tr.resize((size_t)hs.trace_len * kTraceFields);
+    HIP_TRY(hipMemcpyAsync(tr.data(), pl->trace, tr.size() * 8, hipMemcpyDeviceToHost, pl->s));
+    HIP_TRY(hipStreamSynchronize(pl->s));
+    if (trace) std::memcpy(trace, tr.data(), tr.size() * 8);
+  }
+  if (info) {
+    std::memset(info, 0, sizeof(*info));
+    info->status = hs.status;
+    info->outer = hs.outer;
+    info->converged_at = hs.converged_at;
+    info->inner_total = hs.inner_total;
+    info->ls_evals = hs.ls_evals;
+    info->ls_exhausted = hs.ls_exhausted;
+    info->res_WH = hs.res_last;
+    info->res_WWt = hs.resww_last;
+    info->sym_gap = hs.sym_last;
+    info->pg_norm = hs.pg_last;
+    info->objective = hs.f_last;
+    info->normA2 = pl->normA2;
+    info->seconds = hs.trace_len > 0 ? tr[(size_t)(hs.trace_len - 1) * kTraceFields + 5] / hz : 0.0;
+    info->seconds_to_target =
+        hs.converged_at > 0 ? tr[(size_t)(hs.converged_at - 1) * kTraceFields + 5] / hz : -1.0;
+  }
+  if (hs.status != 0) return fail((snmf_status)hs.status, "numeric breakdown during the solve");
+  return SNMF_OK;
+}
+
+snmf_status plan_solve(snmf_plan* pl, const void* W0, void* W_out, void* Ht_out, snmf_info* info,
+                       hipStream_t user, double* trace) {
+  if (!pl) return fail(SNMF_E_ARG, "plan is NULL");
+  if (!W0 || !W_out || !Ht_out) return fail(SNMF_E_ARG, "W0, W_out and Ht_out are required");
+  const int64_t n = pl->n;
+  const int r = pl->r;
+  const size_t nr = (size_t)n * r * pl->esz;
+  if (user) {
+    HIP_TRY(hipEventRecord(pl->ev_in, user));
+    HIP_TRY(hipStreamWaitEvent(pl->s, pl->ev_in, 0));
+  }
+  if (pl->p.validate) {
+    double st3[3];
+    SNMF_TRY(stats_any(pl, W0, n, r, r, st3));
+    SNMF_TRY(check_values(st3, "W0"));
+  }
+  HIP_TRY(hipMemcpyAsync(pl->Wb, W0, nr, hipMemcpyDeviceToDevice, pl->s));
+  HIP_TRY(hipMemcpyAsync(pl->Hb, W0, nr, hipMemcpyDeviceToDevice, pl->s));
+  launch_reset_state(pl->st, pl->normA2, pl->s);
+  HIP_TRY(hipGetLastError());
+  const int every = std::max(1, pl->p.check_every);
+  if (pl->p.use_graph && !pl->gexec) {
+    HIP_TRY(hipStreamBeginCapture(pl->s, hipStreamCaptureModeThreadLocal));
+    snmf_status cs = outer_any(pl, pl->s);
+    hipGraph_t gr = nullptr;
+    hipError_t ce = hipStreamEndCapture(pl->s, &gr);
+    if (cs != SNMF_OK) {
+      if (gr) (void)hipGraphDestroy(gr);
+      return cs;
+    }
+    if (ce != hipSuccess) return fail(SNMF_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(ce));
+    pl->graph = gr;
+    HIP_TRY(hipGraphInstantiate(&pl->gexec, gr, nullptr, nullptr, 0));
+  }
+  for (int i = 0; i < pl->p.max_outer; ++i) {
+    if (pl->gexec) {
+      HIP_TRY(hipGraphLaunch(pl->gexec, pl->s));
+    } else {
+      SNMF_TRY(outer_any(pl, pl->s));
+    }
+    if ((i + 1) % every == 0 && i + 1 < pl->p.max_outer) {
+      int32_t done = 0;
+      HIP_TRY(hipMemcpyAsync(&done, &pl->st->done, sizeof(done), hipMemcpyDeviceToHost, pl->s));
+      HIP_TRY(hipStreamSynchronize(pl->s));
+      if (done) break;
+    }
+  }
+  SNMF_TRY(finalize_any(pl, pl->s));
+  HIP_TRY(hipMemcpyAsync(W_out, pl->Wb, nr, hipMemcpyDeviceToDevice, pl->s));
+  HIP_TRY(hipMemcpyAsync(Ht_out, pl->Hb, nr, hipMemcpyDeviceToDevice, pl->s));
+  snmf_status rs = read_info(pl, info, trace);
+  if (user) {
+    HIP_TRY(hipEventRecord(pl->ev_out, pl->s));
+    HIP_TRY(hipStreamWaitEvent(user, pl->ev_out, 0));
+  }
+  return rs;
+}
+
+}  // namespace
+
+// ================================================================== C ABI
+extern "C" {
+
+snmf_status snmf_params_default(snmf_params* p) {
+  if (!p) return fail(SNMF_E_ARG, "params is NULL");
+  std::memset(p, 0, sizeof(*p));
+  p->lambda = 0.0;
+  p->gamma = 0.0;
+  p->L = nullptr;
+  p->eta = 0.85;
+  p->theta = 1e-3;
+  p->phi = 1.7;
+  p->alpha_min = 1e-10;
+  p->alpha_max = 1e10;
+  p->beta_shrink = 0.5;
+  p->max_ls = 20;
+  p->inner_iters = 5;
+  p->max_outer = 100;
+  p->check_every = 8;
+  p->target_res = 0.0;
+  p->prec = SNMF_F32;
+  p->accept_at_relaxed = 0;
+  p->project_update = 1;
+  p->validate = 1;
+  p->use_graph = 1;
+  return SNMF_OK;
+}
+
+snmf_status snmf_plan_create(const snmf_matrix* A, int32_t r, const snmf_params* p, void* stream,
+                             snmf_plan** out) {
+  return plan_create(A, r, p, (hipStream_t)stream, out);
+}
+
+snmf_status snmf_plan_solve(snmf_plan* plan, const void* W0, void* W_out, void* Ht_out,
+                            snmf_info* info, void* stream, double* trace) {
+  return plan_solve(plan, W0, W_out, Ht_out, info, (hipStream_t)stream, trace);
+}
+
+snmf_status snmf_plan_destroy(snmf_plan* plan) {
+  if (plan) {
+    (void)hipStreamSynchronize(plan->s);
+    delete plan;
+  }
+  return SNMF_OK;
+}
+
+snmf_status snmf_solve(const snmf_matrix* A, int32_t r, const void* W0, const snmf_params* p,
+                       void* W_out, void* Ht_out, snmf_info* info, void* stream, double* trace) {
+  snmf_plan* pl = nullptr;
+  SNMF_TRY(plan_create(A, r, p, (hipStream_t)stream, &pl));
+  snmf_status s = plan_solve(pl, W0, W_out, Ht_out, info, (hipStream_t)stream, trace);
+  std::string keep = g_err;
+  snmf_plan_destroy(pl);
+  g_err = keep;
+  return s;
+}
+
+snmf_status snmf_plan_half_step(snmf_plan* pl, void* X, const void* P, int32_t is_hstep,
+                                void* stream, double* scalars) {
+  if (!pl || !X || !P) return fail(SNMF_E_ARG, "plan, X and P are required");
+  hipStream_t user = (hipStream_t)stream;
+  if (user) {
+    HIP_TRY(hipEventRecord(pl->ev_in, user));
+    HIP_TRY(hipStreamWaitEvent(pl->s, pl->ev_in, 0));
+  }
+  launch_reset_state(pl->st, pl->normA2, pl->s);
+  if (pl->prec == SNMF_F64) {
+    SNMF_TRY(half_start<double>(pl, (double*)X, (const double*)P, is_hstep, true, pl->s));
+    SNMF_TRY(inner_steps<double>(pl, (double*)X, (const double*)P, is_hstep, pl->s));
+  } else {
+    SNMF_TRY(half_start<float>(pl, (float*)X, (const float*)P, is_hstep, true, pl->s));
+    SNMF_TRY(inner_steps<float>(pl, (float*)X, (const float*)P, is_hstep, pl->s));
+  }
+  State hs;
+  HIP_TRY(hipMemcpyAsync(&hs, pl->st, sizeof(State), hipMemcpyDeviceToHost, pl->s));
+  HIP_TRY(hipStreamSynchronize(pl->s));
+  if (scalars) {
+    scalars[0] = hs.rho;
+    scalars[1] = hs.alpha;
+    scalars[2] = hs.beta;
+    scalars[3] = hs.e;
+    scalars[4] = hs.ss;
+    scalars[5] = hs.sy;
+    scalars[6] = (double)hs.ls_evals;
+    scalars[7] = (double)hs.k;
+  }
+  if (user) {
+    HIP_TRY(hipEventRecord(pl->ev_out, pl->s));
+    HIP_TRY(hipStreamWaitEvent(user, pl->ev_out, 0));
+  }
+  if (hs.status != 0) return fail((snmf_status)hs.status, "numeric breakdown");
+  return SNMF_OK;
+}
+
+snmf_status snmf_plan_apass(snmf_plan* pl, const void* P, void* B, void* stream) {
+  if (!pl || !P || !B) return fail(SNMF_E_ARG, "plan, P and B are required");
+  hipStream_t user = (hipStream_t)stream;
+  if (user) {
+    HIP_TRY(hipEventRecord(pl->ev_in, user));
+    HIP_TRY(hipStreamWaitEvent(pl->s, pl->ev_in, 0));
+  }
+  HIP_TRY(hipMemsetAsync(pl->st, 0, sizeof(State), pl->s));
+  if (pl->prec == SNMF_F64)
+    SNMF_TRY(apass<double>(pl, (const double*)P, pl->s));
+  else
+    SNMF_TRY(apass<float>(pl, (const float*)P, pl->s));
+  // add the split-K partials on the device, in the same order as the init kernel
+  const int ks = ksplit_of(pl);
+  const int64_t nr = pl->n * pl->r;
+  if (pl->prec == SNMF_F64)
+    launch_sum_parts<double>((const double*)pl->Bpart, ks, nr, (double*)B, nr, pl->s);
+  else
+    launch_sum_parts<float>((const float*)pl->Bpart, ks, nr, (float*)B, nr, pl->s);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(pl->s));
+  if (user) {
+    HIP_TRY(hipEventRecord(pl->ev_out, pl->s));
+    HIP_TRY(hipStreamWaitEvent(user, pl->ev_out, 0));
+  }
+  return SNMF_OK;
+}
+
+snmf_status snmf_plan_gram(snmf_plan* pl, const void* P, double* G, void* stream) {
+  if (!pl || !P || !G) return fail(SNMF_E_ARG, "plan, P and G are required");
+  hipStream_t user = (hipStream_t)stream;
+  if (user) {
+    HIP_TRY(hipEventRecord(pl->ev_in, user));
+    HIP_TRY(hipStreamWaitEvent(pl->s, pl->ev_in, 0));
+  }
+  HIP_TRY(hipMemsetAsync(pl->st, 0, sizeof(State), pl->s));
+  if (pl->prec == SNMF_F64)
+    launch_gram<double>((const double*)P, pl->n, pl->r, pl->gram_part, pl->gram_blocks, pl->G64[0],
+                        (double*)pl->GT[0], pl->counters + C_GRAM, pl->st, pl->s);
+  else
+    launch_gram<float>((const float*)P, pl->n, pl->r, pl->gram_part, pl->gram_blocks, pl->G64[0],
+                       (float*)pl->GT[0], pl->counters + C_GRAM, pl->st, pl->s);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(G, pl->G64[0], (size_t)pl->r * pl->r * 8, hipMemcpyDeviceToDevice, pl->s));
+  HIP_TRY(hipStreamSynchronize(pl->s));
+  return SNMF_OK;
+}
+
+snmf_status snmf_rho(const double* G, int32_t r, double* rho, void* stream) {
+  if (!G || !rho) return fail(SNMF_E_ARG, "G and rho are required");
+  if (r < 1 || r > kMaxRank) return fail(SNMF_E_SHAPE, "r must lie in [1, 64]");
+  hipStream_t s = (hipStream_t)stream;
+  State* st = nullptr;
+  HIP_TRY(hipMalloc(&st, sizeof(State)));
+  DevBuf keep;
+  keep.p = st;
+  HIP_TRY(hipMemsetAsync(st, 0, sizeof(State), s));
+  launch_rho(G, r, st, s);
+  HIP_TRY(hipGetLastError());
+  State hs;
+  HIP_TRY(hipMemcpyAsync(&hs, st, sizeof(State), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  *rho = hs.rho;
+  return SNMF_OK;
+}
+
+snmf_status snmf_spmm(const snmf_matrix* M, int32_t prec, const void* X, int32_t r, void* Y,
+                      void* stream) {
+  SNMF_TRY(check_matrix(M, "M"));
+  if (M->fmt != SNMF_CSR) return fail(SNMF_E_UNSUPPORTED, "snmf_spmm needs a CSR matrix");
+  if (!X || !Y) return fail(SNMF_E_ARG, "X and Y are required");
+  if (r < 1 || r > kMaxRank) return fail(SNMF_E_SHAPE, "r must lie in [1, 64]");
+  hipStream_t s = (hipStream_t)stream;
+  if (prec == SNMF_F64)
+    launch_spmm<double>(M->rowptr, M->col, (const double*)M->val, (const double*)X, M->n, r,
+                        (double*)Y, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, s);
+  else
+    launch_spmm<float>(M->rowptr, M->col, (const float*)M->val, (const float*)X, M->n, r,
+                       (float*)Y, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, s);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(s));
+  return SNMF_OK;
+}
+
+snmf_status snmf_split_bf16(const float* x, int64_t count, uint16_t* hi, uint16_t* lo,
+                            void* stream) {
+  if (!x || !hi || !lo) return fail(SNMF_E_ARG, "x, hi and lo are required");
+  if (count < 0) return fail(SNMF_E_SHAPE, "count < 0");
+  if (count == 0) return SNMF_OK;
+  hipStream_t s = (hipStream_t)stream;
+  launch_split_flat(x, count, hi, lo, s);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(s));
+  return SNMF_OK;
+}
+
+double snmf_clock_rate_hz(void) {
+  int dev = 0, khz = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 1e8;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
+    return 1e8;
+  return (double)khz * 1e3;
+}
+
+const char* snmf_last_error(void) { return g_err.c_str(); }
+
+int32_t snmf_abi_version(void) { return SNMF_ABI_VERSION; }
+
+}  // extern "C"

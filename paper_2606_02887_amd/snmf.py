@@ -1,0 +1,269 @@
+"""ctypes binding of the HIP SNMPBB library (``libsnmf.so``, C ABI in include/snmf.h).
+
+Argument marshalling only: every step of the solve runs in the library's kernels.
+PyTorch provides device memory (tensors) and the current HIP stream.  Importing this
+module loads the library and raises if it has not been built -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_double, c_int32, c_int64, c_void_p
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsnmf.so")
+
+DENSE, CSR, LOWRANK = 0, 1, 2
+F64, F32, BF16X3 = 0, 1, 2
+TRACE_FIELDS = 10
+TRACE_NAMES = ("res_WH", "res_WWt", "sym_gap", "pg_norm", "objective", "ticks", "ls_evals",
+               "ls_exhausted", "alpha", "inner_total")
+STATUS = {0: "OK", 1: "E_ARG", 2: "E_SHAPE", 3: "E_NOT_SYMMETRIC", 4: "E_NEGATIVE",
+          5: "E_NONFINITE", 6: "E_OOM", 7: "E_DEVICE", 8: "E_UNSUPPORTED", 9: "E_BREAKDOWN"}
+
+
+class SnmfError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"snmf {STATUS.get(status, status)}: {msg}")
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+
+
+class Matrix(ctypes.Structure):
+    _fields_ = [("fmt", c_int32), ("reserved", c_int32), ("n", c_int64), ("dense", c_void_p),
+                ("ld", c_int64), ("rowptr", c_void_p), ("col", c_void_p), ("val", c_void_p),
+                ("nnz", c_int64), ("U", c_void_p), ("ell", c_int64), ("lam", c_void_p)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("lambda_", c_double), ("gamma", c_double), ("L", POINTER(Matrix)),
+                ("eta", c_double), ("theta", c_double), ("phi", c_double),
+                ("alpha_min", c_double), ("alpha_max", c_double), ("beta_shrink", c_double),
+                ("max_ls", c_int32), ("inner_iters", c_int32), ("max_outer", c_int32),
+                ("check_every", c_int32), ("target_res", c_double), ("prec", c_int32),
+                ("accept_at_relaxed", c_int32), ("project_update", c_int32),
+                ("validate", c_int32), ("use_graph", c_int32), ("reserved", c_int32)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("status", c_int32), ("outer", c_int32), ("converged_at", c_int32),
+                ("reserved", c_int32), ("inner_total", c_int64), ("ls_evals", c_int64),
+                ("ls_exhausted", c_int64), ("res_WH", c_double), ("res_WWt", c_double),
+                ("sym_gap", c_double), ("pg_norm", c_double), ("objective", c_double),
+                ("seconds", c_double), ("seconds_to_target", c_double), ("normA2", c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+EXPORTS = ("snmf_params_default", "snmf_solve", "snmf_plan_create", "snmf_plan_solve",
+           "snmf_plan_destroy", "snmf_plan_half_step", "snmf_plan_apass", "snmf_plan_gram",
+           "snmf_rho", "snmf_spmm", "snmf_split_bf16", "snmf_clock_rate_hz", "snmf_last_error",
+           "snmf_abi_version")
+
+
+def load_library(path: str = LIB_PATH):
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with __graft_entry__.build()")
+    lib = ctypes.CDLL(path)
+    vp = c_void_p
+    sig = {
+        "snmf_params_default": ([POINTER(Params)], c_int32),
+        "snmf_solve": ([POINTER(Matrix), c_int32, vp, POINTER(Params), vp, vp, POINTER(Info), vp,
+                        POINTER(c_double)], c_int32),
+        "snmf_plan_create": ([POINTER(Matrix), c_int32, POINTER(Params), vp, POINTER(vp)], c_int32),
+        "snmf_plan_solve": ([vp, vp, vp, vp, POINTER(Info), vp, POINTER(c_double)], c_int32),
+        "snmf_plan_destroy": ([vp], c_int32),
+        "snmf_plan_half_step": ([vp, vp, vp, c_int32, vp, POINTER(c_double)], c_int32),
+        "snmf_plan_apass": ([vp, vp, vp, vp], c_int32),
+        "snmf_plan_gram": ([vp, vp, vp, vp], c_int32),
+        "snmf_rho": ([vp, c_int32, POINTER(c_double), vp], c_int32),
+        "snmf_spmm": ([POINTER(Matrix), c_int32, vp, c_int32, vp, vp], c_int32),
+        "snmf_split_bf16": ([vp, c_int64, vp, vp, vp], c_int32),
+        "snmf_clock_rate_hz": ([], c_double),
+        "snmf_last_error": ([], ctypes.c_char_p),
+        "snmf_abi_version": ([], c_int32),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    return lib
+
+
+_lib = load_library()
+
+
+def _check(status):
+    if status != 0:
+        raise SnmfError(status, _lib.snmf_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def prec_of(dtype) -> int:
+    import torch
+    return F64 if dtype == torch.float64 else F32
+
+
+# ------------------------------------------------------------------ matrix descriptors
+class MatrixRef:
+    """A Matrix descriptor plus the tensors it points to (kept alive with it)."""
+
+    def __init__(self, desc: Matrix, keep):
+        self.desc = desc
+        self.keep = keep
+        self.n = desc.n
+
+
+def dense(A) -> MatrixRef:
+    assert A.is_cuda and A.dim() == 2 and A.stride(1) == 1
+    d = Matrix(fmt=DENSE, n=A.shape[0], dense=A.data_ptr(), ld=A.stride(0))
+    return MatrixRef(d, [A])
+
+
+def csr(rowptr, col, val, n: int) -> MatrixRef:
+    d = Matrix(fmt=CSR, n=n, rowptr=rowptr.data_ptr(), col=col.data_ptr() if col.numel() else 0,
+               val=val.data_ptr() if val.numel() else 0, nnz=val.numel())
+    return MatrixRef(d, [rowptr, col, val])
+
+
+def lowrank(U, lam) -> MatrixRef:
+    d = Matrix(fmt=LOWRANK, n=U.shape[0], U=U.data_ptr(), ell=U.shape[1], lam=lam.data_ptr())
+    return MatrixRef(d, [U, lam])
+
+
+def csr_from_scipy(a, dtype, device="cuda"):
+    """Upload a scipy CSR matrix (sorted indices) as a MatrixRef of the given dtype."""
+    import torch
+    a = a.tocsr()
+    a.sort_indices()
+    rowptr = torch.from_numpy(np.ascontiguousarray(a.indptr, dtype=np.int64)).to(device)
+    col = torch.from_numpy(np.ascontiguousarray(a.indices, dtype=np.int32)).to(device)
+    val = torch.from_numpy(np.ascontiguousarray(a.data)).to(device=device, dtype=dtype)
+    return csr(rowptr, col, val, a.shape[0])
+
+
+# ------------------------------------------------------------------ parameters
+def params(**kw) -> Params:
+    p = Params()
+    _check(_lib.snmf_params_default(ctypes.byref(p)))
+    for k, v in kw.items():
+        if k == "lam":
+            k = "lambda_"
+        if k == "L":
+            continue
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+# ------------------------------------------------------------------ plans
+class Plan:
+    """Owns a library plan: repeated solves of one A (and L) with reused scratch memory."""
+
+    def __init__(self, A: MatrixRef, r: int, prm: Params, L: MatrixRef | None = None):
+        self._A, self._L = A, L
+        self._prm = prm
+        if L is not None:
+            prm.L = ctypes.pointer(L.desc)
+        self.max_outer = prm.max_outer
+        self.r = r
+        self.n = A.n
+        h = ctypes.c_void_p()
+        _check(_lib.snmf_plan_create(ctypes.byref(A.desc), r, ctypes.byref(prm), _stream(),
+                                     ctypes.byref(h)))
+        self._h = h
+
+    def solve(self, W0, W_out=None, Ht_out=None, trace: bool = True):
+        import torch
+        W_out = torch.empty_like(W0) if W_out is None else W_out
+        Ht_out = torch.empty_like(W0) if Ht_out is None else Ht_out
+        info = Info()
+        tr = (c_double * (self.max_outer * TRACE_FIELDS))() if trace else None
+        st = _lib.snmf_plan_solve(self._h, _ptr(W0), _ptr(W_out), _ptr(Ht_out),
+                                  ctypes.byref(info), _stream(), tr)
+        _check(st)
+        out = info.as_dict()
+        if trace:
+            arr = np.frombuffer(tr, dtype=np.float64).reshape(self.max_outer, TRACE_FIELDS)
+            out["trace"] = arr[: info.outer].copy()
+        return W_out, Ht_out, out
+
+    def half_step(self, X, P, is_hstep: bool):
+        sc = (c_double * 8)()
+        _check(_lib.snmf_plan_half_step(self._h, _ptr(X), _ptr(P), int(is_hstep), _stream(), sc))
+        keys = ("rho", "alpha", "beta", "e", "ss", "sy", "ls_evals", "inner_done")
+        return dict(zip(keys, list(sc)))
+
+    def apass(self, P, B):
+        _check(_lib.snmf_plan_apass(self._h, _ptr(P), _ptr(B), _stream()))
+        return B
+
+    def gram(self, P):
+        import torch
+        G = torch.empty((self.r, self.r), dtype=torch.float64, device=P.device)
+        _check(_lib.snmf_plan_gram(self._h, _ptr(P), _ptr(G), _stream()))
+        return G
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.snmf_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+def solve(A: MatrixRef, W0, prm: Params, L: MatrixRef | None = None, trace: bool = True):
+    with Plan(A, W0.shape[1], prm, L) as pl:
+        return pl.solve(W0, trace=trace)
+
+
+def rho(G) -> float:
+    out = c_double()
+    _check(_lib.snmf_rho(_ptr(G), G.shape[0], ctypes.byref(out), _stream()))
+    return out.value
+
+
+def spmm(M: MatrixRef, X, Y=None):
+    import torch
+    Y = torch.empty_like(X) if Y is None else Y
+    _check(_lib.snmf_spmm(ctypes.byref(M.desc), prec_of(X.dtype), _ptr(X), X.shape[1], _ptr(Y),
+                          _stream()))
+    return Y
+
+
+def split_bf16(x):
+    import torch
+    hi = torch.empty(x.shape, dtype=torch.int16, device=x.device)
+    lo = torch.empty(x.shape, dtype=torch.int16, device=x.device)
+    _check(_lib.snmf_split_bf16(_ptr(x), x.numel(), _ptr(hi), _ptr(lo), _stream()))
+    return hi, lo
+
+
+def clock_rate_hz() -> float:
+    return _lib.snmf_clock_rate_hz()
+
+
+def abi_version() -> int:
+    return _lib.snmf_abi_version()

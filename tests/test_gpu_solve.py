@@ -1,0 +1,271 @@
+"""Step-level (lockstep) and whole-solve parity of the HIP SNMPBB path against the oracle.
+
+Lockstep: both sides start a half-step from the same (X, P) and run the same number of
+inner iterations; the results must agree to 1e-12 (FP64) / 1e-5 (FP32) normwise, and
+the device scalars (rho, final BB step, accepted beta, <S,S>, <S,Y>) must match.
+Whole solve: final residual ||A - W H||/||A|| and projected-gradient norm within 1e-3
+relative of the oracle after the same number of outer iterations.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle as O
+from paper_2606_02887_amd import gen
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+@pytest.fixture(scope="module")
+def S():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2606_02887_amd import snmf
+    return snmf
+
+
+def nrel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    d = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (d if d > 0 else 1.0)
+
+
+def _t(x, dtype):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV, dtype)
+
+
+DT = {"f64": torch.float64, "f32": torch.float32}
+
+
+def _prec(S, p):
+    return {"f64": S.F64, "f32": S.F32, "bf16x3": S.BF16X3}[p]
+
+
+def _lockstep(S, Aop_gpu, Aop_oracle, X, P, prec, is_hstep, lam, gamma=0.0, L_gpu=None,
+              L_or=None, inner=5):
+    dt = DT["f32" if prec == "bf16x3" else prec]
+    Xt, Pt = _t(X, dt), _t(P, dt)
+    X_in, P_in = Xt.double().cpu().numpy(), Pt.double().cpu().numpy()
+    prm = S.params(lam=lam, gamma=gamma, prec=_prec(S, prec), inner_iters=inner, max_outer=1,
+                   validate=0)
+    pl = S.Plan(Aop_gpu, X.shape[1], prm, L_gpu)
+    sc = pl.half_step(Xt, Pt, bool(is_hstep))
+    pl.close()
+    log = []
+    oprm = O.Params(lam=lam, gamma=gamma, inner_iters=inner)
+    Xo = O.half_step(Aop_oracle, X_in, P_in, oprm, laplacian=bool(is_hstep) and L_or is not None,
+                     L=L_or, log=log)
+    return Xt.double().cpu().numpy(), Xo, sc, log
+
+
+def _check_scalars(sc, log, tol):
+    last = log[-1]
+    assert abs(sc["rho"] - log[0]["rho"]) <= tol * log[0]["rho"]
+    assert abs(sc["beta"] - last["beta"]) <= tol
+    assert abs(sc["ss"] - last["ss"]) <= tol * max(last["ss"], 1e-300) + 1e-300
+    assert abs(sc["sy"] - last["sy"]) <= tol * max(abs(last["sy"]), 1e-300) + 1e-300
+    assert int(sc["ls_evals"]) == sum(e["evals"] for e in log)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("is_hstep", [0, 1])
+@pytest.mark.parametrize("n,r", [(300, 8), (700, 33)])
+def test_half_step_lockstep_dense(S, prec, is_hstep, n, r):
+    prob = gen.planted_dense(n, r, 101 + n)
+    A = prob["A"]
+    rng = np.random.default_rng(5)
+    X = prob["W0"]
+    P = np.maximum(prob["Wstar"] + 0.05 * rng.standard_normal((n, r)), 0)
+    At = _t(A, DT[prec])
+    A_in = At.double().cpu().numpy()
+    lam = O.default_lambda(A_in)
+    Xg, Xo, sc, log = _lockstep(S, S.dense(At), A_in, X, P, prec, is_hstep, lam)
+    tol = 1e-12 if prec == "f64" else 1e-5
+    assert nrel(Xg, Xo) <= tol
+    _check_scalars(sc, log, 1e-10 if prec == "f64" else 1e-4)
+    assert (Xg >= 0).all()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_half_step_lockstep_graph_laplacian(S, prec):
+    """H-step of Graph-SNMPBB: gradient term gam L Ht and the <D, L D> curvature."""
+    p = gen.sbm_problem(n=600, k=4, r=4, p_in=0.1, p_out=0.01, seed=17)
+    A, L = p["A"], p["L"]
+    rng = np.random.default_rng(2)
+    X = p["W0"]
+    P = rng.random(X.shape) * X.mean()
+    dt = DT[prec]
+    Ag, Lg = S.csr_from_scipy(A, dt), S.csr_from_scipy(L, dt)
+    A_in = sp.csr_matrix((Ag.keep[2].double().cpu().numpy(), A.indices, A.indptr), A.shape)
+    L_in = sp.csr_matrix((Lg.keep[2].double().cpu().numpy(), L.indices, L.indptr), L.shape)
+    lam = O.default_lambda(A_in)
+    Xg, Xo, sc, log = _lockstep(S, Ag, A_in, X, P, prec, 1, lam, gamma=0.2, L_gpu=Lg, L_or=L_in)
+    tol = 1e-12 if prec == "f64" else 1e-5
+    assert nrel(Xg, Xo) <= tol
+    _check_scalars(sc, log, 1e-10 if prec == "f64" else 1e-4)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_half_step_lockstep_lai(S, prec):
+    n, ell, r = 3000, 24, 6
+    a = gen.powerlaw_csr(n=n, seed=9)
+    U, lam_ = gen.range_finder(a, ell, 6, 2, 3)
+    rng = np.random.default_rng(4)
+    X = rng.random((n, r)) * 0.05
+    P = rng.random((n, r)) * 0.05
+    dt = DT[prec]
+    Ut = _t(U, dt)
+    lr_in = O.LowRank(Ut.double().cpu().numpy(), lam_)
+    lam = O.default_lambda(lr_in)
+    Xg, Xo, sc, log = _lockstep(S, S.lowrank(Ut, _t(lam_, torch.float64)), lr_in, X, P, prec, 0,
+                                lam)
+    tol = 1e-12 if prec == "f64" else 1e-5
+    assert nrel(Xg, Xo) <= tol
+    _check_scalars(sc, log, 1e-10 if prec == "f64" else 1e-4)
+
+
+def test_half_step_ragged_rank_and_tail(S):
+    """r = 1 and n not a multiple of any tile: exact FP64 agreement."""
+    prob = gen.planted_dense(517, 1, 3)
+    A = prob["A"]
+    rng = np.random.default_rng(1)
+    P = rng.random((517, 1))
+    Xg, Xo, sc, log = _lockstep(S, S.dense(_t(A, torch.float64)), A, prob["W0"], P, "f64", 0,
+                                O.default_lambda(A), inner=9)
+    assert nrel(Xg, Xo) <= 1e-12
+
+
+# ------------------------------------------------------------------ whole solves
+def _whole(S, A_gpu, A_or, W0, prec, outer, lam, gamma=0.0, L_gpu=None, L_or=None):
+    dt = DT["f32" if prec == "bf16x3" else prec]
+    W0t = _t(W0, dt)
+    prm = S.params(lam=lam, gamma=gamma, prec=_prec(S, prec), max_outer=outer)
+    W, Ht, info = S.solve(A_gpu, W0t, prm, L_gpu)
+    _, _, hist = O.snmpbb(A_or, W0t.double().cpu().numpy(), O.Params(lam=lam, gamma=gamma), outer,
+                          L=L_or)
+    return W.double().cpu().numpy(), Ht.double().cpu().numpy(), info, hist
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3"])
+def test_whole_solve_config0(S, prec):
+    """Config 0: planted dense n=500, r=10, 500 outer iterations."""
+    prob = gen.config(0)
+    A = prob["A"]
+    dt = DT["f32" if prec == "bf16x3" else prec]
+    At = _t(A, dt)
+    A_in = At.double().cpu().numpy()
+    lam = O.default_lambda(A_in)
+    W, Ht, info, hist = _whole(S, S.dense(At), A_in, prob["W0"], prec, 500, lam)
+    ref = hist[-1]
+    assert info["outer"] == 500 and info["status"] == 0
+    assert abs(info["res_WH"] - ref["res_WH"]) <= 1e-3 * ref["res_WH"]
+    assert abs(info["pg_norm"] - ref["pg"]) <= 1e-3 * ref["pg"] or prec != "f64"
+    # the device monitor agrees with the residual of the returned factors
+    direct = O.residual_WH(A_in, W, Ht)
+    tol = 1e-10 if prec == "f64" else 1e-4
+    assert abs(info["res_WH"] - direct) <= tol * direct
+    assert (W >= 0).all() and (Ht >= 0).all()
+    tr = info["trace"]
+    assert tr.shape == (500, 10) and np.all(np.diff(tr[:, 5]) >= 0)
+
+
+def test_whole_solve_trace_matches_oracle_history(S):
+    prob = gen.planted_dense(200, 5, 44)
+    A = prob["A"]
+    lam = O.default_lambda(A)
+    W, Ht, info, hist = _whole(S, S.dense(_t(A, torch.float64)), A, prob["W0"], "f64", 40, lam)
+    tr = info["trace"]
+    ores = np.array([h["res_WH"] for h in hist])
+    opg = np.array([h["pg"] for h in hist])
+    osym = np.array([h["sym_gap"] for h in hist])
+    assert np.abs(tr[:, 0] - ores).max() <= 1e-9 * ores.max()
+    assert np.abs(tr[:, 3] - opg).max() <= 1e-6 * opg.max()
+    assert np.abs(tr[:, 2] - osym).max() <= 1e-9
+
+
+def test_whole_solve_graph(S):
+    p = gen.sbm_problem(n=1000, k=5, r=5, p_in=0.08, p_out=0.004, seed=23)
+    A, L = p["A"], p["L"]
+    Ag, Lg = S.csr_from_scipy(A, torch.float64), S.csr_from_scipy(L, torch.float64)
+    lam = O.default_lambda(A)
+    W, Ht, info, hist = _whole(S, Ag, A, p["W0"], "f64", 60, lam, gamma=0.2, L_gpu=Lg, L_or=L)
+    ref = hist[-1]
+    assert abs(info["res_WH"] - ref["res_WH"]) <= 1e-3 * ref["res_WH"]
+    assert abs(info["pg_norm"] - ref["pg"]) <= 1e-3 * ref["pg"]
+
+
+def test_whole_solve_lai(S):
+    n = 5000
+    a = gen.powerlaw_csr(n=n, seed=31)
+    U, lam_ = gen.range_finder(a, 32, 10, 2, 5)
+    lr = O.LowRank(U, lam_)
+    rng = np.random.default_rng(8)
+    W0 = gen.start_factor(rng, n, 8, gen.mean_of_sparse(a))
+    lam = O.default_lambda(lr)
+    W, Ht, info, hist = _whole(S, S.lowrank(_t(U, torch.float64), _t(lam_, torch.float64)), lr,
+                               W0, "f64", 30, lam)
+    ref = hist[-1]
+    assert abs(info["res_WH"] - ref["res_WH"]) <= 1e-3 * ref["res_WH"]
+
+
+def test_target_residual_stops_early(S):
+    prob = gen.planted_dense(300, 6, 9)
+    A = prob["A"]
+    lam = O.default_lambda(A)
+    _, _, hist = O.snmpbb(A, prob["W0"], O.Params(lam=lam), 200)
+    tgt = hist[30]["res_WH"]
+    prm = S.params(lam=lam, prec=S.F64, max_outer=200, target_res=tgt, check_every=4)
+    W, Ht, info = S.solve(S.dense(_t(A, torch.float64)), _t(prob["W0"], torch.float64), prm)
+    first = next(i for i, h in enumerate(hist) if h["res_WH"] <= tgt) + 1
+    assert info["converged_at"] == first == info["outer"]
+    assert info["seconds_to_target"] > 0
+
+
+def test_deterministic_bitwise(S):
+    prob = gen.planted_dense(400, 12, 10)
+    At = _t(prob["A"], torch.float32)
+    W0 = _t(prob["W0"], torch.float32)
+    prm = S.params(lam=O.default_lambda(prob["A"]), max_outer=30)
+    W1, H1, _ = S.solve(S.dense(At), W0, prm)
+    W2, H2, _ = S.solve(S.dense(At), W0, prm)
+    assert torch.equal(W1, W2) and torch.equal(H1, H2)
+
+
+def test_graph_replay_equals_direct_launches(S):
+    prob = gen.planted_dense(300, 7, 12)
+    At = _t(prob["A"], torch.float32)
+    W0 = _t(prob["W0"], torch.float32)
+    lam = O.default_lambda(prob["A"])
+    Wa, Ha, ia = S.solve(S.dense(At), W0, S.params(lam=lam, max_outer=25, use_graph=1))
+    Wb, Hb, ib = S.solve(S.dense(At), W0, S.params(lam=lam, max_outer=25, use_graph=0))
+    assert torch.equal(Wa, Wb) and torch.equal(Ha, Hb)
+    assert np.array_equal(ia["trace"][:, :5], ib["trace"][:, :5])
+
+
+# ------------------------------------------------------------------ error paths
+def test_error_codes(S):
+    prob = gen.planted_dense(50, 3, 1)
+    A = prob["A"].copy()
+    W0 = prob["W0"].copy()
+    prm = S.params(prec=S.F64, max_outer=2)
+    bad = W0.copy()
+    bad[3, 1] = np.nan
+    with pytest.raises(S.SnmfError) as e:
+        S.solve(S.dense(_t(A, torch.float64)), _t(bad, torch.float64), prm)
+    assert e.value.name == "E_NONFINITE"
+    neg = A.copy()
+    neg[2, 5] = neg[5, 2] = -1.0
+    with pytest.raises(S.SnmfError) as e:
+        S.solve(S.dense(_t(neg, torch.float64)), _t(W0, torch.float64), prm)
+    assert e.value.name == "E_NEGATIVE"
+    a = sp.random(60, 60, density=0.1, random_state=1, format="csr")
+    with pytest.raises(S.SnmfError) as e:
+        S.solve(S.csr_from_scipy(a, torch.float64), _t(np.ones((60, 3)), torch.float64), prm)
+    assert e.value.name == "E_NOT_SYMMETRIC"
+    z = np.zeros((50, 3))
+    with pytest.raises(S.SnmfError) as e:
+        S.solve(S.dense(_t(A, torch.float64)), _t(z, torch.float64), prm)
+    assert e.value.name == "E_BREAKDOWN"
