@@ -1,0 +1,159 @@
+"""SNMPBB benchmark on one MI355X: outer iterations per second and time to target on the
+planted dense workload n=8192, r=64 (A = W* W*^T + E, FP32), plain FP32 form vs the
+split-BF16 form.
+
+A "step" is one outer iteration of the method: a W-step and an H-step, each = Gram,
+rho, the A-pass A P, the gradient, and 5 inner NMPBB iterations.  The timed region runs
+exactly --steps outer iterations through the C ABI with A already resident in HBM.
+Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+N, R = 8192, 64
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+BF16_PEAK_TFLOPS = 2500.0
+
+
+def _args():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--target-outer", type=int, default=2000,
+                    help="iteration cap of the time-to-target runs")
+    ap.add_argument("--no-target", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-outer", type=int, default=0,
+                    help="outer iterations of the CPU-reference sample (0: pick ~15 s)")
+    return ap.parse_args()
+
+
+def _cpu_baseline(A64, W0, lam, outer):
+    """The FP64 CPU reference, timed on a bounded sample of the same workload."""
+    import oracle as O
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()
+                       if i.get("user_api") == "blas"] or [1])
+    except Exception:  # pragma: no cover
+        threads = os.cpu_count() or 1
+    t0 = time.perf_counter()
+    O.snmpbb(A64, W0, O.Params(lam=lam), 1)
+    one = time.perf_counter() - t0
+    if outer <= 0:
+        outer = max(2, min(60, int(15.0 / max(one, 1e-3))))
+    t0 = time.perf_counter()
+    O.snmpbb(A64, W0, O.Params(lam=lam), outer)
+    dt = time.perf_counter() - t0
+    return {"value": outer / dt, "unit": "outer iterations/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": f"{outer} outer iterations of the FP64 numpy reference on the same "
+                      f"n={N}, r={R} workload ({dt:.1f} s)"}
+
+
+def main():
+    a = _args()
+    if a.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported "
+              "(the multi-GPU row sharding is a design, not part of this build).")
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2606_02887_amd import gen
+    from paper_2606_02887_amd import snmf as S
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    prob = gen.config(1)                                  # planted dense n=8192, r=64
+    A64, W064 = prob["A"], prob["W0"]
+    lam = 0.01 * float(np.sqrt(np.sum(A64 * A64)))        # lambda = 0.01 ||A||_F
+    A = torch.from_numpy(A64.astype(np.float32)).to(dev)
+    W0 = torch.from_numpy(W064.astype(np.float32)).to(dev)
+    torch.cuda.synchronize()
+
+    forms = {}
+    plans = {}
+    for name, prec in (("fp32", S.F32), ("bf16x3", S.BF16X3)):
+        pl = S.Plan(S.dense(A), R, S.params(lam=lam, prec=prec, max_outer=a.steps,
+                                            check_every=1 << 30))
+        plans[name] = pl
+        wp = S.Plan(S.dense(A), R, S.params(lam=lam, prec=prec, max_outer=max(1, a.warmup)))
+        wp.solve(W0, trace=False)                        # warmup (graph capture, clocks)
+        wp.close()
+        pl.solve(W0, trace=False)                        # first call captures its graph
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, info = pl.solve(W0, trace=True)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        forms[name] = {"outer_per_s": a.steps / el, "ms_per_outer": 1e3 * el / a.steps,
+                       "device_ms_per_outer": 1e3 * info["seconds"] / max(info["outer"], 1),
+                       "res_WH": info["res_WH"], "pg_norm": info["pg_norm"],
+                       "outer": info["outer"]}
+
+    # ---------------------------------------------------------------- roofline (A-pass)
+    P = W0.clone()
+    ms32 = plans["fp32"].time_apass(P, 50)
+    flops = 2.0 * N * N * R
+    ach32 = flops / (ms32 * 1e-3) / 1e12
+    msbf = plans["bf16x3"].time_apass(P, 50)
+    bytes_bf = 2.0 * 2 * N * N + 2.0 * 2 * N * R + 4.0 * N * R   # A_hi, A_lo, P_hi/lo, B
+    achbf = bytes_bf / (msbf * 1e-3) / 1e9
+    roof = {"bound": "mfma", "achieved": ach32, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": ach32 / FP32_PEAK_TFLOPS, "traffic": None,
+            "kernel": "k_apass_f32 (B = A P, FP32 MFMA)", "ms_per_launch": ms32,
+            "algorithmic_per_launch": f"{flops:.4g} flop (2 n^2 r)"}
+    forms["bf16x3"]["apass"] = {"bound": "hbm", "achieved": achbf, "peak": HBM_PEAK_GBS,
+                                "unit": "GB/s", "frac": achbf / HBM_PEAK_GBS,
+                                "ms_per_launch": msbf,
+                                "tflops": 3 * flops / (msbf * 1e-3) / 1e12}
+
+    # ---------------------------------------------------------------- time to target
+    ref_path = os.path.join(ROOT, "tests", "golden", "c1_reference.json")
+    target = None
+    if not a.no_target and os.path.exists(ref_path):
+        ref = json.load(open(ref_path))
+        target = (1 + 1e-4) * ref["res_ref"]
+        for name, prec in (("fp32", S.F32), ("bf16x3", S.BF16X3)):
+            with S.Plan(S.dense(A), R, S.params(lam=lam, prec=prec, max_outer=a.target_outer,
+                                                target_res=target, check_every=16)) as tp:
+                _, _, info = tp.solve(W0, trace=True)
+            forms[name]["time_to_target_s"] = info["seconds_to_target"] if info["converged_at"] else None
+            forms[name]["outer_to_target"] = info["converged_at"] or None
+            forms[name]["final_res_after_cap"] = info["res_WH"]
+            forms[name]["gap_to_target"] = info["res_WH"] / target - 1.0
+        forms["target"] = {"res": target, "rule": "(1 + 1e-4) x FP64 reference residual after "
+                           f"{ref['outer']} outer iterations", "res_ref": ref["res_ref"]}
+
+    for pl in plans.values():
+        pl.close()
+
+    cpu = None
+    if not a.no_cpu_baseline:
+        cpu = _cpu_baseline(A64, W064, lam, a.cpu_outer)
+
+    f32 = forms["fp32"]
+    out = {"metric": "SNMPBB outer iterations/s (n=8192, r=64, plain FP32)",
+           "value": f32["outer_per_s"], "unit": "outer iterations/s", "n_gpus": 1,
+           "steps": a.steps, "warmup": a.warmup, "ms_per_step": f32["ms_per_outer"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic", "config": {"workload": "planted dense A = W* W*^T + E, seed 1001",
+                                           "n": N, "r": R, "inner_iters": 5,
+                                           "parallelism": "single GPU"},
+           "roofline": roof, "cpu_baseline": cpu, "forms": forms}
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

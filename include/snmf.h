@@ -96,7 +96,7 @@ typedef struct snmf_params {
   double alpha_max;    /*                                                             [1e10] */
   double beta_shrink;  /* backtracking factor, 0 < beta_shrink < 1                     [0.5] */
   int32_t max_ls;      /* backtracking reductions per inner iteration, >= 0             [20] */
-  int32_t inner_iters; /* inner iterations per half-step, >= 1                           [5] */
+  int32_t inner_iters; /* inner iterations per half-step, 1..64                           [5] */
   int32_t max_outer;   /* outer (W-step + H-step) iterations, >= 1                      [100] */
   int32_t check_every; /* host checks the stop flag every this many outer iterations     [8] */
   double target_res;   /* stop at the first outer iteration with ||A - W H||/||A|| <= this
@@ -155,8 +155,9 @@ snmf_status snmf_plan_destroy(snmf_plan* plan);
 /* One half-step of SNMPBB (Algorithm 1 run for inner_iters iterations) with the partner
  * block P fixed: X (n x r, in/out) is W (is_hstep = 0, P = Ht) or Ht (is_hstep = 1,
  * P = W, the Laplacian term applies).  Used to check the method step by step.
- * scalars (host, optional, 8 doubles): {rho, alpha_next, beta_last, e, ss, sy, ls_evals,
- * inner_done}. */
+ * scalars (host, optional, 8 doubles): {rho, alpha, beta, e of the last inner iteration
+ * that ran, <S,S> and <S,Y> of the last update, line-search trials, inner iterations run}.
+ * inner_iters <= 64. */
 snmf_status snmf_plan_half_step(snmf_plan* plan, void* X, const void* P, int32_t is_hstep,
                                 void* stream, double* scalars);
 
@@ -172,6 +173,12 @@ snmf_status snmf_plan_gram(snmf_plan* plan, const void* P, double* G, void* stre
 snmf_status snmf_rho(const double* G, int32_t r, double* rho, void* stream);
 snmf_status snmf_spmm(const snmf_matrix* M, int32_t prec, const void* X, int32_t r, void* Y,
                       void* stream);
+/* Average duration (ms) of the A-pass kernels (the dense MFMA product, the CSR SpMM or
+ * the three LAI kernels; for BF16X3 the partner split runs once, untimed) over `reps`
+ * back-to-back launches on the plan's stream, measured with HIP events after one
+ * untimed launch.  P is an n x r device array; the products land in plan scratch. */
+snmf_status snmf_plan_time_apass(snmf_plan* plan, const void* P, int32_t reps, double* ms);
+
 /* BF16 round-to-nearest-even split of n*ld floats: hi = bf16(x), lo = bf16(x - hi);
  * hi and lo are uint16 device arrays of n*ld elements. */
 snmf_status snmf_split_bf16(const float* x, int64_t count, uint16_t* hi, uint16_t* lo,

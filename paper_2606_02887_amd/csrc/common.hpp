@@ -12,38 +12,40 @@ constexpr int kMaxGrid = 1024;         // row-tile kernels use at most this many
 constexpr int kNumPart = 16;           // FP64 partial sums per workgroup
 constexpr int kTraceFields = 10;       // doubles per outer-iteration trace record
 
-// Counters for the "last workgroup finishes the reduction" pattern; one per kernel kind
-// so that kernels running concurrently on two streams never share one.
+constexpr int kMaxInner = 64;         // largest number of inner iterations per half-step
+constexpr int kInnerGrid = 256;        // workgroups of the row-tile kernels (re-reduced)
+
+// Counters of the setup kernels that finish a reduction in their last workgroup.
 enum Counter { C_GRAM = 0, C_INIT, C_STEP1, C_STEP2, C_NORM, C_LAI, C_LAPRED, C_MISC, C_COUNT };
 
-// Scalars of the iteration that live on the device for the whole solve.  Only the last
-// workgroup of a kernel writes them; every other access is a read at kernel start.
+// Scalars of the iteration that live on the device for the whole solve.
+// Hot-path kernels never finish a reduction inside themselves: each writes FP64 partial
+// sums per workgroup, and the NEXT kernel re-reduces those partials in every workgroup in
+// the same fixed order, so all workgroups derive bit-identical scalars (line-search beta,
+// BB step, stop decisions) without atomics or device-scope fences.  Workgroup 0 stores
+// the scalars here for later kernels.  A kernel never reads a field that it writes: the
+// per-inner-iteration values are indexed by the inner iteration k.
 struct State {
-  // half-step
-  double rho;          // ||P^T P||_2
-  double alpha;        // BB step for the next inner iteration
-  double beta;         // accepted backtracking factor of the current inner iteration
-  double e;            // F_k - f(X_k) >= 0 (nonmonotone reference minus objective)
-  double ss, sy, gs;   // <S,S>, <S,Y>, <g_k,S> of the last update
-  double delta, q, dZ; // <grad f(Z),D>, <D,(G+lam I)D>[+gam<D,LD>], f(Z)-f(X_k)
-  double nd2;          // ||D||^2
-  double normA2;       // ||A||_F^2
-  // monitor staging (written by the H-step, consumed at the next W-step start)
-  double m_CX, m_PX, m_XmP2, m_pgH2, m_CP, m_PP, m_XLX;
-  double pgW2;         // ||min(W, grad_W)||^2 at the last completed outer iteration
+  double rho;                  // ||P^T P||_2 of the current half-step
+  double e[kMaxInner + 1];     // e_k = F_k - f(X_k)
+  double alpha[kMaxInner + 1]; // BB step used by inner iteration k
+  double beta[kMaxInner + 1];  // accepted backtracking factor of inner iteration k
+  int32_t stop[kMaxInner + 1]; // the half-step ended before inner iteration k (S = 0)
+  int32_t pad1;
+  double normA2;               // ||A||_F^2
+  double m_CP;                 // <C, P> of the last H-step (C = A W + lam W, P = W)
+  double last_ss, last_sy;     // BB scalars of the last completed update
   double res_last, resww_last, sym_last, pg_last, f_last;
-  uint64_t t_hstep;    // constant-rate device clock at the end of the last H-step
-  uint64_t t0;         // device clock at solve start
-  int32_t pending;     // an H-step finished and its monitor record awaits the next W-step
-  int32_t pad0;
-  int32_t hs_done;     // current half-step stopped early (S = 0)
-  int32_t done;        // solve finished: every later kernel returns at once
-  int32_t k;           // inner iteration index in the current half-step
-  int32_t outer;       // completed outer iterations
-  int32_t status;      // 0 ok, otherwise a snmf_status breakdown code
-  int32_t converged_at;// first outer iteration whose residual met the target (1-based), 0 none
+  uint64_t t_hstep;            // device clock when the last H-step update finished
+  uint64_t t0;                 // device clock at solve start
+  int32_t pending;             // an H-step finished; its monitor record is still open
+  int32_t snap_pending;        // W-step init's copy of pending
+  int32_t outer;               // completed (recorded) outer iterations
+  int32_t snap_outer;          // W-step init's copy of outer
+  int32_t done;                // the solve is finished: every later kernel returns at once
+  int32_t status;              // 0 ok, otherwise a snmf_status breakdown code
+  int32_t converged_at;        // first outer iteration meeting the target (1-based), 0 none
   int32_t trace_len;
-  int32_t is_hstep;
   int64_t ls_evals, ls_exhausted, inner_total;
 };
 
@@ -53,9 +55,37 @@ struct KParams {
   int32_t max_ls, relaxed, project, max_outer;
 };
 
+// Cross-lane data movement with DPP (GFX9 encoding).  Lanes whose source is outside the
+// row read 0 (bound control), masked-off rows keep 0.
+template <int CTRL, int ROWMASK = 0xf>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWMASK, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWMASK, 0xf, true);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes of a wave in a fixed pattern (row shifts 1, 2, 4, 8, then row
+// broadcasts 15 and 31); the result is wave-uniform.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  v += dpp_d<0x111>(v);        // row_shr:1
+  v += dpp_d<0x112>(v);        // row_shr:2
+  v += dpp_d<0x114>(v);        // row_shr:4
+  v += dpp_d<0x118>(v);        // row_shr:8
+  v += dpp_d<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+  v += dpp_d<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
+  return readlane_d(v, 63);
+}
+
+// Sum over aligned groups of 4 lanes; every lane of the group gets the same bits.
+__device__ __forceinline__ double quad_sum(double v) {
+  v += dpp_d<0xB1>(v);         // quad_perm [1,0,3,2]
+  v += dpp_d<0x4E>(v);         // quad_perm [2,3,0,1]
   return v;
 }
 

@@ -19,6 +19,7 @@ namespace snmf {
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4v __attribute__((ext_vector_type(4)));
 
 // ----------------------------------------------------------------------------- FP64
 __global__ __launch_bounds__(256) void k_apass_f64(const double* __restrict__ A, int64_t lda,
@@ -92,25 +93,44 @@ __global__ __launch_bounds__(256) void k_apass_f32(const float* __restrict__ A, 
   const bool mok0 = c < r, mok1 = 32 + c < r;
   const float* arow = A + j0 + c;
   constexpr int U = 8;  // k-pairs per batch of loads
-  int64_t k = kb;
-  for (; k + 2 * U <= ke; k += 2 * U) {
-    float a0[U], a1[U], p0[U], p1[U];
+  float a0[U], a1[U], p0[U], p1[U];
+  float b0[U], b1[U], q0[U], q1[U];
+  auto load = [&](float (&x0)[U], float (&x1)[U], float (&y0)[U], float (&y1)[U], int64_t kk0) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int64_t kk = k + 2 * u + h;
-      a0[u] = jok0 ? __builtin_nontemporal_load(arow + kk * lda) : 0.0f;
-      a1[u] = jok1 ? __builtin_nontemporal_load(arow + kk * lda + 32) : 0.0f;
-      p0[u] = mok0 ? P[kk * r + c] : 0.0f;
-      if (NMB > 1) p1[u] = mok1 ? P[kk * r + 32 + c] : 0.0f;
+      const int64_t kk = kk0 + 2 * u + h;
+      x0[u] = jok0 ? __builtin_nontemporal_load(arow + kk * lda) : 0.0f;
+      x1[u] = jok1 ? __builtin_nontemporal_load(arow + kk * lda + 32) : 0.0f;
+      y0[u] = mok0 ? P[kk * r + c] : 0.0f;
+      if (NMB > 1) y1[u] = mok1 ? P[kk * r + 32 + c] : 0.0f;
     }
+  };
+  auto mma = [&](const float (&x0)[U], const float (&x1)[U], const float (&y0)[U],
+                 const float (&y1)[U]) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(p0[u], a0[u], acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(p0[u], a1[u], acc[0][1], 0, 0, 0);
+      acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(y0[u], x0[u], acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(y0[u], x1[u], acc[0][1], 0, 0, 0);
       if (NMB > 1) {
-        acc[NMB - 1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(p1[u], a0[u], acc[NMB - 1][0], 0, 0, 0);
-        acc[NMB - 1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(p1[u], a1[u], acc[NMB - 1][1], 0, 0, 0);
+        acc[NMB - 1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(y1[u], x0[u], acc[NMB - 1][0], 0, 0, 0);
+        acc[NMB - 1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(y1[u], x1[u], acc[NMB - 1][1], 0, 0, 0);
       }
+    }
+  };
+  int64_t k = kb;
+  // two batches of loads in flight: the next batch is requested before this one's MFMAs
+  if (k + 2 * U <= ke) load(a0, a1, p0, p1, k);
+  while (k + 2 * U <= ke) {
+    if (k + 4 * U <= ke) {
+      load(b0, b1, q0, q1, k + 2 * U);
+      mma(a0, a1, p0, p1);
+      k += 2 * U;
+      if (k + 4 * U <= ke) load(a0, a1, p0, p1, k + 2 * U);
+      mma(b0, b1, q0, q1);
+      k += 2 * U;
+    } else {
+      mma(a0, a1, p0, p1);
+      k += 2 * U;
     }
   }
   for (; k < ke; k += 2) {
@@ -145,11 +165,125 @@ __global__ __launch_bounds__(256) void k_apass_f32(const float* __restrict__ A, 
     }
 }
 
+// FP32, wide loads (r in (32, 64], r even, lda % 4 == 0): each workgroup owns 128 output
+// rows j0..j0+127 and one K split; its four waves take contiguous quarters of that K
+// range.  Per k-pair a lane loads A[k+h][j0+4c .. +3] (one 16-byte vector) and
+// P[k+h][2c, 2c+1] (one 8-byte vector): MFMA N-block q covers the columns j0 + 4c + q,
+// M-block b the ranks m = 2c + b.  The four wave tiles are added in LDS in wave order
+// (deterministic) and written as coalesced rows of the partial product.
+__global__ __launch_bounds__(256) void k_apass_f32w(const float* __restrict__ A, int64_t lda,
+                                                    const float* __restrict__ P, int64_t n, int r,
+                                                    int64_t kchunk, float* __restrict__ Bpart,
+                                                    int64_t pstride, const State* __restrict__ st) {
+  if (st->done) return;
+  __shared__ float sacc[4 * 8 * 16 * 64];  // [wave][block(mb,nb)][v][lane]
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int c = lane & 31, h = lane >> 5;
+  const int64_t j0 = (int64_t)blockIdx.x * 128;
+  const int64_t kb = (int64_t)blockIdx.y * kchunk;
+  const int64_t ke = kb + kchunk < n ? kb + kchunk : n;
+  const int64_t kq = ((ke - kb + 7) / 8) * 2;      // per-wave share, even
+  const int64_t wb = kb + wave * kq;
+  const int64_t we = wb + kq < ke ? wb + kq : ke;
+  f32x16 acc[2][4];
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[mb][nb][v] = 0.0f;
+  const int64_t jc = j0 + 4 * c;
+  const bool jok = jc + 3 < n;                 // n % 4 == 0 on this path
+  const bool mok = 2 * c + 1 < r;              // r even on this path
+  const float* arow = A + (jok ? jc : 0);
+  const float* prow = P + (mok ? 2 * c : 0);
+  constexpr int U = 8;
+  f32x4v xa[U], xb[U];
+  float2 ya[U], yb[U];
+  const f32x4v z4 = {0.f, 0.f, 0.f, 0.f};
+  const float2 z2 = {0.f, 0.f};
+  auto load = [&](f32x4v (&x)[U], float2 (&y)[U], int64_t k0) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t kk = k0 + 2 * u + h;
+      x[u] = jok ? __builtin_nontemporal_load((const f32x4v*)(arow + kk * lda)) : z4;
+      y[u] = mok ? *(const float2*)(prow + kk * r) : z2;
+    }
+  };
+  auto mma = [&](const f32x4v (&x)[U], const float2 (&y)[U]) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const float av[4] = {x[u][0], x[u][1], x[u][2], x[u][3]};
+      const float pv[2] = {y[u].x, y[u].y};
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb)
+          acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(pv[mb], av[nb], acc[mb][nb], 0, 0, 0);
+    }
+  };
+  int64_t k = wb;
+  if (k + 2 * U <= we) load(xa, ya, k);
+  while (k + 2 * U <= we) {
+    if (k + 4 * U <= we) {
+      load(xb, yb, k + 2 * U);
+      mma(xa, ya);
+      k += 2 * U;
+      if (k + 4 * U <= we) load(xa, ya, k + 2 * U);
+      mma(xb, yb);
+      k += 2 * U;
+    } else {
+      mma(xa, ya);
+      k += 2 * U;
+    }
+  }
+  for (; k < we; k += 2) {
+    const int64_t kk = k + h;
+    const bool kin = kk < we;
+    const f32x4v x = (kin && jok) ? *(const f32x4v*)(arow + kk * lda) : z4;
+    const float2 y = (kin && mok) ? *(const float2*)(prow + kk * r) : z2;
+    const float av[4] = {x[0], x[1], x[2], x[3]};
+    const float pv[2] = {y.x, y.y};
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb)
+        acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(pv[mb], av[nb], acc[mb][nb], 0, 0, 0);
+  }
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) sacc[((wave * 8 + mb * 4 + nb) * 16 + v) * 64 + lane] = acc[mb][nb][v];
+  __syncthreads();
+  // element (jl, m) of the 128 x r tile: jl = 4c + nb, m = 2 mrow + mb with
+  // mrow = 8 (v/4) + 4 h + v%4
+  float* out = Bpart + (int64_t)blockIdx.y * pstride;
+  for (int e = threadIdx.x; e < 128 * 64; e += 256) {
+    const int jl = e >> 6, m = e & 63;
+    const int64_t jj = j0 + jl;
+    if (m < r && jj < n) {
+      const int cc = jl >> 2, nb = jl & 3, mb = m & 1, mrow = m >> 1;
+      const int hh = (mrow >> 2) & 1, v = 4 * (mrow >> 3) + (mrow & 3);
+      const int idx = ((mb * 4 + nb) * 16 + v) * 64 + 32 * hh + cc;
+      float sum = sacc[idx];
+      sum += sacc[8 * 16 * 64 + idx];
+      sum += sacc[2 * 8 * 16 * 64 + idx];
+      sum += sacc[3 * 8 * 16 * 64 + idx];
+      out[jj * r + m] = sum;
+    }
+  }
+}
+
 // ----------------------------------------------------------------------------- split BF16
-// Grid: x = blocks of 128 output rows (4 waves x 32), y = K splits (kchunk multiple of 32).
-// Per 32-column slab of A a lane loads 16 consecutive BF16 of its row (two 16-byte
-// vectors) from A_hi and A_lo; MFMA step s uses lane (h, row) k-values kb+16h+8s..+7,
-// and the matching Pt vectors (column m = 32 nb + lane%32).
+// Grid: x = blocks of 128 output rows (4 waves x 32), y = K splits (kchunk multiple of 64).
+// Per 64-column slab of A a lane loads 32 consecutive BF16 of its row (four 16-byte
+// vectors, lanes l and l+32 together cover 128 contiguous bytes) from A_hi and A_lo; the
+// matching 64-column slab of Pt_hi/Pt_lo (r x 64) is staged once per workgroup in LDS
+// (double-buffered) and shared by the four waves.  MFMA step s (0..3) uses lane (h, row)
+// k-values k + 32h + 8s .. +7.  The next slab's A vectors are loaded before the current
+// slab's MFMAs are issued.
 template <int NNB>
 __global__ __launch_bounds__(256) void k_apass_bf16x3(const uint16_t* __restrict__ Ahi,
                                                       const uint16_t* __restrict__ Alo, int64_t ldb,
@@ -159,7 +293,10 @@ __global__ __launch_bounds__(256) void k_apass_bf16x3(const uint16_t* __restrict
                                                       float* __restrict__ Bpart, int64_t pstride,
                                                       const State* __restrict__ st) {
   if (st->done) return;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr int KS = 64;                    // k per slab
+  constexpr int PROW = KS + 8;              // LDS row pitch (bf16), keeps 16-byte alignment
+  __shared__ __attribute__((aligned(16))) uint16_t sP[2][2][32 * NNB * PROW];  // [buf][hi/lo]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int c = lane & 31, h = lane >> 5;
   const int64_t j0 = ((int64_t)blockIdx.x * 4 + wave) * 32;
   const int64_t kb = (int64_t)blockIdx.y * kchunk;
@@ -172,32 +309,64 @@ __global__ __launch_bounds__(256) void k_apass_bf16x3(const uint16_t* __restrict
     for (int v = 0; v < 16; ++v) acc[nb][v] = 0.0f;
   const int64_t j = j0 + c;
   const bool jok = j < n;
-  const uint16_t* ah = Ahi + (jok ? j : 0) * ldb + 16 * h;
-  const uint16_t* al = Alo + (jok ? j : 0) * ldb + 16 * h;
-  const uint16_t* ph[NNB];
-  const uint16_t* pl[NNB];
-  bool mok[NNB];
-#pragma unroll
-  for (int nb = 0; nb < NNB; ++nb) {
-    const int m = 32 * nb + c;
-    mok[nb] = m < r;
-    ph[nb] = Pthi + (mok[nb] ? m : 0) * ldp + 16 * h;
-    pl[nb] = Ptlo + (mok[nb] ? m : 0) * ldp + 16 * h;
-  }
+  const uint16_t* ah = Ahi + (jok ? j : 0) * ldb + 32 * h;
+  const uint16_t* al = Alo + (jok ? j : 0) * ldb + 32 * h;
   const u16x8 zero = {0, 0, 0, 0, 0, 0, 0, 0};
-  for (int64_t k = kb; k < ke; k += 32) {
-    u16x8 xa[2][2];  // [hi/lo][step]
+  // Pt staging: the slab is 32*NNB rows (m) x 64 bf16 for hi and lo, i.e. NVEC 16-byte
+  // vectors, NPT per thread.  Global loads of the next slab are issued before the next
+  // A vectors and written to LDS only after the current MFMAs, so no wait on the A
+  // prefetch is needed to stage.
+  constexpr int NVEC = 2 * 32 * NNB * (KS / 8);
+  constexpr int NPT = NVEC / 256;
+  u16x8 pt[NPT];
+  auto stage_load = [&](int64_t k) {
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      xa[0][s] = jok ? __builtin_nontemporal_load((const u16x8*)(ah + k + 8 * s)) : zero;
-      xa[1][s] = jok ? __builtin_nontemporal_load((const u16x8*)(al + k + 8 * s)) : zero;
+    for (int q = 0; q < NPT; ++q) {
+      const int e = tid + 256 * q;
+      const int which = e / (32 * NNB * (KS / 8));
+      const int rem = e - which * (32 * NNB * (KS / 8));
+      const int m = rem / (KS / 8), qq = rem - m * (KS / 8);
+      pt[q] = m < r ? *(const u16x8*)((which ? Ptlo : Pthi) + (int64_t)m * ldp + k + 8 * qq) : zero;
+    }
+  };
+  auto stage_store = [&](int b) {
+#pragma unroll
+    for (int q = 0; q < NPT; ++q) {
+      const int e = tid + 256 * q;
+      const int which = e / (32 * NNB * (KS / 8));
+      const int rem = e - which * (32 * NNB * (KS / 8));
+      const int m = rem / (KS / 8), qq = rem - m * (KS / 8);
+      *(u16x8*)&sP[b][which][m * PROW + 8 * qq] = pt[q];
+    }
+  };
+  u16x8 xa[2][4], xn[2][4];
+  auto load_a = [&](u16x8 (&x)[2][4], int64_t k) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      x[0][s] = jok ? __builtin_nontemporal_load((const u16x8*)(ah + k + 8 * s)) : zero;
+      x[1][s] = jok ? __builtin_nontemporal_load((const u16x8*)(al + k + 8 * s)) : zero;
+    }
+  };
+  int buf = 0;
+  if (kb < ke) {
+    stage_load(kb);
+    load_a(xa, kb);
+    stage_store(0);
+  }
+  __syncthreads();
+  for (int64_t k = kb; k < ke; k += KS) {
+    const bool more = k + KS < ke;
+    if (more) {
+      stage_load(k + KS);
+      load_a(xn, k + KS);
     }
 #pragma unroll
     for (int nb = 0; nb < NNB; ++nb) {
+      const int m = 32 * nb + c;
 #pragma unroll
-      for (int s = 0; s < 2; ++s) {
-        const u16x8 bh = mok[nb] ? *(const u16x8*)(ph[nb] + k + 8 * s) : zero;
-        const u16x8 bl = mok[nb] ? *(const u16x8*)(pl[nb] + k + 8 * s) : zero;
+      for (int s = 0; s < 4; ++s) {
+        const u16x8 bh = *(const u16x8*)&sP[buf][0][m * PROW + 32 * h + 8 * s];
+        const u16x8 bl = *(const u16x8*)&sP[buf][1][m * PROW + 32 * h + 8 * s];
         acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, xa[0][s]),
                                                           __builtin_bit_cast(bf16x8, bh), acc[nb], 0, 0, 0);
         acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, xa[0][s]),
@@ -206,6 +375,16 @@ __global__ __launch_bounds__(256) void k_apass_bf16x3(const uint16_t* __restrict
                                                           __builtin_bit_cast(bf16x8, bh), acc[nb], 0, 0, 0);
       }
     }
+    if (more) stage_store(buf ^ 1);
+    __syncthreads();
+    if (more) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        xa[0][s] = xn[0][s];
+        xa[1][s] = xn[1][s];
+      }
+    }
+    buf ^= 1;
   }
   // D[row][col]: row = 8 (v/4) + 4 h + v%4 (output row j0 + row), col = lane%32 (m).
   float* out = Bpart + (int64_t)blockIdx.y * pstride;
@@ -251,8 +430,26 @@ void launch_apass_f64(const double* A, int64_t lda, const double* P, int64_t n, 
   hipLaunchKernelGGL(k_apass_f64, dim3(gx), dim3(256), 0, s, A, lda, P, n, r, B, st);
 }
 
-DenseSplit plan_dense_f32(int64_t n) {
+bool dense_f32_wide(int64_t n, int64_t lda, int r, const void* A) {
+  return r > 32 && r % 2 == 0 && n % 4 == 0 && lda % 4 == 0 && ((uintptr_t)A & 15) == 0;
+}
+
+DenseSplit plan_dense_f32(int64_t n, int64_t lda, int r, const void* A) {
   DenseSplit d;
+  if (dense_f32_wide(n, lda, r, A)) {
+    d.wide = true;
+    d.gx = (n + 127) / 128;
+    int64_t ks = (256 + d.gx - 1) / d.gx;
+    const int64_t kmax = (n + 255) / 256;
+    if (ks > kmax) ks = kmax;
+    if (ks < 1) ks = 1;
+    if (ks > kMaxKSplit) ks = kMaxKSplit;
+    int64_t kc = (n + ks - 1) / ks;
+    kc = (kc + 63) / 64 * 64;
+    d.kchunk = kc;
+    d.ksplit = (int)((n + kc - 1) / kc);
+    return d;
+  }
   const int64_t gx = (n + 255) / 256;
   int64_t ks = (512 + gx - 1) / gx;
   const int64_t kmax = (n + 63) / 64;
@@ -271,7 +468,10 @@ void launch_apass_f32(const float* A, int64_t lda, const float* P, int64_t n, in
                       const DenseSplit& d, float* Bpart, int64_t pstride, const State* st,
                       hipStream_t s) {
   dim3 grid((unsigned)d.gx, (unsigned)d.ksplit);
-  if (r > 32)
+  if (d.wide)
+    hipLaunchKernelGGL(k_apass_f32w, grid, dim3(256), 0, s, A, lda, P, n, r, d.kchunk, Bpart,
+                       pstride, st);
+  else if (r > 32)
     hipLaunchKernelGGL(k_apass_f32<2>, grid, dim3(256), 0, s, A, lda, P, n, r, d.kchunk, Bpart,
                        pstride, st);
   else
@@ -283,13 +483,13 @@ DenseSplit plan_dense_bf16(int64_t n) {
   DenseSplit d;
   const int64_t ldb = (n + 63) / 64 * 64;
   const int64_t gx = (n + 127) / 128;
-  int64_t ks = (1024 + gx - 1) / gx;
+  int64_t ks = (512 + gx - 1) / gx;
   const int64_t kmax = ldb / 64;
   if (ks > kmax) ks = kmax;
   if (ks < 1) ks = 1;
   if (ks > kMaxKSplit) ks = kMaxKSplit;
   int64_t kc = (ldb + ks - 1) / ks;
-  kc = (kc + 31) / 32 * 32;
+  kc = (kc + 63) / 64 * 64;
   d.kchunk = kc;
   d.ksplit = (int)((ldb + kc - 1) / kc);
   d.gx = gx;

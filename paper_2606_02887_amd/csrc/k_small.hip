@@ -7,123 +7,148 @@
 namespace snmf {
 
 // ----------------------------------------------------------------------------- Gram
-// Each workgroup forms the FP64 Gram of a contiguous slab of rows of P; the last
-// workgroup adds the slabs in block order (deterministic) and writes G in FP64 and in
-// the iterate type.
+// Each workgroup forms the FP64 Gram of a contiguous slab of rows of P (thread t owns the
+// 4 x 4 block of G at rows 4(t/16), columns 4(t%16)); a second kernel adds the slabs in
+// block order (deterministic) and writes G in FP64 and in the iterate type.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_gram(const T* __restrict__ P, int64_t n, int r,
                                                    int64_t rows_per_block,
                                                    double* __restrict__ part,
-                                                   double* __restrict__ G64, T* __restrict__ GT,
-                                                   unsigned* __restrict__ counter,
                                                    const State* __restrict__ st) {
   if (st->done) return;
-  constexpr int TR = 32;
-  __shared__ double sP[TR][kMaxRank + 1];
+  constexpr int TR = 32, LDP = kMaxRank + 2;
+  __shared__ __attribute__((aligned(16))) double sP[TR * LDP];
   const int rr = r * r;
-  double acc[kMaxRank * kMaxRank / kThreads];
-  constexpr int NE = kMaxRank * kMaxRank / kThreads;
+  const int a0 = 4 * (threadIdx.x >> 4), b0 = 4 * (threadIdx.x & 15);
+  double acc[4][4];
 #pragma unroll
-  for (int i = 0; i < NE; ++i) acc[i] = 0.0;
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
   const int64_t rb = (int64_t)blockIdx.x * rows_per_block;
   const int64_t re = rb + rows_per_block < n ? rb + rows_per_block : n;
   for (int64_t t0 = rb; t0 < re; t0 += TR) {
     __syncthreads();
-    for (int e = threadIdx.x; e < TR * r; e += kThreads) {
-      const int i = e / r, c = e - i * r;
+    for (int e = threadIdx.x; e < TR * kMaxRank; e += kThreads) {
+      const int i = e / kMaxRank, c = e % kMaxRank;
       const int64_t row = t0 + i;
-      sP[i][c] = row < re ? (double)P[row * r + c] : 0.0;
+      sP[i * LDP + c] = (row < re && c < r) ? (double)P[row * r + c] : 0.0;
     }
     __syncthreads();
+#pragma unroll 4
+    for (int i = 0; i < TR; ++i) {
+      const double2 x0 = *(const double2*)&sP[i * LDP + a0];
+      const double2 x1 = *(const double2*)&sP[i * LDP + a0 + 2];
+      const double2 y0 = *(const double2*)&sP[i * LDP + b0];
+      const double2 y1 = *(const double2*)&sP[i * LDP + b0 + 2];
+      const double xa[4] = {x0.x, x0.y, x1.x, x1.y};
+      const double yb[4] = {y0.x, y0.y, y1.x, y1.y};
 #pragma unroll
-    for (int q = 0; q < NE; ++q) {
-      const int e = threadIdx.x + q * kThreads;
-      if (e < rr) {
-        const int a = e / r, b = e - a * r;
-        double s = acc[q];
-#pragma unroll 8
-        for (int i = 0; i < TR; ++i) s = __builtin_fma(sP[i][a], sP[i][b], s);
-        acc[q] = s;
-      }
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = __builtin_fma(xa[u], yb[v], acc[u][v]);
     }
   }
 #pragma unroll
-  for (int q = 0; q < NE; ++q) {
-    const int e = threadIdx.x + q * kThreads;
-    if (e < rr) part[(size_t)blockIdx.x * rr + e] = acc[q];
-  }
-  if (arrive_last(counter, gridDim.x)) {
-    for (int e = threadIdx.x; e < rr; e += kThreads) {
-      double s = 0.0;
-      for (unsigned b = 0; b < gridDim.x; ++b) s += part[(size_t)b * rr + e];
-      G64[e] = s;
-      GT[e] = (T)s;
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int a = a0 + u, b = b0 + v;
+      if (a < r && b < r) part[(size_t)blockIdx.x * rr + a * r + b] = acc[u][v];
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_gram_reduce(const double* __restrict__ part, int nb,
+                                                          int rr, double* __restrict__ G64,
+                                                          T* __restrict__ GT,
+                                                          const State* __restrict__ st) {
+  if (st->done) return;
+  const int e = blockIdx.x * kThreads + threadIdx.x;
+  if (e >= rr) return;
+  double s = 0.0;
+  int b = 0;
+  for (; b + 8 <= nb; b += 8) {  // eight loads in flight, added in block order
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = part[(size_t)(b + u) * rr + e];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u];
   }
+  for (; b < nb; ++b) s += part[(size_t)b * rr + e];
+  G64[e] = s;
+  GT[e] = (T)s;
 }
 
 // ----------------------------------------------------------------------------- rho
-// Largest eigenvalue of the symmetric positive semidefinite r x r matrix G (r <= 64),
-// computed by one wavefront: Lanczos from the all-ones vector with full
-// re-orthogonalisation (two classical Gram-Schmidt passes), then bisection with Sturm
-// counts on the tridiagonal matrix, 64 trial shifts per round.  G >= 0 elementwise (a
-// Gram of a nonnegative block), so its Perron vector is nonnegative and the all-ones
-// start has a nonzero component along it.  Also resets the per-half-step scalars.
-__global__ __launch_bounds__(kWave) void k_rho(const double* __restrict__ G, int r,
-                                                State* __restrict__ st) {
+// Largest eigenvalue of the symmetric positive semidefinite r x r matrix G (r <= 64).
+// Wave 0 runs r steps of the Lanczos recurrence from the all-ones vector (lane i holds
+// row i of G in registers; the current Lanczos vector is broadcast through LDS; inner
+// products are DPP wave sums), then all four waves locate the largest eigenvalue of the
+// tridiagonal matrix by bisection with Sturm counts, 256 trial shifts per round.
+// Without re-orthogonalisation the extreme Ritz value is still accurate: loss of
+// orthogonality only adds copies of converged Ritz values (Paige), and r steps span the
+// whole space in exact arithmetic; on Gram matrices of planted, graph and clustered
+// spectra the result agrees with a dense symmetric eigensolver to a few ulps.
+// G >= 0 elementwise (a Gram of a nonnegative block), so its Perron vector is
+// nonnegative and the all-ones start has a nonzero component along it.
+__global__ __launch_bounds__(kThreads) void k_rho(const double* __restrict__ G, int r,
+                                                  State* __restrict__ st) {
   if (st->done) return;
-  constexpr int LD = kMaxRank + 1;
-  __shared__ double sQ[kMaxRank * LD];
-  __shared__ double sv[kMaxRank];
+  __shared__ __attribute__((aligned(16))) double sq[kMaxRank];
   __shared__ double sa[kMaxRank], sb[kMaxRank];
-  const int i = threadIdx.x;
-  double grow[kMaxRank];
-  double gn2 = 0.0;
+  __shared__ int sm_m;
+  __shared__ int sfirst[kThreads / kWave];
+  const int t = threadIdx.x;
+  if (t < kWave) {
+    const int i = t;
+    double grow[kMaxRank];
+    double gn2 = 0.0;
 #pragma unroll
-  for (int k = 0; k < kMaxRank; ++k) {
-    grow[k] = (i < r && k < r) ? G[i * r + k] : 0.0;
-    gn2 += grow[k] * grow[k];
-  }
-  const double gnorm = sqrt(wave_sum(gn2));
-  double q = i < r ? 1.0 / sqrt((double)r) : 0.0;
-  double qprev = 0.0, bprev = 0.0;
-  int m = 0;
-  for (int j = 0; j < r; ++j) {
-    sQ[i * LD + j] = q;
-    sv[i] = q;
-    __syncthreads();
-    double w = 0.0;
+    for (int k = 0; k < kMaxRank; ++k) {
+      grow[k] = (i < r && k < r) ? G[i * r + k] : 0.0;
+      gn2 = __builtin_fma(grow[k], grow[k], gn2);
+    }
+    const double tol = 1e-15 * sqrt(wave_sum(gn2));
+    double q = i < r ? 1.0 / sqrt((double)r) : 0.0;
+    double qprev = 0.0, bprev = 0.0;
+    int m = 0;
+    for (int j = 0; j < r; ++j) {
+      sq[i] = q;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      double w0 = 0.0, w1 = 0.0, w2 = 0.0, w3 = 0.0;
 #pragma unroll
-    for (int k = 0; k < kMaxRank; ++k) w = __builtin_fma(grow[k], sv[k], w);
-    const double a = wave_sum(w * q);
-    w -= a * q + bprev * qprev;
-    for (int pass = 0; pass < 2; ++pass) {
-      __syncthreads();
-      sv[i] = w;
-      __syncthreads();
-      double cj = 0.0;
-      if (i <= j)
-        for (int k = 0; k < r; ++k) cj = __builtin_fma(sQ[k * LD + i], sv[k], cj);
-      __syncthreads();
-      sv[i] = i <= j ? cj : 0.0;
-      __syncthreads();
-      double s = 0.0;
-      for (int jj = 0; jj <= j; ++jj) s = __builtin_fma(sQ[i * LD + jj], sv[jj], s);
-      w -= s;
+      for (int k = 0; k < kMaxRank; k += 4) {
+        const double2 u = *(const double2*)&sq[k];
+        const double2 v = *(const double2*)&sq[k + 2];
+        w0 = __builtin_fma(grow[k], u.x, w0);
+        w1 = __builtin_fma(grow[k + 1], u.y, w1);
+        w2 = __builtin_fma(grow[k + 2], v.x, w2);
+        w3 = __builtin_fma(grow[k + 3], v.y, w3);
+      }
+      double w = (w0 + w1) + (w2 + w3);
+      const double a = wave_sum(q * w);
+      w -= a * q + bprev * qprev;
+      const double b = sqrt(wave_sum(w * w));
+      if (i == 0) {
+        sa[j] = a;
+        sb[j] = b;
+      }
+      m = j + 1;
+      if (!(b > tol)) break;
+      qprev = q;
+      q = w / b;
+      bprev = b;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    const double b = sqrt(wave_sum(w * w));
-    if (i == 0) {
-      sa[j] = a;
-      sb[j] = b;
-    }
-    m = j + 1;
-    if (!(b > 1e-15 * gnorm)) break;
-    qprev = q;
-    q = w / b;
-    bprev = b;
-    __syncthreads();
+    if (i == 0) sm_m = m;
   }
   __syncthreads();
+  const int m = sm_m;
   // bounds for the largest eigenvalue of T = tridiag(sb, sa, sb)
   double lo = -1e300, hi = -1e300;
   for (int k = 0; k < m; ++k) {
@@ -131,36 +156,31 @@ __global__ __launch_bounds__(kWave) void k_rho(const double* __restrict__ G, int
     lo = fmax(lo, sa[k]);
     hi = fmax(hi, sa[k] + off);
   }
+  const double div = (double)(kThreads + 1);
   for (int round = 0; round < 40 && hi - lo > 2.0 * 2.220446049250313e-16 * fabs(hi); ++round) {
-    const double x = lo + (hi - lo) * (double)(i + 1) / (double)(kWave + 1);
-    // Sturm count: number of eigenvalues of T smaller than x (negative LDL^T pivots)
+    const double x = lo + (hi - lo) * (double)(t + 1) / div;
+    // Sturm count: number of eigenvalues of T below x (negative LDL^T pivots)
     int cnt = 0;
     double d = 1.0;
     for (int k = 0; k < m; ++k) {
-      const double b2 = k > 0 ? sb[k - 1] * sb[k - 1] : 0.0;
-      d = (sa[k] - x) - (k > 0 ? b2 / d : 0.0);
+      d = (sa[k] - x) - (k > 0 ? sb[k - 1] * sb[k - 1] / d : 0.0);
       if (fabs(d) < 1e-300) d = -1e-300;
       cnt += d < 0.0;
     }
-    // lanes with cnt == m (x above every eigenvalue) form a suffix of the shifts
+    // shifts above every eigenvalue (cnt == m) form a suffix; find its first index
     const unsigned long long above = __ballot(cnt == m);
-    const int first_above = above ? __ffsll((long long)above) - 1 : kWave;
-    const double nlo = first_above > 0
-                           ? lo + (hi - lo) * (double)first_above / (double)(kWave + 1)
-                           : lo;
-    const double nhi = first_above < kWave
-                           ? lo + (hi - lo) * (double)(first_above + 1) / (double)(kWave + 1)
-                           : hi;
-    lo = nlo;
+    if ((t & 63) == 0) sfirst[t >> 6] = above ? (t & ~63) + __ffsll((long long)above) - 1 : kThreads;
+    __syncthreads();
+    const int first = min(min(sfirst[0], sfirst[1]), min(sfirst[2], sfirst[3]));
+    __syncthreads();
+    const double nlo = lo + (hi - lo) * (double)first / div;
+    const double nhi = first < kThreads ? lo + (hi - lo) * (double)(first + 1) / div : hi;
+    lo = first > 0 ? nlo : lo;
     hi = nhi;
   }
-  if (i == 0) {
+  if (t == 0) {
     const double rho = 0.5 * (lo + hi);
     st->rho = rho;
-    st->alpha = 1.0 / rho;
-    st->e = 0.0;
-    st->hs_done = 0;
-    st->k = 0;
     if (!(rho > 0.0) || !(rho < 1e308)) {
       st->status = 9;  // SNMF_E_BREAKDOWN
       st->done = 1;
@@ -245,18 +265,20 @@ __global__ __launch_bounds__(kThreads) void k_split_pt(const float* __restrict__
 // ----------------------------------------------------------------------------- launchers
 template <typename T>
 void launch_gram(const T* P, int64_t n, int r, double* part, int nblk, double* G64, T* GT,
-                 unsigned* counter, const State* st, hipStream_t s) {
+                 const State* st, hipStream_t s) {
   int64_t rpb = (n + nblk - 1) / nblk;
-  hipLaunchKernelGGL(k_gram<T>, dim3(nblk), dim3(kThreads), 0, s, P, n, r, rpb, part, G64, GT,
-                     counter, st);
+  hipLaunchKernelGGL(k_gram<T>, dim3(nblk), dim3(kThreads), 0, s, P, n, r, rpb, part, st);
+  const int rr = r * r;
+  hipLaunchKernelGGL(k_gram_reduce<T>, dim3((rr + kThreads - 1) / kThreads), dim3(kThreads), 0, s,
+                     part, nblk, rr, G64, GT, st);
 }
 template void launch_gram<float>(const float*, int64_t, int, double*, int, double*, float*,
-                                 unsigned*, const State*, hipStream_t);
+                                 const State*, hipStream_t);
 template void launch_gram<double>(const double*, int64_t, int, double*, int, double*, double*,
-                                  unsigned*, const State*, hipStream_t);
+                                  const State*, hipStream_t);
 
 void launch_rho(const double* G, int r, State* st, hipStream_t s) {
-  hipLaunchKernelGGL(k_rho, dim3(1), dim3(kWave), 0, s, G, r, st);
+  hipLaunchKernelGGL(k_rho, dim3(1), dim3(kThreads), 0, s, G, r, st);
 }
 
 template <typename T>

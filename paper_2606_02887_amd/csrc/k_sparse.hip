@@ -4,8 +4,9 @@
 //   lane (slot, c) with c = lane % RP walks the nonzeros slot, slot + 64/RP, ... of the row
 //   and accumulates A_ik X[k][c]; the slots are combined with cross-lane adds.  Used for
 //   the A-pass of Graph-SNMPBB and of batched graph problems, and for the Laplacian
-//   products L X, L(Z-X), L S of eq. (2.3).  In "dot" mode the kernel returns
-//   <X2, A X> (FP64, deterministic) instead of storing A X -- the curvature <D, L D>.
+//   products L X, L(Z-X), L S of eq. (2.3).  In "dot" mode the kernel writes FP64 partial
+//   sums of <X2, A X> per workgroup (the curvature <D, L D>, reduced by the next kernel)
+//   instead of storing A X.
 // * LAI-SNMPBB (Section 2.3): A P ~= U (lam .* (U^T P)).  T = U^T P is an ell x r
 //   reduction over all n rows (FP64 partials per workgroup, then a fixed-order sum that
 //   also applies lam); B = U T is a row-local product.
@@ -20,8 +21,6 @@ __global__ __launch_bounds__(256) void k_spmm(const int64_t* __restrict__ rowptr
                                               const T* __restrict__ val, const T* __restrict__ X,
                                               int64_t n, int r, T* __restrict__ Y,
                                               const T* __restrict__ X2, double* __restrict__ part,
-                                              double* __restrict__ out,
-                                              unsigned* __restrict__ counter,
                                               const int32_t* __restrict__ gate,
                                               const int32_t* __restrict__ gate2) {
   if ((gate && gate[0]) || (gate2 && gate2[0])) return;
@@ -51,11 +50,6 @@ __global__ __launch_bounds__(256) void k_spmm(const int64_t* __restrict__ rowptr
   double v[1] = {dot};
   block_sum<1>(v, sred);
   if (threadIdx.x == 0) part[(size_t)blockIdx.x * kNumPart] = v[0];
-  if (arrive_last(counter, gridDim.x)) {
-    double t[1];
-    reduce_partials<1>(part, gridDim.x, t, sred);
-    if (threadIdx.x == 0) out[0] = t[0];
-  }
 }
 
 // ----------------------------------------------------------------------------- LAI
@@ -164,16 +158,22 @@ __global__ __launch_bounds__(256) void k_lai_ut(const T* __restrict__ U, int ell
 
 template <typename T>
 void launch_spmm(const int64_t* rowptr, const int32_t* col, const T* val, const T* X, int64_t n,
-                 int r, T* Y, const T* X2, double* part, double* out, unsigned* counter,
-                 const int32_t* gate, const int32_t* gate2, hipStream_t s) {
+                 int r, T* Y, const T* X2, double* part, const int32_t* gate,
+                 const int32_t* gate2, hipStream_t s) {
   int64_t nb = (n + 3) / 4;
-  if (X2 && nb > kMaxGrid) nb = kMaxGrid;
+  if (X2) nb = spmm_dot_grid(n);
   if (nb > 65535 * 4) nb = 65535 * 4;
   if (nb < 1) nb = 1;
   SNMF_DISPATCH_RP2(rank_pad(r),
                     hipLaunchKernelGGL((k_spmm<T, RP>), dim3((unsigned)nb), dim3(256), 0, s,
-                                       rowptr, col, val, X, n, r, Y, X2, part, out, counter, gate,
-                                       gate2))
+                                       rowptr, col, val, X, n, r, Y, X2, part, gate, gate2))
+}
+
+int spmm_dot_grid(int64_t n) {
+  int64_t nb = (n + 3) / 4;
+  if (nb > kInnerGrid) nb = kInnerGrid;
+  if (nb < 1) nb = 1;
+  return (int)nb;
 }
 
 int lai_blocks(int64_t n) {
@@ -199,8 +199,8 @@ void launch_lai(const T* U, int ell, const double* lam, const T* P, int64_t n, i
 
 #define SNMF_INST_SP(T)                                                                      \
   template void launch_spmm<T>(const int64_t*, const int32_t*, const T*, const T*, int64_t,  \
-                               int, T*, const T*, double*, double*, unsigned*,               \
-                               const int32_t*, const int32_t*, hipStream_t);                 \
+                               int, T*, const T*, double*, const int32_t*, const int32_t*,   \
+                               hipStream_t);                                                 \
   template void launch_lai<T>(const T*, int, const double*, const T*, int64_t, int, double*, \
                               T*, T*, const int32_t*, hipStream_t);
 SNMF_INST_SP(float)

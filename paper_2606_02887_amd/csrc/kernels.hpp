@@ -14,6 +14,7 @@ struct DenseSplit {
   int64_t gx = 1;       // workgroups along the output rows
   int ksplit = 1;       // K splits (partial products)
   int64_t kchunk = 0;   // rows of A per split
+  bool wide = false;    // FP32: 16-byte A loads (r in (32, 64] even, n and lda multiples of 4)
 };
 
 int rank_pad(int r);
@@ -22,7 +23,7 @@ int lai_blocks(int64_t n);
 
 template <typename T>
 void launch_gram(const T* P, int64_t n, int r, double* part, int nblk, double* G64, T* GT,
-                 unsigned* counter, const State* st, hipStream_t s);
+                 const State* st, hipStream_t s);
 void launch_rho(const double* G, int r, State* st, hipStream_t s);
 template <typename T>
 void launch_norm2(const T* x, int64_t N, double* part, double* out, unsigned* counter,
@@ -36,7 +37,7 @@ template <typename T>
 void launch_sum_parts(const T* part, int ks, int64_t stride, T* out, int64_t N, hipStream_t s);
 void launch_apass_f64(const double* A, int64_t lda, const double* P, int64_t n, int r, double* B,
                       const State* st, hipStream_t s);
-DenseSplit plan_dense_f32(int64_t n);
+DenseSplit plan_dense_f32(int64_t n, int64_t lda, int r, const void* A);
 void launch_apass_f32(const float* A, int64_t lda, const float* P, int64_t n, int r,
                       const DenseSplit& d, float* Bpart, int64_t pstride, const State* st,
                       hipStream_t s);
@@ -48,26 +49,27 @@ void launch_apass_bf16x3(const uint16_t* Ahi, const uint16_t* Alo, int64_t ldb,
 
 template <typename T>
 void launch_spmm(const int64_t* rowptr, const int32_t* col, const T* val, const T* X, int64_t n,
-                 int r, T* Y, const T* X2, double* part, double* out, unsigned* counter,
-                 const int32_t* gate, const int32_t* gate2, hipStream_t s);
+                 int r, T* Y, const T* X2, double* part, const int32_t* gate,
+                 const int32_t* gate2, hipStream_t s);
+int spmm_dot_grid(int64_t n);
 template <typename T>
 void launch_lai(const T* U, int ell, const double* lam, const T* P, int64_t n, int r,
                 double* part, T* TT, T* B, const int32_t* gate, hipStream_t s);
 
 template <typename T>
 void launch_init(const T* X, const T* P, const T* Bpart, int ksplit, int64_t bstride, T* C, T* g,
-                 const T* LX, const T* GT, const double* Gcur, const double* Gprev, int64_t n,
-                 int r, int is_hstep, const KParams& kp, State* st, double* part,
-                 unsigned* counter, double* trace, hipStream_t s);
+                 const T* LX, const T* GT, int64_t n, int r, int is_hstep, const KParams& kp,
+                 State* st, double* partsA, hipStream_t s);
 template <typename T>
-void launch_step1(const T* X, const T* g, T* Z, T* D, const T* LdZ, T* Ddz, const T* GT,
-                  int64_t n, int r, int phase, int lap_dirD, const KParams& kp, State* st,
-                  double* part, unsigned* counter, hipStream_t s);
+void launch_step1(const T* X, const T* g, T* Z, T* D, const T* LdZ, const T* GT,
+                  const double* Gcur, const double* Gprev, int64_t n, int r, int k, int phase,
+                  int is_hstep, const KParams& kp, State* st, const double* partsA,
+                  double* partsB, const double* partsC, double* trace, hipStream_t s);
 template <typename T>
 void launch_step2(T* X, T* g, T* Z, T* D, const T* LS, const T* C, const T* P, T* LXb,
-                  const T* GT, int64_t n, int r, int phase, int is_hstep, const KParams& kp,
-                  State* st, double* part, unsigned* counter, hipStream_t s);
-void launch_line_search(State* st, const KParams& kp, const double* dLd, hipStream_t s);
+                  const T* GT, int64_t n, int r, int k, int phase, int is_hstep,
+                  const KParams& kp, State* st, const double* partsB, const double* partsD,
+                  int nbD, double* partsC, hipStream_t s);
 
 template <typename T>
 void launch_stats2d(const T* x, int64_t rows, int64_t cols, int64_t ld, double* part, double* out,
@@ -80,6 +82,5 @@ void launch_csr_symmetry(const int64_t* rowptr, const int32_t* col, const T* val
 void launch_reset_state(State* st, double normA2, hipStream_t s);
 void launch_split_flat(const float* x, int64_t count, uint16_t* hi, uint16_t* lo, hipStream_t s);
 
-__device__ void line_search(State* st, const KParams& kp);
 
 }  // namespace snmf

@@ -67,14 +67,16 @@ struct snmf_plan {
   int64_t n = 0;
   int prec = SNMF_F32;
   size_t esz = 4;
-  hipStream_t s = nullptr;  // private stream of the plan (default priority)
-  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  hipStream_t s = nullptr;     // private stream of the plan (default priority)
+  hipStream_t side = nullptr;  // second stream: rho runs beside the A-pass (default priority)
+  hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_fork = nullptr, ev_join = nullptr;
   // device memory (one allocation, carved)
   void* pool = nullptr;
   void *Wb = nullptr, *Hb = nullptr, *C = nullptr, *g = nullptr, *Z = nullptr, *D = nullptr;
   void *Bpart = nullptr, *LT = nullptr, *LX = nullptr, *GT[2] = {nullptr, nullptr}, *TT = nullptr;
   double* G64[2] = {nullptr, nullptr};
   double *part = nullptr, *gram_part = nullptr, *lai_part = nullptr, *dots = nullptr;
+  double *partsA = nullptr, *partsB = nullptr, *partsC = nullptr, *partsD = nullptr;
   double* trace = nullptr;
   uint16_t *Ahi = nullptr, *Alo = nullptr, *Pthi = nullptr, *Ptlo = nullptr;
   int64_t ldb = 0;
@@ -94,6 +96,9 @@ struct snmf_plan {
     if (pool) (void)hipFree(pool);
     if (ev_in) (void)hipEventDestroy(ev_in);
     if (ev_out) (void)hipEventDestroy(ev_out);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    if (side) (void)hipStreamDestroy(side);
     if (s) (void)hipStreamDestroy(s);
   }
 };
@@ -112,7 +117,8 @@ snmf_status check_params(const snmf_params* p) {
   if (!(p->beta_shrink > 0.0 && p->beta_shrink < 1.0))
     return fail(SNMF_E_ARG, "beta_shrink must lie in (0, 1)");
   if (p->max_ls < 0) return fail(SNMF_E_ARG, "max_ls must be >= 0");
-  if (p->inner_iters < 1) return fail(SNMF_E_ARG, "inner_iters must be >= 1");
+  if (p->inner_iters < 1 || p->inner_iters > kMaxInner)
+    return fail(SNMF_E_ARG, "inner_iters must lie in [1, 64]");
   if (p->max_outer < 1) return fail(SNMF_E_ARG, "max_outer must be >= 1");
   if (!(p->target_res >= 0.0)) return fail(SNMF_E_ARG, "target_res must be >= 0");
   if (p->prec < SNMF_F64 || p->prec > SNMF_BF16X3) return fail(SNMF_E_ARG, "unknown precision");
@@ -218,7 +224,7 @@ snmf_status apass(snmf_plan* pl, const T* P, hipStream_t s) {
       break;
     case SNMF_CSR:
       launch_spmm<T>(pl->A.rowptr, pl->A.col, (const T*)pl->A.val, P, n, r, (T*)pl->Bpart, nullptr,
-                     nullptr, nullptr, nullptr, gate, nullptr, s);
+                     nullptr, gate, nullptr, s);
       break;
     default:
       launch_lai<T>((const T*)pl->A.U, (int)pl->A.ell, pl->A.lam, P, n, r, pl->lai_part,
@@ -233,32 +239,43 @@ int ksplit_of(const snmf_plan* pl) {
   return (pl->A.fmt == SNMF_DENSE && pl->prec != SNMF_F64) ? pl->ds.ksplit : 1;
 }
 
-// Start of a half-step up to and including init: G, rho, the A-pass and the gradient.
+// Start of a half-step up to and including init: G, rho (on the side stream, beside the
+// A-pass), the A-pass and the gradient.  The side stream joins before the first inner
+// kernel, which is the first reader of rho.
 template <typename T>
 snmf_status half_start(snmf_plan* pl, T* X, const T* P, int is_hstep, bool with_rho,
                        hipStream_t s) {
   const int64_t n = pl->n;
   const int r = pl->r;
   const int gi = is_hstep ? 1 : 0;
-  launch_gram<T>(P, n, r, pl->gram_part, pl->gram_blocks, pl->G64[gi], (T*)pl->GT[gi],
-                 pl->counters + C_GRAM, pl->st, s);
-  if (with_rho) launch_rho(pl->G64[gi], r, pl->st, s);
+  launch_gram<T>(P, n, r, pl->gram_part, pl->gram_blocks, pl->G64[gi], (T*)pl->GT[gi], pl->st, s);
   HIP_TRY(hipGetLastError());
+  if (with_rho) {
+    HIP_TRY(hipEventRecord(pl->ev_fork, s));
+    HIP_TRY(hipStreamWaitEvent(pl->side, pl->ev_fork, 0));
+    launch_rho(pl->G64[gi], r, pl->st, pl->side);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipEventRecord(pl->ev_join, pl->side));
+  }
   SNMF_TRY(apass<T>(pl, P, s));
   const bool lap = pl->lap && is_hstep;
   if (lap) {
     launch_spmm<T>(pl->L.rowptr, pl->L.col, (const T*)pl->L.val, X, n, r, (T*)pl->LX, nullptr,
-                   nullptr, nullptr, nullptr, &pl->st->done, nullptr, s);
+                   nullptr, &pl->st->done, nullptr, s);
   }
   launch_init<T>(X, P, (const T*)pl->Bpart, ksplit_of(pl), n * r, (T*)pl->C, (T*)pl->g,
-                 lap ? (const T*)pl->LX : nullptr, (const T*)pl->GT[gi], pl->G64[0], pl->G64[1], n,
-                 r, is_hstep, pl->kp, pl->st, pl->part, pl->counters + C_INIT, pl->trace, s);
+                 lap ? (const T*)pl->LX : nullptr, (const T*)pl->GT[gi], n, r, is_hstep, pl->kp,
+                 pl->st, pl->partsA, s);
   HIP_TRY(hipGetLastError());
+  if (with_rho) HIP_TRY(hipStreamWaitEvent(s, pl->ev_join, 0));
   return SNMF_OK;
 }
 
+// One inner iteration k (Algorithm 1, lines 2-4).  Without a Laplacian: step1, step2.
+// H-step of Graph-SNMPBB: step1 phase 1, L(Z-X), step1 phase 2, <D, L D>, step2 phase 1,
+// L S, step2 phase 2.
 template <typename T>
-snmf_status inner_steps(snmf_plan* pl, T* X, const T* P, int is_hstep, hipStream_t s) {
+snmf_status inner_step(snmf_plan* pl, T* X, const T* P, int is_hstep, int k, hipStream_t s) {
   const int64_t n = pl->n;
   const int r = pl->r;
   const int gi = is_hstep ? 1 : 0;
@@ -267,35 +284,37 @@ snmf_status inner_steps(snmf_plan* pl, T* X, const T* P, int is_hstep, hipStream
   T* D = (T*)pl->D;
   T* g = (T*)pl->g;
   const bool lap = pl->lap && is_hstep;
-  const int32_t* g1 = &pl->st->hs_done;
-  const int32_t* g2 = &pl->st->done;
-  for (int k = 0; k < pl->p.inner_iters; ++k) {
-    if (!lap) {
-      launch_step1<T>(X, g, Z, D, nullptr, nullptr, GT, n, r, 0, 0, pl->kp, pl->st, pl->part,
-                      pl->counters + C_STEP1, s);
-      launch_step2<T>(X, g, Z, D, nullptr, (const T*)pl->C, P, nullptr, GT, n, r, 0, is_hstep,
-                      pl->kp, pl->st, pl->part, pl->counters + C_STEP2, s);
-    } else {
-      const int64_t* rp = pl->L.rowptr;
-      const int32_t* ci = pl->L.col;
-      const T* lv = (const T*)pl->L.val;
-      T* LT = (T*)pl->LT;
-      launch_step1<T>(X, g, Z, D, nullptr, D, GT, n, r, 1, 1, pl->kp, pl->st, pl->part,
-                      pl->counters + C_STEP1, s);
-      launch_spmm<T>(rp, ci, lv, D, n, r, LT, nullptr, nullptr, nullptr, nullptr, g1, g2, s);
-      launch_step1<T>(X, g, Z, D, LT, nullptr, GT, n, r, 2, 1, pl->kp, pl->st, pl->part,
-                      pl->counters + C_STEP1, s);
-      launch_spmm<T>(rp, ci, lv, D, n, r, nullptr, D, pl->part + kMaxGrid * kNumPart, pl->dots,
-                     pl->counters + C_LAPRED, g1, g2, s);
-      launch_line_search(pl->st, pl->kp, pl->dots, s);
-      launch_step2<T>(X, g, Z, D, nullptr, (const T*)pl->C, P, nullptr, GT, n, r, 1, is_hstep,
-                      pl->kp, pl->st, pl->part, pl->counters + C_STEP2, s);
-      launch_spmm<T>(rp, ci, lv, D, n, r, LT, nullptr, nullptr, nullptr, nullptr, g1, g2, s);
-      launch_step2<T>(X, g, Z, D, LT, (const T*)pl->C, P, (T*)pl->LX, GT, n, r, 2, is_hstep,
-                      pl->kp, pl->st, pl->part, pl->counters + C_STEP2, s);
-    }
+  if (!lap) {
+    launch_step1<T>(X, g, Z, D, nullptr, GT, pl->G64[0], pl->G64[1], n, r, k, 0, is_hstep, pl->kp,
+                    pl->st, pl->partsA, pl->partsB, pl->partsC, pl->trace, s);
+    launch_step2<T>(X, g, Z, D, nullptr, (const T*)pl->C, P, nullptr, GT, n, r, k, 0, is_hstep,
+                    pl->kp, pl->st, pl->partsB, nullptr, 0, pl->partsC, s);
+  } else {
+    const int64_t* rp = pl->L.rowptr;
+    const int32_t* ci = pl->L.col;
+    const T* lv = (const T*)pl->L.val;
+    T* LT = (T*)pl->LT;
+    const int32_t* g1 = &pl->st->done;
+    const int32_t* g2 = &pl->st->stop[k];
+    launch_step1<T>(X, g, Z, D, nullptr, GT, pl->G64[0], pl->G64[1], n, r, k, 1, is_hstep, pl->kp,
+                    pl->st, pl->partsA, pl->partsB, pl->partsC, pl->trace, s);
+    launch_spmm<T>(rp, ci, lv, D, n, r, LT, nullptr, nullptr, g1, g2, s);
+    launch_step1<T>(X, g, Z, D, LT, GT, pl->G64[0], pl->G64[1], n, r, k, 2, is_hstep, pl->kp,
+                    pl->st, pl->partsA, pl->partsB, pl->partsC, pl->trace, s);
+    launch_spmm<T>(rp, ci, lv, D, n, r, nullptr, D, pl->partsD, g1, g2, s);
+    launch_step2<T>(X, g, Z, D, nullptr, (const T*)pl->C, P, nullptr, GT, n, r, k, 1, is_hstep,
+                    pl->kp, pl->st, pl->partsB, pl->partsD, spmm_dot_grid(n), pl->partsC, s);
+    launch_spmm<T>(rp, ci, lv, D, n, r, LT, nullptr, nullptr, g1, g2, s);
+    launch_step2<T>(X, g, Z, D, LT, (const T*)pl->C, P, (T*)pl->LX, GT, n, r, k, 2, is_hstep,
+                    pl->kp, pl->st, pl->partsB, nullptr, 0, pl->partsC, s);
   }
   HIP_TRY(hipGetLastError());
+  return SNMF_OK;
+}
+
+template <typename T>
+snmf_status inner_steps(snmf_plan* pl, T* X, const T* P, int is_hstep, hipStream_t s) {
+  for (int k = 0; k < pl->p.inner_iters; ++k) SNMF_TRY(inner_step<T>(pl, X, P, is_hstep, k, s));
   return SNMF_OK;
 }
 
@@ -314,11 +333,23 @@ snmf_status outer_any(snmf_plan* pl, hipStream_t s) {
   return pl->prec == SNMF_F64 ? outer_iteration<double>(pl, s) : outer_iteration<float>(pl, s);
 }
 
-// Monitor record of the last outer iteration: the first half of a W-step.
+// Monitor record of the last outer iteration: the start of one more W-step, whose first
+// inner kernel completes the record and ends the solve (it has reached max_outer).
+template <typename T>
+snmf_status finalize(snmf_plan* pl, hipStream_t s) {
+  T* W = (T*)pl->Wb;
+  const T* H = (const T*)pl->Hb;
+  SNMF_TRY(half_start<T>(pl, W, H, 0, false, s));
+  const int64_t n = pl->n;
+  launch_step1<T>(W, (const T*)pl->g, (T*)pl->Z, (T*)pl->D, nullptr, (const T*)pl->GT[0],
+                  pl->G64[0], pl->G64[1], n, pl->r, 0, 0, 0, pl->kp, pl->st,
+                  pl->partsA, pl->partsB, pl->partsC, pl->trace, s);
+  HIP_TRY(hipGetLastError());
+  return SNMF_OK;
+}
+
 snmf_status finalize_any(snmf_plan* pl, hipStream_t s) {
-  if (pl->prec == SNMF_F64)
-    return half_start<double>(pl, (double*)pl->Wb, (const double*)pl->Hb, 0, false, s);
-  return half_start<float>(pl, (float*)pl->Wb, (const float*)pl->Hb, 0, false, s);
+  return pl->prec == SNMF_F64 ? finalize<double>(pl, s) : finalize<float>(pl, s);
 }
 
 snmf_status build_kparams(snmf_plan* pl) {
@@ -368,8 +399,11 @@ snmf_status plan_create(const snmf_matrix* A, int32_t r, const snmf_params* p, h
   pl->prec = p->prec;
   pl->esz = elt_size(p->prec);
   HIP_TRY(hipStreamCreateWithFlags(&pl->s, hipStreamNonBlocking));
+  HIP_TRY(hipStreamCreateWithFlags(&pl->side, hipStreamNonBlocking));
   HIP_TRY(hipEventCreateWithFlags(&pl->ev_in, hipEventDisableTiming));
   HIP_TRY(hipEventCreateWithFlags(&pl->ev_out, hipEventDisableTiming));
+  HIP_TRY(hipEventCreateWithFlags(&pl->ev_fork, hipEventDisableTiming));
+  HIP_TRY(hipEventCreateWithFlags(&pl->ev_join, hipEventDisableTiming));
   if (user) {
     HIP_TRY(hipEventRecord(pl->ev_in, user));
     HIP_TRY(hipStreamWaitEvent(pl->s, pl->ev_in, 0));
@@ -377,13 +411,13 @@ snmf_status plan_create(const snmf_matrix* A, int32_t r, const snmf_params* p, h
   const int64_t n = pl->n;
   const size_t nr = (size_t)n * r * pl->esz;
   int ksplit = 1;
-  if (A->fmt == SNMF_DENSE && pl->prec == SNMF_F32) pl->ds = plan_dense_f32(n);
+  if (A->fmt == SNMF_DENSE && pl->prec == SNMF_F32) pl->ds = plan_dense_f32(n, A->ld, r, A->dense);
   if (A->fmt == SNMF_DENSE && pl->prec == SNMF_BF16X3) {
     pl->ds = plan_dense_bf16(n);
     pl->ldb = (n + 63) / 64 * 64;
   }
   if (A->fmt == SNMF_DENSE && pl->prec != SNMF_F64) ksplit = pl->ds.ksplit;
-  pl->gram_blocks = (int)std::min<int64_t>(64, std::max<int64_t>(1, (n + 127) / 128));
+  pl->gram_blocks = (int)std::min<int64_t>(64, std::max<int64_t>(1, (n + 63) / 64));
   const int lai_nb = lai_blocks(n);
   // carve one allocation
   std::vector<std::pair<void**, size_t>> req;
@@ -404,6 +438,10 @@ snmf_status plan_create(const snmf_matrix* A, int32_t r, const snmf_params* p, h
   add((void**)&pl->G64[0], (size_t)r * r * 8);
   add((void**)&pl->G64[1], (size_t)r * r * 8);
   add((void**)&pl->part, (size_t)2 * kMaxGrid * kNumPart * 8);
+  add((void**)&pl->partsA, (size_t)kInnerGrid * kNumPart * 8);
+  add((void**)&pl->partsB, (size_t)kInnerGrid * kNumPart * 8);
+  add((void**)&pl->partsC, (size_t)kInnerGrid * kNumPart * 8);
+  add((void**)&pl->partsD, (size_t)kInnerGrid * kNumPart * 8);
   add((void**)&pl->gram_part, (size_t)pl->gram_blocks * r * r * 8);
   add((void**)&pl->dots, 64 * 8);
   add((void**)&pl->trace, (size_t)p->max_outer * kTraceFields * 8);
@@ -625,25 +663,40 @@ snmf_status snmf_plan_half_step(snmf_plan* pl, void* X, const void* P, int32_t i
     HIP_TRY(hipStreamWaitEvent(pl->s, pl->ev_in, 0));
   }
   launch_reset_state(pl->st, pl->normA2, pl->s);
+  const int K = pl->p.inner_iters;
+  // the inner iterations, then the entry of one more inner iteration (k = K), which
+  // reduces the last update's <S,S>, <S,Y> and forms e_K and alpha_K; its step work only
+  // touches scratch (Z, D), never X.
   if (pl->prec == SNMF_F64) {
     SNMF_TRY(half_start<double>(pl, (double*)X, (const double*)P, is_hstep, true, pl->s));
     SNMF_TRY(inner_steps<double>(pl, (double*)X, (const double*)P, is_hstep, pl->s));
+    launch_step1<double>((const double*)X, (const double*)pl->g, (double*)pl->Z, (double*)pl->D,
+                         nullptr, (const double*)pl->GT[is_hstep ? 1 : 0], pl->G64[0], pl->G64[1],
+                         pl->n, pl->r, K, (pl->lap && is_hstep) ? 1 : 0, is_hstep, pl->kp, pl->st,
+                         pl->partsA, pl->partsB, pl->partsC, pl->trace, pl->s);
   } else {
     SNMF_TRY(half_start<float>(pl, (float*)X, (const float*)P, is_hstep, true, pl->s));
     SNMF_TRY(inner_steps<float>(pl, (float*)X, (const float*)P, is_hstep, pl->s));
+    launch_step1<float>((const float*)X, (const float*)pl->g, (float*)pl->Z, (float*)pl->D,
+                        nullptr, (const float*)pl->GT[is_hstep ? 1 : 0], pl->G64[0], pl->G64[1],
+                        pl->n, pl->r, K, (pl->lap && is_hstep) ? 1 : 0, is_hstep, pl->kp, pl->st,
+                        pl->partsA, pl->partsB, pl->partsC, pl->trace, pl->s);
   }
+  HIP_TRY(hipGetLastError());
   State hs;
   HIP_TRY(hipMemcpyAsync(&hs, pl->st, sizeof(State), hipMemcpyDeviceToHost, pl->s));
   HIP_TRY(hipStreamSynchronize(pl->s));
   if (scalars) {
+    int last = 0;  // last inner iteration that ran
+    while (last + 1 < K && !hs.stop[last + 1]) ++last;
     scalars[0] = hs.rho;
-    scalars[1] = hs.alpha;
-    scalars[2] = hs.beta;
-    scalars[3] = hs.e;
-    scalars[4] = hs.ss;
-    scalars[5] = hs.sy;
+    scalars[1] = hs.alpha[last];
+    scalars[2] = hs.beta[last];
+    scalars[3] = hs.e[last];
+    scalars[4] = hs.last_ss;
+    scalars[5] = hs.last_sy;
     scalars[6] = (double)hs.ls_evals;
-    scalars[7] = (double)hs.k;
+    scalars[7] = (double)hs.inner_total;
   }
   if (user) {
     HIP_TRY(hipEventRecord(pl->ev_out, pl->s));
@@ -681,6 +734,42 @@ snmf_status snmf_plan_apass(snmf_plan* pl, const void* P, void* B, void* stream)
   return SNMF_OK;
 }
 
+snmf_status snmf_plan_time_apass(snmf_plan* pl, const void* P, int32_t reps, double* ms) {
+  if (!pl || !P || !ms) return fail(SNMF_E_ARG, "plan, P and ms are required");
+  if (reps < 1) return fail(SNMF_E_ARG, "reps must be >= 1");
+  HIP_TRY(hipMemsetAsync(pl->st, 0, sizeof(State), pl->s));
+  const int64_t n = pl->n;
+  const int r = pl->r;
+  auto launch = [&]() -> snmf_status {
+    if (pl->A.fmt == SNMF_DENSE && pl->prec == SNMF_BF16X3) {
+      launch_apass_bf16x3(pl->Ahi, pl->Alo, pl->ldb, pl->Pthi, pl->Ptlo, pl->ldb, n, r, pl->ds,
+                          (float*)pl->Bpart, n * r, pl->st, pl->s);
+      HIP_TRY(hipGetLastError());
+      return SNMF_OK;
+    }
+    if (pl->prec == SNMF_F64) return apass<double>(pl, (const double*)P, pl->s);
+    return apass<float>(pl, (const float*)P, pl->s);
+  };
+  if (pl->A.fmt == SNMF_DENSE && pl->prec == SNMF_BF16X3) {
+    launch_split_pt((const float*)P, n, r, pl->ldb, pl->Pthi, pl->Ptlo, pl->st, pl->s);
+    HIP_TRY(hipGetLastError());
+  }
+  SNMF_TRY(launch());
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  HIP_TRY(hipEventRecord(e0, pl->s));
+  for (int i = 0; i < reps; ++i) SNMF_TRY(launch());
+  HIP_TRY(hipEventRecord(e1, pl->s));
+  HIP_TRY(hipEventSynchronize(e1));
+  float tot = 0.0f;
+  HIP_TRY(hipEventElapsedTime(&tot, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *ms = (double)tot / reps;
+  return SNMF_OK;
+}
+
 snmf_status snmf_plan_gram(snmf_plan* pl, const void* P, double* G, void* stream) {
   if (!pl || !P || !G) return fail(SNMF_E_ARG, "plan, P and G are required");
   hipStream_t user = (hipStream_t)stream;
@@ -691,10 +780,10 @@ snmf_status snmf_plan_gram(snmf_plan* pl, const void* P, double* G, void* stream
   HIP_TRY(hipMemsetAsync(pl->st, 0, sizeof(State), pl->s));
   if (pl->prec == SNMF_F64)
     launch_gram<double>((const double*)P, pl->n, pl->r, pl->gram_part, pl->gram_blocks, pl->G64[0],
-                        (double*)pl->GT[0], pl->counters + C_GRAM, pl->st, pl->s);
+                        (double*)pl->GT[0], pl->st, pl->s);
   else
     launch_gram<float>((const float*)P, pl->n, pl->r, pl->gram_part, pl->gram_blocks, pl->G64[0],
-                       (float*)pl->GT[0], pl->counters + C_GRAM, pl->st, pl->s);
+                       (float*)pl->GT[0], pl->st, pl->s);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipMemcpyAsync(G, pl->G64[0], (size_t)pl->r * pl->r * 8, hipMemcpyDeviceToDevice, pl->s));
   HIP_TRY(hipStreamSynchronize(pl->s));
@@ -728,10 +817,10 @@ snmf_status snmf_spmm(const snmf_matrix* M, int32_t prec, const void* X, int32_t
   hipStream_t s = (hipStream_t)stream;
   if (prec == SNMF_F64)
     launch_spmm<double>(M->rowptr, M->col, (const double*)M->val, (const double*)X, M->n, r,
-                        (double*)Y, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, s);
+                        (double*)Y, nullptr, nullptr, nullptr, nullptr, s);
   else
     launch_spmm<float>(M->rowptr, M->col, (const float*)M->val, (const float*)X, M->n, r,
-                       (float*)Y, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, s);
+                       (float*)Y, nullptr, nullptr, nullptr, nullptr, s);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(s));
   return SNMF_OK;

@@ -60,7 +60,7 @@ class Info(ctypes.Structure):
 
 EXPORTS = ("snmf_params_default", "snmf_solve", "snmf_plan_create", "snmf_plan_solve",
            "snmf_plan_destroy", "snmf_plan_half_step", "snmf_plan_apass", "snmf_plan_gram",
-           "snmf_rho", "snmf_spmm", "snmf_split_bf16", "snmf_clock_rate_hz", "snmf_last_error",
+           "snmf_plan_time_apass", "snmf_rho", "snmf_spmm", "snmf_split_bf16", "snmf_clock_rate_hz", "snmf_last_error",
            "snmf_abi_version")
 
 
@@ -79,6 +79,7 @@ def load_library(path: str = LIB_PATH):
         "snmf_plan_half_step": ([vp, vp, vp, c_int32, vp, POINTER(c_double)], c_int32),
         "snmf_plan_apass": ([vp, vp, vp, vp], c_int32),
         "snmf_plan_gram": ([vp, vp, vp, vp], c_int32),
+        "snmf_plan_time_apass": ([vp, vp, c_int32, POINTER(c_double)], c_int32),
         "snmf_rho": ([vp, c_int32, POINTER(c_double), vp], c_int32),
         "snmf_spmm": ([POINTER(Matrix), c_int32, vp, c_int32, vp, vp], c_int32),
         "snmf_split_bf16": ([vp, c_int64, vp, vp, vp], c_int32),
@@ -209,6 +210,14 @@ class Plan:
     def apass(self, P, B):
         _check(_lib.snmf_plan_apass(self._h, _ptr(P), _ptr(B), _stream()))
         return B
+
+    def time_apass(self, P, reps: int = 50) -> float:
+        """Average A-pass kernel time in ms (HIP events on the plan's stream)."""
+        import torch
+        torch.cuda.synchronize()
+        ms = c_double()
+        _check(_lib.snmf_plan_time_apass(self._h, _ptr(P), int(reps), ctypes.byref(ms)))
+        return ms.value
 
     def gram(self, P):
         import torch
