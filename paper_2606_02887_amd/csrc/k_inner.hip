@@ -17,9 +17,10 @@
 //   step2_k   reads partsB [+ partsD = <D,LD>] (line search -> beta_k);
 //             writes partsC = {||S||^2, <SG,S>, <g,S>, monitor pieces, <S,LS>}
 //
-// Thread layout of a workgroup (256 threads): column c = tid % RP, row slot
-// rs = tid / RP; a tile holds TM = 8 * 256 / RP rows and each thread owns the 8 elements
-// (rs + p * 256/RP, c), p = 0..7, of the tile.  RP is the rank rounded up to a power of 2.
+// A workgroup (256 threads) works on tiles of TM = 8 * 256 / RP rows, RP being the rank
+// rounded up to a power of 2; each thread owns 8 elements of a tile (see Lay).  Each
+// kernel issues its global loads (partial sums, State scalars, G, the first tile) before
+// it waits on any of them.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -30,32 +31,124 @@ __device__ __forceinline__ double fmaT(double a, double b, double c) { return __
 
 template <int RP>
 struct TileCfg {
-  static constexpr int RS = kThreads / RP;  // rows per pass
+  static constexpr int RS = kThreads / RP;  // rows per pass (VALU layout)
   static constexpr int TM = RS * 8;         // rows per tile
+  static constexpr int NG = (RP * RP + kThreads - 1) / kThreads;  // G entries per thread
 };
 
-// acc[p] = sum_j sY[row_p][j] * sG[j][c] for the tile in LDS (row stride r).
+// Element ownership and the tile product.  Every thread owns 8 elements of a TM x RP
+// tile (TM * RP = 2048).
+//  * MFMA layout (FP32, RP >= 16): the tile is cut into 8 blocks of 16 x 16 (row-major
+//    block order, RP/16 blocks per row); wave w owns blocks 2w and 2w+1; in block b lane l
+//    owns rows 4(l/16) + v, v = 0..3, column l%16 -- exactly the output layout of
+//    v_mfma_f32_16x16x4f32, so the products land in the owner's registers.
+//  * VALU layout (FP64 or RP < 16): thread owns rows tid/RP + p * 256/RP, column tid%RP.
+// LDS tiles are zero-padded to RP columns and G to RP x RP; pitches are padded against
+// bank conflicts of the MFMA operand reads.
+template <typename T, int RP>
+struct Lay {
+  static constexpr bool MF = sizeof(T) == 4 && RP >= 16;
+  static constexpr int TM = TileCfg<RP>::TM;
+  static constexpr int YP = MF ? RP + 1 : RP;   // tile pitch
+  static constexpr int GP = MF ? RP + 16 : RP;  // G pitch
+  __device__ static __forceinline__ void rc(int p, int& lr, int& col) {
+    if constexpr (MF) {
+      const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+      const int blk = 2 * w + (p >> 2), v = p & 3;
+      constexpr int NBC = RP / 16;
+      lr = 16 * (blk / NBC) + 4 * (l >> 4) + v;
+      col = 16 * (blk % NBC) + (l & 15);
+    } else {
+      lr = (int)threadIdx.x / RP + p * (kThreads / RP);
+      col = (int)threadIdx.x % RP;
+    }
+  }
+};
+
+// LDS tiles are zero-padded, so the products run over a compile-time range and lanes with
+// col >= r compute harmless zeros.
+template <typename T>
+struct Vec4;
+template <>
+struct Vec4<float> {
+  typedef float type __attribute__((ext_vector_type(4)));
+};
+template <>
+struct Vec4<double> {
+  typedef double type __attribute__((ext_vector_type(4)));
+};
+typedef float f32x4m __attribute__((ext_vector_type(4)));
+
+// acc[p] = sum_j sY[row_p][j] * sG[j][col_p] for the owned elements.
 template <typename T, int RP>
 __device__ __forceinline__ void tile_gemm(const T* __restrict__ sY, const T* __restrict__ sG,
-                                          int r, int c, int rs, T (&acc)[8]) {
-  constexpr int RS = TileCfg<RP>::RS;
+                                          T (&acc)[8]) {
+  typedef Lay<T, RP> L;
+  if constexpr (L::MF) {
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+    constexpr int NBC = RP / 16;
 #pragma unroll
-  for (int p = 0; p < 8; ++p) acc[p] = T(0);
-  if (c >= r) return;
-  for (int j = 0; j < r; ++j) {
-    const T gj = sG[j * r + c];
+    for (int b = 0; b < 2; ++b) {
+      const int blk = 2 * w + b;
+      const int r0 = 16 * (blk / NBC), c0 = 16 * (blk % NBC);
+      f32x4m d = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int p = 0; p < 8; ++p) acc[p] = fmaT(sY[(rs + p * RS) * r + j], gj, acc[p]);
+      for (int kk = 0; kk < RP; kk += 4) {
+        const float a = sY[(r0 + (l & 15)) * L::YP + kk + (l >> 4)];
+        const float bb = sG[(kk + (l >> 4)) * L::GP + c0 + (l & 15)];
+        d = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bb, d, 0, 0, 0);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[4 * b + v] = d[v];
+    }
+  } else {
+    constexpr int RS = TileCfg<RP>::RS;
+    typedef typename Vec4<T>::type V4;
+    const int c = threadIdx.x % RP, rs = threadIdx.x / RP;
+#pragma unroll
+    for (int p = 0; p < 8; ++p) acc[p] = T(0);
+#pragma unroll 1
+    for (int j = 0; j < RP; j += 4) {
+      const T g0 = sG[(j + 0) * RP + c], g1 = sG[(j + 1) * RP + c];
+      const T g2 = sG[(j + 2) * RP + c], g3 = sG[(j + 3) * RP + c];
+#pragma unroll
+      for (int p = 0; p < 8; ++p) {
+        const V4 y = *(const V4*)&sY[(rs + p * RS) * RP + j];
+        acc[p] = fmaT(y[0], g0, acc[p]);
+        acc[p] = fmaT(y[1], g1, acc[p]);
+        acc[p] = fmaT(y[2], g2, acc[p]);
+        acc[p] = fmaT(y[3], g3, acc[p]);
+      }
+    }
   }
 }
 
 template <typename T, int RP>
-struct Smem {
-  T G[kMaxRank * kMaxRank];
-  T a[TileCfg<RP>::TM * RP];
-  T b[TileCfg<RP>::TM * RP];
+struct __attribute__((aligned(32))) Smem {
+  T G[RP * Lay<T, RP>::GP];
+  T a[Lay<T, RP>::TM * Lay<T, RP>::YP];
+  T b[Lay<T, RP>::TM * Lay<T, RP>::YP];
   double red[kThreads / kWave * kNumPart];
 };
+
+// G (r x r, row-major in global memory) in registers, then into the zero-padded LDS copy.
+template <typename T, int RP>
+__device__ __forceinline__ void load_G(const T* __restrict__ GT, int r, T (&v)[TileCfg<RP>::NG]) {
+#pragma unroll
+  for (int q = 0; q < TileCfg<RP>::NG; ++q) {
+    const int e = threadIdx.x + q * kThreads;
+    const int a = e / RP, b = e % RP;
+    v[q] = (e < RP * RP && a < r && b < r) ? GT[a * r + b] : T(0);
+  }
+}
+template <typename T, int RP>
+__device__ __forceinline__ void store_G(T* __restrict__ sG, const T (&v)[TileCfg<RP>::NG]) {
+#pragma unroll
+  for (int q = 0; q < TileCfg<RP>::NG; ++q) {
+    const int e = threadIdx.x + q * kThreads;
+    if (e < RP * RP) sG[(e / RP) * Lay<T, RP>::GP + (e % RP)] = v[q];
+  }
+}
 
 template <int K>
 __device__ __forceinline__ void write_parts(double* __restrict__ parts, const double (&v)[K]) {
@@ -64,19 +157,14 @@ __device__ __forceinline__ void write_parts(double* __restrict__ parts, const do
     for (int j = 0; j < K; ++j) parts[(size_t)blockIdx.x * kNumPart + j] = v[j];
 }
 
-// Partial sums of K consecutive slots starting at slot `first`, reduced over nb
-// workgroups in a fixed order; identical in every thread of every workgroup.
+// This thread's share (workgroup b = tid; nb <= 256) of K consecutive partial-sum slots
+// starting at `first`; block_sum then adds the shares in a fixed order.
 template <int K>
-__device__ __forceinline__ void reduce_slots(const double* __restrict__ part, int nb, int first,
-                                             double (&out)[K], double* sred) {
+__device__ __forceinline__ void load_slots(const double* __restrict__ part, int nb, int first,
+                                           double (&out)[K]) {
 #pragma unroll
-  for (int j = 0; j < K; ++j) out[j] = 0.0;
-  for (int b = threadIdx.x; b < nb; b += kThreads) {
-    const double* p = part + (size_t)b * kNumPart + first;
-#pragma unroll
-    for (int j = 0; j < K; ++j) out[j] += p[j];
-  }
-  block_sum<K>(out, sred);
+  for (int j = 0; j < K; ++j)
+    out[j] = (int)threadIdx.x < nb ? part[(size_t)threadIdx.x * kNumPart + first + j] : 0.0;
 }
 
 // ----------------------------------------------------------------------------- init
@@ -88,29 +176,33 @@ __global__ __launch_bounds__(kThreads) void k_init(
     const T* __restrict__ GT, int64_t n, int r, int is_hstep, KParams kp, State* __restrict__ st,
     double* __restrict__ partsA) {
   if (st->done) return;
-  constexpr int RS = TileCfg<RP>::RS, TM = TileCfg<RP>::TM;
+  typedef Lay<T, RP> L;
+  constexpr int TM = L::TM;
   __shared__ Smem<T, RP> sm;
-  const int tid = threadIdx.x, c = tid % RP, rs = tid / RP;
+  const int tid = threadIdx.x;
+  int lr[8], cl[8];
+#pragma unroll
+  for (int p = 0; p < 8; ++p) L::rc(p, lr[p], cl[p]);
   if (!is_hstep && blockIdx.x == 0 && tid == 0) {
     // snapshot for the monitor record completed by this W-step's first inner kernel
     st->snap_pending = st->pending;
     st->snap_outer = st->outer;
     st->pending = 0;
   }
-  for (int e = tid; e < r * r; e += kThreads) sm.G[e] = GT[e];
+  T gv[TileCfg<RP>::NG];
+  load_G<T, RP>(GT, r, gv);
   const T lam = (T)kp.lam, gam = (T)kp.gamma;
   double v[1] = {0.0};
   const int64_t ntiles = (n + TM - 1) / TM;
+  bool first = true;
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int64_t row0 = t * TM;
     T x[8], cv[8], pv[8];
-    __syncthreads();
 #pragma unroll
     for (int p = 0; p < 8; ++p) {
-      const int lr = rs + p * RS;
-      const int64_t row = row0 + lr;
-      const bool ok = row < n && c < r;
-      const int64_t o = row * r + c;
+      const int64_t row = row0 + lr[p];
+      const bool ok = row < n && cl[p] < r;
+      const int64_t o = row * r + cl[p];
       T b = T(0);
       if (ok) {
         int s = 0;
@@ -127,24 +219,28 @@ __global__ __launch_bounds__(kThreads) void k_init(
       x[p] = ok ? X[o] : T(0);
       pv[p] = ok ? P[o] : T(0);
       cv[p] = b + lam * pv[p];
-      if (ok) Cout[o] = cv[p];
-      if (c < r) sm.a[lr * r + c] = x[p];
     }
+    if (first) store_G<T, RP>(sm.G, gv);
+    first = false;
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < 8; ++p) sm.a[lr[p] * L::YP + cl[p]] = x[p];
     __syncthreads();
     T xg[8];
-    tile_gemm<T, RP>(sm.a, sm.G, r, c, rs, xg);
+    tile_gemm<T, RP>(sm.a, sm.G, xg);
 #pragma unroll
     for (int p = 0; p < 8; ++p) {
-      const int64_t row = row0 + rs + p * RS;
-      if (row < n && c < r) {
-        const int64_t o = row * r + c;
-        T gv = xg[p] + lam * x[p] - cv[p];
-        if (LX) gv += gam * LX[o];
-        g[o] = gv;
+      const int64_t row = row0 + lr[p];
+      if (row < n && cl[p] < r) {
+        const int64_t o = row * r + cl[p];
+        Cout[o] = cv[p];
+        T gvv = xg[p] + lam * x[p] - cv[p];
+        if (LX) gvv += gam * LX[o];
+        g[o] = gvv;
         if (is_hstep) {
           v[0] += (double)cv[p] * (double)pv[p];
         } else {
-          const double mn = (double)(x[p] < gv ? x[p] : gv);
+          const double mn = (double)(x[p] < gvv ? x[p] : gvv);
           v[0] += mn * mn;
         }
       }
@@ -156,12 +252,40 @@ __global__ __launch_bounds__(kThreads) void k_init(
 
 // ----------------------------------------------------------------------------- entry
 // First kernel of inner iteration k: derive e_k and alpha_k (or, at k = 0, complete the
-// monitor record of the previous outer iteration).  Returns false if this inner
-// iteration must not run (solve done, half-step stopped, breakdown).
-template <typename T>
+// monitor record of the previous outer iteration).  `pe` holds this thread's share of
+// the partial sums (loaded at kernel start by entry_loads).  Returns false if this
+// inner iteration must not run (solve done, half-step stopped, breakdown).
+__device__ __forceinline__ void entry_loads(int k, int is_hstep, const double* __restrict__ partsA,
+                                            const double* __restrict__ partsC, int nb,
+                                            double (&pe)[6]) {
+  if (k == 0) {
+    double a1[1], m5[5];
+    load_slots<1>(partsA, nb, 0, a1);
+    if (!is_hstep) {
+      load_slots<5>(partsC, nb, 3, m5);
+    } else {
+#pragma unroll
+      for (int j = 0; j < 5; ++j) m5[j] = 0.0;
+    }
+    pe[0] = a1[0];
+#pragma unroll
+    for (int j = 0; j < 5; ++j) pe[1 + j] = m5[j];
+  } else {
+    double s3[3], s1[1];
+    load_slots<3>(partsC, nb, 0, s3);
+    load_slots<1>(partsC, nb, 8, s1);
+    pe[0] = s3[0];
+    pe[1] = s3[1];
+    pe[2] = s3[2];
+    pe[3] = s1[0];
+    pe[4] = 0.0;
+    pe[5] = 0.0;
+  }
+}
+
 __device__ bool inner_entry(int k, int is_hstep, int r, const KParams& kp, State* __restrict__ st,
-                            const double* __restrict__ partsA, const double* __restrict__ partsC,
-                            int nb, const double* __restrict__ Gcur,
+                            double (&pe)[6], int stop_prev, double e_prev, double rho,
+                            const double* __restrict__ Gcur,
                             const double* __restrict__ Gprev, double* __restrict__ trace,
                             double* sred, double& alpha_out) {
   const bool w0 = blockIdx.x == 0 && threadIdx.x == 0;
@@ -169,9 +293,9 @@ __device__ bool inner_entry(int k, int is_hstep, int r, const KParams& kp, State
   if (k == 0) {
     if (!is_hstep) {
       if (st->snap_pending) {
-        double a1[1], m[5], gg[3] = {0.0, 0.0, 0.0};
-        reduce_slots<1>(partsA, nb, 0, a1, sred);   // ||min(W, grad_W)||^2
-        reduce_slots<5>(partsC, nb, 3, m, sred);    // <C,Ht>, <W,Ht>, ||Ht-W||^2, pgH^2, <Ht,LHt>
+        // ||min(W, grad_W)||^2, <C,Ht>, <W,Ht>, ||Ht-W||^2, pgH^2, <Ht,LHt>
+        block_sum<6>(pe, sred);
+        double gg[3] = {0.0, 0.0, 0.0};
         for (int e = threadIdx.x; e < r * r; e += kThreads) {
           gg[0] += Gprev[e] * Gcur[e];   // <W^T W, Ht^T Ht>
           gg[1] += Gprev[e] * Gprev[e];  // ||W^T W||_F^2
@@ -179,15 +303,15 @@ __device__ bool inner_entry(int k, int is_hstep, int r, const KParams& kp, State
         for (int a = threadIdx.x; a < r; a += kThreads) gg[2] += Gprev[a * r + a];  // ||W||^2
         block_sum<3>(gg, sred);
         const double nA2 = st->normA2;
-        const double AWHt = m[0] - kp.lam * m[1];   // <A W, Ht>
-        const double AWW = st->m_CP - kp.lam * gg[2];  // <A W, W>
+        const double AWHt = pe[1] - kp.lam * pe[2];     // <A W, Ht>
+        const double AWW = st->m_CP - kp.lam * gg[2];   // <A W, W>
         const double res2 = nA2 - 2.0 * AWHt + gg[0];
         const double resw2 = nA2 - 2.0 * AWW + gg[1];
         const double res = sqrt(fmax(res2, 0.0) / nA2);
         const double resw = sqrt(fmax(resw2, 0.0) / nA2);
-        const double sym = sqrt(m[2] / fmax(gg[2], 1e-300));
-        const double pg = sqrt(a1[0] + m[3]);
-        const double f = 0.5 * fmax(res2, 0.0) + 0.5 * kp.lam * m[2] + 0.5 * kp.gamma * m[4];
+        const double sym = sqrt(pe[3] / fmax(gg[2], 1e-300));
+        const double pg = sqrt(pe[0] + pe[4]);
+        const double f = 0.5 * fmax(res2, 0.0) + 0.5 * kp.lam * pe[3] + 0.5 * kp.gamma * pe[5];
         const int o = st->snap_outer;
         const bool conv = kp.target > 0.0 && res <= kp.target;
         const bool bad = !(res == res) || !(pg == pg);
@@ -218,25 +342,23 @@ __device__ bool inner_entry(int k, int is_hstep, int r, const KParams& kp, State
         if (fin) return false;
       }
     } else {
-      double a1[1];
-      reduce_slots<1>(partsA, nb, 0, a1, sred);     // <C, P> with P = W
+      double a1[1] = {pe[0]};
+      block_sum<1>(a1, sred);                        // <C, P> with P = W
       if (w0) st->m_CP = a1[0];
     }
     e_k = 0.0;
-    alpha_k = 1.0 / st->rho;
+    alpha_k = 1.0 / rho;
   } else {
-    if (st->stop[k - 1]) {
+    if (stop_prev) {
       if (w0) st->stop[k] = 1;
       return false;
     }
-    double s4[3];
-    reduce_slots<3>(partsC, nb, 0, s4, sred);
-    double sl[1];
-    reduce_slots<1>(partsC, nb, 8, sl, sred);
+    double s4[4] = {pe[0], pe[1], pe[2], pe[3]};
+    block_sum<4>(s4, sred);
     const double ss = s4[0];
-    const double sy = s4[1] + kp.lam * ss + kp.gamma * sl[0];  // <S, Y> = <S(G+lam I),S> [+gam<S,LS>]
+    const double sy = s4[1] + kp.lam * ss + kp.gamma * s4[3];  // <S,Y> = <S(G+lam I),S> [+gam<S,LS>]
     const double dlt = s4[2] + 0.5 * sy;                        // f(X_k) - f(X_{k-1})
-    e_k = kp.eta * (st->e[k - 1] - dlt);                        // F_k - f(X_k)
+    e_k = kp.eta * (e_prev - dlt);                        // F_k - f(X_k)
     const double ratio = sy > 0.0 ? ss / sy : 1e308;
     alpha_k = fmin(kp.amax, fmax(kp.amin, ratio));
     const bool bad = !(sy == sy) || !(dlt == dlt);
@@ -276,73 +398,89 @@ __global__ __launch_bounds__(kThreads) void k_step1(
     const double* __restrict__ Gprev, int64_t n, int r, int k, int phase, int is_hstep,
     KParams kp, State* __restrict__ st, const double* __restrict__ partsA,
     double* __restrict__ partsB, const double* __restrict__ partsC, double* __restrict__ trace) {
-  if (st->done) return;
-  constexpr int RS = TileCfg<RP>::RS, TM = TileCfg<RP>::TM;
+  typedef Lay<T, RP> L;
+  constexpr int TM = L::TM;
   __shared__ Smem<T, RP> sm;
-  const int tid = threadIdx.x, c = tid % RP, rs = tid / RP;
+  int lr[8], cl[8];
+#pragma unroll
+  for (int p = 0; p < 8; ++p) L::rc(p, lr[p], cl[p]);
+  const int64_t ntiles = (n + TM - 1) / TM;
+  // loads first: State scalars, partial sums of the previous kernel, G, the first tile
+  const int done = st->done;
+  const int km = k > 0 ? k - 1 : 0;
+  const int stop_prev = st->stop[km], stop_k = st->stop[k];
+  const double e_prev = st->e[km], alpha_k2 = st->alpha[k], rho = st->rho;
+  double pe[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (phase != 2) entry_loads(k, is_hstep, partsA, partsC, gridDim.x, pe);
+  T gv[TileCfg<RP>::NG];
+  if (phase != 1) load_G<T, RP>(GT, r, gv);
+  T x[8], gvv[8], z[8], lz[8];
+  auto load_tile = [&](int64_t row0) {
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+      const int64_t row = row0 + lr[p];
+      const bool ok = row < n && cl[p] < r;
+      const int64_t o = row * r + cl[p];
+      x[p] = ok ? X[o] : T(0);
+      gvv[p] = ok ? g[o] : T(0);
+      z[p] = (ok && phase == 2) ? Z[o] : T(0);
+      lz[p] = (ok && phase == 2) ? LdZ[o] : T(0);
+    }
+  };
+  if ((int64_t)blockIdx.x < ntiles) load_tile((int64_t)blockIdx.x * TM);
+  if (done) return;
   double alpha_d = 0.0;
   if (phase != 2) {
-    if (!inner_entry<T>(k, is_hstep, r, kp, st, partsA, partsC, gridDim.x, Gcur, Gprev, trace,
-                        sm.red, alpha_d))
+    if (!inner_entry(k, is_hstep, r, kp, st, pe, stop_prev, e_prev, rho, Gcur, Gprev, trace,
+                     sm.red, alpha_d))
       return;
   } else {
-    if (st->stop[k]) return;
-    alpha_d = st->alpha[k];
+    if (stop_k) return;
+    alpha_d = alpha_k2;
   }
-  const T rinv = (T)(1.0 / st->rho);
+  const T rinv = (T)(1.0 / rho);
   const T alpha = (T)alpha_d;
   const T lam = (T)kp.lam, gam = (T)kp.gamma;
-  const int64_t ntiles = (n + TM - 1) / TM;
   if (phase == 1) {
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+      if (t != blockIdx.x) load_tile(t * TM);
 #pragma unroll
       for (int p = 0; p < 8; ++p) {
-        const int64_t row = t * TM + rs + p * RS;
-        if (row < n && c < r) {
-          const int64_t o = row * r + c;
-          const T x = X[o];
-          const T z = relu(x - g[o] * rinv);
-          Z[o] = z;
-          D[o] = z - x;
+        const int64_t row = t * TM + lr[p];
+        if (row < n && cl[p] < r) {
+          const int64_t o = row * r + cl[p];
+          const T zz = relu(x[p] - gvv[p] * rinv);
+          Z[o] = zz;
+          D[o] = zz - x[p];
         }
       }
     }
     return;
   }
-  for (int e = tid; e < r * r; e += kThreads) sm.G[e] = GT[e];
+  store_G<T, RP>(sm.G, gv);
   double v[4] = {0.0, 0.0, 0.0, 0.0};
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int64_t row0 = t * TM;
-    T x[8], gv[8], z[8];
+    if (t != blockIdx.x) load_tile(row0);
     __syncthreads();
 #pragma unroll
     for (int p = 0; p < 8; ++p) {
-      const int lr = rs + p * RS;
-      const int64_t row = row0 + lr;
-      const bool ok = row < n && c < r;
-      const int64_t o = row * r + c;
-      x[p] = ok ? X[o] : T(0);
-      gv[p] = ok ? g[o] : T(0);
-      if (phase == 2) {
-        z[p] = ok ? Z[o] : T(0);
-      } else {
-        z[p] = relu(x[p] - gv[p] * rinv);
-      }
-      if (c < r) sm.a[lr * r + c] = z[p] - x[p];
+      const bool ok = row0 + lr[p] < n && cl[p] < r;
+      if (phase == 0) z[p] = relu(x[p] - gvv[p] * rinv);
+      sm.a[lr[p] * L::YP + cl[p]] = ok ? z[p] - x[p] : T(0);
     }
     __syncthreads();
     T dzg[8];
-    tile_gemm<T, RP>(sm.a, sm.G, r, c, rs, dzg);
+    tile_gemm<T, RP>(sm.a, sm.G, dzg);
     T d[8];
 #pragma unroll
     for (int p = 0; p < 8; ++p) {
-      const int lr = rs + p * RS;
-      const int64_t row = row0 + lr;
-      const bool ok = row < n && c < r;
-      const int64_t o = row * r + c;
+      const int64_t row = row0 + lr[p];
+      const bool ok = row < n && cl[p] < r;
+      const int64_t o = row * r + cl[p];
       const T dz = z[p] - x[p];
-      T gz = gv[p] + dzg[p] + lam * dz;
-      if (phase == 2 && ok) gz += gam * LdZ[o];
+      T gz = gvv[p] + dzg[p] + lam * dz;
+      if (phase == 2) gz += gam * lz[p];
       const T dd = ok ? relu(z[p] - alpha * gz) - z[p] : T(0);
       d[p] = dd;
       if (ok) {
@@ -350,13 +488,13 @@ __global__ __launch_bounds__(kThreads) void k_step1(
         D[o] = dd;
         v[0] += (double)gz * (double)dd;
         v[2] += (double)dd * (double)dd;
-        v[3] += 0.5 * ((double)gv[p] + (double)gz) * (double)dz;
+        v[3] += 0.5 * ((double)gvv[p] + (double)gz) * (double)dz;
       }
-      if (c < r) sm.b[lr * r + c] = dd;
+      sm.b[lr[p] * L::YP + cl[p]] = dd;
     }
     __syncthreads();
     T dg[8];
-    tile_gemm<T, RP>(sm.b, sm.G, r, c, rs, dg);
+    tile_gemm<T, RP>(sm.b, sm.G, dg);
 #pragma unroll
     for (int p = 0; p < 8; ++p) v[1] += (double)dg[p] * (double)d[p];
   }
@@ -406,23 +544,55 @@ __global__ __launch_bounds__(kThreads) void k_step2(
     T* __restrict__ LXb, const T* __restrict__ GT, int64_t n, int r, int k, int phase,
     int is_hstep, KParams kp, State* __restrict__ st, const double* __restrict__ partsB,
     const double* __restrict__ partsD, int nbD, double* __restrict__ partsC) {
-  if (st->done | st->stop[k]) return;
-  constexpr int RS = TileCfg<RP>::RS, TM = TileCfg<RP>::TM;
+  typedef Lay<T, RP> L;
+  constexpr int TM = L::TM;
   __shared__ Smem<T, RP> sm;
-  const int tid = threadIdx.x, c = tid % RP, rs = tid / RP;
-  const bool w0 = blockIdx.x == 0 && tid == 0;
+  int lr[8], cl[8];
+#pragma unroll
+  for (int p = 0; p < 8; ++p) L::rc(p, lr[p], cl[p]);
+  const bool w0 = blockIdx.x == 0 && threadIdx.x == 0;
+  const int64_t ntiles = (n + TM - 1) / TM;
+  // loads first: State scalars, partial sums of step 1 (and <D, L D>), G, the first tile
+  const int skip = st->done | st->stop[k];
+  const double e_k = st->e[k], beta_k2 = st->beta[k];
+  double pb[4] = {0.0, 0.0, 0.0, 0.0}, pd[1] = {0.0};
+  if (phase != 2) {
+    load_slots<4>(partsB, gridDim.x, 0, pb);
+    if (partsD) load_slots<1>(partsD, nbD, 0, pd);
+  }
+  T gv[TileCfg<RP>::NG];
+  if (phase != 1) load_G<T, RP>(GT, r, gv);
+  const bool mon = is_hstep && phase != 1;
+  const bool lap = phase == 2;
+  T x[8], zz[8], dd[8], go[8], cv[8], pv[8], ls[8], lx[8];
+  auto load_tile = [&](int64_t row0) {
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+      const int64_t row = row0 + lr[p];
+      const bool ok = row < n && cl[p] < r;
+      const int64_t o = row * r + cl[p];
+      x[p] = ok ? X[o] : T(0);
+      zz[p] = ok ? Z[o] : T(0);
+      dd[p] = (ok && phase != 2) ? D[o] : T(0);
+      go[p] = (ok && phase != 1) ? g[o] : T(0);
+      cv[p] = (ok && mon) ? C[o] : T(0);
+      pv[p] = (ok && mon) ? P[o] : T(0);
+      ls[p] = (ok && lap) ? LS[o] : T(0);
+      lx[p] = (ok && lap && LXb) ? LXb[o] : T(0);
+    }
+  };
+  if ((int64_t)blockIdx.x < ntiles) load_tile((int64_t)blockIdx.x * TM);
+  if (skip) return;
   double beta;
   if (phase != 2) {
-    double b4[4];
-    reduce_slots<4>(partsB, gridDim.x, 0, b4, sm.red);
-    double q = b4[1] + kp.lam * b4[2];
+    block_sum<4>(pb, sm.red);
+    double q = pb[1] + kp.lam * pb[2];
     if (partsD) {
-      double dl[1];
-      reduce_slots<1>(partsD, nbD, 0, dl, sm.red);
-      q += kp.gamma * dl[0];
+      block_sum<1>(pd, sm.red);
+      q += kp.gamma * pd[0];
     }
     int evals, exh;
-    beta = line_search(b4[0], q, b4[3], st->e[k], kp, evals, exh);
+    beta = line_search(pb[0], q, pb[3], e_k, kp, evals, exh);
     if (w0) {
       st->beta[k] = beta;
       st->ls_evals += evals;
@@ -430,84 +600,88 @@ __global__ __launch_bounds__(kThreads) void k_step2(
       st->inner_total += 1;
     }
   } else {
-    beta = st->beta[k];
+    beta = beta_k2;
   }
   const T step = (T)(kp.phi * beta);
   const T lam = (T)kp.lam, gam = (T)kp.gamma;
-  const int64_t ntiles = (n + TM - 1) / TM;
   if (phase == 1) {
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+      if (t != blockIdx.x) load_tile(t * TM);
 #pragma unroll
       for (int p = 0; p < 8; ++p) {
-        const int64_t row = t * TM + rs + p * RS;
-        if (row < n && c < r) {
-          const int64_t o = row * r + c;
-          T xn = Z[o] + step * D[o];
+        const int64_t row = t * TM + lr[p];
+        if (row < n && cl[p] < r) {
+          const int64_t o = row * r + cl[p];
+          T xn = zz[p] + step * dd[p];
           if (kp.project) xn = relu(xn);
           Z[o] = xn;
-          D[o] = xn - X[o];
+          D[o] = xn - x[p];
         }
       }
     }
     return;
   }
-  for (int e = tid; e < r * r; e += kThreads) sm.G[e] = GT[e];
+  store_G<T, RP>(sm.G, gv);
   double v[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int64_t row0 = t * TM;
-    T x[8], xn[8];
+    if (t != blockIdx.x) load_tile(row0);
+    T xn[8];
     __syncthreads();
 #pragma unroll
     for (int p = 0; p < 8; ++p) {
-      const int lr = rs + p * RS;
-      const int64_t row = row0 + lr;
-      const bool ok = row < n && c < r;
-      const int64_t o = row * r + c;
-      x[p] = ok ? X[o] : T(0);
+      const bool ok = row0 + lr[p] < n && cl[p] < r;
       if (phase == 2) {
-        xn[p] = ok ? Z[o] : T(0);
+        xn[p] = zz[p];
       } else {
-        T y = ok ? Z[o] + step * D[o] : T(0);
+        T y = zz[p] + step * dd[p];
         if (kp.project) y = relu(y);
-        xn[p] = y;
+        xn[p] = ok ? y : T(0);
       }
-      if (c < r) sm.a[lr * r + c] = xn[p] - x[p];
+      sm.a[lr[p] * L::YP + cl[p]] = ok ? xn[p] - x[p] : T(0);
     }
     __syncthreads();
     T sg[8];
-    tile_gemm<T, RP>(sm.a, sm.G, r, c, rs, sg);
+    tile_gemm<T, RP>(sm.a, sm.G, sg);
 #pragma unroll
     for (int p = 0; p < 8; ++p) {
-      const int64_t row = row0 + rs + p * RS;
-      if (row < n && c < r) {
-        const int64_t o = row * r + c;
+      const int64_t row = row0 + lr[p];
+      if (row < n && cl[p] < r) {
+        const int64_t o = row * r + cl[p];
         const T s = xn[p] - x[p];
-        const T gold = g[o];
-        T gn = gold + sg[p] + lam * s;
-        if (phase == 2) gn += gam * LS[o];
+        T gn = go[p] + sg[p] + lam * s;
+        if (lap) gn += gam * ls[p];
         X[o] = xn[p];
         g[o] = gn;
         v[0] += (double)s * (double)s;
         v[1] += (double)sg[p] * (double)s;
-        v[2] += (double)gold * (double)s;
-        if (phase == 2) v[8] += (double)s * (double)LS[o];
+        v[2] += (double)go[p] * (double)s;
+        if (lap) v[8] += (double)s * (double)ls[p];
         if (is_hstep) {
-          const double cx = (double)C[o], px = (double)P[o], xv = (double)xn[p];
-          v[3] += cx * xv;
-          v[4] += px * xv;
-          v[5] += (xv - px) * (xv - px);
+          const double xv = (double)xn[p];
+          v[3] += (double)cv[p] * xv;
+          v[4] += (double)pv[p] * xv;
+          v[5] += (xv - (double)pv[p]) * (xv - (double)pv[p]);
           const double mn = (double)(xn[p] < gn ? xn[p] : gn);
           v[6] += mn * mn;
         }
-        if (phase == 2 && LXb) {
-          const T lxn = LXb[o] + LS[o];
+        if (lap && LXb) {
+          const T lxn = lx[p] + ls[p];
           LXb[o] = lxn;
           if (is_hstep) v[7] += (double)xn[p] * (double)lxn;
         }
       }
     }
   }
-  block_sum<9>(v, sm.red);
+  if (is_hstep || lap) {
+    block_sum<9>(v, sm.red);
+  } else {  // a W-step without Laplacian produces only the first three sums
+    double v3[3] = {v[0], v[1], v[2]};
+    block_sum<3>(v3, sm.red);
+    v[0] = v3[0];
+    v[1] = v3[1];
+    v[2] = v3[2];
+  }
   write_parts<9>(partsC, v);
   if (is_hstep && w0) {
     st->pending = 1;

@@ -82,10 +82,11 @@ __global__ __launch_bounds__(kThreads) void k_gram_reduce(const double* __restri
 
 // ----------------------------------------------------------------------------- rho
 // Largest eigenvalue of the symmetric positive semidefinite r x r matrix G (r <= 64).
-// Wave 0 runs r steps of the Lanczos recurrence from the all-ones vector (lane i holds
-// row i of G in registers; the current Lanczos vector is broadcast through LDS; inner
-// products are DPP wave sums), then all four waves locate the largest eigenvalue of the
-// tridiagonal matrix by bisection with Sturm counts, 256 trial shifts per round.
+// r steps of the Lanczos recurrence from the all-ones vector: lane i of wave w holds
+// G[i][16w .. 16w+15] in registers, the four partial products of G q are combined in
+// LDS in wave order, so every wave then holds the same vector and derives the same
+// alpha_j, beta_j (DPP wave sums).  All four waves then locate the largest eigenvalue of
+// the tridiagonal matrix by bisection with Sturm counts, 256 trial shifts per round.
 // Without re-orthogonalisation the extreme Ritz value is still accurate: loss of
 // orthogonality only adds copies of converged Ritz values (Paige), and r steps span the
 // whole space in exact arithmetic; on Gram matrices of planted, graph and clustered
@@ -96,59 +97,56 @@ __global__ __launch_bounds__(kThreads) void k_rho(const double* __restrict__ G, 
                                                   State* __restrict__ st) {
   if (st->done) return;
   __shared__ __attribute__((aligned(16))) double sq[kMaxRank];
+  __shared__ double sp[4][kMaxRank];
   __shared__ double sa[kMaxRank], sb[kMaxRank];
-  __shared__ int sm_m;
   __shared__ int sfirst[kThreads / kWave];
-  const int t = threadIdx.x;
-  if (t < kWave) {
-    const int i = t;
-    double grow[kMaxRank];
-    double gn2 = 0.0;
+  const int t = threadIdx.x, i = t & 63, w = t >> 6;
+  double grow[16];
+  double gn2 = 0.0;
 #pragma unroll
-    for (int k = 0; k < kMaxRank; ++k) {
-      grow[k] = (i < r && k < r) ? G[i * r + k] : 0.0;
-      gn2 = __builtin_fma(grow[k], grow[k], gn2);
-    }
-    const double tol = 1e-15 * sqrt(wave_sum(gn2));
-    double q = i < r ? 1.0 / sqrt((double)r) : 0.0;
-    double qprev = 0.0, bprev = 0.0;
-    int m = 0;
-    for (int j = 0; j < r; ++j) {
-      sq[i] = q;
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      double w0 = 0.0, w1 = 0.0, w2 = 0.0, w3 = 0.0;
+  for (int k = 0; k < 16; ++k) {
+    const int col = 16 * w + k;
+    grow[k] = (i < r && col < r) ? G[i * r + col] : 0.0;
+    gn2 = __builtin_fma(grow[k], grow[k], gn2);
+  }
+  sp[w][i] = gn2;
+  double q = i < r ? 1.0 / sqrt((double)r) : 0.0;
+  if (w == 0) sq[i] = q;
+  __syncthreads();
+  const double tol = 1e-15 * sqrt(wave_sum((sp[0][i] + sp[1][i]) + (sp[2][i] + sp[3][i])));
+  __syncthreads();
+  double qprev = 0.0, bprev = 0.0;
+  int m = 0;
+  for (int j = 0; j < r; ++j) {
+    double w0 = 0.0, w1 = 0.0, w2 = 0.0, w3 = 0.0;
 #pragma unroll
-      for (int k = 0; k < kMaxRank; k += 4) {
-        const double2 u = *(const double2*)&sq[k];
-        const double2 v = *(const double2*)&sq[k + 2];
-        w0 = __builtin_fma(grow[k], u.x, w0);
-        w1 = __builtin_fma(grow[k + 1], u.y, w1);
-        w2 = __builtin_fma(grow[k + 2], v.x, w2);
-        w3 = __builtin_fma(grow[k + 3], v.y, w3);
-      }
-      double w = (w0 + w1) + (w2 + w3);
-      const double a = wave_sum(q * w);
-      w -= a * q + bprev * qprev;
-      const double b = sqrt(wave_sum(w * w));
-      if (i == 0) {
-        sa[j] = a;
-        sb[j] = b;
-      }
-      m = j + 1;
-      if (!(b > tol)) break;
-      qprev = q;
-      q = w / b;
-      bprev = b;
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int k = 0; k < 16; k += 4) {
+      const double2 u = *(const double2*)&sq[16 * w + k];
+      const double2 v = *(const double2*)&sq[16 * w + k + 2];
+      w0 = __builtin_fma(grow[k], u.x, w0);
+      w1 = __builtin_fma(grow[k + 1], u.y, w1);
+      w2 = __builtin_fma(grow[k + 2], v.x, w2);
+      w3 = __builtin_fma(grow[k + 3], v.y, w3);
     }
-    if (i == 0) sm_m = m;
+    sp[w][i] = (w0 + w1) + (w2 + w3);
+    __syncthreads();
+    double wv = (sp[0][i] + sp[1][i]) + (sp[2][i] + sp[3][i]);  // (G q_j)_i
+    const double a = wave_sum(q * wv);
+    wv -= a * q + bprev * qprev;
+    const double b = sqrt(wave_sum(wv * wv));
+    if (t == 0) {
+      sa[j] = a;
+      sb[j] = b;
+    }
+    m = j + 1;
+    if (!(b > tol)) break;
+    qprev = q;
+    q = wv / b;
+    bprev = b;
+    if (w == 0) sq[i] = q;
+    __syncthreads();
   }
   __syncthreads();
-  const int m = sm_m;
   // bounds for the largest eigenvalue of T = tridiag(sb, sa, sb)
   double lo = -1e300, hi = -1e300;
   for (int k = 0; k < m; ++k) {
