@@ -35,6 +35,9 @@ def _args():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-outer", type=int, default=0,
                     help="outer iterations of the CPU-reference sample (0: pick ~15 s)")
+    ap.add_argument("--apass-only", action="store_true",
+                    help="only a 256 MiB device copy (the counter scale reference) and 20 "
+                         "A-pass launches of each form; for hardware-counter runs")
     return ap.parse_args()
 
 
@@ -61,6 +64,44 @@ def _cpu_baseline(A64, W0, lam, outer):
                       f"n={N}, r={R} workload ({dt:.1f} s)"}
 
 
+COPY_BYTES = 256 << 20
+
+
+def _apass_only(torch, S, A, W0, lam):
+    """A plain copy of COPY_BYTES (its FETCH_SIZE / WRITE_SIZE calibrate the counters) and
+    20 launches of each A-pass form, nothing else."""
+    src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=A.device)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    for prec in (S.F32, S.BF16X3):
+        with S.Plan(S.dense(A), R, S.params(lam=lam, prec=prec, max_outer=1)) as pl:
+            B = torch.empty_like(W0)
+            for _ in range(20):
+                pl.apass(W0, B)
+            torch.cuda.synchronize()
+    print(json.dumps({"apass_only": True, "copy_bytes": COPY_BYTES}))
+
+
+def _traffic(kernel_src, name):
+    """HBM bytes per launch of `name` from the committed hardware-counter summary, or None
+    if that summary is missing or was taken on a different kernel source."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "apass_c1_hbm_traffic.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    try:
+        blob = json.loads(txt.split("```json")[1].split("```")[0])
+    except (IndexError, ValueError):
+        return None
+    src = os.path.join(ROOT, "paper_2606_02887_amd", "csrc", kernel_src)
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if blob.get("source_sha256") != sha or name not in blob.get("kernels", {}):
+        return None
+    return blob["kernels"][name]["bytes_per_launch"]
+
+
 def main():
     a = _args()
     if a.gpus != 1:
@@ -81,6 +122,10 @@ def main():
     A = torch.from_numpy(A64.astype(np.float32)).to(dev)
     W0 = torch.from_numpy(W064.astype(np.float32)).to(dev)
     torch.cuda.synchronize()
+
+    if a.apass_only:
+        _apass_only(torch, S, A, W0, lam)
+        return
 
     forms = {}
     plans = {}
@@ -111,11 +156,13 @@ def main():
     bytes_bf = 2.0 * 2 * N * N + 2.0 * 2 * N * R + 4.0 * N * R   # A_hi, A_lo, P_hi/lo, B
     achbf = bytes_bf / (msbf * 1e-3) / 1e9
     roof = {"bound": "mfma", "achieved": ach32, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": ach32 / FP32_PEAK_TFLOPS, "traffic": None,
+            "frac": ach32 / FP32_PEAK_TFLOPS,
+            "traffic": _traffic("k_apass_dense.hip", "k_apass_f32w"),
             "kernel": "k_apass_f32 (B = A P, FP32 MFMA)", "ms_per_launch": ms32,
             "algorithmic_per_launch": f"{flops:.4g} flop (2 n^2 r)"}
     forms["bf16x3"]["apass"] = {"bound": "hbm", "achieved": achbf, "peak": HBM_PEAK_GBS,
                                 "unit": "GB/s", "frac": achbf / HBM_PEAK_GBS,
+                                "traffic": _traffic("k_apass_dense.hip", "k_apass_bf16x3"),
                                 "ms_per_launch": msbf,
                                 "tflops": 3 * flops / (msbf * 1e-3) / 1e12}
 
