@@ -184,6 +184,49 @@ snmf_status snmf_plan_time_apass(snmf_plan* plan, const void* P, int32_t reps, d
 snmf_status snmf_split_bf16(const float* x, int64_t count, uint16_t* hi, uint16_t* lo,
                             void* stream);
 
+/* ---------------------------------------------------------------- batched solves
+ * The batching form: many independent SNMPBB solves (problem g, restart s) run together,
+ * every kernel of a half-step covering all of them in one launch (one per distinct rank
+ * for the row-tile kernels), the whole outer iteration replayed as one hipGraph.  Each
+ * instance keeps its own scalars (rho, BB steps, line search, nonmonotone reference,
+ * monitor, stop flag), so instance (g, s) follows exactly the iteration of a single
+ * solve of problem g from its start; the restarts of a problem share one sweep over its
+ * CSR matrix in the A-pass (B_s = A P_s for all s at once).  This form is not in the
+ * paper: it serves many-small-graph workloads and multi-start runs.
+ *
+ * A:        nprob matrices, all CSR or all DENSE, symmetric, n_g >= 1 (LOWRANK and a
+ *           Laplacian term are not supported: E_UNSUPPORTED).
+ * r:        nprob ranks, 1 <= r_g <= min(64, n_g).
+ * lam:      nprob penalties lambda_g (host), or NULL to use p->lambda for every problem.
+ * restarts: S >= 1 starts per problem.
+ * p:        shared parameters (precision F64 or F32; max_outer, target_res and
+ *           check_every apply per instance; gamma and L are ignored).
+ * W0[g]:    device array of S * n_g * r_g values: restart s is the n_g x r_g row-major
+ *           block at offset s * n_g * r_g.  W_out[g], Ht_out[g] have the same layout.
+ * infos:    host array of nprob * S records, instance g * S + s.
+ * traces:   optional host array of nprob * S * max_outer * SNMF_TRACE_FIELDS doubles,
+ *           instance-major, the records of snmf_solve.
+ * The library keeps the A pointers until destroy; all other buffers are the caller's.
+ * Errors as for the single solve; instance breakdowns are reported in infos[].status and
+ * the call returns E_BREAKDOWN if any instance broke down. */
+typedef struct snmf_batch snmf_batch;
+snmf_status snmf_batch_create(int32_t nprob, const snmf_matrix* A, const int32_t* r,
+                              const double* lam, int32_t restarts, const snmf_params* p,
+                              void* stream, snmf_batch** out);
+snmf_status snmf_batch_solve(snmf_batch* b, const void* const* W0, void* const* W_out,
+                             void* const* Ht_out, snmf_info* infos, void* stream,
+                             double* traces);
+snmf_status snmf_batch_destroy(snmf_batch* b);
+snmf_status snmf_solve_batched(int32_t nprob, const snmf_matrix* A, const int32_t* r,
+                               const double* lam, int32_t restarts, const void* const* W0,
+                               const snmf_params* p, void* const* W_out, void* const* Ht_out,
+                               snmf_info* infos, void* stream, double* traces);
+/* The batch's A-pass alone: P and B are device arrays holding every instance's n_g x r_g
+ * block one after another in instance order (g * S + s), B = A_g P for each. */
+snmf_status snmf_batch_apass(snmf_batch* b, const void* P, void* B, void* stream);
+/* Number of instances and the total element count sum_g S n_g r_g of a batch buffer. */
+snmf_status snmf_batch_size(const snmf_batch* b, int32_t* ninst, int64_t* elements);
+
 /* Device clock rate (Hz) of the trace ticks and info.seconds. */
 double snmf_clock_rate_hz(void);
 const char* snmf_last_error(void);

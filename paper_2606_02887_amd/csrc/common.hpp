@@ -38,6 +38,7 @@ struct State {
   double res_last, resww_last, sym_last, pg_last, f_last;
   uint64_t t_hstep;            // device clock when the last H-step update finished
   uint64_t t0;                 // device clock at solve start
+  uint64_t t_conv;             // device ticks from t0 to the H-step that met the target
   int32_t pending;             // an H-step finished; its monitor record is still open
   int32_t snap_pending;        // W-step init's copy of pending
   int32_t outer;               // completed (recorded) outer iterations
@@ -53,6 +54,50 @@ struct State {
 struct KParams {
   double lam, gamma, eta, theta, phi, amin, amax, shrink, target;
   int32_t max_ls, relaxed, project, max_outer;
+};
+
+// Batched solves: many independent instances (problem g, restart s), each an n x r block
+// stored contiguously (instance-major) in shared batch buffers.  Device table entry:
+struct BInst {
+  int64_t off;     // element offset of the instance's n x r arrays
+  int64_t n;
+  int32_t r;
+  int32_t blk0;    // inner kernels: first workgroup of the instance in its class launch
+  int32_t nblk;    //   and its number of workgroups (<= kInnerGrid)
+  int32_t part0;   //   first row of its partial sums
+  int64_t goff;    // element offset of its r x r Gram (FP64 and iterate-type copies)
+  int64_t gpoff;   // element offset of its Gram partials (gnb x r*r)
+  int32_t gblk0;   // Gram: first workgroup, number of workgroups, rows per workgroup
+  int32_t gnb;
+  int64_t grpb;
+  double lam;      // its penalty lambda
+  double normA2;   // ||A||_F^2 of its problem
+  int32_t prob;    // index of its problem
+  int32_t restart;
+};
+
+// One problem of a batched CSR solve: its restarts are the instances inst0 .. inst0+S-1,
+// stored one after another (restart s at element offset off0 + s n r).
+struct BGraph {
+  const int64_t* rowptr;
+  const int32_t* col;
+  const void* val;
+  int64_t n;
+  int64_t off0;
+  int32_t r, S;
+  int32_t blk0, nblk;  // workgroups of the stacked SpMM launch
+  int32_t inst0;
+  int32_t pad;
+};
+
+// Passed by value to the inner kernels; blk_inst == nullptr means a single solve whose
+// pointers, sizes and State come from the kernel arguments.
+struct BMap {
+  const int32_t* blk_inst;  // workgroup of the launch -> instance
+  const BInst* inst;
+  State* states;            // one State per instance
+  double* traces;           // per-instance traces of trace_stride doubles (nullable)
+  int64_t trace_stride;
 };
 
 // Cross-lane data movement with DPP (GFX9 encoding).  Lanes whose source is outside the

@@ -1,0 +1,49 @@
+// Host-side helpers shared by the single-solve and batched-solve orchestration.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <string>
+
+#include "../../include/snmf.h"
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace snmf {
+
+// The thread-local message behind snmf_last_error().
+std::string& err_ref();
+
+inline snmf_status fail(snmf_status s, const std::string& msg) {
+  err_ref() = msg;
+  return s;
+}
+
+#define HIP_TRY(call)                                                                  \
+  do {                                                                                 \
+    hipError_t _e = (call);                                                            \
+    if (_e != hipSuccess)                                                              \
+      return ::snmf::fail(_e == hipErrorOutOfMemory ? SNMF_E_OOM : SNMF_E_DEVICE,      \
+                          std::string(#call) + ": " + hipGetErrorString(_e));          \
+  } while (0)
+
+#define SNMF_TRY(call)                  \
+  do {                                  \
+    snmf_status _s = (call);            \
+    if (_s != SNMF_OK) return _s;       \
+  } while (0)
+
+inline size_t elt_size(int prec) { return prec == SNMF_F64 ? 8 : 4; }
+
+struct DevBuf {
+  void* p = nullptr;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+snmf_status check_params(const snmf_params* p);
+snmf_status check_matrix(const snmf_matrix* A, const char* what);
+KParams kparams_of(const snmf_params& p, bool lap);
+
+}  // namespace snmf

@@ -151,10 +151,10 @@ __device__ __forceinline__ void store_G(T* __restrict__ sG, const T (&v)[TileCfg
 }
 
 template <int K>
-__device__ __forceinline__ void write_parts(double* __restrict__ parts, const double (&v)[K]) {
+__device__ __forceinline__ void write_parts(double* __restrict__ parts, int bid, const double (&v)[K]) {
   if (threadIdx.x == 0)
 #pragma unroll
-    for (int j = 0; j < K; ++j) parts[(size_t)blockIdx.x * kNumPart + j] = v[j];
+    for (int j = 0; j < K; ++j) parts[(size_t)bid * kNumPart + j] = v[j];
 }
 
 // This thread's share (workgroup b = tid; nb <= 256) of K consecutive partial-sum slots
@@ -167,6 +167,46 @@ __device__ __forceinline__ void load_slots(const double* __restrict__ part, int 
     out[j] = (int)threadIdx.x < nb ? part[(size_t)threadIdx.x * kNumPart + first + j] : 0.0;
 }
 
+// ----------------------------------------------------------------------------- instances
+// Where this workgroup works: a single solve takes everything from the kernel arguments;
+// in a batched launch the workgroup looks up its instance (two dependent scalar loads)
+// and offsets the batch buffers, Gram copies, partial sums, State and trace by it.
+struct Loc {
+  int64_t off, n, goff, poff;
+  int bid, nb;
+  State* st;
+  double* trace;
+  double lam;
+};
+__device__ __forceinline__ Loc locate(const BMap& bm, int64_t n, State* st, double* trace,
+                                      double lam) {
+  Loc l;
+  if (bm.blk_inst == nullptr) {
+    l.off = 0;
+    l.n = n;
+    l.goff = 0;
+    l.poff = 0;
+    l.bid = blockIdx.x;
+    l.nb = gridDim.x;
+    l.st = st;
+    l.trace = trace;
+    l.lam = lam;
+  } else {
+    const int i = bm.blk_inst[blockIdx.x];
+    const BInst* d = bm.inst + i;
+    l.off = d->off;
+    l.n = d->n;
+    l.goff = d->goff;
+    l.poff = (int64_t)d->part0 * kNumPart;
+    l.bid = (int)blockIdx.x - d->blk0;
+    l.nb = d->nblk;
+    l.st = bm.states + i;
+    l.trace = bm.traces ? bm.traces + (size_t)i * bm.trace_stride : nullptr;
+    l.lam = d->lam;
+  }
+  return l;
+}
+
 // ----------------------------------------------------------------------------- init
 // C = (sum of the A-pass partials) + lam P;  g = X G + lam X - C [+ gam LX].
 template <typename T, int RP>
@@ -174,8 +214,20 @@ __global__ __launch_bounds__(kThreads) void k_init(
     const T* __restrict__ X, const T* __restrict__ P, const T* __restrict__ Bpart, int ksplit,
     int64_t bstride, T* __restrict__ Cout, T* __restrict__ g, const T* __restrict__ LX,
     const T* __restrict__ GT, int64_t n, int r, int is_hstep, KParams kp, State* __restrict__ st,
-    double* __restrict__ partsA) {
+    double* __restrict__ partsA, BMap bm) {
+  const Loc lc = locate(bm, n, st, nullptr, kp.lam);
+  st = lc.st;
   if (st->done) return;
+  n = lc.n;
+  kp.lam = lc.lam;
+  X += lc.off;
+  P += lc.off;
+  Bpart += lc.off;
+  Cout += lc.off;
+  g += lc.off;
+  if (LX) LX += lc.off;
+  GT += lc.goff;
+  partsA += lc.poff;
   typedef Lay<T, RP> L;
   constexpr int TM = L::TM;
   __shared__ Smem<T, RP> sm;
@@ -183,7 +235,7 @@ __global__ __launch_bounds__(kThreads) void k_init(
   int lr[8], cl[8];
 #pragma unroll
   for (int p = 0; p < 8; ++p) L::rc(p, lr[p], cl[p]);
-  if (!is_hstep && blockIdx.x == 0 && tid == 0) {
+  if (!is_hstep && lc.bid == 0 && tid == 0) {
     // snapshot for the monitor record completed by this W-step's first inner kernel
     st->snap_pending = st->pending;
     st->snap_outer = st->outer;
@@ -195,7 +247,7 @@ __global__ __launch_bounds__(kThreads) void k_init(
   double v[1] = {0.0};
   const int64_t ntiles = (n + TM - 1) / TM;
   bool first = true;
-  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+  for (int64_t t = lc.bid; t < ntiles; t += lc.nb) {
     const int64_t row0 = t * TM;
     T x[8], cv[8], pv[8];
 #pragma unroll
@@ -247,7 +299,7 @@ __global__ __launch_bounds__(kThreads) void k_init(
     }
   }
   block_sum<1>(v, sm.red);
-  write_parts<1>(partsA, v);
+  write_parts<1>(partsA, lc.bid, v);
 }
 
 // ----------------------------------------------------------------------------- entry
@@ -287,8 +339,7 @@ __device__ bool inner_entry(int k, int is_hstep, int r, const KParams& kp, State
                             double (&pe)[6], int stop_prev, double e_prev, double rho,
                             const double* __restrict__ Gcur,
                             const double* __restrict__ Gprev, double* __restrict__ trace,
-                            double* sred, double& alpha_out) {
-  const bool w0 = blockIdx.x == 0 && threadIdx.x == 0;
+                            double* sred, bool w0, double& alpha_out) {
   double e_k, alpha_k;
   if (k == 0) {
     if (!is_hstep) {
@@ -317,17 +368,19 @@ __device__ bool inner_entry(int k, int is_hstep, int r, const KParams& kp, State
         const bool bad = !(res == res) || !(pg == pg);
         const bool fin = conv || bad || o + 1 >= kp.max_outer;
         if (w0) {
-          double* rec = trace + (size_t)o * kTraceFields;
-          rec[0] = res;
-          rec[1] = resw;
-          rec[2] = sym;
-          rec[3] = pg;
-          rec[4] = f;
-          rec[5] = (double)(st->t_hstep - st->t0);
-          rec[6] = (double)st->ls_evals;
-          rec[7] = (double)st->ls_exhausted;
-          rec[8] = st->last_sy > 0.0 ? st->last_ss / st->last_sy : 0.0;
-          rec[9] = (double)st->inner_total;
+          if (trace) {
+            double* rec = trace + (size_t)o * kTraceFields;
+            rec[0] = res;
+            rec[1] = resw;
+            rec[2] = sym;
+            rec[3] = pg;
+            rec[4] = f;
+            rec[5] = (double)(st->t_hstep - st->t0);
+            rec[6] = (double)st->ls_evals;
+            rec[7] = (double)st->ls_exhausted;
+            rec[8] = st->last_sy > 0.0 ? st->last_ss / st->last_sy : 0.0;
+            rec[9] = (double)st->inner_total;
+          }
           st->res_last = res;
           st->resww_last = resw;
           st->sym_last = sym;
@@ -335,7 +388,10 @@ __device__ bool inner_entry(int k, int is_hstep, int r, const KParams& kp, State
           st->f_last = f;
           st->outer = o + 1;
           st->trace_len = o + 1;
-          if (conv && st->converged_at == 0) st->converged_at = o + 1;
+          if (conv && st->converged_at == 0) {
+            st->converged_at = o + 1;
+            st->t_conv = st->t_hstep - st->t0;
+          }
           if (bad) st->status = 9;
           if (fin) st->done = 1;
         }
@@ -397,7 +453,24 @@ __global__ __launch_bounds__(kThreads) void k_step1(
     const T* __restrict__ LdZ, const T* __restrict__ GT, const double* __restrict__ Gcur,
     const double* __restrict__ Gprev, int64_t n, int r, int k, int phase, int is_hstep,
     KParams kp, State* __restrict__ st, const double* __restrict__ partsA,
-    double* __restrict__ partsB, const double* __restrict__ partsC, double* __restrict__ trace) {
+    double* __restrict__ partsB, const double* __restrict__ partsC, double* __restrict__ trace,
+    BMap bm) {
+  const Loc lc = locate(bm, n, st, trace, kp.lam);
+  st = lc.st;
+  trace = lc.trace;
+  n = lc.n;
+  kp.lam = lc.lam;
+  X += lc.off;
+  g += lc.off;
+  Z += lc.off;
+  D += lc.off;
+  if (LdZ) LdZ += lc.off;
+  GT += lc.goff;
+  Gcur += lc.goff;
+  Gprev += lc.goff;
+  partsA += lc.poff;
+  partsB += lc.poff;
+  partsC += lc.poff;
   typedef Lay<T, RP> L;
   constexpr int TM = L::TM;
   __shared__ Smem<T, RP> sm;
@@ -411,7 +484,7 @@ __global__ __launch_bounds__(kThreads) void k_step1(
   const int stop_prev = st->stop[km], stop_k = st->stop[k];
   const double e_prev = st->e[km], alpha_k2 = st->alpha[k], rho = st->rho;
   double pe[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  if (phase != 2) entry_loads(k, is_hstep, partsA, partsC, gridDim.x, pe);
+  if (phase != 2) entry_loads(k, is_hstep, partsA, partsC, lc.nb, pe);
   T gv[TileCfg<RP>::NG];
   if (phase != 1) load_G<T, RP>(GT, r, gv);
   T x[8], gvv[8], z[8], lz[8];
@@ -427,12 +500,12 @@ __global__ __launch_bounds__(kThreads) void k_step1(
       lz[p] = (ok && phase == 2) ? LdZ[o] : T(0);
     }
   };
-  if ((int64_t)blockIdx.x < ntiles) load_tile((int64_t)blockIdx.x * TM);
+  if (lc.bid < ntiles) load_tile((int64_t)lc.bid * TM);
   if (done) return;
   double alpha_d = 0.0;
   if (phase != 2) {
     if (!inner_entry(k, is_hstep, r, kp, st, pe, stop_prev, e_prev, rho, Gcur, Gprev, trace,
-                     sm.red, alpha_d))
+                     sm.red, lc.bid == 0 && threadIdx.x == 0, alpha_d))
       return;
   } else {
     if (stop_k) return;
@@ -442,8 +515,8 @@ __global__ __launch_bounds__(kThreads) void k_step1(
   const T alpha = (T)alpha_d;
   const T lam = (T)kp.lam, gam = (T)kp.gamma;
   if (phase == 1) {
-    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-      if (t != blockIdx.x) load_tile(t * TM);
+    for (int64_t t = lc.bid; t < ntiles; t += lc.nb) {
+      if (t != lc.bid) load_tile(t * TM);
 #pragma unroll
       for (int p = 0; p < 8; ++p) {
         const int64_t row = t * TM + lr[p];
@@ -459,9 +532,9 @@ __global__ __launch_bounds__(kThreads) void k_step1(
   }
   store_G<T, RP>(sm.G, gv);
   double v[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+  for (int64_t t = lc.bid; t < ntiles; t += lc.nb) {
     const int64_t row0 = t * TM;
-    if (t != blockIdx.x) load_tile(row0);
+    if (t != lc.bid) load_tile(row0);
     __syncthreads();
 #pragma unroll
     for (int p = 0; p < 8; ++p) {
@@ -499,7 +572,7 @@ __global__ __launch_bounds__(kThreads) void k_step1(
     for (int p = 0; p < 8; ++p) v[1] += (double)dg[p] * (double)d[p];
   }
   block_sum<4>(v, sm.red);
-  write_parts<4>(partsB, v);
+  write_parts<4>(partsB, lc.bid, v);
 }
 
 // ----------------------------------------------------------------------------- line search
@@ -543,21 +616,36 @@ __global__ __launch_bounds__(kThreads) void k_step2(
     const T* __restrict__ LS, const T* __restrict__ C, const T* __restrict__ P,
     T* __restrict__ LXb, const T* __restrict__ GT, int64_t n, int r, int k, int phase,
     int is_hstep, KParams kp, State* __restrict__ st, const double* __restrict__ partsB,
-    const double* __restrict__ partsD, int nbD, double* __restrict__ partsC) {
+    const double* __restrict__ partsD, int nbD, double* __restrict__ partsC, BMap bm) {
+  const Loc lc = locate(bm, n, st, nullptr, kp.lam);
+  st = lc.st;
+  n = lc.n;
+  kp.lam = lc.lam;
+  X += lc.off;
+  g += lc.off;
+  Z += lc.off;
+  D += lc.off;
+  if (LS) LS += lc.off;
+  if (C) C += lc.off;
+  if (P) P += lc.off;
+  if (LXb) LXb += lc.off;
+  GT += lc.goff;
+  partsB += lc.poff;
+  partsC += lc.poff;
   typedef Lay<T, RP> L;
   constexpr int TM = L::TM;
   __shared__ Smem<T, RP> sm;
   int lr[8], cl[8];
 #pragma unroll
   for (int p = 0; p < 8; ++p) L::rc(p, lr[p], cl[p]);
-  const bool w0 = blockIdx.x == 0 && threadIdx.x == 0;
+  const bool w0 = lc.bid == 0 && threadIdx.x == 0;
   const int64_t ntiles = (n + TM - 1) / TM;
   // loads first: State scalars, partial sums of step 1 (and <D, L D>), G, the first tile
   const int skip = st->done | st->stop[k];
   const double e_k = st->e[k], beta_k2 = st->beta[k];
   double pb[4] = {0.0, 0.0, 0.0, 0.0}, pd[1] = {0.0};
   if (phase != 2) {
-    load_slots<4>(partsB, gridDim.x, 0, pb);
+    load_slots<4>(partsB, lc.nb, 0, pb);
     if (partsD) load_slots<1>(partsD, nbD, 0, pd);
   }
   T gv[TileCfg<RP>::NG];
@@ -581,7 +669,7 @@ __global__ __launch_bounds__(kThreads) void k_step2(
       lx[p] = (ok && lap && LXb) ? LXb[o] : T(0);
     }
   };
-  if ((int64_t)blockIdx.x < ntiles) load_tile((int64_t)blockIdx.x * TM);
+  if (lc.bid < ntiles) load_tile((int64_t)lc.bid * TM);
   if (skip) return;
   double beta;
   if (phase != 2) {
@@ -605,8 +693,8 @@ __global__ __launch_bounds__(kThreads) void k_step2(
   const T step = (T)(kp.phi * beta);
   const T lam = (T)kp.lam, gam = (T)kp.gamma;
   if (phase == 1) {
-    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-      if (t != blockIdx.x) load_tile(t * TM);
+    for (int64_t t = lc.bid; t < ntiles; t += lc.nb) {
+      if (t != lc.bid) load_tile(t * TM);
 #pragma unroll
       for (int p = 0; p < 8; ++p) {
         const int64_t row = t * TM + lr[p];
@@ -623,9 +711,9 @@ __global__ __launch_bounds__(kThreads) void k_step2(
   }
   store_G<T, RP>(sm.G, gv);
   double v[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+  for (int64_t t = lc.bid; t < ntiles; t += lc.nb) {
     const int64_t row0 = t * TM;
-    if (t != blockIdx.x) load_tile(row0);
+    if (t != lc.bid) load_tile(row0);
     T xn[8];
     __syncthreads();
 #pragma unroll
@@ -682,7 +770,7 @@ __global__ __launch_bounds__(kThreads) void k_step2(
     v[1] = v3[1];
     v[2] = v3[2];
   }
-  write_parts<9>(partsC, v);
+  write_parts<9>(partsC, lc.bid, v);
   if (is_hstep && w0) {
     st->pending = 1;
     st->t_hstep = wall_clock64();
@@ -715,49 +803,51 @@ int inner_grid(int64_t n, int r) {
 template <typename T>
 void launch_init(const T* X, const T* P, const T* Bpart, int ksplit, int64_t bstride, T* C, T* g,
                  const T* LX, const T* GT, int64_t n, int r, int is_hstep, const KParams& kp,
-                 State* st, double* partsA, hipStream_t s) {
-  const int grid = inner_grid(n, r);
+                 State* st, double* partsA, hipStream_t s, const BMap& bm, int grid) {
+  if (grid <= 0) grid = inner_grid(n, r);
   SNMF_DISPATCH_RP(rank_pad(r),
                    hipLaunchKernelGGL((k_init<T, RP>), dim3(grid), dim3(kThreads), 0, s, X, P,
                                       Bpart, ksplit, bstride, C, g, LX, GT, n, r, is_hstep, kp, st,
-                                      partsA))
+                                      partsA, bm))
 }
 
 template <typename T>
 void launch_step1(const T* X, const T* g, T* Z, T* D, const T* LdZ, const T* GT,
                   const double* Gcur, const double* Gprev, int64_t n, int r, int k, int phase,
                   int is_hstep, const KParams& kp, State* st, const double* partsA,
-                  double* partsB, const double* partsC, double* trace, hipStream_t s) {
-  const int grid = inner_grid(n, r);
+                  double* partsB, const double* partsC, double* trace, hipStream_t s,
+                  const BMap& bm, int grid) {
+  if (grid <= 0) grid = inner_grid(n, r);
   SNMF_DISPATCH_RP(rank_pad(r),
                    hipLaunchKernelGGL((k_step1<T, RP>), dim3(grid), dim3(kThreads), 0, s, X, g,
                                       Z, D, LdZ, GT, Gcur, Gprev, n, r, k, phase, is_hstep, kp, st,
-                                      partsA, partsB, partsC, trace))
+                                      partsA, partsB, partsC, trace, bm))
 }
 
 template <typename T>
 void launch_step2(T* X, T* g, T* Z, T* D, const T* LS, const T* C, const T* P, T* LXb,
                   const T* GT, int64_t n, int r, int k, int phase, int is_hstep,
                   const KParams& kp, State* st, const double* partsB, const double* partsD,
-                  int nbD, double* partsC, hipStream_t s) {
-  const int grid = inner_grid(n, r);
+                  int nbD, double* partsC, hipStream_t s, const BMap& bm, int grid) {
+  if (grid <= 0) grid = inner_grid(n, r);
   SNMF_DISPATCH_RP(rank_pad(r),
                    hipLaunchKernelGGL((k_step2<T, RP>), dim3(grid), dim3(kThreads), 0, s, X, g,
                                       Z, D, LS, C, P, LXb, GT, n, r, k, phase, is_hstep, kp, st,
-                                      partsB, partsD, nbD, partsC))
+                                      partsB, partsD, nbD, partsC, bm))
 }
 
 #define SNMF_INST(T)                                                                            \
   template void launch_init<T>(const T*, const T*, const T*, int, int64_t, T*, T*, const T*,   \
                                const T*, int64_t, int, int, const KParams&, State*, double*,   \
-                               hipStream_t);                                                    \
+                               hipStream_t, const BMap&, int);                                  \
   template void launch_step1<T>(const T*, const T*, T*, T*, const T*, const T*, const double*, \
                                 const double*, int64_t, int, int, int, int, const KParams&,     \
                                 State*, const double*, double*, const double*, double*,         \
-                                hipStream_t);                                                   \
+                                hipStream_t, const BMap&, int);                                 \
   template void launch_step2<T>(T*, T*, T*, T*, const T*, const T*, const T*, T*, const T*,    \
                                 int64_t, int, int, int, int, const KParams&, State*,            \
-                                const double*, const double*, int, double*, hipStream_t);
+                                const double*, const double*, int, double*, hipStream_t,        \
+                                const BMap&, int);
 SNMF_INST(float)
 SNMF_INST(double)
 

@@ -11,22 +11,16 @@ namespace snmf {
 // 4 x 4 block of G at rows 4(t/16), columns 4(t%16)); a second kernel adds the slabs in
 // block order (deterministic) and writes G in FP64 and in the iterate type.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_gram(const T* __restrict__ P, int64_t n, int r,
-                                                   int64_t rows_per_block,
-                                                   double* __restrict__ part,
-                                                   const State* __restrict__ st) {
-  if (st->done) return;
+__device__ __forceinline__ void gram_slab(const T* __restrict__ P, int r, int64_t rb, int64_t re,
+                                          double* __restrict__ out) {
   constexpr int TR = 32, LDP = kMaxRank + 2;
   __shared__ __attribute__((aligned(16))) double sP[TR * LDP];
-  const int rr = r * r;
   const int a0 = 4 * (threadIdx.x >> 4), b0 = 4 * (threadIdx.x & 15);
   double acc[4][4];
 #pragma unroll
   for (int u = 0; u < 4; ++u)
 #pragma unroll
     for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
-  const int64_t rb = (int64_t)blockIdx.x * rows_per_block;
-  const int64_t re = rb + rows_per_block < n ? rb + rows_per_block : n;
   for (int64_t t0 = rb; t0 < re; t0 += TR) {
     __syncthreads();
     for (int e = threadIdx.x; e < TR * kMaxRank; e += kThreads) {
@@ -54,8 +48,55 @@ __global__ __launch_bounds__(kThreads) void k_gram(const T* __restrict__ P, int6
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int a = a0 + u, b = b0 + v;
-      if (a < r && b < r) part[(size_t)blockIdx.x * rr + a * r + b] = acc[u][v];
+      if (a < r && b < r) out[a * r + b] = acc[u][v];
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_gram(const T* __restrict__ P, int64_t n, int r,
+                                                   int64_t rows_per_block,
+                                                   double* __restrict__ part,
+                                                   const State* __restrict__ st) {
+  if (st->done) return;
+  const int64_t rb = (int64_t)blockIdx.x * rows_per_block;
+  const int64_t re = rb + rows_per_block < n ? rb + rows_per_block : n;
+  gram_slab<T>(P, r, rb, re, part + (size_t)blockIdx.x * r * r);
+}
+
+// Batched: workgroup -> (instance, slab) through gblk_inst; the same slabs as a single
+// solve of that instance, so its G is bitwise the same.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_bgram(const T* __restrict__ P,
+                                                    const int32_t* __restrict__ gblk_inst,
+                                                    const BInst* __restrict__ inst,
+                                                    const State* __restrict__ states,
+                                                    double* __restrict__ gpart) {
+  const int i = gblk_inst[blockIdx.x];
+  const BInst* d = inst + i;
+  if (states[i].done) return;
+  const int j = (int)blockIdx.x - d->gblk0;
+  const int64_t rb = (int64_t)j * d->grpb;
+  const int64_t re = rb + d->grpb < d->n ? rb + d->grpb : d->n;
+  gram_slab<T>(P + d->off, d->r, rb, re, gpart + d->gpoff + (size_t)j * d->r * d->r);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_bgram_reduce(const BInst* __restrict__ inst,
+                                                           const State* __restrict__ states,
+                                                           const double* __restrict__ gpart,
+                                                           double* __restrict__ G64,
+                                                           T* __restrict__ GT) {
+  const int i = blockIdx.x;
+  const BInst* d = inst + i;
+  if (states[i].done) return;
+  const int rr = d->r * d->r;
+  const double* part = gpart + d->gpoff;
+  for (int e = threadIdx.x; e < rr; e += kThreads) {
+    double s = 0.0;
+    for (int b = 0; b < d->gnb; ++b) s += part[(size_t)b * rr + e];
+    G64[d->goff + e] = s;
+    GT[d->goff + e] = (T)s;
+  }
 }
 
 template <typename T>
@@ -93,9 +134,8 @@ __global__ __launch_bounds__(kThreads) void k_gram_reduce(const double* __restri
 // spectra the result agrees with a dense symmetric eigensolver to a few ulps.
 // G >= 0 elementwise (a Gram of a nonnegative block), so its Perron vector is
 // nonnegative and the all-ones start has a nonzero component along it.
-__global__ __launch_bounds__(kThreads) void k_rho(const double* __restrict__ G, int r,
-                                                  State* __restrict__ st) {
-  if (st->done) return;
+__device__ __forceinline__ void rho_body(const double* __restrict__ G, int r,
+                                         State* __restrict__ st) {
   __shared__ __attribute__((aligned(16))) double sq[kMaxRank];
   __shared__ double sp[4][kMaxRank];
   __shared__ double sa[kMaxRank], sb[kMaxRank];
@@ -184,6 +224,21 @@ __global__ __launch_bounds__(kThreads) void k_rho(const double* __restrict__ G, 
       st->done = 1;
     }
   }
+}
+
+__global__ __launch_bounds__(kThreads) void k_rho(const double* __restrict__ G, int r,
+                                                  State* __restrict__ st) {
+  if (st->done) return;
+  rho_body(G, r, st);
+}
+
+// Batched: one workgroup per instance.
+__global__ __launch_bounds__(kThreads) void k_brho(const BInst* __restrict__ inst,
+                                                   State* __restrict__ states,
+                                                   const double* __restrict__ G64) {
+  const int i = blockIdx.x;
+  if (states[i].done) return;
+  rho_body(G64 + inst[i].goff, inst[i].r, states + i);
 }
 
 // ----------------------------------------------------------------------------- ||A||^2
@@ -277,6 +332,25 @@ template void launch_gram<double>(const double*, int64_t, int, double*, int, dou
 
 void launch_rho(const double* G, int r, State* st, hipStream_t s) {
   hipLaunchKernelGGL(k_rho, dim3(1), dim3(kThreads), 0, s, G, r, st);
+}
+
+template <typename T>
+void launch_bgram(const T* P, const int32_t* gblk_inst, int gblocks, const BInst* inst, int ninst,
+                  int max_r, const State* states, double* gpart, double* G64, T* GT,
+                  hipStream_t s) {
+  hipLaunchKernelGGL(k_bgram<T>, dim3(gblocks), dim3(kThreads), 0, s, P, gblk_inst, inst, states,
+                     gpart);
+  (void)max_r;
+  hipLaunchKernelGGL(k_bgram_reduce<T>, dim3(ninst), dim3(kThreads), 0, s, inst, states, gpart,
+                     G64, GT);
+}
+template void launch_bgram<float>(const float*, const int32_t*, int, const BInst*, int, int,
+                                  const State*, double*, double*, float*, hipStream_t);
+template void launch_bgram<double>(const double*, const int32_t*, int, const BInst*, int, int,
+                                   const State*, double*, double*, double*, hipStream_t);
+
+void launch_brho(const BInst* inst, int ninst, State* states, const double* G64, hipStream_t s) {
+  hipLaunchKernelGGL(k_brho, dim3(ninst), dim3(kThreads), 0, s, inst, states, G64);
 }
 
 template <typename T>

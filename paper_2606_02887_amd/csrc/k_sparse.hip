@@ -52,6 +52,62 @@ __global__ __launch_bounds__(256) void k_spmm(const int64_t* __restrict__ rowptr
   if (threadIdx.x == 0) part[(size_t)blockIdx.x * kNumPart] = v[0];
 }
 
+// ----------------------------------------------------------------------------- batched
+// Stacked A-pass of a batched solve: B_s = A P_s for all S restarts of a problem in one
+// sweep over its CSR (the restarts form one n x (S r) operand).  One wavefront per row;
+// lane c of a chunk of cw columns (cw = 64, or the smallest power of two >= S r) serves
+// stacked column c0 + c = s r + j, and the 64 / cw lane groups split the row's nonzeros.
+template <typename T>
+__global__ __launch_bounds__(256) void k_bspmm(const BGraph* __restrict__ graphs,
+                                               const int32_t* __restrict__ sblk_graph,
+                                               const State* __restrict__ states,
+                                               const T* __restrict__ P, T* __restrict__ B) {
+  const BGraph* G = graphs + sblk_graph[blockIdx.x];
+  const int r = G->r, S = G->S;
+  bool all_done = true;
+  for (int s = 0; s < S; ++s) all_done = all_done && states[G->inst0 + s].done;
+  if (all_done) return;
+  const int64_t n = G->n;
+  const int width = r * S;
+  int cw = 64;
+  while (cw > 1 && cw / 2 >= width) cw >>= 1;
+  const int ns = kWave / cw;
+  const int lane = threadIdx.x & 63;
+  const int c = lane % cw, slot = lane / cw;
+  const int64_t wave = ((int64_t)blockIdx.x - G->blk0) * (kThreads / kWave) + threadIdx.x / kWave;
+  const int64_t nw = (int64_t)G->nblk * (kThreads / kWave);
+  const int64_t* __restrict__ rowptr = G->rowptr;
+  const int32_t* __restrict__ col = G->col;
+  const T* __restrict__ val = (const T*)G->val;
+  const int64_t nr = n * r;
+  const T* __restrict__ Pg = P + G->off0;
+  T* __restrict__ Bg = B + G->off0;
+  for (int64_t row = wave; row < n; row += nw) {
+    const int64_t b = rowptr[row], e = rowptr[row + 1];
+    for (int c0 = 0; c0 < width; c0 += cw) {
+      const int cc = c0 + c;
+      const int s = cc / r, j = cc - (cc / r) * r;
+      T acc = T(0);
+      if (cc < width) {
+        const T* __restrict__ Ps = Pg + s * nr + j;
+        for (int64_t z = b + slot; z < e; z += ns) acc += val[z] * Ps[(int64_t)col[z] * r];
+      }
+      for (int o = cw; o < kWave; o <<= 1) acc += __shfl_xor(acc, o, kWave);
+      if (slot == 0 && cc < width) Bg[s * nr + row * r + j] = acc;
+    }
+  }
+}
+
+template <typename T>
+void launch_bspmm(const BGraph* graphs, const int32_t* sblk_graph, int sblocks,
+                  const State* states, const T* P, T* B, hipStream_t s) {
+  hipLaunchKernelGGL(k_bspmm<T>, dim3(sblocks), dim3(256), 0, s, graphs, sblk_graph, states, P, B);
+}
+template void launch_bspmm<float>(const BGraph*, const int32_t*, int, const State*, const float*,
+                                  float*, hipStream_t);
+template void launch_bspmm<double>(const BGraph*, const int32_t*, int, const State*,
+                                   const double*, double*, hipStream_t);
+
 // ----------------------------------------------------------------------------- LAI
 // Partial T_b = U_b^T P_b over a slab of rows, FP64.  ell <= 128, r <= 64.
 template <typename T>

@@ -148,6 +148,35 @@ void launch_reset_state(State* st, double normA2, hipStream_t s) {
   hipLaunchKernelGGL(k_reset_state, dim3(1), dim3(64), 0, s, st, normA2);
 }
 
+// Batched solve start: one State per instance.
+__global__ void k_breset(State* states, const BInst* inst, int ninst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ninst) {
+    State z = {};
+    z.normA2 = inst[i].normA2;
+    z.t0 = wall_clock64();
+    states[i] = z;
+  }
+}
+void launch_breset(State* states, const BInst* inst, int ninst, hipStream_t s) {
+  hipLaunchKernelGGL(k_breset, dim3((ninst + 63) / 64), dim3(64), 0, s, states, inst, ninst);
+}
+
+// flag = 1 when every instance of a batched solve is done.
+__global__ __launch_bounds__(256) void k_all_done(const State* states, int ninst, int32_t* flag) {
+  __shared__ int s_any;
+  if (threadIdx.x == 0) s_any = 0;
+  __syncthreads();
+  int open = 0;
+  for (int i = threadIdx.x; i < ninst; i += blockDim.x) open |= states[i].done == 0;
+  if (open) s_any = 1;
+  __syncthreads();
+  if (threadIdx.x == 0) flag[0] = s_any ? 0 : 1;
+}
+void launch_all_done(const State* states, int ninst, int32_t* flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_all_done, dim3(1), dim3(256), 0, s, states, ninst, flag);
+}
+
 // Flat BF16 split of count floats.
 __device__ __forceinline__ uint16_t bf16_rne_v(float f) {
   uint32_t u = __float_as_uint(f);

@@ -26,6 +26,11 @@ void launch_gram(const T* P, int64_t n, int r, double* part, int nblk, double* G
                  const State* st, hipStream_t s);
 void launch_rho(const double* G, int r, State* st, hipStream_t s);
 template <typename T>
+void launch_bgram(const T* P, const int32_t* gblk_inst, int gblocks, const BInst* inst, int ninst,
+                  int max_r, const State* states, double* gpart, double* G64, T* GT,
+                  hipStream_t s);
+void launch_brho(const BInst* inst, int ninst, State* states, const double* G64, hipStream_t s);
+template <typename T>
 void launch_norm2(const T* x, int64_t N, double* part, double* out, unsigned* counter,
                   hipStream_t s);
 void launch_split_rows(const float* A, int64_t n, int64_t lda, int64_t ldb, uint16_t* hi,
@@ -53,23 +58,29 @@ void launch_spmm(const int64_t* rowptr, const int32_t* col, const T* val, const 
                  const int32_t* gate2, hipStream_t s);
 int spmm_dot_grid(int64_t n);
 template <typename T>
+void launch_bspmm(const BGraph* graphs, const int32_t* sblk_graph, int sblocks,
+                  const State* states, const T* P, T* B, hipStream_t s);
+void launch_breset(State* states, const BInst* inst, int ninst, hipStream_t s);
+void launch_all_done(const State* states, int ninst, int32_t* flag, hipStream_t s);
+template <typename T>
 void launch_lai(const T* U, int ell, const double* lam, const T* P, int64_t n, int r,
                 double* part, T* TT, T* B, const int32_t* gate, hipStream_t s);
 
 template <typename T>
 void launch_init(const T* X, const T* P, const T* Bpart, int ksplit, int64_t bstride, T* C, T* g,
                  const T* LX, const T* GT, int64_t n, int r, int is_hstep, const KParams& kp,
-                 State* st, double* partsA, hipStream_t s);
+                 State* st, double* partsA, hipStream_t s, const BMap& bm = BMap{}, int grid = 0);
 template <typename T>
 void launch_step1(const T* X, const T* g, T* Z, T* D, const T* LdZ, const T* GT,
                   const double* Gcur, const double* Gprev, int64_t n, int r, int k, int phase,
                   int is_hstep, const KParams& kp, State* st, const double* partsA,
-                  double* partsB, const double* partsC, double* trace, hipStream_t s);
+                  double* partsB, const double* partsC, double* trace, hipStream_t s,
+                  const BMap& bm = BMap{}, int grid = 0);
 template <typename T>
 void launch_step2(T* X, T* g, T* Z, T* D, const T* LS, const T* C, const T* P, T* LXb,
                   const T* GT, int64_t n, int r, int k, int phase, int is_hstep,
                   const KParams& kp, State* st, const double* partsB, const double* partsD,
-                  int nbD, double* partsC, hipStream_t s);
+                  int nbD, double* partsC, hipStream_t s, const BMap& bm = BMap{}, int grid = 0);
 
 template <typename T>
 void launch_stats2d(const T* x, int64_t rows, int64_t cols, int64_t ld, double* part, double* out,

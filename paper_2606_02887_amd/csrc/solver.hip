@@ -20,43 +20,17 @@
 
 #include "../../include/snmf.h"
 #include "common.hpp"
+#include "host.hpp"
 #include "kernels.hpp"
 
 using namespace snmf;
 
-namespace {
-
-thread_local std::string g_err;
-
-snmf_status fail(snmf_status s, const std::string& msg) {
-  g_err = msg;
-  return s;
+namespace snmf {
+std::string& err_ref() {
+  thread_local std::string e;
+  return e;
 }
-
-#define HIP_TRY(call)                                                                  \
-  do {                                                                                 \
-    hipError_t _e = (call);                                                            \
-    if (_e != hipSuccess)                                                              \
-      return fail(_e == hipErrorOutOfMemory ? SNMF_E_OOM : SNMF_E_DEVICE,              \
-                  std::string(#call) + ": " + hipGetErrorString(_e));                  \
-  } while (0)
-
-#define SNMF_TRY(call)                  \
-  do {                                  \
-    snmf_status _s = (call);            \
-    if (_s != SNMF_OK) return _s;       \
-  } while (0)
-
-size_t elt_size(int prec) { return prec == SNMF_F64 ? 8 : 4; }
-
-struct DevBuf {
-  void* p = nullptr;
-  ~DevBuf() {
-    if (p) (void)hipFree(p);
-  }
-};
-
-}  // namespace
+}  // namespace snmf
 
 struct snmf_plan {
   snmf_matrix A{};
@@ -103,7 +77,7 @@ struct snmf_plan {
   }
 };
 
-namespace {
+namespace snmf {
 
 snmf_status check_params(const snmf_params* p) {
   if (!p) return fail(SNMF_E_ARG, "params is NULL");
@@ -153,6 +127,28 @@ snmf_status check_matrix(const snmf_matrix* A, const char* what) {
   }
   return SNMF_OK;
 }
+
+KParams kparams_of(const snmf_params& p, bool lap) {
+  KParams k{};
+  k.lam = p.lambda;
+  k.gamma = lap ? p.gamma : 0.0;
+  k.eta = p.eta;
+  k.theta = p.theta;
+  k.phi = p.phi;
+  k.amin = p.alpha_min;
+  k.amax = p.alpha_max;
+  k.shrink = p.beta_shrink;
+  k.target = p.target_res;
+  k.max_ls = p.max_ls;
+  k.relaxed = p.accept_at_relaxed;
+  k.project = p.project_update;
+  k.max_outer = p.max_outer;
+  return k;
+}
+
+}  // namespace snmf
+
+namespace {
 
 template <typename T>
 snmf_status stats(snmf_plan* pl, const T* x, int64_t rows, int64_t cols, int64_t ld, double* out3) {
@@ -353,21 +349,7 @@ snmf_status finalize_any(snmf_plan* pl, hipStream_t s) {
 }
 
 snmf_status build_kparams(snmf_plan* pl) {
-  KParams& k = pl->kp;
-  const snmf_params& p = pl->p;
-  k.lam = p.lambda;
-  k.gamma = pl->lap ? p.gamma : 0.0;
-  k.eta = p.eta;
-  k.theta = p.theta;
-  k.phi = p.phi;
-  k.amin = p.alpha_min;
-  k.amax = p.alpha_max;
-  k.shrink = p.beta_shrink;
-  k.target = p.target_res;
-  k.max_ls = p.max_ls;
-  k.relaxed = p.accept_at_relaxed;
-  k.project = p.project_update;
-  k.max_outer = p.max_outer;
+  pl->kp = kparams_of(pl->p, pl->lap);
   return SNMF_OK;
 }
 
@@ -648,9 +630,9 @@ snmf_status snmf_solve(const snmf_matrix* A, int32_t r, const void* W0, const sn
   snmf_plan* pl = nullptr;
   SNMF_TRY(plan_create(A, r, p, (hipStream_t)stream, &pl));
   snmf_status s = plan_solve(pl, W0, W_out, Ht_out, info, (hipStream_t)stream, trace);
-  std::string keep = g_err;
+  std::string keep = snmf::err_ref();
   snmf_plan_destroy(pl);
-  g_err = keep;
+  snmf::err_ref() = keep;
   return s;
 }
 
@@ -846,7 +828,7 @@ double snmf_clock_rate_hz(void) {
   return (double)khz * 1e3;
 }
 
-const char* snmf_last_error(void) { return g_err.c_str(); }
+const char* snmf_last_error(void) { return snmf::err_ref().c_str(); }
 
 int32_t snmf_abi_version(void) { return SNMF_ABI_VERSION; }
 

@@ -60,7 +60,9 @@ class Info(ctypes.Structure):
 
 EXPORTS = ("snmf_params_default", "snmf_solve", "snmf_plan_create", "snmf_plan_solve",
            "snmf_plan_destroy", "snmf_plan_half_step", "snmf_plan_apass", "snmf_plan_gram",
-           "snmf_plan_time_apass", "snmf_rho", "snmf_spmm", "snmf_split_bf16", "snmf_clock_rate_hz", "snmf_last_error",
+           "snmf_plan_time_apass", "snmf_rho", "snmf_spmm", "snmf_split_bf16",
+           "snmf_batch_create", "snmf_batch_solve", "snmf_batch_destroy", "snmf_solve_batched",
+           "snmf_batch_apass", "snmf_batch_size", "snmf_clock_rate_hz", "snmf_last_error",
            "snmf_abi_version")
 
 
@@ -83,6 +85,16 @@ def load_library(path: str = LIB_PATH):
         "snmf_rho": ([vp, c_int32, POINTER(c_double), vp], c_int32),
         "snmf_spmm": ([POINTER(Matrix), c_int32, vp, c_int32, vp, vp], c_int32),
         "snmf_split_bf16": ([vp, c_int64, vp, vp, vp], c_int32),
+        "snmf_batch_create": ([c_int32, POINTER(Matrix), POINTER(c_int32), POINTER(c_double),
+                               c_int32, POINTER(Params), vp, POINTER(vp)], c_int32),
+        "snmf_batch_solve": ([vp, POINTER(vp), POINTER(vp), POINTER(vp), POINTER(Info), vp,
+                              POINTER(c_double)], c_int32),
+        "snmf_batch_destroy": ([vp], c_int32),
+        "snmf_solve_batched": ([c_int32, POINTER(Matrix), POINTER(c_int32), POINTER(c_double),
+                                c_int32, POINTER(vp), POINTER(Params), POINTER(vp), POINTER(vp),
+                                POINTER(Info), vp, POINTER(c_double)], c_int32),
+        "snmf_batch_apass": ([vp, vp, vp, vp], c_int32),
+        "snmf_batch_size": ([vp, POINTER(c_int32), POINTER(c_int64)], c_int32),
         "snmf_clock_rate_hz": ([], c_double),
         "snmf_last_error": ([], ctypes.c_char_p),
         "snmf_abi_version": ([], c_int32),
@@ -228,6 +240,68 @@ class Plan:
     def close(self):
         if getattr(self, "_h", None):
             _lib.snmf_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+class Batch:
+    """Batched solves (snmf_batch_*): problems As[g] with ranks r[g], each from `restarts`
+    starts.  Starts and results are per-problem tensors of shape (restarts, n_g, r_g)."""
+
+    def __init__(self, As, r, prm: Params, restarts: int = 1, lam=None):
+        self._As = list(As)
+        self.nprob = len(self._As)
+        self.r = [int(x) for x in r]
+        self.n = [int(a.n) for a in self._As]
+        self.S = int(restarts)
+        self.max_outer = prm.max_outer
+        self._prm = prm
+        self._descs = (Matrix * self.nprob)(*[a.desc for a in self._As])
+        self._r = (c_int32 * self.nprob)(*self.r)
+        self._lam = None if lam is None else (c_double * self.nprob)(*[float(x) for x in lam])
+        h = ctypes.c_void_p()
+        _check(_lib.snmf_batch_create(self.nprob, self._descs, self._r, self._lam, self.S,
+                                      ctypes.byref(prm), _stream(), ctypes.byref(h)))
+        self._h = h
+        ni, ne = c_int32(), c_int64()
+        _check(_lib.snmf_batch_size(self._h, ctypes.byref(ni), ctypes.byref(ne)))
+        self.ninst, self.elements = ni.value, ne.value
+
+    def solve(self, W0s, trace: bool = False):
+        import torch
+        Ws = [torch.empty_like(w) for w in W0s]
+        Hs = [torch.empty_like(w) for w in W0s]
+        vpa = ctypes.c_void_p * self.nprob
+        infos = (Info * self.ninst)()
+        tr = (c_double * (self.ninst * self.max_outer * TRACE_FIELDS))() if trace else None
+        _check(_lib.snmf_batch_solve(self._h, vpa(*[w.data_ptr() for w in W0s]),
+                                     vpa(*[w.data_ptr() for w in Ws]),
+                                     vpa(*[w.data_ptr() for w in Hs]), infos, _stream(), tr))
+        out = [i.as_dict() for i in infos]
+        traces = None
+        if trace:
+            traces = np.frombuffer(tr, dtype=np.float64).reshape(self.ninst, self.max_outer,
+                                                                 TRACE_FIELDS).copy()
+        return Ws, Hs, out, traces
+
+    def apass(self, P, B):
+        _check(_lib.snmf_batch_apass(self._h, _ptr(P), _ptr(B), _stream()))
+        return B
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.snmf_batch_destroy(self._h)
             self._h = None
 
     def __del__(self):

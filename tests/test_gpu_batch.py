@@ -1,0 +1,202 @@
+"""Parity of the batching form (snmf_batch_*) on the GPU.
+
+Every instance (problem g, restart s) of a batched solve must follow the oracle's single
+solve of problem g from start s; instances must not see each other (identical starts give
+bitwise identical results, equal to the single-solve path); the stacked CSR A-pass must
+equal A_g P_s for every instance; per-instance stopping must match the instance's own
+trajectory.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2606_02887_amd import gen
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+DT = {"f64": torch.float64, "f32": torch.float32}
+
+
+@pytest.fixture(scope="module")
+def S():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2606_02887_amd import snmf
+    return snmf
+
+
+def nrel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    d = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (d if d > 0 else 1.0)
+
+
+def _graphs(seed, shapes, restarts):
+    """Small SBM graphs (n, r) with `restarts` random starts each, float64."""
+    out = []
+    for g, (n, r) in enumerate(shapes):
+        rng = np.random.default_rng(seed + g)
+        adj, _ = gen.sbm_adjacency(n, max(2, r), 0.25, 0.02, rng)
+        a = gen.normalized_adjacency(adj)
+        w0 = np.stack([gen.start_factor(rng, n, r, gen.mean_of_sparse(a))
+                       for _ in range(restarts)])
+        out.append((a, r, w0))
+    return out
+
+
+# ragged shapes: ranks of three tile classes (4, 8, 32 padded), n not a tile multiple
+SHAPES = [(157, 3), (333, 8), (410, 20), (75, 8)]
+
+
+def _batch_inputs(S, graphs, dt):
+    As = [S.csr_from_scipy(a, dt) for a, _, _ in graphs]
+    a_in = [sp_round(a, dt) for a, _, _ in graphs]
+    W0s = [torch.from_numpy(w).to(DEV, dt).contiguous() for _, _, w in graphs]
+    w_in = [w.double().cpu().numpy() for w in W0s]
+    return As, a_in, W0s, w_in
+
+
+def sp_round(a, dt):
+    """The matrix as the device holds it (values rounded to dt), in float64."""
+    b = a.copy().astype(np.float64)
+    b.data = torch.from_numpy(a.data).to(dt).double().numpy()
+    return b
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_batch_instances_follow_the_oracle(S, prec):
+    """Config-0-like budget (20 outer iterations, before rounding differences grow): every
+    instance's residual and PG norm match the oracle's solve of its problem and start."""
+    dt = DT[prec]
+    graphs = _graphs(500, SHAPES, restarts=2)
+    As, a_in, W0s, w_in = _batch_inputs(S, graphs, dt)
+    lams = [O.default_lambda(a) for a in a_in]
+    prm = S.params(prec=S.F64 if prec == "f64" else S.F32, max_outer=20)
+    with S.Batch(As, [r for _, r, _ in graphs], prm, restarts=2, lam=lams) as b:
+        Ws, Hs, infos, _ = b.solve(W0s)
+    tol = 1e-9 if prec == "f64" else 1e-3
+    for g, (a, r, _) in enumerate(graphs):
+        for s in range(2):
+            info = infos[g * 2 + s]
+            _, _, hist = O.snmpbb(a_in[g], w_in[g][s], O.Params(lam=lams[g]), 20)
+            ref = hist[-1]
+            assert info["status"] == 0 and info["outer"] == 20
+            assert abs(info["res_WH"] - ref["res_WH"]) <= tol * ref["res_WH"], (g, s)
+            assert abs(info["pg_norm"] - ref["pg"]) <= tol * ref["pg"], (g, s)
+            W = Ws[g][s].double().cpu().numpy()
+            Ht = Hs[g][s].double().cpu().numpy()
+            assert (W >= 0).all() and (Ht >= 0).all()
+            direct = O.residual_WH(a_in[g], W, Ht)
+            assert abs(info["res_WH"] - direct) <= (1e-10 if prec == "f64" else 1e-4) * direct
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_batch_equal_starts_are_bitwise_equal_and_match_single_solve(S, prec):
+    """Instances are isolated: S copies of one start give bitwise identical factors, and
+    (dense A: the same kernels as the single path) bitwise the single solve's factors."""
+    dt = DT[prec]
+    prob = gen.planted_dense(240, 6, 77)
+    At = torch.from_numpy(prob["A"]).to(DEV, dt)
+    W0 = torch.from_numpy(prob["W0"]).to(DEV, dt)
+    lam = O.default_lambda(prob["A"])
+    p = S.F64 if prec == "f64" else S.F32
+    W1, H1, i1 = S.solve(S.dense(At), W0, S.params(lam=lam, prec=p, max_outer=30))
+    W0s = [W0.unsqueeze(0).repeat(3, 1, 1).contiguous()]
+    with S.Batch([S.dense(At)], [6], S.params(lam=lam, prec=p, max_outer=30), restarts=3) as b:
+        Ws, Hs, infos, _ = b.solve(W0s)
+    for s in range(3):
+        assert torch.equal(Ws[0][s], W1) and torch.equal(Hs[0][s], H1)
+        assert infos[s]["res_WH"] == i1["res_WH"] and infos[s]["outer"] == i1["outer"]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_batch_stacked_apass(S, prec):
+    dt = DT[prec]
+    graphs = _graphs(900, SHAPES + [(64, 64)], restarts=3)
+    As, a_in, _, _ = _batch_inputs(S, graphs, dt)
+    prm = S.params(prec=S.F64 if prec == "f64" else S.F32, max_outer=1)
+    with S.Batch(As, [r for _, r, _ in graphs], prm, restarts=3) as b:
+        rng = np.random.default_rng(3)
+        P = torch.from_numpy(rng.random(b.elements)).to(DEV, dt)
+        B = torch.empty_like(P)
+        b.apass(P, B)
+        Pn, Bn = P.double().cpu().numpy(), B.double().cpu().numpy()
+    off = 0
+    tol = 1e-12 if prec == "f64" else 1e-5
+    for g, (a, r, _) in enumerate(graphs):
+        n = a.shape[0]
+        for s in range(3):
+            Pi = Pn[off: off + n * r].reshape(n, r)
+            Bi = Bn[off: off + n * r].reshape(n, r)
+            assert nrel(Bi, a_in[g] @ Pi) <= tol, (g, s)
+            off += n * r
+    assert off == Pn.size
+
+
+def test_batch_per_instance_target_stop(S):
+    """A residual target stops each instance at its own first monitored hit; the others
+    keep iterating, and their trajectories are unchanged by the stop of the first."""
+    graphs = _graphs(1300, [(200, 4), (260, 6)], restarts=2)
+    As, a_in, W0s, _ = _batch_inputs(S, graphs, torch.float64)
+    lams = [O.default_lambda(a) for a in a_in]
+    rs = [r for _, r, _ in graphs]
+    with S.Batch(As, rs, S.params(prec=S.F64, max_outer=30), restarts=2, lam=lams) as b:
+        _, _, base, tr = b.solve(W0s, trace=True)
+    tau = tr[0, 9, 0]          # instance 0's residual after 10 outer iterations
+    with S.Batch(As, rs, S.params(prec=S.F64, max_outer=30, target_res=tau, check_every=4),
+                 restarts=2, lam=lams) as b:
+        _, _, infos, tr2 = b.solve(W0s, trace=True)
+    for i in range(4):
+        hits = np.nonzero(tr[i, :, 0] <= tau)[0]
+        if hits.size:
+            assert infos[i]["converged_at"] == hits[0] + 1
+            assert infos[i]["outer"] == hits[0] + 1
+            assert infos[i]["seconds_to_target"] > 0
+        else:
+            assert infos[i]["converged_at"] == 0 and infos[i]["outer"] == 30
+        k = infos[i]["outer"]
+        assert np.array_equal(tr2[i, :k, :5], tr[i, :k, :5])
+    assert 1 <= infos[0]["converged_at"] <= 10
+
+
+def test_batch_graph_replay_equals_direct(S):
+    graphs = _graphs(1700, SHAPES[:3], restarts=2)
+    As, a_in, W0s, _ = _batch_inputs(S, graphs, torch.float32)
+    rs = [r for _, r, _ in graphs]
+    lams = [O.default_lambda(a) for a in a_in]
+    out = []
+    for ug in (1, 0):
+        with S.Batch(As, rs, S.params(prec=S.F32, max_outer=12, use_graph=ug), restarts=2,
+                     lam=lams) as b:
+            out.append(b.solve(W0s))
+    for g in range(len(graphs)):
+        assert torch.equal(out[0][0][g], out[1][0][g]) and torch.equal(out[0][1][g], out[1][1][g])
+
+
+def test_batch_error_codes(S):
+    graphs = _graphs(2100, [(60, 3), (80, 4)], restarts=1)
+    As, _, W0s, _ = _batch_inputs(S, graphs, torch.float64)
+    with pytest.raises(S.SnmfError) as e:
+        S.Batch(As, [3, 4], S.params(prec=S.BF16X3), restarts=1)
+    assert e.value.name == "E_UNSUPPORTED"
+    dense = S.dense(torch.eye(60, dtype=torch.float64, device=DEV))
+    with pytest.raises(S.SnmfError) as e:
+        S.Batch([As[0], dense], [3, 3], S.params(prec=S.F64), restarts=1)
+    assert e.value.name == "E_UNSUPPORTED"
+    with pytest.raises(S.SnmfError) as e:
+        S.Batch(As, [3, 81], S.params(prec=S.F64), restarts=1)
+    assert e.value.name == "E_SHAPE"
+    with pytest.raises(S.SnmfError) as e:
+        S.Batch(As, [3, 4], S.params(prec=S.F64), restarts=0)
+    assert e.value.name == "E_ARG"
+    with pytest.raises(S.SnmfError) as e:
+        S.Batch(As, [3, 4], S.params(prec=S.F64), restarts=1, lam=[0.1, -1.0])
+    assert e.value.name == "E_ARG"
+    with S.Batch(As, [3, 4], S.params(prec=S.F64, max_outer=2), restarts=1) as b:
+        bad = [W0s[0].clone(), W0s[1].clone()]
+        bad[1][0, 3, 1] = -1.0
+        with pytest.raises(S.SnmfError) as e:
+            b.solve(bad)
+        assert e.value.name == "E_NEGATIVE"
