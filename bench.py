@@ -35,6 +35,9 @@ def _args():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-outer", type=int, default=0,
                     help="outer iterations of the CPU-reference sample (0: pick ~15 s)")
+    ap.add_argument("--workload", choices=("c1", "c4"), default="c1",
+                    help="c1: dense n=8192, r=64 (the headline line); c4: 256 SBM graphs, "
+                         "8 restarts each, in one batched solve")
     ap.add_argument("--apass-only", action="store_true",
                     help="only a 256 MiB device copy (the counter scale reference) and 20 "
                          "A-pass launches of each form; for hardware-counter runs")
@@ -102,6 +105,80 @@ def _traffic(kernel_src, name):
     return blob["kernels"][name]["bytes_per_launch"]
 
 
+def _bench_c4(a, torch, np, S, gen):
+    """256 SBM graphs (n ~ U[500, 5000], r in {8, 16, 32}), 8 random starts each, solved
+    together by the batching form in FP32.  value: instance outer iterations per second."""
+    dev = torch.device("cuda:0")
+    graphs = gen.config(4)
+    restarts = len(graphs[0]["W0"])
+    As = [S.csr_from_scipy(g["A"], torch.float32) for g in graphs]
+    rs = [g["r"] for g in graphs]
+    lams = [0.01 * float(np.sqrt(np.sum(g["A"].data.astype(np.float32).astype(np.float64) ** 2)))
+            for g in graphs]
+    W0s = [torch.from_numpy(np.stack(g["W0"])).to(dev, torch.float32).contiguous() for g in graphs]
+    torch.cuda.synchronize()
+    steps = a.steps
+    with S.Batch(As, rs, S.params(prec=S.F32, max_outer=steps, check_every=1 << 30), restarts,
+                 lam=lams) as b:
+        b.solve(W0s)                                   # graph capture + warm clocks
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, infos, _ = b.solve(W0s)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        ninst = b.ninst
+        elements = b.elements
+    out = {"metric": "batched SNMPBB instance outer iterations/s (256 SBM graphs x 8 restarts)",
+           "value": ninst * steps / el, "unit": "instance outer iterations/s", "n_gpus": 1,
+           "steps": steps, "warmup": steps, "ms_per_step": 1e3 * el / steps,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": "256 SBM graphs, n ~ U[500,5000], r in {8,16,32}, seed 1004",
+                      "instances": ninst, "restarts": restarts,
+                      "sum_n": int(sum(g["n"] for g in graphs)),
+                      "sum_nnz": int(sum(g["A"].nnz for g in graphs)),
+                      "elements_per_buffer": int(elements), "parallelism": "single GPU"}}
+    if not a.no_target:
+        # tau_g = (1 + 1e-4) x best final residual over the graph's restarts after
+        # target_outer iterations; time to target = when its best restart first meets it
+        T = a.target_outer
+        with S.Batch(As, rs, S.params(prec=S.F32, max_outer=T, check_every=1 << 30), restarts,
+                     lam=lams) as b:
+            _, _, infos, tr = b.solve(W0s, trace=True)
+        hz = S.clock_rate_hz()
+        tts, its, frac, broken, no_valid = [], [], [], 0, 0
+        for g in range(len(graphs)):
+            valid = []
+            for s_ in range(restarts):
+                i = g * restarts + s_
+                if infos[i]["status"] != 0 or infos[i]["outer"] < 1:
+                    broken += 1
+                    continue
+                k = infos[i]["outer"]
+                valid.append((tr[i, :k, 0], tr[i, :k, 5]))
+            if not valid:
+                no_valid += 1
+                continue
+            tau = (1 + 1e-4) * min(r_[-1] for r_, _ in valid)
+            firsts = []
+            for r_, t_ in valid:
+                hit = np.nonzero(r_ <= tau)[0]
+                firsts.append((int(hit[0]), t_[hit[0]]) if hit.size else None)
+            ok = [f for f in firsts if f is not None]
+            frac.append(len(ok) / restarts)
+            best = min(ok)
+            its.append(best[0] + 1)
+            tts.append(best[1] / hz)
+        out["time_to_target"] = {
+            "rule": f"tau_g = (1 + 1e-4) x best restart residual after {T} outer iterations",
+            "median_seconds": float(np.median(tts)), "max_seconds": float(np.max(tts)),
+            "median_outer": float(np.median(its)),
+            "fraction_of_restarts_reaching": float(np.mean(frac)),
+            "restarts_broken_down": broken, "graphs_without_a_valid_restart": no_valid}
+    out["instances_broken_down"] = int(sum(i["status"] != 0 for i in infos))
+    print(json.dumps(out))
+
+
 def main():
     a = _args()
     if a.gpus != 1:
@@ -110,6 +187,11 @@ def main():
         sys.exit(2)
     import numpy as np
     import torch
+    if a.workload == "c4":
+        from paper_2606_02887_amd import gen
+        from paper_2606_02887_amd import snmf as S
+        _bench_c4(a, torch, np, S, gen)
+        return
 
     from paper_2606_02887_amd import gen
     from paper_2606_02887_amd import snmf as S
@@ -146,6 +228,23 @@ def main():
                        "device_ms_per_outer": 1e3 * info["seconds"] / max(info["outer"], 1),
                        "res_WH": info["res_WH"], "pg_norm": info["pg_norm"],
                        "outer": info["outer"]}
+
+    # ---------------------------------------------------------------- batched restarts
+    # the batching form on the same problem: 8 random starts solved together
+    rng = np.random.default_rng(1101)
+    W0b = torch.from_numpy(np.stack([gen.start_factor(rng, N, R, float(A64.mean()))
+                                     for _ in range(8)])).to(dev, torch.float32).contiguous()
+    with S.Batch([S.dense(A)], [R], S.params(lam=lam, prec=S.F32, max_outer=a.steps,
+                                             check_every=1 << 30), 8) as bt:
+        bt.solve([W0b])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, binf, _ = bt.solve([W0b])
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+    forms["batched8_fp32"] = {"restart_outer_per_s": 8 * a.steps / el,
+                              "ms_per_outer": 1e3 * el / a.steps,
+                              "res_WH_best": min(i["res_WH"] for i in binf)}
 
     # ---------------------------------------------------------------- roofline (A-pass)
     P = W0.clone()

@@ -207,8 +207,10 @@ snmf_status snmf_split_bf16(const float* x, int64_t count, uint16_t* hi, uint16_
  * traces:   optional host array of nprob * S * max_outer * SNMF_TRACE_FIELDS doubles,
  *           instance-major, the records of snmf_solve.
  * The library keeps the A pointers until destroy; all other buffers are the caller's.
- * Errors as for the single solve; instance breakdowns are reported in infos[].status and
- * the call returns E_BREAKDOWN if any instance broke down. */
+ * Errors as for the single solve, except numeric breakdown: an instance whose iteration
+ * breaks down (a non-finite scalar, or rho = 0 after its factor collapsed to zero) stops,
+ * keeps its last iterate and reports SNMF_E_BREAKDOWN in infos[i].status while the call
+ * returns SNMF_OK.  Trace records beyond infos[i].outer are unspecified. */
 typedef struct snmf_batch snmf_batch;
 snmf_status snmf_batch_create(int32_t nprob, const snmf_matrix* A, const int32_t* r,
                               const double* lam, int32_t restarts, const snmf_params* p,

@@ -207,6 +207,28 @@ __device__ __forceinline__ Loc locate(const BMap& bm, int64_t n, State* st, doub
   return l;
 }
 
+// Element access inside a tile: a uniform base pointer (the tile's first row, held in
+// scalar registers) plus this thread's fixed byte offset, so the loads take the
+// scalar-base + 32-bit vector-offset form and one offset register serves every array.
+template <typename T>
+__device__ __forceinline__ T ldo(const T* __restrict__ base, uint32_t bo) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + bo);
+}
+template <typename T>
+__device__ __forceinline__ void sto(T* __restrict__ base, uint32_t bo, T v) {
+  *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + bo) = v;
+}
+// A tile's pointer into one array, pinned as an opaque uniform (scalar-register) value:
+// the empty asm emits nothing, but it stops the compiler from re-associating
+// (array + tile) + offset into (array + offset) + tile and hoisting the 64 per-element
+// 64-bit sums (array, element) out of the tile loop into vector registers.
+template <typename P>
+__device__ __forceinline__ P tile_ptr(P base, int64_t tb) {
+  P q = base + tb;
+  asm volatile("" : "+s"(q));
+  return q;
+}
+
 // ----------------------------------------------------------------------------- init
 // C = (sum of the A-pass partials) + lam P;  g = X G + lam X - C [+ gam LX].
 template <typename T, int RP>
@@ -233,8 +255,12 @@ __global__ __launch_bounds__(kThreads) void k_init(
   __shared__ Smem<T, RP> sm;
   const int tid = threadIdx.x;
   int lr[8], cl[8];
+  uint32_t bo[8];
 #pragma unroll
-  for (int p = 0; p < 8; ++p) L::rc(p, lr[p], cl[p]);
+  for (int p = 0; p < 8; ++p) {
+    L::rc(p, lr[p], cl[p]);
+    bo[p] = (uint32_t)((lr[p] * r + cl[p]) * (int)sizeof(T));
+  }
   if (!is_hstep && lc.bid == 0 && tid == 0) {
     // snapshot for the monitor record completed by this W-step's first inner kernel
     st->snap_pending = st->pending;
@@ -248,28 +274,27 @@ __global__ __launch_bounds__(kThreads) void k_init(
   const int64_t ntiles = (n + TM - 1) / TM;
   bool first = true;
   for (int64_t t = lc.bid; t < ntiles; t += lc.nb) {
-    const int64_t row0 = t * TM;
+    const int64_t row0 = t * TM, tb = row0 * r;
+    const T* __restrict__ Bt = tile_ptr(Bpart, tb);
     T x[8], cv[8], pv[8];
 #pragma unroll
     for (int p = 0; p < 8; ++p) {
-      const int64_t row = row0 + lr[p];
-      const bool ok = row < n && cl[p] < r;
-      const int64_t o = row * r + cl[p];
+      const bool ok = row0 + lr[p] < n && cl[p] < r;
       T b = T(0);
       if (ok) {
         int s = 0;
         for (; s + 4 <= ksplit; s += 4) {  // four split-K partials in flight, added in order
-          const T b0 = Bpart[s * bstride + o], b1 = Bpart[(s + 1) * bstride + o];
-          const T b2 = Bpart[(s + 2) * bstride + o], b3 = Bpart[(s + 3) * bstride + o];
+          const T b0 = ldo(Bt + s * bstride, bo[p]), b1 = ldo(Bt + (s + 1) * bstride, bo[p]);
+          const T b2 = ldo(Bt + (s + 2) * bstride, bo[p]), b3 = ldo(Bt + (s + 3) * bstride, bo[p]);
           b += b0;
           b += b1;
           b += b2;
           b += b3;
         }
-        for (; s < ksplit; ++s) b += Bpart[s * bstride + o];
+        for (; s < ksplit; ++s) b += ldo(Bt + s * bstride, bo[p]);
       }
-      x[p] = ok ? X[o] : T(0);
-      pv[p] = ok ? P[o] : T(0);
+      x[p] = ok ? ldo(tile_ptr(X, tb), bo[p]) : T(0);
+      pv[p] = ok ? ldo(tile_ptr(P, tb), bo[p]) : T(0);
       cv[p] = b + lam * pv[p];
     }
     if (first) store_G<T, RP>(sm.G, gv);
@@ -282,13 +307,11 @@ __global__ __launch_bounds__(kThreads) void k_init(
     tile_gemm<T, RP>(sm.a, sm.G, xg);
 #pragma unroll
     for (int p = 0; p < 8; ++p) {
-      const int64_t row = row0 + lr[p];
-      if (row < n && cl[p] < r) {
-        const int64_t o = row * r + cl[p];
-        Cout[o] = cv[p];
+      if (row0 + lr[p] < n && cl[p] < r) {
+        sto(tile_ptr(Cout, tb), bo[p], cv[p]);
         T gvv = xg[p] + lam * x[p] - cv[p];
-        if (LX) gvv += gam * LX[o];
-        g[o] = gvv;
+        if (LX) gvv += gam * ldo(tile_ptr(LX, tb), bo[p]);
+        sto(tile_ptr(g, tb), bo[p], gvv);
         if (is_hstep) {
           v[0] += (double)cv[p] * (double)pv[p];
         } else {
@@ -441,6 +464,21 @@ __device__ bool inner_entry(int k, int is_hstep, int r, const KParams& kp, State
   return true;
 }
 
+// ----------------------------------------------------------------------------- Z and D
+// The two projections of Algorithm 1 and the gradient at Z.
+template <typename T>
+__device__ __forceinline__ T first_proj(T x, T g, T rinv) {  // max(0, X - g / rho)
+  return relu(fmaT(-g, rinv, x));
+}
+template <typename T>
+__device__ __forceinline__ T grad_at_z(T g, T dzg, T lam, T dz) {  // g + (Z-X)(G + lam I)
+  return fmaT(lam, dz, g + dzg);
+}
+template <typename T>
+__device__ __forceinline__ T second_dir(T z, T gz, T alpha) {  // max(0, Z - alpha gZ) - Z
+  return relu(fmaT(-alpha, gz, z)) - z;
+}
+
 // ----------------------------------------------------------------------------- step 1
 // Z = max(0, X - g/rho);  grad f(Z) = g + (Z - X)(G + lam I) [+ gam L(Z-X)];
 // D = max(0, Z - alpha grad f(Z)) - Z.  Partials: <grad f(Z), D>, <D G, D>, ||D||^2 and
@@ -475,8 +513,12 @@ __global__ __launch_bounds__(kThreads) void k_step1(
   constexpr int TM = L::TM;
   __shared__ Smem<T, RP> sm;
   int lr[8], cl[8];
+  uint32_t bo[8];
 #pragma unroll
-  for (int p = 0; p < 8; ++p) L::rc(p, lr[p], cl[p]);
+  for (int p = 0; p < 8; ++p) {
+    L::rc(p, lr[p], cl[p]);
+    bo[p] = (uint32_t)((lr[p] * r + cl[p]) * (int)sizeof(T));
+  }
   const int64_t ntiles = (n + TM - 1) / TM;
   // loads first: State scalars, partial sums of the previous kernel, G, the first tile
   const int done = st->done;
@@ -489,15 +531,14 @@ __global__ __launch_bounds__(kThreads) void k_step1(
   if (phase != 1) load_G<T, RP>(GT, r, gv);
   T x[8], gvv[8], z[8], lz[8];
   auto load_tile = [&](int64_t row0) {
+    const int64_t tb = row0 * r;
 #pragma unroll
     for (int p = 0; p < 8; ++p) {
-      const int64_t row = row0 + lr[p];
-      const bool ok = row < n && cl[p] < r;
-      const int64_t o = row * r + cl[p];
-      x[p] = ok ? X[o] : T(0);
-      gvv[p] = ok ? g[o] : T(0);
-      z[p] = (ok && phase == 2) ? Z[o] : T(0);
-      lz[p] = (ok && phase == 2) ? LdZ[o] : T(0);
+      const bool ok = row0 + lr[p] < n && cl[p] < r;
+      x[p] = ok ? ldo(tile_ptr(X, tb), bo[p]) : T(0);
+      gvv[p] = ok ? ldo(tile_ptr(g, tb), bo[p]) : T(0);
+      z[p] = (ok && phase == 2) ? ldo(tile_ptr(Z, tb), bo[p]) : T(0);
+      lz[p] = (ok && phase == 2) ? ldo(tile_ptr(LdZ, tb), bo[p]) : T(0);
     }
   };
   if (lc.bid < ntiles) load_tile((int64_t)lc.bid * TM);
@@ -517,14 +558,13 @@ __global__ __launch_bounds__(kThreads) void k_step1(
   if (phase == 1) {
     for (int64_t t = lc.bid; t < ntiles; t += lc.nb) {
       if (t != lc.bid) load_tile(t * TM);
+      const int64_t tb = t * TM * r;
 #pragma unroll
       for (int p = 0; p < 8; ++p) {
-        const int64_t row = t * TM + lr[p];
-        if (row < n && cl[p] < r) {
-          const int64_t o = row * r + cl[p];
-          const T zz = relu(x[p] - gvv[p] * rinv);
-          Z[o] = zz;
-          D[o] = zz - x[p];
+        if (t * TM + lr[p] < n && cl[p] < r) {
+          const T zz = first_proj(x[p], gvv[p], rinv);
+          sto(tile_ptr(Z, tb), bo[p], zz);
+          sto(tile_ptr(D, tb), bo[p], zz - x[p]);
         }
       }
     }
@@ -539,26 +579,25 @@ __global__ __launch_bounds__(kThreads) void k_step1(
 #pragma unroll
     for (int p = 0; p < 8; ++p) {
       const bool ok = row0 + lr[p] < n && cl[p] < r;
-      if (phase == 0) z[p] = relu(x[p] - gvv[p] * rinv);
+      if (phase == 0) z[p] = first_proj(x[p], gvv[p], rinv);
       sm.a[lr[p] * L::YP + cl[p]] = ok ? z[p] - x[p] : T(0);
     }
     __syncthreads();
     T dzg[8];
     tile_gemm<T, RP>(sm.a, sm.G, dzg);
     T d[8];
+    const int64_t tb = row0 * r;
 #pragma unroll
     for (int p = 0; p < 8; ++p) {
-      const int64_t row = row0 + lr[p];
-      const bool ok = row < n && cl[p] < r;
-      const int64_t o = row * r + cl[p];
+      const bool ok = row0 + lr[p] < n && cl[p] < r;
       const T dz = z[p] - x[p];
-      T gz = gvv[p] + dzg[p] + lam * dz;
+      T gz = grad_at_z(gvv[p], dzg[p], lam, dz);
       if (phase == 2) gz += gam * lz[p];
-      const T dd = ok ? relu(z[p] - alpha * gz) - z[p] : T(0);
+      const T dd = ok ? second_dir(z[p], gz, alpha) : T(0);
       d[p] = dd;
       if (ok) {
-        if (phase == 0) Z[o] = z[p];
-        D[o] = dd;
+        if (phase == 0) sto(tile_ptr(Z, tb), bo[p], z[p]);
+        sto(tile_ptr(D, tb), bo[p], dd);
         v[0] += (double)gz * (double)dd;
         v[2] += (double)dd * (double)dd;
         v[3] += 0.5 * ((double)gvv[p] + (double)gz) * (double)dz;
@@ -636,8 +675,12 @@ __global__ __launch_bounds__(kThreads) void k_step2(
   constexpr int TM = L::TM;
   __shared__ Smem<T, RP> sm;
   int lr[8], cl[8];
+  uint32_t bo[8];
 #pragma unroll
-  for (int p = 0; p < 8; ++p) L::rc(p, lr[p], cl[p]);
+  for (int p = 0; p < 8; ++p) {
+    L::rc(p, lr[p], cl[p]);
+    bo[p] = (uint32_t)((lr[p] * r + cl[p]) * (int)sizeof(T));
+  }
   const bool w0 = lc.bid == 0 && threadIdx.x == 0;
   const int64_t ntiles = (n + TM - 1) / TM;
   // loads first: State scalars, partial sums of step 1 (and <D, L D>), G, the first tile
@@ -654,19 +697,18 @@ __global__ __launch_bounds__(kThreads) void k_step2(
   const bool lap = phase == 2;
   T x[8], zz[8], dd[8], go[8], cv[8], pv[8], ls[8], lx[8];
   auto load_tile = [&](int64_t row0) {
+    const int64_t tb = row0 * r;
 #pragma unroll
     for (int p = 0; p < 8; ++p) {
-      const int64_t row = row0 + lr[p];
-      const bool ok = row < n && cl[p] < r;
-      const int64_t o = row * r + cl[p];
-      x[p] = ok ? X[o] : T(0);
-      zz[p] = ok ? Z[o] : T(0);
-      dd[p] = (ok && phase != 2) ? D[o] : T(0);
-      go[p] = (ok && phase != 1) ? g[o] : T(0);
-      cv[p] = (ok && mon) ? C[o] : T(0);
-      pv[p] = (ok && mon) ? P[o] : T(0);
-      ls[p] = (ok && lap) ? LS[o] : T(0);
-      lx[p] = (ok && lap && LXb) ? LXb[o] : T(0);
+      const bool ok = row0 + lr[p] < n && cl[p] < r;
+      x[p] = ok ? ldo(tile_ptr(X, tb), bo[p]) : T(0);
+      zz[p] = ok ? ldo(tile_ptr(Z, tb), bo[p]) : T(0);
+      dd[p] = (ok && phase != 2) ? ldo(tile_ptr(D, tb), bo[p]) : T(0);
+      go[p] = (ok && phase != 1) ? ldo(tile_ptr(g, tb), bo[p]) : T(0);
+      cv[p] = (ok && mon) ? ldo(tile_ptr(C, tb), bo[p]) : T(0);
+      pv[p] = (ok && mon) ? ldo(tile_ptr(P, tb), bo[p]) : T(0);
+      ls[p] = (ok && lap) ? ldo(tile_ptr(LS, tb), bo[p]) : T(0);
+      lx[p] = (ok && lap && LXb) ? ldo(tile_ptr(LXb, tb), bo[p]) : T(0);
     }
   };
   if (lc.bid < ntiles) load_tile((int64_t)lc.bid * TM);
@@ -695,15 +737,14 @@ __global__ __launch_bounds__(kThreads) void k_step2(
   if (phase == 1) {
     for (int64_t t = lc.bid; t < ntiles; t += lc.nb) {
       if (t != lc.bid) load_tile(t * TM);
+      const int64_t tb = t * TM * r;
 #pragma unroll
       for (int p = 0; p < 8; ++p) {
-        const int64_t row = t * TM + lr[p];
-        if (row < n && cl[p] < r) {
-          const int64_t o = row * r + cl[p];
+        if (t * TM + lr[p] < n && cl[p] < r) {
           T xn = zz[p] + step * dd[p];
           if (kp.project) xn = relu(xn);
-          Z[o] = xn;
-          D[o] = xn - x[p];
+          sto(tile_ptr(Z, tb), bo[p], xn);
+          sto(tile_ptr(D, tb), bo[p], xn - x[p]);
         }
       }
     }
@@ -726,21 +767,20 @@ __global__ __launch_bounds__(kThreads) void k_step2(
         if (kp.project) y = relu(y);
         xn[p] = ok ? y : T(0);
       }
-      sm.a[lr[p] * L::YP + cl[p]] = ok ? xn[p] - x[p] : T(0);
+      sm.b[lr[p] * L::YP + cl[p]] = ok ? xn[p] - x[p] : T(0);
     }
     __syncthreads();
     T sg[8];
-    tile_gemm<T, RP>(sm.a, sm.G, sg);
+    tile_gemm<T, RP>(sm.b, sm.G, sg);
+    const int64_t tb = row0 * r;
 #pragma unroll
     for (int p = 0; p < 8; ++p) {
-      const int64_t row = row0 + lr[p];
-      if (row < n && cl[p] < r) {
-        const int64_t o = row * r + cl[p];
+      if (row0 + lr[p] < n && cl[p] < r) {
         const T s = xn[p] - x[p];
         T gn = go[p] + sg[p] + lam * s;
         if (lap) gn += gam * ls[p];
-        X[o] = xn[p];
-        g[o] = gn;
+        sto(tile_ptr(X, tb), bo[p], xn[p]);
+        sto(tile_ptr(g, tb), bo[p], gn);
         v[0] += (double)s * (double)s;
         v[1] += (double)sg[p] * (double)s;
         v[2] += (double)go[p] * (double)s;
@@ -755,7 +795,7 @@ __global__ __launch_bounds__(kThreads) void k_step2(
         }
         if (lap && LXb) {
           const T lxn = lx[p] + ls[p];
-          LXb[o] = lxn;
+          sto(tile_ptr(LXb, tb), bo[p], lxn);
           if (is_hstep) v[7] += (double)xn[p] * (double)lxn;
         }
       }

@@ -7,52 +7,94 @@
 namespace snmf {
 
 // ----------------------------------------------------------------------------- Gram
-// Each workgroup forms the FP64 Gram of a contiguous slab of rows of P (thread t owns the
-// 4 x 4 block of G at rows 4(t/16), columns 4(t%16)); a second kernel adds the slabs in
-// block order (deterministic) and writes G in FP64 and in the iterate type.
-template <typename T>
+// Each workgroup forms the FP64 Gram of a contiguous slab of rows of P; a second kernel
+// adds the slabs in block order (deterministic) and writes G in FP64 and in the iterate
+// type.  RPG is the rank rounded up to a power of two: with E = RPG^2 >= 256 entries each
+// thread owns a BS x BS block of G; with E < 256 the 256 / E row groups of the workgroup
+// each take every (256/E)-th row of the tile and their sums are added in group order.
+template <int RPG>
+struct GramCfg {
+  static constexpr int E = RPG * RPG;
+  static constexpr int RG = E >= kThreads ? 1 : kThreads / E;
+  static constexpr int EPT = E >= kThreads ? E / kThreads : 1;
+  static constexpr int BS = EPT == 16 ? 4 : (EPT == 4 ? 2 : 1);
+  static constexpr int TR = 64;                   // rows per LDS tile
+  static constexpr int LDP = RPG + (BS > 1 ? 2 : 1);
+};
+
+template <typename T, int RPG>
 __device__ __forceinline__ void gram_slab(const T* __restrict__ P, int r, int64_t rb, int64_t re,
                                           double* __restrict__ out) {
-  constexpr int TR = 32, LDP = kMaxRank + 2;
+  typedef GramCfg<RPG> C;
+  constexpr int BS = C::BS, TR = C::TR, LDP = C::LDP, RG = C::RG, E = C::E;
   __shared__ __attribute__((aligned(16))) double sP[TR * LDP];
-  const int a0 = 4 * (threadIdx.x >> 4), b0 = 4 * (threadIdx.x & 15);
-  double acc[4][4];
+  __shared__ double sR[RG > 1 ? kThreads : 1];
+  const int t = threadIdx.x;
+  int a0, b0, grp;
+  if constexpr (RG > 1) {
+    const int e = t % E;
+    grp = t / E;
+    a0 = e / RPG;
+    b0 = e % RPG;
+  } else {
+    grp = 0;
+    a0 = BS * (t / (RPG / BS));
+    b0 = BS * (t % (RPG / BS));
+  }
+  double acc[BS][BS];
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
+  for (int u = 0; u < BS; ++u)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+    for (int v = 0; v < BS; ++v) acc[u][v] = 0.0;
   for (int64_t t0 = rb; t0 < re; t0 += TR) {
     __syncthreads();
-    for (int e = threadIdx.x; e < TR * kMaxRank; e += kThreads) {
-      const int i = e / kMaxRank, c = e % kMaxRank;
+    for (int e = t; e < TR * RPG; e += kThreads) {
+      const int i = e / RPG, c = e % RPG;
       const int64_t row = t0 + i;
       sP[i * LDP + c] = (row < re && c < r) ? (double)P[row * r + c] : 0.0;
     }
     __syncthreads();
+    if constexpr (RG > 1) {
+      double s0 = acc[0][0];
+      for (int i = grp; i < TR; i += RG) s0 = __builtin_fma(sP[i * LDP + a0], sP[i * LDP + b0], s0);
+      acc[0][0] = s0;
+    } else {
 #pragma unroll 4
-    for (int i = 0; i < TR; ++i) {
-      const double2 x0 = *(const double2*)&sP[i * LDP + a0];
-      const double2 x1 = *(const double2*)&sP[i * LDP + a0 + 2];
-      const double2 y0 = *(const double2*)&sP[i * LDP + b0];
-      const double2 y1 = *(const double2*)&sP[i * LDP + b0 + 2];
-      const double xa[4] = {x0.x, x0.y, x1.x, x1.y};
-      const double yb[4] = {y0.x, y0.y, y1.x, y1.y};
+      for (int i = 0; i < TR; ++i) {
+        double x[BS], y[BS];
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < BS; ++u) {
+          x[u] = sP[i * LDP + a0 + u];
+          y[u] = sP[i * LDP + b0 + u];
+        }
 #pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] = __builtin_fma(xa[u], yb[v], acc[u][v]);
+        for (int u = 0; u < BS; ++u)
+#pragma unroll
+          for (int v = 0; v < BS; ++v) acc[u][v] = __builtin_fma(x[u], y[v], acc[u][v]);
+      }
     }
   }
+  if constexpr (RG > 1) {
+    sR[t] = acc[0][0];
+    __syncthreads();
+    if (t < E) {
+      double sum = 0.0;
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int a = a0 + u, b = b0 + v;
-      if (a < r && b < r) out[a * r + b] = acc[u][v];
+      for (int g = 0; g < RG; ++g) sum += sR[g * E + t];
+      if (a0 < r && b0 < r) out[a0 * r + b0] = sum;
     }
+  } else {
+#pragma unroll
+    for (int u = 0; u < BS; ++u)
+#pragma unroll
+      for (int v = 0; v < BS; ++v) {
+        const int a = a0 + u, b = b0 + v;
+        if (a < r && b < r) out[a * r + b] = acc[u][v];
+      }
+  }
 }
 
-template <typename T>
+template <typename T, int RPG>
 __global__ __launch_bounds__(kThreads) void k_gram(const T* __restrict__ P, int64_t n, int r,
                                                    int64_t rows_per_block,
                                                    double* __restrict__ part,
@@ -60,12 +102,12 @@ __global__ __launch_bounds__(kThreads) void k_gram(const T* __restrict__ P, int6
   if (st->done) return;
   const int64_t rb = (int64_t)blockIdx.x * rows_per_block;
   const int64_t re = rb + rows_per_block < n ? rb + rows_per_block : n;
-  gram_slab<T>(P, r, rb, re, part + (size_t)blockIdx.x * r * r);
+  gram_slab<T, RPG>(P, r, rb, re, part + (size_t)blockIdx.x * r * r);
 }
 
-// Batched: workgroup -> (instance, slab) through gblk_inst; the same slabs as a single
-// solve of that instance, so its G is bitwise the same.
-template <typename T>
+// Batched: the workgroups of one rank class; workgroup -> (instance, slab) through
+// gblk_inst.  The same slabs as a single solve of that instance, so G is bitwise equal.
+template <typename T, int RPG>
 __global__ __launch_bounds__(kThreads) void k_bgram(const T* __restrict__ P,
                                                     const int32_t* __restrict__ gblk_inst,
                                                     const BInst* __restrict__ inst,
@@ -77,26 +119,7 @@ __global__ __launch_bounds__(kThreads) void k_bgram(const T* __restrict__ P,
   const int j = (int)blockIdx.x - d->gblk0;
   const int64_t rb = (int64_t)j * d->grpb;
   const int64_t re = rb + d->grpb < d->n ? rb + d->grpb : d->n;
-  gram_slab<T>(P + d->off, d->r, rb, re, gpart + d->gpoff + (size_t)j * d->r * d->r);
-}
-
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_bgram_reduce(const BInst* __restrict__ inst,
-                                                           const State* __restrict__ states,
-                                                           const double* __restrict__ gpart,
-                                                           double* __restrict__ G64,
-                                                           T* __restrict__ GT) {
-  const int i = blockIdx.x;
-  const BInst* d = inst + i;
-  if (states[i].done) return;
-  const int rr = d->r * d->r;
-  const double* part = gpart + d->gpoff;
-  for (int e = threadIdx.x; e < rr; e += kThreads) {
-    double s = 0.0;
-    for (int b = 0; b < d->gnb; ++b) s += part[(size_t)b * rr + e];
-    G64[d->goff + e] = s;
-    GT[d->goff + e] = (T)s;
-  }
+  gram_slab<T, RPG>(P + d->off, d->r, rb, re, gpart + d->gpoff + (size_t)j * d->r * d->r);
 }
 
 template <typename T>
@@ -119,6 +142,26 @@ __global__ __launch_bounds__(kThreads) void k_gram_reduce(const double* __restri
   for (; b < nb; ++b) s += part[(size_t)b * rr + e];
   G64[e] = s;
   GT[e] = (T)s;
+}
+
+// Batched: one workgroup per instance adds its Gram slabs in slab order.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_bgram_reduce(const BInst* __restrict__ inst,
+                                                           const State* __restrict__ states,
+                                                           const double* __restrict__ gpart,
+                                                           double* __restrict__ G64,
+                                                           T* __restrict__ GT) {
+  const int i = blockIdx.x;
+  const BInst* d = inst + i;
+  if (states[i].done) return;
+  const int rr = d->r * d->r;
+  const double* part = gpart + d->gpoff;
+  for (int e = threadIdx.x; e < rr; e += kThreads) {
+    double s = 0.0;
+    for (int b = 0; b < d->gnb; ++b) s += part[(size_t)b * rr + e];
+    G64[d->goff + e] = s;
+    GT[d->goff + e] = (T)s;
+  }
 }
 
 // ----------------------------------------------------------------------------- rho
@@ -316,11 +359,21 @@ __global__ __launch_bounds__(kThreads) void k_split_pt(const float* __restrict__
 }
 
 // ----------------------------------------------------------------------------- launchers
+#define SNMF_DISPATCH_RPG(rp, ...)                                  \
+  switch (rp) {                                                     \
+    case 4: { constexpr int RPG = 4; __VA_ARGS__; } break;          \
+    case 8: { constexpr int RPG = 8; __VA_ARGS__; } break;          \
+    case 16: { constexpr int RPG = 16; __VA_ARGS__; } break;        \
+    case 32: { constexpr int RPG = 32; __VA_ARGS__; } break;        \
+    default: { constexpr int RPG = 64; __VA_ARGS__; } break;        \
+  }
+
 template <typename T>
 void launch_gram(const T* P, int64_t n, int r, double* part, int nblk, double* G64, T* GT,
                  const State* st, hipStream_t s) {
   int64_t rpb = (n + nblk - 1) / nblk;
-  hipLaunchKernelGGL(k_gram<T>, dim3(nblk), dim3(kThreads), 0, s, P, n, r, rpb, part, st);
+  SNMF_DISPATCH_RPG(rank_pad(r), hipLaunchKernelGGL((k_gram<T, RPG>), dim3(nblk), dim3(kThreads),
+                                                    0, s, P, n, r, rpb, part, st))
   const int rr = r * r;
   hipLaunchKernelGGL(k_gram_reduce<T>, dim3((rr + kThreads - 1) / kThreads), dim3(kThreads), 0, s,
                      part, nblk, rr, G64, GT, st);
@@ -335,19 +388,26 @@ void launch_rho(const double* G, int r, State* st, hipStream_t s) {
 }
 
 template <typename T>
-void launch_bgram(const T* P, const int32_t* gblk_inst, int gblocks, const BInst* inst, int ninst,
-                  int max_r, const State* states, double* gpart, double* G64, T* GT,
-                  hipStream_t s) {
-  hipLaunchKernelGGL(k_bgram<T>, dim3(gblocks), dim3(kThreads), 0, s, P, gblk_inst, inst, states,
-                     gpart);
-  (void)max_r;
+void launch_bgram(const T* P, int r, const int32_t* gblk_inst, int gblocks, const BInst* inst,
+                  const State* states, double* gpart, hipStream_t s) {
+  SNMF_DISPATCH_RPG(rank_pad(r),
+                    hipLaunchKernelGGL((k_bgram<T, RPG>), dim3(gblocks), dim3(kThreads), 0, s, P,
+                                       gblk_inst, inst, states, gpart))
+}
+template <typename T>
+void launch_bgram_reduce(const BInst* inst, int ninst, const State* states, const double* gpart,
+                         double* G64, T* GT, hipStream_t s) {
   hipLaunchKernelGGL(k_bgram_reduce<T>, dim3(ninst), dim3(kThreads), 0, s, inst, states, gpart,
                      G64, GT);
 }
-template void launch_bgram<float>(const float*, const int32_t*, int, const BInst*, int, int,
-                                  const State*, double*, double*, float*, hipStream_t);
-template void launch_bgram<double>(const double*, const int32_t*, int, const BInst*, int, int,
-                                   const State*, double*, double*, double*, hipStream_t);
+template void launch_bgram<float>(const float*, int, const int32_t*, int, const BInst*,
+                                  const State*, double*, hipStream_t);
+template void launch_bgram<double>(const double*, int, const int32_t*, int, const BInst*,
+                                   const State*, double*, hipStream_t);
+template void launch_bgram_reduce<float>(const BInst*, int, const State*, const double*, double*,
+                                         float*, hipStream_t);
+template void launch_bgram_reduce<double>(const BInst*, int, const State*, const double*,
+                                          double*, double*, hipStream_t);
 
 void launch_brho(const BInst* inst, int ninst, State* states, const double* G64, hipStream_t s) {
   hipLaunchKernelGGL(k_brho, dim3(ninst), dim3(kThreads), 0, s, inst, states, G64);

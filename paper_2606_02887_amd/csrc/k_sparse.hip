@@ -57,6 +57,8 @@ __global__ __launch_bounds__(256) void k_spmm(const int64_t* __restrict__ rowptr
 // sweep over its CSR (the restarts form one n x (S r) operand).  One wavefront per row;
 // lane c of a chunk of cw columns (cw = 64, or the smallest power of two >= S r) serves
 // stacked column c0 + c = s r + j, and the 64 / cw lane groups split the row's nonzeros.
+// The wave loads up to 64 (column, value) pairs of the row at once and broadcasts them
+// with cross-lane shuffles, so the gathers of four nonzeros are in flight together.
 template <typename T>
 __global__ __launch_bounds__(256) void k_bspmm(const BGraph* __restrict__ graphs,
                                                const int32_t* __restrict__ sblk_graph,
@@ -86,14 +88,40 @@ __global__ __launch_bounds__(256) void k_bspmm(const BGraph* __restrict__ graphs
     const int64_t b = rowptr[row], e = rowptr[row + 1];
     for (int c0 = 0; c0 < width; c0 += cw) {
       const int cc = c0 + c;
-      const int s = cc / r, j = cc - (cc / r) * r;
+      const bool cok = cc < width;
+      const int s = cok ? cc / r : 0;
+      const int j = cc - s * r;
+      const T* __restrict__ Ps = Pg + s * nr + j;
       T acc = T(0);
-      if (cc < width) {
-        const T* __restrict__ Ps = Pg + s * nr + j;
-        for (int64_t z = b + slot; z < e; z += ns) acc += val[z] * Ps[(int64_t)col[z] * r];
+      for (int64_t zb = b; zb < e; zb += kWave) {
+        const int cnt = e - zb < kWave ? (int)(e - zb) : kWave;
+        const int mc = lane < cnt ? col[zb + lane] : 0;
+        const T mv = lane < cnt ? val[zb + lane] : T(0);
+        for (int k0 = 0; k0 < cnt; k0 += 4 * ns) {  // uniform trip count: all lanes shuffle
+          int ck[4];
+          T vk[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int k = k0 + slot + u * ns;
+            const int src = k < kWave ? k : kWave - 1;
+            ck[u] = __shfl(mc, src, kWave);
+            vk[u] = __shfl(mv, src, kWave);
+          }
+          T pk[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int k = k0 + slot + u * ns;
+            pk[u] = (cok && k < cnt) ? Ps[(int64_t)ck[u] * r] : T(0);
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int k = k0 + slot + u * ns;
+            if (k < cnt) acc += vk[u] * pk[u];
+          }
+        }
       }
       for (int o = cw; o < kWave; o <<= 1) acc += __shfl_xor(acc, o, kWave);
-      if (slot == 0 && cc < width) Bg[s * nr + row * r + j] = acc;
+      if (slot == 0 && cok) Bg[s * nr + row * r + j] = acc;
     }
   }
 }

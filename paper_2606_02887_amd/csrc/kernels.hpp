@@ -26,9 +26,11 @@ void launch_gram(const T* P, int64_t n, int r, double* part, int nblk, double* G
                  const State* st, hipStream_t s);
 void launch_rho(const double* G, int r, State* st, hipStream_t s);
 template <typename T>
-void launch_bgram(const T* P, const int32_t* gblk_inst, int gblocks, const BInst* inst, int ninst,
-                  int max_r, const State* states, double* gpart, double* G64, T* GT,
-                  hipStream_t s);
+void launch_bgram(const T* P, int r, const int32_t* gblk_inst, int gblocks, const BInst* inst,
+                  const State* states, double* gpart, hipStream_t s);
+template <typename T>
+void launch_bgram_reduce(const BInst* inst, int ninst, const State* states, const double* gpart,
+                         double* G64, T* GT, hipStream_t s);
 void launch_brho(const BInst* inst, int ninst, State* states, const double* G64, hipStream_t s);
 template <typename T>
 void launch_norm2(const T* x, int64_t N, double* part, double* out, unsigned* counter,

@@ -161,6 +161,24 @@ def test_batch_per_instance_target_stop(S):
     assert 1 <= infos[0]["converged_at"] <= 10
 
 
+def test_batch_breakdown_stays_in_its_instance(S):
+    """A zero start makes G = 0 and rho = 0 in restart 1 (a breakdown); restart 0 of the
+    same problem and the other problem must still follow the oracle."""
+    graphs = _graphs(1500, [(180, 5), (120, 4)], restarts=2)
+    As, a_in, W0s, w_in = _batch_inputs(S, graphs, torch.float64)
+    W0s[0][1].zero_()
+    lams = [O.default_lambda(a) for a in a_in]
+    with S.Batch(As, [5, 4], S.params(prec=S.F64, max_outer=15), restarts=2, lam=lams) as b:
+        Ws, Hs, infos, _ = b.solve(W0s)
+    names = {v: k for k, v in S.STATUS.items()}
+    assert infos[1]["status"] == names["E_BREAKDOWN"]
+    for i in (0, 2, 3):
+        g, s = divmod(i, 2)
+        _, _, hist = O.snmpbb(a_in[g], w_in[g][s], O.Params(lam=lams[g]), 15)
+        assert infos[i]["status"] == 0 and infos[i]["outer"] == 15
+        assert abs(infos[i]["res_WH"] - hist[-1]["res_WH"]) <= 1e-9 * hist[-1]["res_WH"]
+
+
 def test_batch_graph_replay_equals_direct(S):
     graphs = _graphs(1700, SHAPES[:3], restarts=2)
     As, a_in, W0s, _ = _batch_inputs(S, graphs, torch.float32)
