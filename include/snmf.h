@@ -229,6 +229,57 @@ snmf_status snmf_batch_apass(snmf_batch* b, const void* P, void* B, void* stream
 /* Number of instances and the total element count sum_g S n_g r_g of a batch buffer. */
 snmf_status snmf_batch_size(const snmf_batch* b, int32_t* ninst, int64_t* elements);
 
+/* ---------------------------------------------------------------- learned warm start
+ * Not in the paper (its closest analogue is the SVD-based start of Section 4.2).  A start
+ * W0 for each instance of a batch (CSR problems) from a Gaussian sketch Omega:
+ *   Y = A Omega; SPA (successive projection, Gillis & Vavasis 2014) on the rows Y_i / d_i,
+ *   d = A 1, gives r anchor rows K; C = Y Y_K^T (Y_K Y_K^T + eps I)^{-1},
+ *   eps = 1e-12 tr(Y_K Y_K^T) / r (the coordinates in the anchor frame);
+ *   W0_i = s softplus(M2 relu(M1 c_i + b1) + b2), s = (sqrt(r) ||A||_F / (n r))^(1/2).
+ * The network (one per rank r) is trained on converged factors whose columns are matched
+ * to the anchor order (linear assignment on column cosines) and divided by s; the loss is
+ * mean((y - t)^2) + mu (mean(y^2) - mean(t^2))^2, the optimiser Adam (beta1 0.9, beta2
+ * 0.999, eps 1e-8).  All arrays below are device arrays; the caller owns them. */
+typedef struct snmf_mlp {
+  int32_t r;          /* 1..64 */
+  int32_t hidden;     /* must be 128 */
+  float* M1;          /* hidden x r, FP32 master weights */
+  float* b1;          /* hidden */
+  float* M2;          /* r x hidden */
+  float* b2;          /* r */
+  uint16_t* M1h;      /* BF16 (round to nearest even) copies of M1, M2 used by the forward */
+  uint16_t* M2h;
+  float* adam_m;      /* Adam moments, 2 hidden r + hidden + r floats each, in the order */
+  float* adam_v;      /*   M1, b1, M2, b2 (needed by training only; zero before step 1) */
+} snmf_mlp;
+/* Refresh M1h, M2h from M1, M2. */
+snmf_status snmf_mlp_sync(const snmf_mlp* m, void* stream);
+/* Y (rows x r) = row_scale[i] * net(C_i) for every row (row_scale NULL: scale 1). */
+snmf_status snmf_mlp_forward(const snmf_mlp* m, int64_t rows, const float* C,
+                             const float* row_scale, float* Y, void* stream);
+/* One training step on the `batch` rows idx[0..batch) of the row pools C and T
+ * (pool_rows x r each; indices outside [0, pool_rows) are clamped into it): loss,
+ * gradients reduced in a fixed order, Adam step number `step` (from 1), BF16 copies
+ * refreshed.  work: device scratch of snmf_mlp_workspace_bytes(r, batch) bytes.
+ * loss (host, optional): the minibatch loss before the update (synchronises). */
+size_t snmf_mlp_workspace_bytes(int32_t r, int64_t batch);
+snmf_status snmf_mlp_train_step(const snmf_mlp* m, int64_t pool_rows, const float* C,
+                                const float* T, const int32_t* idx, int64_t batch, float mu,
+                                float lr, int32_t step, void* work, size_t work_bytes,
+                                void* stream, double* loss);
+/* The frame of every instance of a CSR batch: Omega, Y, C are batch buffers (the
+ * instance-major layout of snmf_batch_apass); anchors (optional): 64 ints per instance. */
+snmf_status snmf_batch_frame(snmf_batch* b, const void* Omega, void* Y, void* C,
+                             int32_t* anchors, void* stream);
+/* Training targets: T[:, j] = Ht[:, p[j]] / s per instance, p the column assignment
+ * maximising sum_j cos(C_j, Ht_p[j]); perm (optional): 64 ints per instance. */
+snmf_status snmf_batch_targets(snmf_batch* b, const void* C, const void* Ht, void* T,
+                               int32_t* perm, void* stream);
+/* W0 (batch buffer) for every instance: frame of Omega, then the network whose r matches
+ * the instance's rank (E_ARG if none).  FP32 batches only. */
+snmf_status snmf_batch_warmstart(snmf_batch* b, int32_t nmodels, const snmf_mlp* models,
+                                 const void* Omega, void* W0, void* stream);
+
 /* Device clock rate (Hz) of the trace ticks and info.seconds. */
 double snmf_clock_rate_hz(void);
 const char* snmf_last_error(void);

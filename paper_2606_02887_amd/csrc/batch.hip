@@ -22,75 +22,11 @@
 
 #include "../../include/snmf.h"
 #include "common.hpp"
+#include "batch_impl.hpp"
 #include "host.hpp"
 #include "kernels.hpp"
 
 using namespace snmf;
-
-struct snmf_batch {
-  int nprob = 0, S = 1, ninst = 0, prec = SNMF_F32;
-  size_t esz = 4;
-  bool dense = false;
-  snmf_params p{};
-  KParams kp{};
-  std::vector<snmf_matrix> A;
-  std::vector<int> r;
-  std::vector<int64_t> n;
-  std::vector<double> normA2;
-  std::vector<BInst> hinst;
-  std::vector<BGraph> hgraph;
-  std::vector<DenseSplit> ds;
-  struct Cls {
-    int r = 0;
-    int blocks = 0;        // inner-kernel workgroups
-    int64_t tab_off = 0;   // their first entry in blk_tab
-    int gblocks = 0;       // Gram workgroups
-    int64_t gtab_off = 0;  // their first entry in gblk_tab
-  };
-  std::vector<Cls> cls;
-  int gblocks = 0, sblocks = 0, max_r = 0, part_rows = 0;
-  int64_t total = 0, max_nr = 0, gsum = 0, gpsum = 0;
-  int ksplit_max = 1;
-  int64_t trace_stride = 0;
-  hipStream_t s = nullptr, side = nullptr;
-  hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_fork = nullptr, ev_join = nullptr;
-  void* pool = nullptr;
-  void *Wb = nullptr, *Hb = nullptr, *C = nullptr, *g = nullptr, *Z = nullptr, *D = nullptr;
-  void *B = nullptr, *Bpart = nullptr, *GT[2] = {nullptr, nullptr};
-  double* G64[2] = {nullptr, nullptr};
-  double *gpart = nullptr, *partsA = nullptr, *partsB = nullptr, *partsC = nullptr;
-  double *traces = nullptr, *part = nullptr, *dots = nullptr;
-  State* states = nullptr;
-  int32_t* flag = nullptr;
-  unsigned *counters = nullptr, *flags = nullptr;
-  BInst* dinst = nullptr;
-  int32_t *blk_tab = nullptr, *gblk_tab = nullptr, *sblk_tab = nullptr;
-  BGraph* dgraph = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t gexec = nullptr;
-
-  BMap bmap(const Cls& c) const {
-    BMap m{};
-    m.blk_inst = blk_tab + c.tab_off;
-    m.inst = dinst;
-    m.states = states;
-    m.traces = traces;
-    m.trace_stride = trace_stride;
-    return m;
-  }
-
-  ~snmf_batch() {
-    if (gexec) (void)hipGraphExecDestroy(gexec);
-    if (graph) (void)hipGraphDestroy(graph);
-    if (pool) (void)hipFree(pool);
-    if (ev_in) (void)hipEventDestroy(ev_in);
-    if (ev_out) (void)hipEventDestroy(ev_out);
-    if (ev_fork) (void)hipEventDestroy(ev_fork);
-    if (ev_join) (void)hipEventDestroy(ev_join);
-    if (side) (void)hipStreamDestroy(side);
-    if (s) (void)hipStreamDestroy(s);
-  }
-};
 
 namespace {
 
@@ -568,6 +504,11 @@ snmf_status batch_solve(snmf_batch* b, const void* const* W0, void* const* W_out
 }
 
 }  // namespace
+
+snmf_status batch_apass_async(snmf_batch* b, const void* P, void* B, hipStream_t s) {
+  if (b->prec == SNMF_F64) return bapass<double>(b, (const double*)P, (double*)B, s);
+  return bapass<float>(b, (const float*)P, (float*)B, s);
+}
 
 extern "C" {
 

@@ -18,6 +18,33 @@ struct DenseSplit {
 };
 
 int rank_pad(int r);
+
+// ---- learned warm start
+constexpr int kMlpHidden = 128;  // hidden width of the warm-start network
+struct MlpDev {                  // device view of a warm-start network r -> 128 -> r
+  int32_t r;
+  float *M1, *b1, *M2, *b2;      // FP32 masters: M1 H x r, b1 H, M2 r x H, b2 r
+  uint16_t *M1h, *M2h;           // BF16 copies used by the forward pass
+  float *mom, *vel;              // Adam moments (order M1, b1, M2, b2)
+};
+struct MlpWork {                 // per-minibatch scratch of a training step
+  float *y, *cache_a, *cache_o, *dO, *dA, *grad;
+  double* part;                  // kMaxGrid x kNumPart loss partials; part[kMaxGrid*kNumPart]: loss
+};
+int mlp_params(int r);
+void launch_mlp_sync(const MlpDev& m, hipStream_t s);
+void launch_mlp_forward(const MlpDev& m, int64_t N, const float* C, const float* row_scale,
+                        float* Y, const BMap& bm, int grid, const int32_t* idx, int64_t pool,
+                        float* cache_a, float* cache_o, hipStream_t s);
+void launch_mlp_train_step(const MlpDev& m, int64_t pool, int64_t B, const float* C,
+                           const float* T, const int32_t* idx, float mu, float lr, int step,
+                           const MlpWork& w, hipStream_t s);
+template <typename T>
+void launch_ws_frame(const BInst* inst, int ninst, int max_r, const BGraph* graphs, const T* Y,
+                     double* R, T* C, int32_t* anchors, hipStream_t s);
+template <typename T>
+void launch_ws_match(const BInst* inst, int ninst, const T* C, const T* H, T* Tout, int32_t* perm,
+                     hipStream_t s);
 int inner_grid(int64_t n, int r);
 int lai_blocks(int64_t n);
 

@@ -316,3 +316,20 @@ def config(c: int, **over):
     if c == 4:
         return batched_sbm(seed=seed, **over)
     raise ValueError(f"unknown workload {c}")
+
+
+# --------------------------------------------------------------------------- warm start
+def sketch_matrix(n: int, r: int, seed: int):
+    """Gaussian sketch Omega (n x r, float64) for the warm start's Y = A Omega."""
+    return np.random.default_rng(seed).standard_normal((n, r))
+
+
+def mlp_init(r: int, hidden: int = 128, seed: int = SEED_BASE + 16):
+    """Initial weights of the warm-start network r -> hidden -> r: He-normal M1, M2 scaled
+    by 1/sqrt(fan_in) x 0.5, zero b1 and b2 = log(e - 1) (softplus(b2) = 1 for zero input:
+    the untrained net returns the unit-scale start)."""
+    rng = np.random.default_rng(seed)
+    return {"M1": rng.standard_normal((hidden, r)) * np.sqrt(2.0 / r),
+            "b1": np.zeros(hidden),
+            "M2": rng.standard_normal((r, hidden)) * (0.5 / np.sqrt(hidden)),
+            "b2": np.full(r, np.log(np.e - 1.0))}

@@ -58,12 +58,20 @@ class Info(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
+class MlpC(ctypes.Structure):
+    _fields_ = [("r", c_int32), ("hidden", c_int32), ("M1", c_void_p), ("b1", c_void_p),
+                ("M2", c_void_p), ("b2", c_void_p), ("M1h", c_void_p), ("M2h", c_void_p),
+                ("adam_m", c_void_p), ("adam_v", c_void_p)]
+
+
 EXPORTS = ("snmf_params_default", "snmf_solve", "snmf_plan_create", "snmf_plan_solve",
            "snmf_plan_destroy", "snmf_plan_half_step", "snmf_plan_apass", "snmf_plan_gram",
            "snmf_plan_time_apass", "snmf_rho", "snmf_spmm", "snmf_split_bf16",
            "snmf_batch_create", "snmf_batch_solve", "snmf_batch_destroy", "snmf_solve_batched",
-           "snmf_batch_apass", "snmf_batch_size", "snmf_clock_rate_hz", "snmf_last_error",
-           "snmf_abi_version")
+           "snmf_batch_apass", "snmf_batch_size", "snmf_mlp_sync", "snmf_mlp_forward",
+           "snmf_mlp_workspace_bytes", "snmf_mlp_train_step", "snmf_batch_frame",
+           "snmf_batch_targets", "snmf_batch_warmstart", "snmf_clock_rate_hz",
+           "snmf_last_error", "snmf_abi_version")
 
 
 def load_library(path: str = LIB_PATH):
@@ -95,6 +103,15 @@ def load_library(path: str = LIB_PATH):
                                 POINTER(Info), vp, POINTER(c_double)], c_int32),
         "snmf_batch_apass": ([vp, vp, vp, vp], c_int32),
         "snmf_batch_size": ([vp, POINTER(c_int32), POINTER(c_int64)], c_int32),
+        "snmf_mlp_sync": ([POINTER(MlpC), vp], c_int32),
+        "snmf_mlp_forward": ([POINTER(MlpC), c_int64, vp, vp, vp, vp], c_int32),
+        "snmf_mlp_workspace_bytes": ([c_int32, c_int64], ctypes.c_size_t),
+        "snmf_mlp_train_step": ([POINTER(MlpC), c_int64, vp, vp, vp, c_int64, ctypes.c_float,
+                                 ctypes.c_float, c_int32, vp, ctypes.c_size_t, vp,
+                                 POINTER(c_double)], c_int32),
+        "snmf_batch_frame": ([vp, vp, vp, vp, vp, vp], c_int32),
+        "snmf_batch_targets": ([vp, vp, vp, vp, vp, vp], c_int32),
+        "snmf_batch_warmstart": ([vp, c_int32, POINTER(MlpC), vp, vp, vp], c_int32),
         "snmf_clock_rate_hz": ([], c_double),
         "snmf_last_error": ([], ctypes.c_char_p),
         "snmf_abi_version": ([], c_int32),
@@ -299,6 +316,45 @@ class Batch:
         _check(_lib.snmf_batch_apass(self._h, _ptr(P), _ptr(B), _stream()))
         return B
 
+    def offsets(self):
+        """Element offset of every problem's block (restart 0) in a batch buffer."""
+        out, at = [], 0
+        for n, r in zip(self.n, self.r):
+            out.append(at)
+            at += self.S * n * r
+        return out
+
+    def split(self, buf):
+        """Per-problem (S, n_g, r_g) views of a batch buffer."""
+        return [buf[o: o + self.S * n * r].view(self.S, n, r)
+                for o, n, r in zip(self.offsets(), self.n, self.r)]
+
+    def frame(self, Omega):
+        """Sketch Y = A Omega and anchor-frame coordinates C (batch buffers), anchors."""
+        import torch
+        Y = torch.empty_like(Omega)
+        C = torch.empty_like(Omega)
+        anc = torch.empty((self.ninst, 64), dtype=torch.int32, device=Omega.device)
+        _check(_lib.snmf_batch_frame(self._h, _ptr(Omega), _ptr(Y), _ptr(C), _ptr(anc),
+                                     _stream()))
+        return Y, C, anc
+
+    def targets(self, C, Ht):
+        import torch
+        T = torch.empty_like(C)
+        perm = torch.empty((self.ninst, 64), dtype=torch.int32, device=C.device)
+        _check(_lib.snmf_batch_targets(self._h, _ptr(C), _ptr(Ht), _ptr(T), _ptr(perm),
+                                       _stream()))
+        return T, perm
+
+    def warmstart(self, models, Omega):
+        import torch
+        W0 = torch.empty_like(Omega)
+        arr = (MlpC * len(models))(*[m.desc for m in models])
+        _check(_lib.snmf_batch_warmstart(self._h, len(models), arr, _ptr(Omega), _ptr(W0),
+                                         _stream()))
+        return W0
+
     def close(self):
         if getattr(self, "_h", None):
             _lib.snmf_batch_destroy(self._h)
@@ -315,6 +371,55 @@ class Batch:
 
     def __exit__(self, *a):
         self.close()
+
+
+class Mlp:
+    """A warm-start network r -> 128 -> r in device memory (FP32 masters, BF16 copies,
+    Adam moments), initialised from host arrays {M1, b1, M2, b2}."""
+
+    def __init__(self, init, device="cuda"):
+        import torch
+        M1 = np.asarray(init["M1"], dtype=np.float32)
+        self.r = int(M1.shape[1])
+        self.hidden = int(M1.shape[0])
+        f = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(device)
+        self.M1, self.b1, self.M2, self.b2 = f(init["M1"]), f(init["b1"]), f(init["M2"]), f(init["b2"])
+        self.M1h = torch.empty(self.M1.shape, dtype=torch.int16, device=device)
+        self.M2h = torch.empty(self.M2.shape, dtype=torch.int16, device=device)
+        n = 2 * self.hidden * self.r + self.hidden + self.r
+        self.adam_m = torch.zeros(n, dtype=torch.float32, device=device)
+        self.adam_v = torch.zeros(n, dtype=torch.float32, device=device)
+        self.desc = MlpC(self.r, self.hidden, self.M1.data_ptr(), self.b1.data_ptr(),
+                         self.M2.data_ptr(), self.b2.data_ptr(), self.M1h.data_ptr(),
+                         self.M2h.data_ptr(), self.adam_m.data_ptr(), self.adam_v.data_ptr())
+        self.step = 0
+        self._work = None
+        _check(_lib.snmf_mlp_sync(ctypes.byref(self.desc), _stream()))
+
+    def params(self):
+        return {k: getattr(self, k).double().cpu().numpy() for k in ("M1", "b1", "M2", "b2")}
+
+    def forward(self, C, row_scale=None):
+        import torch
+        Y = torch.empty_like(C)
+        _check(_lib.snmf_mlp_forward(ctypes.byref(self.desc), C.shape[0], _ptr(C),
+                                     _ptr(row_scale), _ptr(Y), _stream()))
+        return Y
+
+    def train_step(self, C, T, idx, mu, lr, want_loss=False):
+        import torch
+        B = int(idx.numel())
+        need = _lib.snmf_mlp_workspace_bytes(self.r, B)
+        if self._work is None or self._work.numel() < need:
+            self._work = torch.empty(need, dtype=torch.uint8, device=C.device)
+        self.step += 1
+        loss = c_double(0.0)
+        _check(_lib.snmf_mlp_train_step(ctypes.byref(self.desc), C.shape[0], _ptr(C), _ptr(T),
+                                        _ptr(idx), B,
+                                        float(mu), float(lr), self.step, _ptr(self._work),
+                                        self._work.numel(), _stream(),
+                                        ctypes.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
 
 
 def solve(A: MatrixRef, W0, prm: Params, L: MatrixRef | None = None, trace: bool = True):

@@ -19,7 +19,7 @@ def S():
 
 def _declared_functions():
     txt = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:snmf_status|double|const char\*|int32_t)\s+(snmf_\w+)\s*\(",
+    return sorted(set(re.findall(r"^\s*(?:snmf_status|double|const char\*|int32_t|size_t)\s+(snmf_\w+)\s*\(",
                                  txt, re.M)))
 
 
@@ -42,6 +42,7 @@ def test_struct_layout_matches_c(S, tmp_path):
         "snmf_params": ["gamma", "L", "eta", "beta_shrink", "max_ls", "check_every",
                         "target_res", "prec", "use_graph"],
         "snmf_info": ["inner_total", "ls_exhausted", "res_WH", "seconds_to_target", "normA2"],
+        "snmf_mlp": ["hidden", "M1", "b1", "M2", "b2", "M1h", "M2h", "adam_m", "adam_v"],
     }
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "snmf.h"', 'int main(void){']
     for st, fields in checks.items():
@@ -53,7 +54,8 @@ def test_struct_layout_matches_c(S, tmp_path):
     exe = tmp_path / "layout"
     subprocess.check_call([gcc, "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)])
     out = dict(l.split() for l in subprocess.check_output([str(exe)]).decode().splitlines())
-    py = {"snmf_matrix": S.Matrix, "snmf_params": S.Params, "snmf_info": S.Info}
+    py = {"snmf_matrix": S.Matrix, "snmf_params": S.Params, "snmf_info": S.Info,
+          "snmf_mlp": S.MlpC}
     for st, cls in py.items():
         assert int(out[st]) == ctypes.sizeof(cls)
         for f in checks[st]:

@@ -1,0 +1,214 @@
+"""GPU parity of the learned warm start against the oracle (oracle/warmstart.py).
+
+Frame (sketch, SPA anchors, coordinates), column matching of the targets, the network's
+forward pass, one training step (the gradient is read back from Adam's first moment,
+m = (1 - beta1) g after step 1) and the batched warm start end to end.  Where a
+floating-point comparison decides an integer (the SPA argmax, the assignment), the oracle
+is run on the device's own floating-point inputs and must take the same decisions.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import warmstart as WS
+from paper_2606_02887_amd import gen
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+DT = {"f64": torch.float64, "f32": torch.float32}
+
+
+@pytest.fixture(scope="module")
+def S():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2606_02887_amd import snmf
+    return snmf
+
+
+def nrel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    d = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (d if d > 0 else 1.0)
+
+
+SHAPES = [(140, 3), (261, 8), (300, 16), (90, 5)]
+
+
+def _setup(S, dt, shapes=SHAPES, restarts=2, seed=31):
+    graphs, As, a_in = [], [], []
+    for g, (n, r) in enumerate(shapes):
+        rng = np.random.default_rng(seed + g)
+        adj, _ = gen.sbm_adjacency(n, r, 0.3, 0.02, rng)
+        a = gen.normalized_adjacency(adj)
+        As.append(S.csr_from_scipy(a, dt))
+        b = a.copy()
+        b.data = torch.from_numpy(a.data).to(dt).double().numpy()
+        a_in.append(b)
+        graphs.append((n, r))
+    om = []
+    for g, (n, r) in enumerate(shapes):
+        for s in range(restarts):
+            om.append(gen.sketch_matrix(n, r, 500 + 10 * g + s).ravel())
+    Omega = torch.from_numpy(np.concatenate(om)).to(DEV, dt)
+    return graphs, As, a_in, Omega
+
+
+def _blocks(buf, graphs, restarts):
+    out, at = [], 0
+    for n, r in graphs:
+        for _ in range(restarts):
+            out.append(buf[at: at + n * r].reshape(n, r))
+            at += n * r
+    return out
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_frame_matches_oracle(S, prec):
+    dt = DT[prec]
+    graphs, As, a_in, Omega = _setup(S, dt)
+    p = S.F64 if prec == "f64" else S.F32
+    with S.Batch(As, [r for _, r in graphs], S.params(prec=p), restarts=2) as b:
+        Y, C, anc = b.frame(Omega)
+    Yb = _blocks(Y.double().cpu().numpy(), graphs, 2)
+    Cb = _blocks(C.double().cpu().numpy(), graphs, 2)
+    Ob = _blocks(Omega.double().cpu().numpy(), graphs, 2)
+    anc = anc.cpu().numpy()
+    ytol, ctol = (1e-12, 1e-9) if prec == "f64" else (1e-5, 1e-5)
+    for i in range(len(Yb)):
+        g = i // 2
+        n, r = graphs[g]
+        assert nrel(Yb[i], WS.sketch(a_in[g], Ob[i])) <= ytol, i
+        # decisions taken on the device's own sketch
+        K = WS.spa(WS.row_normalise(Yb[i], WS.row_sums(a_in[g])), r)
+        assert list(anc[i, :r]) == K, i
+        assert nrel(Cb[i], WS.coords(Yb[i], K)) <= ctol, i
+        assert np.allclose(Cb[i][K], np.eye(r), atol=1e-6 if prec == "f64" else 1e-3)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_targets_match_oracle(S, prec):
+    dt = DT[prec]
+    graphs, As, a_in, Omega = _setup(S, dt, seed=77)
+    p = S.F64 if prec == "f64" else S.F32
+    with S.Batch(As, [r for _, r in graphs], S.params(prec=p), restarts=2) as b:
+        _, C, _ = b.frame(Omega)
+        rng = np.random.default_rng(4)
+        Cn = C.double().cpu().numpy()
+        Hs = []
+        for i, Ci in enumerate(_blocks(Cn, graphs, 2)):
+            n, r = graphs[i // 2]
+            Hs.append((np.abs(Ci[:, rng.permutation(r)]) * rng.uniform(0.5, 2, r)
+                       + 1e-3 * rng.random((n, r))).ravel())
+        Ht = torch.from_numpy(np.concatenate(Hs)).to(DEV, dt)
+        T, perm = b.targets(C, Ht)
+    Tb = _blocks(T.double().cpu().numpy(), graphs, 2)
+    Hb = _blocks(Ht.double().cpu().numpy(), graphs, 2)
+    Cb = _blocks(Cn, graphs, 2)
+    perm = perm.cpu().numpy()
+    for i in range(len(Tb)):
+        g = i // 2
+        n, r = graphs[g]
+        pi = WS.match_columns(Cb[i], Hb[i])
+        assert list(perm[i, :r]) == list(pi), i
+        s = WS.scale(np.sqrt(O.norm2_A(a_in[g])), n, r)
+        assert nrel(Tb[i], Hb[i][:, pi] / s) <= (1e-12 if prec == "f64" else 1e-6), i
+
+
+def _rand_init(r, seed):
+    rng = np.random.default_rng(seed)
+    init = gen.mlp_init(r, 128, seed)
+    init["b1"] = 0.1 * rng.standard_normal(128)
+    init["b2"] = 0.3 * rng.standard_normal(r)
+    return init
+
+
+@pytest.mark.parametrize("r", [3, 8, 16, 32, 64])
+def test_mlp_forward_matches_oracle(S, r):
+    m = S.Mlp(_rand_init(r, 10 + r))
+    rng = np.random.default_rng(r)
+    N = 1000 + 37
+    C = rng.standard_normal((N, r))
+    sc = rng.uniform(0.5, 2.0, N)
+    Ct = torch.from_numpy(C).to(DEV, torch.float32)
+    Y = m.forward(Ct, torch.from_numpy(sc).to(DEV, torch.float32)).double().cpu().numpy()
+    prm = m.params()
+    yo, _ = WS.forward(prm, Ct.double().cpu().numpy())
+    assert nrel(Y, sc.astype(np.float32).astype(np.float64)[:, None] * yo) <= 2e-6
+    # the BF16 copies are the round-to-nearest-even values of the FP32 masters
+    bits = m.M1h.cpu().numpy().astype(np.uint16).astype(np.uint32) << 16
+    assert np.array_equal(bits.view(np.float32).astype(np.float64), WS.bf16_round(prm["M1"]))
+
+
+@pytest.mark.parametrize("r", [4, 16, 32])
+def test_mlp_train_step_gradient_and_adam(S, r):
+    m = S.Mlp(_rand_init(r, 40 + r))
+    prm0 = m.params()
+    rng = np.random.default_rng(7 + r)
+    N, B, mu, lr = 900, 333, 0.5, 1e-3
+    C = rng.standard_normal((N, r))
+    T = rng.random((N, r))
+    idx = rng.choice(N, size=B, replace=False).astype(np.int32)
+    Ct = torch.from_numpy(C).to(DEV, torch.float32)
+    Tt = torch.from_numpy(T).to(DEV, torch.float32)
+    loss = m.train_step(Ct, Tt, torch.from_numpy(idx).to(DEV), mu, lr, want_loss=True)
+    Cin, Tin = Ct.double().cpu().numpy()[idx], Tt.double().cpu().numpy()[idx]
+    lo, go = WS.loss_and_grad(prm0, Cin, Tin, mu)
+    assert abs(loss - lo) <= 1e-5 * abs(lo)
+    b1c = float(np.float32(1) - np.float32(0.9))       # (1 - beta1) and (1 - beta2) as the
+    b2c = float(np.float32(1) - np.float32(0.999))     # device forms them in FP32
+    gdev = m.adam_m.double().cpu().numpy() / b1c       # m = (1 - beta1) g after step 1
+    H = 128
+    parts = {"M1": gdev[:H * r].reshape(H, r), "b1": gdev[H * r:H * r + H],
+             "M2": gdev[H * r + H:H * r + H + r * H].reshape(r, H), "b2": gdev[-r:]}
+    for k in ("M1", "b1", "M2", "b2"):
+        assert nrel(parts[k], go[k]) <= 1e-4, k
+    prm1 = m.params()
+    v = m.adam_v.double().cpu().numpy()
+    mm = m.adam_m.double().cpu().numpy()
+    assert np.allclose(v, b2c * (mm / b1c) ** 2, rtol=1e-5, atol=1e-30)
+    flat0 = np.concatenate([prm0[k].ravel() for k in ("M1", "b1", "M2", "b2")])
+    flat1 = np.concatenate([prm1[k].ravel() for k in ("M1", "b1", "M2", "b2")])
+    ref, _, _ = WS.adam_step(flat0, mm / b1c, np.zeros_like(mm), np.zeros_like(mm), 1, lr)
+    assert np.max(np.abs(flat1 - ref)) <= 1e-6
+    bits = m.M2h.cpu().numpy().astype(np.uint16).astype(np.uint32) << 16
+    assert np.array_equal(bits.view(np.float32).astype(np.float64), WS.bf16_round(prm1["M2"]))
+
+
+def test_batch_warmstart_end_to_end(S):
+    graphs, As, a_in, Omega = _setup(S, torch.float32, seed=91)
+    ranks = sorted({r for _, r in graphs})
+    models = [S.Mlp(_rand_init(r, 200 + r)) for r in ranks]
+    with S.Batch(As, [r for _, r in graphs], S.params(prec=S.F32), restarts=2) as b:
+        _, C, _ = b.frame(Omega)
+        W0 = b.warmstart(models, Omega)
+    Cb = _blocks(C.double().cpu().numpy(), graphs, 2)
+    Wb = _blocks(W0.double().cpu().numpy(), graphs, 2)
+    for i in range(len(Cb)):
+        g = i // 2
+        n, r = graphs[g]
+        prm = models[ranks.index(r)].params()
+        s = WS.scale(np.sqrt(O.norm2_A(a_in[g])), n, r)
+        yo, _ = WS.forward(prm, Cb[i])
+        assert nrel(Wb[i], s * yo) <= 2e-6, i
+        assert (Wb[i] > 0).all()
+
+
+def test_warmstart_error_codes(S):
+    graphs, As, _, Omega = _setup(S, torch.float32, shapes=[(80, 4)], restarts=1)
+    with S.Batch(As, [4], S.params(prec=S.F32), restarts=1) as b:
+        with pytest.raises(S.SnmfError) as e:
+            b.warmstart([S.Mlp(_rand_init(5, 1))], Omega)
+        assert e.value.name == "E_ARG"
+    _, As64, _, Om64 = _setup(S, torch.float64, shapes=[(80, 4)], restarts=1)
+    with S.Batch(As64, [4], S.params(prec=S.F64), restarts=1) as b:
+        with pytest.raises(S.SnmfError) as e:
+            b.warmstart([S.Mlp(_rand_init(4, 1))], Om64)
+        assert e.value.name == "E_UNSUPPORTED"
+    A = torch.eye(40, dtype=torch.float32, device=DEV)
+    with S.Batch([S.dense(A)], [4], S.params(prec=S.F32), restarts=1) as b:
+        with pytest.raises(S.SnmfError) as e:
+            b.frame(torch.ones(160, dtype=torch.float32, device=DEV))
+        assert e.value.name == "E_UNSUPPORTED"
