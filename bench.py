@@ -35,9 +35,13 @@ def _args():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-outer", type=int, default=0,
                     help="outer iterations of the CPU-reference sample (0: pick ~15 s)")
-    ap.add_argument("--workload", choices=("c1", "c4"), default="c1",
+    ap.add_argument("--workload", choices=("c1", "c4", "c4ws"), default="c1",
                     help="c1: dense n=8192, r=64 (the headline line); c4: 256 SBM graphs, "
-                         "8 restarts each, in one batched solve")
+                         "8 restarts each, in one batched solve; c4ws: the learned warm start "
+                         "(trained here) against random starts and the frame alone on c4")
+    ap.add_argument("--train-graphs", type=int, default=2048)
+    ap.add_argument("--train-outer", type=int, default=300)
+    ap.add_argument("--epochs", type=int, default=4)
     ap.add_argument("--apass-only", action="store_true",
                     help="only a 256 MiB device copy (the counter scale reference) and 20 "
                          "A-pass launches of each form; for hardware-counter runs")
@@ -179,6 +183,108 @@ def _bench_c4(a, torch, np, S, gen):
     print(json.dumps(out))
 
 
+def _arm_stats(np, graphs, restarts, infos, tr, hz, taus, extra_s=0.0):
+    its, secs, reached, frac = [], [], 0, []
+    for g in range(len(graphs)):
+        best, nhit = None, 0
+        for s_ in range(restarts):
+            i = g * restarts + s_
+            if infos[i]["status"] != 0 or infos[i]["outer"] < 1:
+                continue
+            k = infos[i]["outer"]
+            hit = np.nonzero(tr[i, :k, 0] <= taus[g])[0]
+            if hit.size:
+                nhit += 1
+                cand = (int(hit[0]), tr[i, hit[0], 5] / hz)
+                best = cand if best is None or cand < best else best
+        frac.append(nhit / restarts)
+        if best is not None:
+            reached += 1
+            its.append(best[0] + 1)
+            secs.append(best[1] + extra_s)
+    return {"graphs_reaching": reached, "median_outer": float(np.median(its)) if its else None,
+            "mean_outer": float(np.mean(its)) if its else None,
+            "median_seconds": float(np.median(secs)) if secs else None,
+            "fraction_of_starts_reaching": float(np.mean(frac))}
+
+
+def _bench_c4ws(a, torch, np, S, gen):
+    """Learned warm start on the 256-graph workload: train the per-rank networks on
+    separately seeded graphs, then time-to-target of random, frame-only and learned starts
+    (8 starts per graph each).  tau_g = (1 + 1e-4) x best random-start residual."""
+    from paper_2606_02887_amd import train_ws
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    train_graphs = gen.batched_sbm(num_graphs=a.train_graphs, restarts=1, seed=20000)
+    t_gen = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    pools = train_ws.training_pools(S, torch, train_graphs, outer=a.train_outer)
+    torch.cuda.synchronize()
+    t_pool = time.perf_counter() - t0
+    log = []
+    t0 = time.perf_counter()
+    models = train_ws.train(S, torch, pools, epochs=a.epochs, log=log)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    graphs = gen.config(4)
+    restarts = len(graphs[0]["W0"])
+    As = [S.csr_from_scipy(g["A"], torch.float32) for g in graphs]
+    rs = [g["r"] for g in graphs]
+    lams = train_ws.lambdas(graphs)
+    W0r = torch.from_numpy(np.concatenate([np.stack(g["W0"]).ravel() for g in graphs])).to(
+        dev, torch.float32)
+    T = a.target_outer
+    hz = S.clock_rate_hz()
+    out_arms = {}
+    with S.Batch(As, rs, S.params(prec=S.F32, max_outer=T, check_every=1 << 30), restarts,
+                 lam=lams) as b:
+        Om = train_ws._sketch_buffer(torch, graphs, restarts, 9000, dev, torch.float32)
+        b.warmstart([], Om)                                  # warm up (lazy scratch)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        W0s = b.warmstart([], Om)
+        torch.cuda.synchronize()
+        t_spa = time.perf_counter() - t1
+        mlist = [models[r] for r in sorted(models)]
+        t1 = time.perf_counter()
+        W0l = b.warmstart(mlist, Om)
+        torch.cuda.synchronize()
+        t_ml = time.perf_counter() - t1
+        runs = {}
+        for arm, W in (("random", W0r), ("frame_only", W0s), ("learned", W0l)):
+            _, _, infos, tr = b.solve(b.split(W), trace=True)
+            runs[arm] = (infos, tr)
+    infos, tr = runs["random"]
+    taus = []
+    for g in range(len(graphs)):
+        fin = [tr[g * restarts + s_, infos[g * restarts + s_]["outer"] - 1, 0]
+               for s_ in range(restarts)
+               if infos[g * restarts + s_]["status"] == 0 and infos[g * restarts + s_]["outer"] > 0]
+        taus.append((1 + 1e-4) * min(fin) if fin else -1.0)
+    for arm, (inf, trr) in runs.items():
+        extra = {"random": 0.0, "frame_only": t_spa, "learned": t_ml}[arm]
+        out_arms[arm] = _arm_stats(np, graphs, restarts, inf, trr, hz, taus, extra)
+        out_arms[arm]["start_seconds"] = extra
+        out_arms[arm]["median_final_res"] = float(np.median(
+            [i["res_WH"] for i in inf if i["status"] == 0]))
+    out = {"metric": "median outer iterations to tau_g, learned warm start vs random starts "
+                     "(256 SBM graphs x 8 starts)",
+           "value": out_arms["learned"]["median_outer"], "unit": "outer iterations",
+           "higher_is_better": False, "n_gpus": 1, "dtype": "f32", "data": "synthetic",
+           "vs_baseline": None,
+           "config": {"workload": "256 SBM graphs, n ~ U[500,5000], r in {8,16,32}, seed 1004",
+                      "train_graphs": a.train_graphs, "train_seed": 20000,
+                      "train_outer": a.train_outer, "epochs": a.epochs,
+                      "target_outer": T, "parallelism": "single GPU"},
+           "tau_rule": f"(1 + 1e-4) x best random-start residual after {T} outer iterations",
+           "arms": out_arms,
+           "training": {"generate_s": t_gen, "solve_frame_targets_s": t_pool,
+                        "train_s": t_train, "log": log,
+                        "target_solves_ok": {str(r): v[2] for r, v in pools.items()},
+                        "pool_rows": {str(r): int(v[0].shape[0]) for r, v in pools.items()}}}
+    print(json.dumps(out))
+
+
 def main():
     a = _args()
     if a.gpus != 1:
@@ -187,10 +293,10 @@ def main():
         sys.exit(2)
     import numpy as np
     import torch
-    if a.workload == "c4":
+    if a.workload in ("c4", "c4ws"):
         from paper_2606_02887_amd import gen
         from paper_2606_02887_amd import snmf as S
-        _bench_c4(a, torch, np, S, gen)
+        (_bench_c4 if a.workload == "c4" else _bench_c4ws)(a, torch, np, S, gen)
         return
 
     from paper_2606_02887_amd import gen

@@ -276,7 +276,8 @@ snmf_status snmf_batch_frame(snmf_batch* b, const void* Omega, void* Y, void* C,
 snmf_status snmf_batch_targets(snmf_batch* b, const void* C, const void* Ht, void* T,
                                int32_t* perm, void* stream);
 /* W0 (batch buffer) for every instance: frame of Omega, then the network whose r matches
- * the instance's rank (E_ARG if none).  FP32 batches only. */
+ * the instance's rank (E_ARG if none; FP32 batches only).  nmodels = 0: the frame alone,
+ * W0 = s relu(C) / rms(relu(C)) per instance (the ablation without the network). */
 snmf_status snmf_batch_warmstart(snmf_batch* b, int32_t nmodels, const snmf_mlp* models,
                                  const void* Omega, void* W0, void* stream);
 

@@ -350,6 +350,38 @@ template void launch_ws_match<float>(const BInst*, int, const float*, const floa
 template void launch_ws_match<double>(const BInst*, int, const double*, const double*, double*,
                                       int32_t*, hipStream_t);
 
+// ----------------------------------------------------------------------------- frame only
+// The ablation without the network: W0 = s relu(C) / rms(relu(C)) per instance (one
+// workgroup each; s as for the network's output).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_ws_spa_only(const BInst* __restrict__ inst,
+                                                          const T* __restrict__ Cbuf,
+                                                          T* __restrict__ Wbuf) {
+  __shared__ double sred[kThreads / kWave * kNumPart];
+  const BInst d = inst[blockIdx.x];
+  const int64_t cnt = d.n * d.r;
+  const T* __restrict__ C = Cbuf + d.off;
+  double v[1] = {0.0};
+  for (int64_t e = threadIdx.x; e < cnt; e += kThreads) {
+    const double c = fmax((double)C[e], 0.0);
+    v[0] = __builtin_fma(c, c, v[0]);
+  }
+  block_sum<1>(v, sred);
+  const double rms = sqrt(v[0] / (double)cnt);
+  const double s = sqrt(sqrt((double)d.r) * sqrt(d.normA2) / ((double)cnt));
+  const double f = rms > 0.0 ? s / rms : 0.0;
+  T* __restrict__ W = Wbuf + d.off;
+  for (int64_t e = threadIdx.x; e < cnt; e += kThreads)
+    W[e] = rms > 0.0 ? (T)(fmax((double)C[e], 0.0) * f) : (T)s;
+}
+
+template <typename T>
+void launch_ws_spa_only(const BInst* inst, int ninst, const T* C, T* W, hipStream_t s) {
+  hipLaunchKernelGGL(k_ws_spa_only<T>, dim3(ninst), dim3(kThreads), 0, s, inst, C, W);
+}
+template void launch_ws_spa_only<float>(const BInst*, int, const float*, float*, hipStream_t);
+template void launch_ws_spa_only<double>(const BInst*, int, const double*, double*, hipStream_t);
+
 // ----------------------------------------------------------------------------- network
 // Weights staged in LDS as FP32 (dequantised BF16): M1 (H x r) and M2^T (H x r), so row
 // k of each is contiguous.  One thread per row: a_k = M1_k c + b1_k, h_k = relu(a_k),

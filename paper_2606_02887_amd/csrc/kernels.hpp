@@ -43,6 +43,8 @@ template <typename T>
 void launch_ws_frame(const BInst* inst, int ninst, int max_r, const BGraph* graphs, const T* Y,
                      double* R, T* C, int32_t* anchors, hipStream_t s);
 template <typename T>
+void launch_ws_spa_only(const BInst* inst, int ninst, const T* C, T* W, hipStream_t s);
+template <typename T>
 void launch_ws_match(const BInst* inst, int ninst, const T* C, const T* H, T* Tout, int32_t* perm,
                      hipStream_t s);
 int inner_grid(int64_t n, int r);

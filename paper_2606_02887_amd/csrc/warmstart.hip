@@ -197,6 +197,18 @@ snmf_status snmf_batch_warmstart(snmf_batch* b, int32_t nmodels, const snmf_mlp*
                                  const void* Omega, void* W0, void* stream) {
   if (!b || !Omega || !W0 || (nmodels > 0 && !models))
     return fail(SNMF_E_ARG, "batch, models, Omega and W0 are required");
+  hipStream_t user = (hipStream_t)stream;
+  if (nmodels == 0) {  // the frame alone: W0 = s relu(C) / rms(relu(C))
+    SNMF_TRY(begin(b, user));
+    SNMF_TRY(frame_async(b, Omega, b->B, b->C, nullptr));
+    if (b->prec == SNMF_F64)
+      launch_ws_spa_only<double>(b->dinst, b->ninst, (const double*)b->C, (double*)W0, b->s);
+    else
+      launch_ws_spa_only<float>(b->dinst, b->ninst, (const float*)b->C, (float*)W0, b->s);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(b->s));
+    return finish(b, user);
+  }
   if (b->prec != SNMF_F32) return fail(SNMF_E_UNSUPPORTED, "the warm start network runs in FP32");
   const snmf_mlp* pick[kMaxRank + 1] = {};
   for (int q = 0; q < nmodels; ++q) {
@@ -205,7 +217,6 @@ snmf_status snmf_batch_warmstart(snmf_batch* b, int32_t nmodels, const snmf_mlp*
   }
   for (const auto& c : b->cls)
     if (!pick[c.r]) return fail(SNMF_E_ARG, "no network for rank " + std::to_string(c.r));
-  hipStream_t user = (hipStream_t)stream;
   SNMF_TRY(begin(b, user));
   // the sketch lands in B, the coordinates in C (solve scratch, free between solves)
   SNMF_TRY(frame_async(b, Omega, b->B, b->C, nullptr));

@@ -350,7 +350,7 @@ class Batch:
     def warmstart(self, models, Omega):
         import torch
         W0 = torch.empty_like(Omega)
-        arr = (MlpC * len(models))(*[m.desc for m in models])
+        arr = (MlpC * len(models))(*[m.desc for m in models]) if models else None
         _check(_lib.snmf_batch_warmstart(self._h, len(models), arr, _ptr(Omega), _ptr(W0),
                                          _stream()))
         return W0

@@ -212,3 +212,39 @@ def test_warmstart_error_codes(S):
         with pytest.raises(S.SnmfError) as e:
             b.frame(torch.ones(160, dtype=torch.float32, device=DEV))
         assert e.value.name == "E_UNSUPPORTED"
+
+
+def test_warm_start_gain_on_detectable_graphs(S):
+    """Trained on 48 separately seeded SBM graphs (clusters detectable), the learned start
+    and the frame alone are closer to the end point after the first outer iteration than
+    random starts on 12 held-out graphs (median over graphs of res_1 / best final - 1)."""
+    from paper_2606_02887_amd import train_ws
+    mk = lambda num, seed: gen.batched_sbm(num_graphs=num, n_lo=240, n_hi=480, ranks=(8,),
+                                           restarts=3, p_in=0.2, p_out=0.01, seed=seed)
+    train = mk(48, 30000)
+    pools = train_ws.training_pools(S, torch, train, outer=120)
+    models = train_ws.train(S, torch, pools, epochs=6, batch=1024, lr=2e-3)
+    test = mk(12, 31000)
+    As = [S.csr_from_scipy(g["A"], torch.float32) for g in test]
+    W0r = torch.from_numpy(np.concatenate([np.stack(g["W0"]).ravel() for g in test])).to(
+        DEV, torch.float32)
+    T = 200
+    with S.Batch(As, [8] * len(test), S.params(prec=S.F32, max_outer=T), 3,
+                 lam=train_ws.lambdas(test)) as b:
+        Om = train_ws._sketch_buffer(torch, test, 3, 4242, DEV, torch.float32)
+        starts = {"random": W0r, "frame": b.warmstart([], Om), "learned": b.warmstart([models[8]], Om)}
+        runs = {k: b.solve(b.split(W), trace=True) for k, W in starts.items()}
+    best = []
+    for g in range(len(test)):
+        best.append(min(runs[k][3][g * 3 + s, T - 1, 0] for k in runs for s in range(3)
+                        if runs[k][2][g * 3 + s]["status"] == 0))
+    gap = {}
+    for it in (1, 2, 4):
+        for k, (_, _, infos, tr) in runs.items():
+            per = [min(tr[g * 3 + s, it - 1, 0] for s in range(3)) / best[g] - 1.0
+                   for g in range(len(test))]
+            gap[(k, it)] = float(np.median(per))
+    print("median gap after 1, 2, 4 outer iterations:", gap)
+    gap = {k: gap[(k, 1)] for k in runs}
+    assert gap["learned"] < gap["random"]
+    assert gap["frame"] < gap["random"]
