@@ -225,7 +225,7 @@ snmf_status batch_create(int32_t nprob, const snmf_matrix* A, const int32_t* r, 
     const int rg = b->r[g];
     b->max_r = std::max(b->max_r, rg);
     b->max_nr = std::max(b->max_nr, ng * rg);
-    const int gnb = (int)std::min<int64_t>(64, std::max<int64_t>(1, (ng + 63) / 64));
+    const int gnb = gram_blocks(ng);
     for (int s = 0; s < restarts; ++s) {
       BInst& d = b->hinst[g * restarts + s];
       std::memset(&d, 0, sizeof(d));

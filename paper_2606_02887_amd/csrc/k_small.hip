@@ -122,29 +122,44 @@ __global__ __launch_bounds__(kThreads) void k_bgram(const T* __restrict__ P,
   gram_slab<T, RPG>(P + d->off, d->r, rb, re, gpart + d->gpoff + (size_t)j * d->r * d->r);
 }
 
+// Sum over the slabs b = q, q + 4, q + 8, ... (in increasing b) of entry e; the Gram is
+// (s_0 + s_1) + s_2 + s_3, the same order in the single and the batched reduction.
+__device__ __forceinline__ double gram_sum4(const double* __restrict__ part, int nb, int rr, int e,
+                                           int q) {
+  double s = 0.0;
+  int b = q;
+  for (; b + 12 < nb; b += 16) {
+    const double v0 = part[(size_t)b * rr + e], v1 = part[(size_t)(b + 4) * rr + e];
+    const double v2 = part[(size_t)(b + 8) * rr + e], v3 = part[(size_t)(b + 12) * rr + e];
+    s += v0;
+    s += v1;
+    s += v2;
+    s += v3;
+  }
+  for (; b < nb; b += 4) s += part[(size_t)b * rr + e];
+  return s;
+}
+
+// 64 entries per workgroup, four threads per entry.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_gram_reduce(const double* __restrict__ part, int nb,
                                                           int rr, double* __restrict__ G64,
                                                           T* __restrict__ GT,
                                                           const State* __restrict__ st) {
   if (st->done) return;
-  const int e = blockIdx.x * kThreads + threadIdx.x;
-  if (e >= rr) return;
-  double s = 0.0;
-  int b = 0;
-  for (; b + 8 <= nb; b += 8) {  // eight loads in flight, added in block order
-    double v[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = part[(size_t)(b + u) * rr + e];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) s += v[u];
+  __shared__ double sq[4][64];
+  const int e = blockIdx.x * 64 + (threadIdx.x & 63), q = threadIdx.x >> 6;
+  sq[q][threadIdx.x & 63] = e < rr ? gram_sum4(part, nb, rr, e, q) : 0.0;
+  __syncthreads();
+  if (q == 0 && e < rr) {
+    const int t = threadIdx.x;
+    const double s = ((sq[0][t] + sq[1][t]) + sq[2][t]) + sq[3][t];
+    G64[e] = s;
+    GT[e] = (T)s;
   }
-  for (; b < nb; ++b) s += part[(size_t)b * rr + e];
-  G64[e] = s;
-  GT[e] = (T)s;
 }
 
-// Batched: one workgroup per instance adds its Gram slabs in slab order.
+// Batched: one workgroup per instance adds its Gram slabs in the order above.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_bgram_reduce(const BInst* __restrict__ inst,
                                                            const State* __restrict__ states,
@@ -157,8 +172,9 @@ __global__ __launch_bounds__(kThreads) void k_bgram_reduce(const BInst* __restri
   const int rr = d->r * d->r;
   const double* part = gpart + d->gpoff;
   for (int e = threadIdx.x; e < rr; e += kThreads) {
-    double s = 0.0;
-    for (int b = 0; b < d->gnb; ++b) s += part[(size_t)b * rr + e];
+    const double s = ((gram_sum4(part, d->gnb, rr, e, 0) + gram_sum4(part, d->gnb, rr, e, 1)) +
+                      gram_sum4(part, d->gnb, rr, e, 2)) +
+                     gram_sum4(part, d->gnb, rr, e, 3);
     G64[d->goff + e] = s;
     GT[d->goff + e] = (T)s;
   }
@@ -359,6 +375,13 @@ __global__ __launch_bounds__(kThreads) void k_split_pt(const float* __restrict__
 }
 
 // ----------------------------------------------------------------------------- launchers
+int gram_blocks(int64_t n) {
+  int64_t g = (n + 127) / 128;
+  if (g < 1) g = 1;
+  if (g > 256) g = 256;
+  return (int)g;
+}
+
 #define SNMF_DISPATCH_RPG(rp, ...)                                  \
   switch (rp) {                                                     \
     case 4: { constexpr int RPG = 4; __VA_ARGS__; } break;          \
@@ -375,8 +398,8 @@ void launch_gram(const T* P, int64_t n, int r, double* part, int nblk, double* G
   SNMF_DISPATCH_RPG(rank_pad(r), hipLaunchKernelGGL((k_gram<T, RPG>), dim3(nblk), dim3(kThreads),
                                                     0, s, P, n, r, rpb, part, st))
   const int rr = r * r;
-  hipLaunchKernelGGL(k_gram_reduce<T>, dim3((rr + kThreads - 1) / kThreads), dim3(kThreads), 0, s,
-                     part, nblk, rr, G64, GT, st);
+  hipLaunchKernelGGL(k_gram_reduce<T>, dim3((rr + 63) / 64), dim3(kThreads), 0, s, part, nblk, rr,
+                     G64, GT, st);
 }
 template void launch_gram<float>(const float*, int64_t, int, double*, int, double*, float*,
                                  const State*, hipStream_t);

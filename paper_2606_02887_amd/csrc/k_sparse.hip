@@ -230,6 +230,169 @@ __global__ __launch_bounds__(256) void k_lai_ut(const T* __restrict__ U, int ell
   }
 }
 
+// ----------------------------------------------------------------------------- LAI, FP32
+// The FP32 products on MFMA v_mfma_f32_16x16x4f32 with slabs of 64 rows staged in LDS by
+// coalesced 16-byte loads (a slab of U or P is one contiguous block of memory).
+// Lane l of an MFMA supplies A[l%16][l/16] and B[l/16][l%16] and receives
+// D[4(l/16)+v][l%16], v = 0..3.
+typedef float f32x4l __attribute__((ext_vector_type(4)));
+constexpr int kLaiRows = 64;                    // rows per LDS slab
+constexpr int kLaiMaxTiles = 8;                 // 16x16 output tiles per wave
+constexpr int kLaiPitchA = kMaxEll + 16;        // U slab pitch (== 16 mod 64: k-major reads)
+constexpr int kLaiPitchP = kMaxRank + 16;       // P slab / T pitch
+
+// Stage rows [row0, row0 + 64) of an n x w row-major array into LDS (pitch `pitch`),
+// zero beyond n and w; float4 loads when w % 4 == 0.
+__device__ __forceinline__ void lai_stage(const float* __restrict__ X, int64_t n, int w,
+                                          int64_t row0, float* __restrict__ sX, int pitch) {
+  const int64_t rows = n - row0 < kLaiRows ? n - row0 : kLaiRows;
+  if ((w & 3) == 0 && (reinterpret_cast<uintptr_t>(X) & 15) == 0) {
+    const int w4 = w >> 2;
+    const float4* src = reinterpret_cast<const float4*>(X + row0 * w);
+    for (int e = threadIdx.x; e < kLaiRows * w4; e += 256) {
+      const int i = e / w4, c = (e - i * w4) * 4;
+      const float4 v = i < rows ? src[e] : make_float4(0.f, 0.f, 0.f, 0.f);
+      *reinterpret_cast<float4*>(&sX[i * pitch + c]) = v;
+    }
+  } else {
+    for (int e = threadIdx.x; e < kLaiRows * w; e += 256) {
+      const int i = e / w, c = e - i * w;
+      sX[i * pitch + c] = i < rows ? X[(row0 + i) * w + c] : 0.f;
+    }
+  }
+}
+
+// Partial T_b = U_b^T P_b over a contiguous slab of rows; FP32 partial (ell x r) per
+// workgroup.  Output tiles (ell/16) x (r/16), tile t handled by wave t % 4.
+__global__ __launch_bounds__(256) void k_lai_utp32(const float* __restrict__ U, int ell,
+                                                   const float* __restrict__ P, int64_t n, int r,
+                                                   int64_t rows_per_block,
+                                                   float* __restrict__ part,
+                                                   const int32_t* __restrict__ gate) {
+  if (gate && gate[0]) return;
+  __shared__ __attribute__((aligned(16))) float sU[kLaiRows * kLaiPitchA];
+  __shared__ __attribute__((aligned(16))) float sP[kLaiRows * kLaiPitchP];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int TL = (ell + 15) / 16, TRr = (r + 15) / 16, nt = TL * TRr;
+  f32x4l acc[kLaiMaxTiles];
+#pragma unroll
+  for (int q = 0; q < kLaiMaxTiles; ++q) acc[q] = f32x4l{0.f, 0.f, 0.f, 0.f};
+  const int64_t rb = (int64_t)blockIdx.x * rows_per_block;
+  const int64_t re = rb + rows_per_block < n ? rb + rows_per_block : n;
+  for (int64_t t0 = rb; t0 < re; t0 += kLaiRows) {
+    __syncthreads();
+    lai_stage(U, re, ell, t0, sU, kLaiPitchA);
+    lai_stage(P, re, r, t0, sP, kLaiPitchP);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kLaiMaxTiles; ++q) {
+      const int t = w + 4 * q;
+      if (t < nt) {
+        const int i0 = 16 * (t / TRr), j0 = 16 * (t % TRr);
+        f32x4l d = acc[q];
+        for (int k0 = 0; k0 < kLaiRows; k0 += 4) {
+          const int k = k0 + (lane >> 4);
+          const float a = sU[k * kLaiPitchA + i0 + (lane & 15)];
+          const float b = sP[k * kLaiPitchP + j0 + (lane & 15)];
+          d = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, d, 0, 0, 0);
+        }
+        acc[q] = d;
+      }
+    }
+  }
+  float* out = part + (size_t)blockIdx.x * ell * r;
+#pragma unroll
+  for (int q = 0; q < kLaiMaxTiles; ++q) {
+    const int t = w + 4 * q;
+    if (t < nt) {
+      const int i0 = 16 * (t / TRr), j0 = 16 * (t % TRr);
+      const int j = j0 + (lane & 15);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = i0 + 4 * (lane >> 4) + v;
+        if (i < ell && j < r) out[i * r + j] = acc[q][v];
+      }
+    }
+  }
+}
+
+// TT[a][c] = lam[a] * sum_b part[b][a][c] in FP64, blocks in order: four threads per
+// entry take every fourth block, their sums are added in thread order.
+__global__ __launch_bounds__(256) void k_lai_reduce32(const float* __restrict__ part, int nb,
+                                                      int ell, int r,
+                                                      const double* __restrict__ lam,
+                                                      float* __restrict__ TT,
+                                                      const int32_t* __restrict__ gate) {
+  if (gate && gate[0]) return;
+  __shared__ double sq[4][64];
+  const int ne = ell * r;
+  const int e = blockIdx.x * 64 + (threadIdx.x & 63), q = threadIdx.x >> 6;
+  double s = 0.0;
+  if (e < ne) {
+    int b = q;
+    for (; b + 12 < nb; b += 16) {
+      const float v0 = part[(size_t)b * ne + e], v1 = part[(size_t)(b + 4) * ne + e];
+      const float v2 = part[(size_t)(b + 8) * ne + e], v3 = part[(size_t)(b + 12) * ne + e];
+      s += v0;
+      s += v1;
+      s += v2;
+      s += v3;
+    }
+    for (; b < nb; b += 4) s += part[(size_t)b * ne + e];
+  }
+  sq[q][threadIdx.x & 63] = s;
+  __syncthreads();
+  if (q == 0 && e < ne) {
+    const double t = ((sq[0][threadIdx.x] + sq[1][threadIdx.x]) + sq[2][threadIdx.x]) + sq[3][threadIdx.x];
+    TT[e] = (float)(lam[e / r] * t);
+  }
+}
+
+// B = U TT, 64-row slabs: output tiles 4 x (r/16), tile t handled by wave t % 4; TT
+// (ell x r) staged once per workgroup.
+__global__ __launch_bounds__(256) void k_lai_ut32(const float* __restrict__ U, int ell,
+                                                  const float* __restrict__ TT, int64_t n, int r,
+                                                  float* __restrict__ B,
+                                                  const int32_t* __restrict__ gate) {
+  if (gate && gate[0]) return;
+  constexpr int PA = kMaxEll + 4;  // U slab pitch (== 4 mod 64: row-major reads)
+  __shared__ __attribute__((aligned(16))) float sU[kLaiRows * PA];
+  __shared__ float sT[kMaxEll * kLaiPitchP];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int ellp = (ell + 3) & ~3;  // K padded to the MFMA step (zeros beyond ell)
+  for (int e = threadIdx.x; e < ellp * kLaiPitchP; e += 256) {
+    const int k = e / kLaiPitchP, c = e - k * kLaiPitchP;
+    sT[e] = (k < ell && c < r) ? TT[k * r + c] : 0.f;
+  }
+  const int TRr = (r + 15) / 16, nt = 4 * TRr;
+  const int64_t ntiles = (n + kLaiRows - 1) / kLaiRows;
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int64_t row0 = tile * kLaiRows;
+    __syncthreads();
+    lai_stage(U, n, ell, row0, sU, PA);
+    if ((ell & 3) != 0)  // zero the K padding columns of the slab
+      for (int e = threadIdx.x; e < kLaiRows * (ellp - ell); e += 256)
+        sU[(e / (ellp - ell)) * PA + ell + e % (ellp - ell)] = 0.f;
+    __syncthreads();
+    for (int t = w; t < nt; t += 4) {
+      const int i0 = 16 * (t / TRr), j0 = 16 * (t % TRr);
+      f32x4l d = {0.f, 0.f, 0.f, 0.f};
+      for (int k0 = 0; k0 < ellp; k0 += 4) {
+        const int k = k0 + (lane >> 4);
+        const float a = sU[(i0 + (lane & 15)) * PA + k];
+        const float b = sT[k * kLaiPitchP + j0 + (lane & 15)];
+        d = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, d, 0, 0, 0);
+      }
+      const int j = j0 + (lane & 15);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t row = row0 + i0 + 4 * (lane >> 4) + v;
+        if (row < n && j < r) B[row * r + j] = d[v];
+      }
+    }
+  }
+}
+
 // ----------------------------------------------------------------------------- launchers
 #define SNMF_DISPATCH_RP2(rp, ...)                                  \
   switch (rp) {                                                     \
@@ -270,6 +433,21 @@ int lai_blocks(int64_t n) {
 template <typename T>
 void launch_lai(const T* U, int ell, const double* lam, const T* P, int64_t n, int r,
                 double* part, T* TT, T* B, const int32_t* gate, hipStream_t s) {
+  if constexpr (sizeof(T) == 4) {
+    int nb = lai_blocks(n);
+    if (nb > 256) nb = 256;
+    const int64_t rpb = ((n + nb - 1) / nb + kLaiRows - 1) / kLaiRows * kLaiRows;
+    nb = (int)((n + rpb - 1) / rpb);
+    hipLaunchKernelGGL(k_lai_utp32, dim3(nb), dim3(256), 0, s, (const float*)U, ell,
+                       (const float*)P, n, r, rpb, (float*)part, gate);
+    hipLaunchKernelGGL(k_lai_reduce32, dim3((ell * r + 63) / 64), dim3(256), 0, s,
+                       (const float*)part, nb, ell, r, lam, (float*)TT, gate);
+    int64_t tiles = (n + kLaiRows - 1) / kLaiRows;
+    if (tiles > 2048) tiles = 2048;
+    hipLaunchKernelGGL(k_lai_ut32, dim3((unsigned)tiles), dim3(256), 0, s, (const float*)U, ell,
+                       (const float*)TT, n, r, (float*)B, gate);
+    return;
+  }
   const int nb = lai_blocks(n);
   const int64_t rpb = (n + nb - 1) / nb;
   hipLaunchKernelGGL(k_lai_utp<T>, dim3(nb), dim3(256), 0, s, U, ell, P, n, r, rpb, part, gate);

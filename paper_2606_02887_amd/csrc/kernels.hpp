@@ -18,6 +18,7 @@ struct DenseSplit {
 };
 
 int rank_pad(int r);
+int gram_blocks(int64_t n);  // Gram slabs of an n-row partner (shared by single and batched solves)
 
 // ---- learned warm start
 constexpr int kMlpHidden = 128;  // hidden width of the warm-start network

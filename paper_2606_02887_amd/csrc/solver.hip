@@ -399,7 +399,7 @@ snmf_status plan_create(const snmf_matrix* A, int32_t r, const snmf_params* p, h
     pl->ldb = (n + 63) / 64 * 64;
   }
   if (A->fmt == SNMF_DENSE && pl->prec != SNMF_F64) ksplit = pl->ds.ksplit;
-  pl->gram_blocks = (int)std::min<int64_t>(64, std::max<int64_t>(1, (n + 63) / 64));
+  pl->gram_blocks = gram_blocks(n);
   const int lai_nb = lai_blocks(n);
   // carve one allocation
   std::vector<std::pair<void**, size_t>> req;
