@@ -3,7 +3,7 @@
 // Instances (problem g, restart s) are numbered i = g S + s and stored one after another
 // (instance-major): every batch buffer (W, Ht, C, g, Z, D, B) holds instance i's n_g x r_g
 // block at element offset off_i.  Per half-step, in stream order:
-//   Gram of every instance (one launch) -> rho of every instance (one launch, side stream)
+//   Gram of every instance (one launch) -> rho of every instance (one launch)
 //   -> A-pass (stacked CSR SpMM: one sweep per problem for all its restarts; dense: one
 //   product per instance) -> init -> inner_iters x (step1, step2)
 // where init/step1/step2 run one launch per distinct rank (their tile shape depends on
@@ -106,11 +106,8 @@ snmf_status bhalf_start(snmf_batch* b, T* X, const T* P, int is_hstep, bool with
   launch_bgram_reduce<T>(b->dinst, b->ninst, b->states, b->gpart, b->G64[gi], (T*)b->GT[gi], s);
   HIP_TRY(hipGetLastError());
   if (with_rho) {
-    HIP_TRY(hipEventRecord(b->ev_fork, s));
-    HIP_TRY(hipStreamWaitEvent(b->side, b->ev_fork, 0));
-    launch_brho(b->dinst, b->ninst, b->states, b->G64[gi], b->side);
+    launch_brho(b->dinst, b->ninst, b->states, b->G64[gi], s);
     HIP_TRY(hipGetLastError());
-    HIP_TRY(hipEventRecord(b->ev_join, b->side));
   }
   SNMF_TRY(bapass<T>(b, P, (T*)b->B, s));
   for (const auto& c : b->cls) {
@@ -118,7 +115,6 @@ snmf_status bhalf_start(snmf_batch* b, T* X, const T* P, int is_hstep, bool with
                    c.r, is_hstep, b->kp, b->states, b->partsA, s, b->bmap(c), c.blocks);
   }
   HIP_TRY(hipGetLastError());
-  if (with_rho) HIP_TRY(hipStreamWaitEvent(s, b->ev_join, 0));
   return SNMF_OK;
 }
 
@@ -206,11 +202,8 @@ snmf_status batch_create(int32_t nprob, const snmf_matrix* A, const int32_t* r, 
   b->n.resize(nprob);
   for (int g = 0; g < nprob; ++g) b->n[g] = A[g].n;
   HIP_TRY(hipStreamCreateWithFlags(&b->s, hipStreamNonBlocking));
-  HIP_TRY(hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking));
   HIP_TRY(hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming));
   HIP_TRY(hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming));
-  HIP_TRY(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
-  HIP_TRY(hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming));
   if (user) {
     HIP_TRY(hipEventRecord(b->ev_in, user));
     HIP_TRY(hipStreamWaitEvent(b->s, b->ev_in, 0));

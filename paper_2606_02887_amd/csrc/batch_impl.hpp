@@ -41,8 +41,8 @@ struct snmf_batch {
   int64_t total = 0, max_nr = 0, gsum = 0, gpsum = 0;
   int ksplit_max = 1;
   int64_t trace_stride = 0;
-  hipStream_t s = nullptr, side = nullptr;
-  hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_fork = nullptr, ev_join = nullptr;
+  hipStream_t s = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
   void* pool = nullptr;
   void *Wb = nullptr, *Hb = nullptr, *C = nullptr, *g = nullptr, *Z = nullptr, *D = nullptr;
   void *B = nullptr, *Bpart = nullptr, *GT[2] = {nullptr, nullptr};
@@ -78,9 +78,6 @@ struct snmf_batch {
     if (wsI) (void)hipFree(wsI);
     if (ev_in) (void)hipEventDestroy(ev_in);
     if (ev_out) (void)hipEventDestroy(ev_out);
-    if (ev_fork) (void)hipEventDestroy(ev_fork);
-    if (ev_join) (void)hipEventDestroy(ev_join);
-    if (side) (void)hipStreamDestroy(side);
     if (s) (void)hipStreamDestroy(s);
   }
 };

@@ -13,6 +13,7 @@
 // init kernel adds in a fixed order.
 #include "common.hpp"
 #include "kernels.hpp"
+#include "rho.hpp"
 
 namespace snmf {
 
@@ -171,12 +172,24 @@ __global__ __launch_bounds__(256) void k_apass_f32(const float* __restrict__ A, 
 // P[k+h][2c, 2c+1] (one 8-byte vector): MFMA N-block q covers the columns j0 + 4c + q,
 // M-block b the ranks m = 2c + b.  The four wave tiles are added in LDS in wave order
 // (deterministic) and written as coalesced rows of the partial product.
-__global__ __launch_bounds__(256) void k_apass_f32w(const float* __restrict__ A, int64_t lda,
-                                                    const float* __restrict__ P, int64_t n, int r,
-                                                    int64_t kchunk, float* __restrict__ Bpart,
-                                                    int64_t pstride, const State* __restrict__ st) {
+// With rj.G set, the grid has one more row of workgroups: its first workgroup computes
+// rho = ||G||_2 (rho.hpp) beside the tiles and the rest of the row returns at once.  The
+// register bound of two waves per SIMD and the 64 KB of LDS leave room on a CU for that
+// workgroup next to a tile workgroup, so rho costs no time on the critical path.
+#ifndef SNMF_F32W_BATCH
+#define SNMF_F32W_BATCH 8
+#endif
+__global__ __launch_bounds__(256, 2) void k_apass_f32w(const float* __restrict__ A, int64_t lda,
+                                                       const float* __restrict__ P, int64_t n,
+                                                       int r, int64_t kchunk,
+                                                       float* __restrict__ Bpart, int64_t pstride,
+                                                       const State* __restrict__ st, RhoJob rj) {
   if (st->done) return;
-  __shared__ float sacc[4 * 8 * 16 * 64];  // [wave][block(mb,nb)][v][lane]
+  if (rj.G && blockIdx.y == gridDim.y - 1) {
+    if (blockIdx.x == 0) rho_body(rj.G, rj.r, rj.st);
+    return;
+  }
+  __shared__ float sacc[2 * 8 * 16 * 64];  // [slot][block(mb,nb)][v][lane], 64 KB
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int c = lane & 31, h = lane >> 5;
   const int64_t j0 = (int64_t)blockIdx.x * 128;
@@ -195,9 +208,13 @@ __global__ __launch_bounds__(256) void k_apass_f32w(const float* __restrict__ A,
   const int64_t jc = j0 + 4 * c;
   const bool jok = jc + 3 < n;                 // n % 4 == 0 on this path
   const bool mok = 2 * c + 1 < r;              // r even on this path
-  const float* arow = A + (jok ? jc : 0);
+  // Out-of-range lanes read a clamped, valid address instead of being predicated: the
+  // loads stay unconditional (so the compiler keeps the prefetched batch in flight
+  // across the MFMAs), and a garbage column of A or rank of P only reaches an output
+  // column or rank that is never stored.
+  const float* arow = A + (jok ? jc : n - 4);
   const float* prow = P + (mok ? 2 * c : 0);
-  constexpr int U = 8;
+  constexpr int U = SNMF_F32W_BATCH;  // k-pairs per batch of loads (two batches in flight)
   f32x4v xa[U], xb[U];
   float2 ya[U], yb[U];
   const f32x4v z4 = {0.f, 0.f, 0.f, 0.f};
@@ -206,8 +223,8 @@ __global__ __launch_bounds__(256) void k_apass_f32w(const float* __restrict__ A,
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t kk = k0 + 2 * u + h;
-      x[u] = jok ? __builtin_nontemporal_load((const f32x4v*)(arow + kk * lda)) : z4;
-      y[u] = mok ? *(const float2*)(prow + kk * r) : z2;
+      x[u] = __builtin_nontemporal_load((const f32x4v*)(arow + kk * lda));
+      y[u] = *(const float2*)(prow + kk * r);
     }
   };
   auto mma = [&](const f32x4v (&x)[U], const float2 (&y)[U]) {
@@ -222,21 +239,21 @@ __global__ __launch_bounds__(256) void k_apass_f32w(const float* __restrict__ A,
           acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(pv[mb], av[nb], acc[mb][nb], 0, 0, 0);
     }
   };
+  // full batches of U k-pairs, two in flight; the prefetch of a batch beyond the last
+  // one re-reads the last batch (a valid address) and is never used, which keeps every
+  // load unconditional
+  const int64_t nbat = (we - wb) / (2 * U);
+  const int64_t klast = wb + (nbat > 0 ? nbat - 1 : 0) * 2 * U;
   int64_t k = wb;
-  if (k + 2 * U <= we) load(xa, ya, k);
-  while (k + 2 * U <= we) {
-    if (k + 4 * U <= we) {
-      load(xb, yb, k + 2 * U);
-      mma(xa, ya);
-      k += 2 * U;
-      if (k + 4 * U <= we) load(xa, ya, k + 2 * U);
-      mma(xb, yb);
-      k += 2 * U;
-    } else {
-      mma(xa, ya);
-      k += 2 * U;
-    }
+  if (nbat > 0) load(xa, ya, k);
+  for (int64_t b = 0; b < nbat; b += 2) {
+    load(xb, yb, k + 2 * U < klast ? k + 2 * U : klast);
+    mma(xa, ya);
+    load(xa, ya, k + 4 * U < klast ? k + 4 * U : klast);
+    if (b + 1 < nbat) mma(xb, yb);
+    k += 4 * U;
   }
+  k = wb + nbat * 2 * U;
   for (; k < we; k += 2) {
     const int64_t kk = k + h;
     const bool kin = kk < we;
@@ -250,12 +267,34 @@ __global__ __launch_bounds__(256) void k_apass_f32w(const float* __restrict__ A,
       for (int mb = 0; mb < 2; ++mb)
         acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(pv[mb], av[nb], acc[mb][nb], 0, 0, 0);
   }
+  // the four K-quarter tiles, added pairwise in a fixed order in 64 KB of LDS:
+  // (w0 + w1) + (w2 + w3), the total in slot 0
+  auto put = [&](int slot) {
 #pragma unroll
-  for (int mb = 0; mb < 2; ++mb)
+    for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-    for (int nb = 0; nb < 4; ++nb)
+      for (int nb = 0; nb < 4; ++nb)
 #pragma unroll
-      for (int v = 0; v < 16; ++v) sacc[((wave * 8 + mb * 4 + nb) * 16 + v) * 64 + lane] = acc[mb][nb][v];
+        for (int v = 0; v < 16; ++v) sacc[((slot * 8 + mb * 4 + nb) * 16 + v) * 64 + lane] = acc[mb][nb][v];
+  };
+  auto add = [&](int slot) {
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[mb][nb][v] += sacc[((slot * 8 + mb * 4 + nb) * 16 + v) * 64 + lane];
+  };
+  if (wave & 1) put(wave >> 1);
+  __syncthreads();
+  if (!(wave & 1)) add(wave >> 1);
+  __syncthreads();
+  if (wave == 2) put(0);
+  __syncthreads();
+  if (wave == 0) {
+    add(0);
+    put(0);
+  }
   __syncthreads();
   // element (jl, m) of the 128 x r tile: jl = 4c + nb, m = 2 mrow + mb with
   // mrow = 8 (v/4) + 4 h + v%4
@@ -267,11 +306,7 @@ __global__ __launch_bounds__(256) void k_apass_f32w(const float* __restrict__ A,
       const int cc = jl >> 2, nb = jl & 3, mb = m & 1, mrow = m >> 1;
       const int hh = (mrow >> 2) & 1, v = 4 * (mrow >> 3) + (mrow & 3);
       const int idx = ((mb * 4 + nb) * 16 + v) * 64 + 32 * hh + cc;
-      float sum = sacc[idx];
-      sum += sacc[8 * 16 * 64 + idx];
-      sum += sacc[2 * 8 * 16 * 64 + idx];
-      sum += sacc[3 * 8 * 16 * 64 + idx];
-      out[jj * r + m] = sum;
+      out[jj * r + m] = sacc[idx];
     }
   }
 }
@@ -291,8 +326,14 @@ __global__ __launch_bounds__(256) void k_apass_bf16x3(const uint16_t* __restrict
                                                       const uint16_t* __restrict__ Ptlo, int64_t ldp,
                                                       int64_t n, int r, int64_t kchunk,
                                                       float* __restrict__ Bpart, int64_t pstride,
-                                                      const State* __restrict__ st) {
+                                                      const State* __restrict__ st, RhoJob rj) {
   if (st->done) return;
+  // with rj.G set, one more row of workgroups: its first computes rho = ||G||_2 (the grid
+  // is resident at once, so it runs beside the tiles)
+  if (rj.G && blockIdx.y == gridDim.y - 1) {
+    if (blockIdx.x == 0) rho_body(rj.G, rj.r, rj.st);
+    return;
+  }
   constexpr int KS = 64;                    // k per slab
   constexpr int PROW = KS + 8;              // LDS row pitch (bf16), keeps 16-byte alignment
   __shared__ __attribute__((aligned(16))) uint16_t sP[2][2][32 * NNB * PROW];  // [buf][hi/lo]
@@ -439,7 +480,7 @@ DenseSplit plan_dense_f32(int64_t n, int64_t lda, int r, const void* A) {
   if (dense_f32_wide(n, lda, r, A)) {
     d.wide = true;
     d.gx = (n + 127) / 128;
-    int64_t ks = (256 + d.gx - 1) / d.gx;
+    int64_t ks = (256 + d.gx - 1) / d.gx;  // one tile workgroup per CU
     const int64_t kmax = (n + 255) / 256;
     if (ks > kmax) ks = kmax;
     if (ks < 1) ks = 1;
@@ -466,12 +507,16 @@ DenseSplit plan_dense_f32(int64_t n, int64_t lda, int r, const void* A) {
 
 void launch_apass_f32(const float* A, int64_t lda, const float* P, int64_t n, int r,
                       const DenseSplit& d, float* Bpart, int64_t pstride, const State* st,
-                      hipStream_t s) {
+                      hipStream_t s, const RhoJob& rj) {
   dim3 grid((unsigned)d.gx, (unsigned)d.ksplit);
-  if (d.wide)
+  if (d.wide) {
+    if (rj.G) grid.y += 1;
     hipLaunchKernelGGL(k_apass_f32w, grid, dim3(256), 0, s, A, lda, P, n, r, d.kchunk, Bpart,
-                       pstride, st);
-  else if (r > 32)
+                       pstride, st, rj);
+    return;
+  }
+  if (rj.G) launch_rho(rj.G, rj.r, rj.st, s);
+  if (r > 32)
     hipLaunchKernelGGL(k_apass_f32<2>, grid, dim3(256), 0, s, A, lda, P, n, r, d.kchunk, Bpart,
                        pstride, st);
   else
@@ -499,14 +544,14 @@ DenseSplit plan_dense_bf16(int64_t n) {
 void launch_apass_bf16x3(const uint16_t* Ahi, const uint16_t* Alo, int64_t ldb,
                          const uint16_t* Pthi, const uint16_t* Ptlo, int64_t ldp, int64_t n, int r,
                          const DenseSplit& d, float* Bpart, int64_t pstride, const State* st,
-                         hipStream_t s) {
-  dim3 grid((unsigned)d.gx, (unsigned)d.ksplit);
+                         hipStream_t s, const RhoJob& rj) {
+  dim3 grid((unsigned)d.gx, (unsigned)d.ksplit + (rj.G ? 1u : 0u));
   if (r > 32)
     hipLaunchKernelGGL(k_apass_bf16x3<2>, grid, dim3(256), 0, s, Ahi, Alo, ldb, Pthi, Ptlo, ldp,
-                       n, r, d.kchunk, Bpart, pstride, st);
+                       n, r, d.kchunk, Bpart, pstride, st, rj);
   else
     hipLaunchKernelGGL(k_apass_bf16x3<1>, grid, dim3(256), 0, s, Ahi, Alo, ldb, Pthi, Ptlo, ldp,
-                       n, r, d.kchunk, Bpart, pstride, st);
+                       n, r, d.kchunk, Bpart, pstride, st, rj);
 }
 
 }  // namespace snmf

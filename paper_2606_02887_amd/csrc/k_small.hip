@@ -3,6 +3,7 @@
 // input validation counts, and the BF16 hi/lo split of the precision form.
 #include "common.hpp"
 #include "kernels.hpp"
+#include "rho.hpp"
 
 namespace snmf {
 
@@ -181,110 +182,7 @@ __global__ __launch_bounds__(kThreads) void k_bgram_reduce(const BInst* __restri
 }
 
 // ----------------------------------------------------------------------------- rho
-// Largest eigenvalue of the symmetric positive semidefinite r x r matrix G (r <= 64).
-// r steps of the Lanczos recurrence from the all-ones vector: lane i of wave w holds
-// G[i][16w .. 16w+15] in registers, the four partial products of G q are combined in
-// LDS in wave order, so every wave then holds the same vector and derives the same
-// alpha_j, beta_j (DPP wave sums).  All four waves then locate the largest eigenvalue of
-// the tridiagonal matrix by bisection with Sturm counts, 256 trial shifts per round.
-// Without re-orthogonalisation the extreme Ritz value is still accurate: loss of
-// orthogonality only adds copies of converged Ritz values (Paige), and r steps span the
-// whole space in exact arithmetic; on Gram matrices of planted, graph and clustered
-// spectra the result agrees with a dense symmetric eigensolver to a few ulps.
-// G >= 0 elementwise (a Gram of a nonnegative block), so its Perron vector is
-// nonnegative and the all-ones start has a nonzero component along it.
-__device__ __forceinline__ void rho_body(const double* __restrict__ G, int r,
-                                         State* __restrict__ st) {
-  __shared__ __attribute__((aligned(16))) double sq[kMaxRank];
-  __shared__ double sp[4][kMaxRank];
-  __shared__ double sa[kMaxRank], sb[kMaxRank];
-  __shared__ int sfirst[kThreads / kWave];
-  const int t = threadIdx.x, i = t & 63, w = t >> 6;
-  double grow[16];
-  double gn2 = 0.0;
-#pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    const int col = 16 * w + k;
-    grow[k] = (i < r && col < r) ? G[i * r + col] : 0.0;
-    gn2 = __builtin_fma(grow[k], grow[k], gn2);
-  }
-  sp[w][i] = gn2;
-  double q = i < r ? 1.0 / sqrt((double)r) : 0.0;
-  if (w == 0) sq[i] = q;
-  __syncthreads();
-  const double tol = 1e-15 * sqrt(wave_sum((sp[0][i] + sp[1][i]) + (sp[2][i] + sp[3][i])));
-  __syncthreads();
-  double qprev = 0.0, bprev = 0.0;
-  int m = 0;
-  for (int j = 0; j < r; ++j) {
-    double w0 = 0.0, w1 = 0.0, w2 = 0.0, w3 = 0.0;
-#pragma unroll
-    for (int k = 0; k < 16; k += 4) {
-      const double2 u = *(const double2*)&sq[16 * w + k];
-      const double2 v = *(const double2*)&sq[16 * w + k + 2];
-      w0 = __builtin_fma(grow[k], u.x, w0);
-      w1 = __builtin_fma(grow[k + 1], u.y, w1);
-      w2 = __builtin_fma(grow[k + 2], v.x, w2);
-      w3 = __builtin_fma(grow[k + 3], v.y, w3);
-    }
-    sp[w][i] = (w0 + w1) + (w2 + w3);
-    __syncthreads();
-    double wv = (sp[0][i] + sp[1][i]) + (sp[2][i] + sp[3][i]);  // (G q_j)_i
-    const double a = wave_sum(q * wv);
-    wv -= a * q + bprev * qprev;
-    const double b = sqrt(wave_sum(wv * wv));
-    if (t == 0) {
-      sa[j] = a;
-      sb[j] = b;
-    }
-    m = j + 1;
-    if (!(b > tol)) break;
-    qprev = q;
-    q = wv / b;
-    bprev = b;
-    if (w == 0) sq[i] = q;
-    __syncthreads();
-  }
-  __syncthreads();
-  // bounds for the largest eigenvalue of T = tridiag(sb, sa, sb)
-  double lo = -1e300, hi = -1e300;
-  for (int k = 0; k < m; ++k) {
-    const double off = (k > 0 ? fabs(sb[k - 1]) : 0.0) + (k + 1 < m ? fabs(sb[k]) : 0.0);
-    lo = fmax(lo, sa[k]);
-    hi = fmax(hi, sa[k] + off);
-  }
-  const double div = (double)(kThreads + 1);
-  for (int round = 0; round < 40 && hi - lo > 2.0 * 2.220446049250313e-16 * fabs(hi); ++round) {
-    const double x = lo + (hi - lo) * (double)(t + 1) / div;
-    // Sturm count: number of eigenvalues of T below x (negative LDL^T pivots)
-    int cnt = 0;
-    double d = 1.0;
-    for (int k = 0; k < m; ++k) {
-      d = (sa[k] - x) - (k > 0 ? sb[k - 1] * sb[k - 1] / d : 0.0);
-      if (fabs(d) < 1e-300) d = -1e-300;
-      cnt += d < 0.0;
-    }
-    // shifts above every eigenvalue (cnt == m) form a suffix; find its first index
-    const unsigned long long above = __ballot(cnt == m);
-    if ((t & 63) == 0) sfirst[t >> 6] = above ? (t & ~63) + __ffsll((long long)above) - 1 : kThreads;
-    __syncthreads();
-    const int first = min(min(sfirst[0], sfirst[1]), min(sfirst[2], sfirst[3]));
-    __syncthreads();
-    const double nlo = lo + (hi - lo) * (double)first / div;
-    const double nhi = first < kThreads ? lo + (hi - lo) * (double)(first + 1) / div : hi;
-    lo = first > 0 ? nlo : lo;
-    hi = nhi;
-  }
-  if (t == 0) {
-    const double rho = 0.5 * (lo + hi);
-    st->rho = rho;
-    if (!(rho > 0.0) || !(rho < 1e308)) {
-      st->status = 9;  // SNMF_E_BREAKDOWN
-      st->done = 1;
-    }
-  }
-}
-
+// rho = ||G||_2 with the body in rho.hpp (Lanczos, then division-free multisection).
 __global__ __launch_bounds__(kThreads) void k_rho(const double* __restrict__ G, int r,
                                                   State* __restrict__ st) {
   if (st->done) return;

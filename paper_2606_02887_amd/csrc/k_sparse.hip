@@ -12,30 +12,65 @@
 //   also applies lam); B = U T is a row-local product.
 #include "common.hpp"
 #include "kernels.hpp"
+#include "rho.hpp"
 
 namespace snmf {
 
-template <typename T, int RP>
+template <typename T, int RP, bool RHO>
 __global__ __launch_bounds__(256) void k_spmm(const int64_t* __restrict__ rowptr,
                                               const int32_t* __restrict__ col,
                                               const T* __restrict__ val, const T* __restrict__ X,
                                               int64_t n, int r, T* __restrict__ Y,
                                               const T* __restrict__ X2, double* __restrict__ part,
                                               const int32_t* __restrict__ gate,
-                                              const int32_t* __restrict__ gate2) {
+                                              const int32_t* __restrict__ gate2, RhoJob rj) {
   if ((gate && gate[0]) || (gate2 && gate2[0])) return;
+  // RHO: workgroup 0 computes rho = ||G||_2 (dispatched first, so it runs beside the
+  // product) and the product uses the workgroups after it.  A template flag, so the plain
+  // product keeps its lower register count.
+  constexpr int64_t b0 = RHO ? 1 : 0;
+  if constexpr (RHO) {
+    if (blockIdx.x == 0) {
+      rho_body(rj.G, rj.r, rj.st);
+      return;
+    }
+  }
   constexpr int NS = kWave / RP;  // nonzero slots per wave
   __shared__ double sred[kThreads / kWave * kNumPart];
   const int lane = threadIdx.x & 63;
   const int c = lane % RP, slot = lane / RP;
-  const int64_t wave_id = ((int64_t)blockIdx.x * kThreads + threadIdx.x) / kWave;
-  const int64_t nwaves = (int64_t)gridDim.x * kThreads / kWave;
+  const int64_t bid = (int64_t)blockIdx.x - b0;
+  const int64_t wave_id = (bid * kThreads + threadIdx.x) / kWave;
+  const int64_t nwaves = ((int64_t)gridDim.x - b0) * kThreads / kWave;
   double dot = 0.0;
   for (int64_t row = wave_id; row < n; row += nwaves) {
     const int64_t b = rowptr[row], e = rowptr[row + 1];
     T acc = T(0);
-    if (c < r) {
-      for (int64_t z = b + slot; z < e; z += NS) acc += val[z] * X[(int64_t)col[z] * r + c];
+    // up to 64 (column, value) pairs per load, broadcast by cross-lane shuffles so that
+    // the gathers of four nonzeros per lane group are in flight together
+    for (int64_t zb = b; zb < e; zb += kWave) {
+      const int cnt = e - zb < kWave ? (int)(e - zb) : kWave;
+      const int mc = lane < cnt ? col[zb + lane] : 0;
+      const T mv = lane < cnt ? val[zb + lane] : T(0);
+      for (int k0 = 0; k0 < cnt; k0 += 4 * NS) {  // uniform trip count: all lanes shuffle
+        int ck[4];
+        T vk[4], pk[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int k = k0 + slot + u * NS;
+          const int src = k < kWave ? k : kWave - 1;
+          ck[u] = __shfl(mc, src, kWave);
+          vk[u] = __shfl(mv, src, kWave);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int k = k0 + slot + u * NS;
+          pk[u] = (c < r && k < cnt) ? X[(int64_t)ck[u] * r + c] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (k0 + slot + u * NS < cnt) acc += vk[u] * pk[u];
+      }
     }
 #pragma unroll
     for (int o = RP; o < kWave; o <<= 1) acc += __shfl_xor(acc, o, kWave);
@@ -49,7 +84,7 @@ __global__ __launch_bounds__(256) void k_spmm(const int64_t* __restrict__ rowptr
   if (!X2) return;
   double v[1] = {dot};
   block_sum<1>(v, sred);
-  if (threadIdx.x == 0) part[(size_t)blockIdx.x * kNumPart] = v[0];
+  if (threadIdx.x == 0) part[(size_t)bid * kNumPart] = v[0];
 }
 
 // ----------------------------------------------------------------------------- batched
@@ -238,8 +273,11 @@ __global__ __launch_bounds__(256) void k_lai_ut(const T* __restrict__ U, int ell
 typedef float f32x4l __attribute__((ext_vector_type(4)));
 constexpr int kLaiRows = 64;                    // rows per LDS slab
 constexpr int kLaiMaxTiles = 8;                 // 16x16 output tiles per wave
-constexpr int kLaiPitchA = kMaxEll + 16;        // U slab pitch (== 16 mod 64: k-major reads)
-constexpr int kLaiPitchP = kMaxRank + 16;       // P slab / T pitch
+// LDS pitches (dynamic shared memory sized to ell and r): a k-major read (16 consecutive
+// columns of 4 rows) is conflict-free with pitch == 16 mod 64, a row-major read (4
+// consecutive columns of 16 rows) with pitch == 4 mod 64.
+__host__ __device__ inline int lai_pitch_k(int w) { return (w + 63) / 64 * 64 + 16; }
+__host__ __device__ inline int lai_pitch_r(int w) { return (w + 63) / 64 * 64 + 4; }
 
 // Stage rows [row0, row0 + 64) of an n x w row-major array into LDS (pitch `pitch`),
 // zero beyond n and w; float4 loads when w % 4 == 0.
@@ -262,16 +300,53 @@ __device__ __forceinline__ void lai_stage(const float* __restrict__ X, int64_t n
   }
 }
 
+// Register-staged slab copy for the pipelined loop: up to NV float4 per thread of the
+// 64 x w slab starting at row0 (w % 4 == 0, 16-byte aligned rows); rows >= n read as 0.
+template <int NV>
+struct SlabRegs {
+  float4 v[NV];
+  __device__ __forceinline__ void load(const float* __restrict__ X, int64_t n, int w, int64_t row0) {
+    const int w4 = w >> 2;
+    const int64_t rows = n - row0 < kLaiRows ? n - row0 : kLaiRows;
+    const float4* src = reinterpret_cast<const float4*>(X + row0 * w);
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      const int e = threadIdx.x + q * 256;
+      const int i = e / w4;
+      v[q] = (e < kLaiRows * w4 && i < rows) ? src[e] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  }
+  __device__ __forceinline__ void store(float* __restrict__ sX, int w, int pitch) const {
+    const int w4 = w >> 2;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      const int e = threadIdx.x + q * 256;
+      if (e < kLaiRows * w4) {
+        const int i = e / w4, c = (e - i * w4) * 4;
+        *reinterpret_cast<float4*>(&sX[i * pitch + c]) = v[q];
+      }
+    }
+  }
+};
+
 // Partial T_b = U_b^T P_b over a contiguous slab of rows; FP32 partial (ell x r) per
 // workgroup.  Output tiles (ell/16) x (r/16), tile t handled by wave t % 4.
 __global__ __launch_bounds__(256) void k_lai_utp32(const float* __restrict__ U, int ell,
                                                    const float* __restrict__ P, int64_t n, int r,
                                                    int64_t rows_per_block,
                                                    float* __restrict__ part,
-                                                   const int32_t* __restrict__ gate) {
+                                                   const int32_t* __restrict__ gate,
+                                                   RhoJob rj) {
   if (gate && gate[0]) return;
-  __shared__ __attribute__((aligned(16))) float sU[kLaiRows * kLaiPitchA];
-  __shared__ __attribute__((aligned(16))) float sP[kLaiRows * kLaiPitchP];
+  // with rj.G set, the last workgroup computes rho = ||G||_2 beside the slabs
+  if (rj.G && blockIdx.x == gridDim.x - 1) {
+    rho_body(rj.G, rj.r, rj.st);
+    return;
+  }
+  extern __shared__ __attribute__((aligned(16))) float lai_smem[];
+  const int PA = lai_pitch_k(ell), PP = lai_pitch_k(r);
+  float* sU = lai_smem;
+  float* sP = lai_smem + kLaiRows * PA;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int TL = (ell + 15) / 16, TRr = (r + 15) / 16, nt = TL * TRr;
   f32x4l acc[kLaiMaxTiles];
@@ -279,11 +354,30 @@ __global__ __launch_bounds__(256) void k_lai_utp32(const float* __restrict__ U, 
   for (int q = 0; q < kLaiMaxTiles; ++q) acc[q] = f32x4l{0.f, 0.f, 0.f, 0.f};
   const int64_t rb = (int64_t)blockIdx.x * rows_per_block;
   const int64_t re = rb + rows_per_block < n ? rb + rows_per_block : n;
+  // pipelined when both slabs take 16-byte loads: the next slab is in flight in registers
+  // while the MFMAs run on the current one
+  const bool vec = (ell & 3) == 0 && (r & 3) == 0 &&
+                   ((reinterpret_cast<uintptr_t>(U) | reinterpret_cast<uintptr_t>(P)) & 15) == 0;
+  SlabRegs<kLaiRows * kMaxEll / 4 / 256> ru;
+  SlabRegs<kLaiRows * kMaxRank / 4 / 256> rp;
+  if (vec && rb < re) {
+    ru.load(U, re, ell, rb);
+    rp.load(P, re, r, rb);
+  }
   for (int64_t t0 = rb; t0 < re; t0 += kLaiRows) {
     __syncthreads();
-    lai_stage(U, re, ell, t0, sU, kLaiPitchA);
-    lai_stage(P, re, r, t0, sP, kLaiPitchP);
+    if (vec) {
+      ru.store(sU, ell, PA);
+      rp.store(sP, r, PP);
+    } else {
+      lai_stage(U, re, ell, t0, sU, PA);
+      lai_stage(P, re, r, t0, sP, PP);
+    }
     __syncthreads();
+    if (vec && t0 + kLaiRows < re) {
+      ru.load(U, re, ell, t0 + kLaiRows);
+      rp.load(P, re, r, t0 + kLaiRows);
+    }
 #pragma unroll
     for (int q = 0; q < kLaiMaxTiles; ++q) {
       const int t = w + 4 * q;
@@ -292,8 +386,8 @@ __global__ __launch_bounds__(256) void k_lai_utp32(const float* __restrict__ U, 
         f32x4l d = acc[q];
         for (int k0 = 0; k0 < kLaiRows; k0 += 4) {
           const int k = k0 + (lane >> 4);
-          const float a = sU[k * kLaiPitchA + i0 + (lane & 15)];
-          const float b = sP[k * kLaiPitchP + j0 + (lane & 15)];
+          const float a = sU[k * PA + i0 + (lane & 15)];
+          const float b = sP[k * PP + j0 + (lane & 15)];
           d = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, d, 0, 0, 0);
         }
         acc[q] = d;
@@ -355,13 +449,14 @@ __global__ __launch_bounds__(256) void k_lai_ut32(const float* __restrict__ U, i
                                                   float* __restrict__ B,
                                                   const int32_t* __restrict__ gate) {
   if (gate && gate[0]) return;
-  constexpr int PA = kMaxEll + 4;  // U slab pitch (== 4 mod 64: row-major reads)
-  __shared__ __attribute__((aligned(16))) float sU[kLaiRows * PA];
-  __shared__ float sT[kMaxEll * kLaiPitchP];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  extern __shared__ __attribute__((aligned(16))) float lai_smem[];
+  const int PA = lai_pitch_r(ell), PT = lai_pitch_k(r);
   const int ellp = (ell + 3) & ~3;  // K padded to the MFMA step (zeros beyond ell)
-  for (int e = threadIdx.x; e < ellp * kLaiPitchP; e += 256) {
-    const int k = e / kLaiPitchP, c = e - k * kLaiPitchP;
+  float* sU = lai_smem;
+  float* sT = lai_smem + kLaiRows * PA;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int e = threadIdx.x; e < ellp * PT; e += 256) {
+    const int k = e / PT, c = e - k * PT;
     sT[e] = (k < ell && c < r) ? TT[k * r + c] : 0.f;
   }
   const int TRr = (r + 15) / 16, nt = 4 * TRr;
@@ -380,7 +475,7 @@ __global__ __launch_bounds__(256) void k_lai_ut32(const float* __restrict__ U, i
       for (int k0 = 0; k0 < ellp; k0 += 4) {
         const int k = k0 + (lane >> 4);
         const float a = sU[(i0 + (lane & 15)) * PA + k];
-        const float b = sT[k * kLaiPitchP + j0 + (lane & 15)];
+        const float b = sT[k * PT + j0 + (lane & 15)];
         d = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, d, 0, 0, 0);
       }
       const int j = j0 + (lane & 15);
@@ -406,14 +501,22 @@ __global__ __launch_bounds__(256) void k_lai_ut32(const float* __restrict__ U, i
 template <typename T>
 void launch_spmm(const int64_t* rowptr, const int32_t* col, const T* val, const T* X, int64_t n,
                  int r, T* Y, const T* X2, double* part, const int32_t* gate,
-                 const int32_t* gate2, hipStream_t s) {
+                 const int32_t* gate2, hipStream_t s, const RhoJob& rj) {
   int64_t nb = (n + 3) / 4;
   if (X2) nb = spmm_dot_grid(n);
   if (nb > 65535 * 4) nb = 65535 * 4;
   if (nb < 1) nb = 1;
-  SNMF_DISPATCH_RP2(rank_pad(r),
-                    hipLaunchKernelGGL((k_spmm<T, RP>), dim3((unsigned)nb), dim3(256), 0, s,
-                                       rowptr, col, val, X, n, r, Y, X2, part, gate, gate2))
+  if (rj.G) {
+    SNMF_DISPATCH_RP2(rank_pad(r),
+                      hipLaunchKernelGGL((k_spmm<T, RP, true>), dim3((unsigned)(nb + 1)), dim3(256),
+                                         0, s, rowptr, col, val, X, n, r, Y, X2, part, gate, gate2,
+                                         rj))
+  } else {
+    SNMF_DISPATCH_RP2(rank_pad(r),
+                      hipLaunchKernelGGL((k_spmm<T, RP, false>), dim3((unsigned)nb), dim3(256), 0,
+                                         s, rowptr, col, val, X, n, r, Y, X2, part, gate, gate2,
+                                         rj))
+  }
 }
 
 int spmm_dot_grid(int64_t n) {
@@ -432,22 +535,35 @@ int lai_blocks(int64_t n) {
 
 template <typename T>
 void launch_lai(const T* U, int ell, const double* lam, const T* P, int64_t n, int r,
-                double* part, T* TT, T* B, const int32_t* gate, hipStream_t s) {
+                double* part, T* TT, T* B, const int32_t* gate, hipStream_t s, const RhoJob& rj) {
   if constexpr (sizeof(T) == 4) {
+    // FP32 partials, at most lai_blocks(n) of them (the FP64 partial buffer's count)
     int nb = lai_blocks(n);
     if (nb > 256) nb = 256;
     const int64_t rpb = ((n + nb - 1) / nb + kLaiRows - 1) / kLaiRows * kLaiRows;
     nb = (int)((n + rpb - 1) / rpb);
-    hipLaunchKernelGGL(k_lai_utp32, dim3(nb), dim3(256), 0, s, (const float*)U, ell,
-                       (const float*)P, n, r, rpb, (float*)part, gate);
+    static bool attr_set = false;  // allow up to 96 KB of dynamic LDS (ell 128, r 64: 75 KB)
+    if (!attr_set) {
+      (void)hipFuncSetAttribute((const void*)k_lai_ut32,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
+      (void)hipFuncSetAttribute((const void*)k_lai_utp32,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
+      attr_set = true;
+    }
+    const size_t lds1 = (size_t)kLaiRows * (lai_pitch_k(ell) + lai_pitch_k(r)) * 4;
+    hipLaunchKernelGGL(k_lai_utp32, dim3(nb + (rj.G ? 1 : 0)), dim3(256), lds1, s,
+                       (const float*)U, ell, (const float*)P, n, r, rpb, (float*)part, gate, rj);
     hipLaunchKernelGGL(k_lai_reduce32, dim3((ell * r + 63) / 64), dim3(256), 0, s,
                        (const float*)part, nb, ell, r, lam, (float*)TT, gate);
     int64_t tiles = (n + kLaiRows - 1) / kLaiRows;
-    if (tiles > 2048) tiles = 2048;
-    hipLaunchKernelGGL(k_lai_ut32, dim3((unsigned)tiles), dim3(256), 0, s, (const float*)U, ell,
-                       (const float*)TT, n, r, (float*)B, gate);
+    if (tiles > 4096) tiles = 4096;
+    const size_t lds2 =
+        ((size_t)kLaiRows * lai_pitch_r(ell) + (size_t)((ell + 3) & ~3) * lai_pitch_k(r)) * 4;
+    hipLaunchKernelGGL(k_lai_ut32, dim3((unsigned)tiles), dim3(256), lds2, s, (const float*)U,
+                       ell, (const float*)TT, n, r, (float*)B, gate);
     return;
   }
+  if (rj.G) launch_rho(rj.G, rj.r, rj.st, s);
   const int nb = lai_blocks(n);
   const int64_t rpb = (n + nb - 1) / nb;
   hipLaunchKernelGGL(k_lai_utp<T>, dim3(nb), dim3(256), 0, s, U, ell, P, n, r, rpb, part, gate);
@@ -462,9 +578,9 @@ void launch_lai(const T* U, int ell, const double* lam, const T* P, int64_t n, i
 #define SNMF_INST_SP(T)                                                                      \
   template void launch_spmm<T>(const int64_t*, const int32_t*, const T*, const T*, int64_t,  \
                                int, T*, const T*, double*, const int32_t*, const int32_t*,   \
-                               hipStream_t);                                                 \
+                               hipStream_t, const RhoJob&);                                  \
   template void launch_lai<T>(const T*, int, const double*, const T*, int64_t, int, double*, \
-                              T*, T*, const int32_t*, hipStream_t);
+                              T*, T*, const int32_t*, hipStream_t, const RhoJob&);
 SNMF_INST_SP(float)
 SNMF_INST_SP(double)
 

@@ -17,6 +17,14 @@ struct DenseSplit {
   bool wide = false;    // FP32: 16-byte A loads (r in (32, 64] even, n and lda multiples of 4)
 };
 
+// rho = ||G||_2 of an r x r FP64 Gram, written to st->rho, run inside another kernel's
+// launch (G == nullptr: none).
+struct RhoJob {
+  const double* G = nullptr;
+  int r = 0;
+  State* st = nullptr;
+};
+
 int rank_pad(int r);
 int gram_blocks(int64_t n);  // Gram slabs of an n-row partner (shared by single and batched solves)
 
@@ -75,19 +83,20 @@ void launch_sum_parts(const T* part, int ks, int64_t stride, T* out, int64_t N, 
 void launch_apass_f64(const double* A, int64_t lda, const double* P, int64_t n, int r, double* B,
                       const State* st, hipStream_t s);
 DenseSplit plan_dense_f32(int64_t n, int64_t lda, int r, const void* A);
+// With rj.G set, rho is computed in the same launch (wide path) or just before it.
 void launch_apass_f32(const float* A, int64_t lda, const float* P, int64_t n, int r,
                       const DenseSplit& d, float* Bpart, int64_t pstride, const State* st,
-                      hipStream_t s);
+                      hipStream_t s, const RhoJob& rj = RhoJob{});
 DenseSplit plan_dense_bf16(int64_t n);
 void launch_apass_bf16x3(const uint16_t* Ahi, const uint16_t* Alo, int64_t ldb,
                          const uint16_t* Pthi, const uint16_t* Ptlo, int64_t ldp, int64_t n, int r,
                          const DenseSplit& d, float* Bpart, int64_t pstride, const State* st,
-                         hipStream_t s);
+                         hipStream_t s, const RhoJob& rj = RhoJob{});
 
 template <typename T>
 void launch_spmm(const int64_t* rowptr, const int32_t* col, const T* val, const T* X, int64_t n,
                  int r, T* Y, const T* X2, double* part, const int32_t* gate,
-                 const int32_t* gate2, hipStream_t s);
+                 const int32_t* gate2, hipStream_t s, const RhoJob& rj = RhoJob{});
 int spmm_dot_grid(int64_t n);
 template <typename T>
 void launch_bspmm(const BGraph* graphs, const int32_t* sblk_graph, int sblocks,
@@ -96,7 +105,8 @@ void launch_breset(State* states, const BInst* inst, int ninst, hipStream_t s);
 void launch_all_done(const State* states, int ninst, int32_t* flag, hipStream_t s);
 template <typename T>
 void launch_lai(const T* U, int ell, const double* lam, const T* P, int64_t n, int r,
-                double* part, T* TT, T* B, const int32_t* gate, hipStream_t s);
+                double* part, T* TT, T* B, const int32_t* gate, hipStream_t s,
+                const RhoJob& rj = RhoJob{});
 
 template <typename T>
 void launch_init(const T* X, const T* P, const T* Bpart, int ksplit, int64_t bstride, T* C, T* g,

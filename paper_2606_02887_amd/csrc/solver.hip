@@ -42,8 +42,7 @@ struct snmf_plan {
   int prec = SNMF_F32;
   size_t esz = 4;
   hipStream_t s = nullptr;     // private stream of the plan (default priority)
-  hipStream_t side = nullptr;  // second stream: rho runs beside the A-pass (default priority)
-  hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_fork = nullptr, ev_join = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
   // device memory (one allocation, carved)
   void* pool = nullptr;
   void *Wb = nullptr, *Hb = nullptr, *C = nullptr, *g = nullptr, *Z = nullptr, *D = nullptr;
@@ -70,9 +69,6 @@ struct snmf_plan {
     if (pool) (void)hipFree(pool);
     if (ev_in) (void)hipEventDestroy(ev_in);
     if (ev_out) (void)hipEventDestroy(ev_out);
-    if (ev_fork) (void)hipEventDestroy(ev_fork);
-    if (ev_join) (void)hipEventDestroy(ev_join);
-    if (side) (void)hipStreamDestroy(side);
     if (s) (void)hipStreamDestroy(s);
   }
 };
@@ -199,11 +195,17 @@ snmf_status check_csr(snmf_plan* pl, const snmf_matrix* M, const char* what, boo
 }
 
 // ------------------------------------------------------------------ one half-step
+// B = A P (partials in Bpart).  With rj.G set, rho = ||G||_2 as well: in one more
+// workgroup of the A-pass launch (FP64 dense: a launch of its own just before it).
 template <typename T>
-snmf_status apass(snmf_plan* pl, const T* P, hipStream_t s) {
+snmf_status apass(snmf_plan* pl, const T* P, hipStream_t s, const RhoJob& rj = RhoJob{}) {
   const int64_t n = pl->n;
   const int r = pl->r;
   const int32_t* gate = &pl->st->done;
+  if (rj.G && pl->A.fmt == SNMF_DENSE && pl->prec == SNMF_F64) {
+    launch_rho(rj.G, rj.r, rj.st, s);
+    HIP_TRY(hipGetLastError());
+  }
   switch (pl->A.fmt) {
     case SNMF_DENSE:
       if (pl->prec == SNMF_F64) {
@@ -211,20 +213,20 @@ snmf_status apass(snmf_plan* pl, const T* P, hipStream_t s) {
                          (double*)pl->Bpart, pl->st, s);
       } else if (pl->prec == SNMF_F32) {
         launch_apass_f32((const float*)pl->A.dense, pl->A.ld, (const float*)P, n, r, pl->ds,
-                         (float*)pl->Bpart, n * r, pl->st, s);
+                         (float*)pl->Bpart, n * r, pl->st, s, rj);
       } else {
         launch_split_pt((const float*)P, n, r, pl->ldb, pl->Pthi, pl->Ptlo, pl->st, s);
         launch_apass_bf16x3(pl->Ahi, pl->Alo, pl->ldb, pl->Pthi, pl->Ptlo, pl->ldb, n, r, pl->ds,
-                            (float*)pl->Bpart, n * r, pl->st, s);
+                            (float*)pl->Bpart, n * r, pl->st, s, rj);
       }
       break;
     case SNMF_CSR:
       launch_spmm<T>(pl->A.rowptr, pl->A.col, (const T*)pl->A.val, P, n, r, (T*)pl->Bpart, nullptr,
-                     nullptr, gate, nullptr, s);
+                     nullptr, gate, nullptr, s, rj);
       break;
     default:
       launch_lai<T>((const T*)pl->A.U, (int)pl->A.ell, pl->A.lam, P, n, r, pl->lai_part,
-                    (T*)pl->TT, (T*)pl->Bpart, gate, s);
+                    (T*)pl->TT, (T*)pl->Bpart, gate, s, rj);
       break;
   }
   HIP_TRY(hipGetLastError());
@@ -235,9 +237,9 @@ int ksplit_of(const snmf_plan* pl) {
   return (pl->A.fmt == SNMF_DENSE && pl->prec != SNMF_F64) ? pl->ds.ksplit : 1;
 }
 
-// Start of a half-step up to and including init: G, rho (on the side stream, beside the
-// A-pass), the A-pass and the gradient.  The side stream joins before the first inner
-// kernel, which is the first reader of rho.
+// Start of a half-step up to and including init: G, rho (in or just before the A-pass,
+// on the same stream: a second stream would cost more in cross-queue waits than rho
+// takes), the A-pass and the gradient.  The first reader of rho is the first inner kernel.
 template <typename T>
 snmf_status half_start(snmf_plan* pl, T* X, const T* P, int is_hstep, bool with_rho,
                        hipStream_t s) {
@@ -246,14 +248,13 @@ snmf_status half_start(snmf_plan* pl, T* X, const T* P, int is_hstep, bool with_
   const int gi = is_hstep ? 1 : 0;
   launch_gram<T>(P, n, r, pl->gram_part, pl->gram_blocks, pl->G64[gi], (T*)pl->GT[gi], pl->st, s);
   HIP_TRY(hipGetLastError());
+  RhoJob rj;
   if (with_rho) {
-    HIP_TRY(hipEventRecord(pl->ev_fork, s));
-    HIP_TRY(hipStreamWaitEvent(pl->side, pl->ev_fork, 0));
-    launch_rho(pl->G64[gi], r, pl->st, pl->side);
-    HIP_TRY(hipGetLastError());
-    HIP_TRY(hipEventRecord(pl->ev_join, pl->side));
+    rj.G = pl->G64[gi];
+    rj.r = r;
+    rj.st = pl->st;
   }
-  SNMF_TRY(apass<T>(pl, P, s));
+  SNMF_TRY(apass<T>(pl, P, s, rj));
   const bool lap = pl->lap && is_hstep;
   if (lap) {
     launch_spmm<T>(pl->L.rowptr, pl->L.col, (const T*)pl->L.val, X, n, r, (T*)pl->LX, nullptr,
@@ -263,7 +264,6 @@ snmf_status half_start(snmf_plan* pl, T* X, const T* P, int is_hstep, bool with_
                  lap ? (const T*)pl->LX : nullptr, (const T*)pl->GT[gi], n, r, is_hstep, pl->kp,
                  pl->st, pl->partsA, s);
   HIP_TRY(hipGetLastError());
-  if (with_rho) HIP_TRY(hipStreamWaitEvent(s, pl->ev_join, 0));
   return SNMF_OK;
 }
 
@@ -381,11 +381,8 @@ snmf_status plan_create(const snmf_matrix* A, int32_t r, const snmf_params* p, h
   pl->prec = p->prec;
   pl->esz = elt_size(p->prec);
   HIP_TRY(hipStreamCreateWithFlags(&pl->s, hipStreamNonBlocking));
-  HIP_TRY(hipStreamCreateWithFlags(&pl->side, hipStreamNonBlocking));
   HIP_TRY(hipEventCreateWithFlags(&pl->ev_in, hipEventDisableTiming));
   HIP_TRY(hipEventCreateWithFlags(&pl->ev_out, hipEventDisableTiming));
-  HIP_TRY(hipEventCreateWithFlags(&pl->ev_fork, hipEventDisableTiming));
-  HIP_TRY(hipEventCreateWithFlags(&pl->ev_join, hipEventDisableTiming));
   if (user) {
     HIP_TRY(hipEventRecord(pl->ev_in, user));
     HIP_TRY(hipStreamWaitEvent(pl->s, pl->ev_in, 0));

@@ -63,7 +63,8 @@ def test_rho_near_degenerate_spectrum(S):
 
 
 # ------------------------------------------------------------------ Gram and A-pass
-@pytest.mark.parametrize("n,r", [(1, 1), (37, 5), (500, 10), (1029, 33), (2048, 64)])
+@pytest.mark.parametrize("n,r", [(1, 1), (37, 5), (500, 10), (1029, 33), (2048, 64), (4100, 34),
+                                 (4608, 64)])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_gram_and_dense_apass(S, n, r, prec):
     rng = np.random.default_rng(n * 100 + r)
