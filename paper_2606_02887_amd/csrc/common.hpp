@@ -13,7 +13,7 @@ constexpr int kNumPart = 16;           // FP64 partial sums per workgroup
 constexpr int kTraceFields = 10;       // doubles per outer-iteration trace record
 
 constexpr int kMaxInner = 64;         // largest number of inner iterations per half-step
-constexpr int kInnerGrid = 256;        // workgroups of the row-tile kernels (re-reduced)
+constexpr int kInnerGrid = 1024;       // workgroups of the row-tile kernels (re-reduced)
 
 // Counters of the setup kernels that finish a reduction in their last workgroup.
 enum Counter { C_GRAM = 0, C_INIT, C_STEP1, C_STEP2, C_NORM, C_LAI, C_LAPRED, C_MISC, C_COUNT };

@@ -157,14 +157,17 @@ __device__ __forceinline__ void write_parts(double* __restrict__ parts, int bid,
     for (int j = 0; j < K; ++j) parts[(size_t)bid * kNumPart + j] = v[j];
 }
 
-// This thread's share (workgroup b = tid; nb <= 256) of K consecutive partial-sum slots
-// starting at `first`; block_sum then adds the shares in a fixed order.
+// This thread's share (workgroups b = tid, tid + 256, ... in increasing b) of K consecutive
+// partial-sum slots starting at `first`; block_sum then adds the shares in a fixed order.
 template <int K>
 __device__ __forceinline__ void load_slots(const double* __restrict__ part, int nb, int first,
                                            double (&out)[K]) {
 #pragma unroll
-  for (int j = 0; j < K; ++j)
-    out[j] = (int)threadIdx.x < nb ? part[(size_t)threadIdx.x * kNumPart + first + j] : 0.0;
+  for (int j = 0; j < K; ++j) out[j] = 0.0;
+  for (int b = threadIdx.x; b < nb; b += kThreads) {
+#pragma unroll
+    for (int j = 0; j < K; ++j) out[j] += part[(size_t)b * kNumPart + first + j];
+  }
 }
 
 // ----------------------------------------------------------------------------- instances

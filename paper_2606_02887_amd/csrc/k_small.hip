@@ -8,89 +8,125 @@
 namespace snmf {
 
 // ----------------------------------------------------------------------------- Gram
-// Each workgroup forms the FP64 Gram of a contiguous slab of rows of P; a second kernel
-// adds the slabs in block order (deterministic) and writes G in FP64 and in the iterate
-// type.  RPG is the rank rounded up to a power of two: with E = RPG^2 >= 256 entries each
-// thread owns a BS x BS block of G; with E < 256 the 256 / E row groups of the workgroup
-// each take every (256/E)-th row of the tile and their sums are added in group order.
+// Each workgroup forms the FP64 Gram of a contiguous slab of rows of P on the FP64 matrix
+// cores; a second kernel adds the slabs in block order (deterministic) and writes G in
+// FP64 and in the iterate type.  The slab is cut into k-steps of four rows, dealt to the
+// four wavefronts in turn (k-step j to wavefront j % 4).  RPG, the rank rounded up to a
+// power of two, gives NB = max(1, RPG/16) column blocks of 16; a wavefront accumulates the
+// NB (NB + 1) / 2 tiles (qa <= qb) of the upper block triangle with
+//   D(qa, qb) += A B,  A = P[k rows][16 qa + 0..15]^T (16 x 4),  B = P[k rows][16 qb + 0..15],
+// where lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16], both the value of row
+// l / 16 of the k-step and column 16 q + l % 16, and holds D[l / 16 + 4 v][l % 16].
+// The four wavefront sums are added as (w0 + w1) + (w2 + w3) in LDS, and each entry a <= b
+// is written to both (a, b) and (b, a), so the slab Gram is exactly symmetric.
+typedef double gd4 __attribute__((ext_vector_type(4)));
+
 template <int RPG>
 struct GramCfg {
-  static constexpr int E = RPG * RPG;
-  static constexpr int RG = E >= kThreads ? 1 : kThreads / E;
-  static constexpr int EPT = E >= kThreads ? E / kThreads : 1;
-  static constexpr int BS = EPT == 16 ? 4 : (EPT == 4 ? 2 : 1);
-  static constexpr int TR = 64;                   // rows per LDS tile
-  static constexpr int LDP = RPG + (BS > 1 ? 2 : 1);
+  static constexpr int NB = RPG >= 16 ? RPG / 16 : 1;  // 16-column blocks
+  static constexpr int NT = NB * (NB + 1) / 2;         // upper-triangle tiles
+  static constexpr int U = 4;                          // k-steps per batch of loads
 };
+
+template <int NB>
+__device__ __forceinline__ constexpr int gram_tile(int qa, int qb) {
+  // index of tile (qa, qb), qa <= qb, in row-major order of the upper triangle
+  return qa * NB - qa * (qa - 1) / 2 + (qb - qa);
+}
 
 template <typename T, int RPG>
 __device__ __forceinline__ void gram_slab(const T* __restrict__ P, int r, int64_t rb, int64_t re,
                                           double* __restrict__ out) {
   typedef GramCfg<RPG> C;
-  constexpr int BS = C::BS, TR = C::TR, LDP = C::LDP, RG = C::RG, E = C::E;
-  __shared__ __attribute__((aligned(16))) double sP[TR * LDP];
-  __shared__ double sR[RG > 1 ? kThreads : 1];
-  const int t = threadIdx.x;
-  int a0, b0, grp;
-  if constexpr (RG > 1) {
-    const int e = t % E;
-    grp = t / E;
-    a0 = e / RPG;
-    b0 = e % RPG;
-  } else {
-    grp = 0;
-    a0 = BS * (t / (RPG / BS));
-    b0 = BS * (t % (RPG / BS));
+  constexpr int NB = C::NB, NT = C::NT, U = C::U;
+  __shared__ __attribute__((aligned(16))) double sacc[2][NT][4][kWave];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int kr = lane >> 4, c16 = lane & 15;
+  gd4 acc[NT];
+#pragma unroll
+  for (int q = 0; q < NT; ++q) acc[q] = gd4{0.0, 0.0, 0.0, 0.0};
+  const int64_t nst = (re - rb + 3) / 4;  // k-steps of the slab
+  // column of block q: clamped to a valid one, the value masked when out of range
+  bool cok[NB];
+  int ccl[NB];
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    const int cc = 16 * q + c16;
+    cok[q] = cc < r;
+    ccl[q] = cc < r ? cc : r - 1;
   }
-  double acc[BS][BS];
+  auto load = [&](double (&x)[U][NB], int64_t j0) {
 #pragma unroll
-  for (int u = 0; u < BS; ++u)
+    for (int u = 0; u < U; ++u) {
+      const int64_t row = rb + 4 * (j0 + 4 * u) + kr;
+      const bool rok = row < re;
+      const int64_t rc = rok ? row : re - 1;
 #pragma unroll
-    for (int v = 0; v < BS; ++v) acc[u][v] = 0.0;
-  for (int64_t t0 = rb; t0 < re; t0 += TR) {
-    __syncthreads();
-    for (int e = t; e < TR * RPG; e += kThreads) {
-      const int i = e / RPG, c = e % RPG;
-      const int64_t row = t0 + i;
-      sP[i * LDP + c] = (row < re && c < r) ? (double)P[row * r + c] : 0.0;
-    }
-    __syncthreads();
-    if constexpr (RG > 1) {
-      double s0 = acc[0][0];
-      for (int i = grp; i < TR; i += RG) s0 = __builtin_fma(sP[i * LDP + a0], sP[i * LDP + b0], s0);
-      acc[0][0] = s0;
-    } else {
-#pragma unroll 4
-      for (int i = 0; i < TR; ++i) {
-        double x[BS], y[BS];
-#pragma unroll
-        for (int u = 0; u < BS; ++u) {
-          x[u] = sP[i * LDP + a0 + u];
-          y[u] = sP[i * LDP + b0 + u];
-        }
-#pragma unroll
-        for (int u = 0; u < BS; ++u)
-#pragma unroll
-          for (int v = 0; v < BS; ++v) acc[u][v] = __builtin_fma(x[u], y[v], acc[u][v]);
+      for (int q = 0; q < NB; ++q) {
+        const double v = (double)P[rc * r + ccl[q]];
+        x[u][q] = (rok && cok[q]) ? v : 0.0;
       }
     }
+  };
+  auto mma = [&](const double (&x)[U][NB]) {
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int qa = 0; qa < NB; ++qa)
+#pragma unroll
+        for (int qb = qa; qb < NB; ++qb) {
+          const int tq = gram_tile<NB>(qa, qb);
+          acc[tq] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[u][qa], x[u][qb], acc[tq], 0, 0, 0);
+        }
+  };
+  // wavefront `wave` takes k-steps wave, wave + 4, ...; batches of U of them, two in
+  // flight (the k-steps past the slab load clamped rows and contribute zeros)
+  const int64_t mine = nst > wave ? (nst - wave + 3) / 4 : 0;
+  const int64_t nbat = (mine + U - 1) / U;
+  double xa[U][NB], xb[U][NB];
+  if (nbat > 0) load(xa, wave);
+  for (int64_t bt = 0; bt < nbat; bt += 2) {
+    const int64_t j0 = wave + 4 * U * bt;
+    if (bt + 1 < nbat) load(xb, j0 + 4 * U);
+    mma(xa);
+    if (bt + 2 < nbat) load(xa, j0 + 8 * U);
+    if (bt + 1 < nbat) mma(xb);
   }
-  if constexpr (RG > 1) {
-    sR[t] = acc[0][0];
-    __syncthreads();
-    if (t < E) {
-      double sum = 0.0;
+  // (w0 + w1) + (w2 + w3): odd waves park their sums, even waves add them; wave 2 parks
+  // its pair sum and wave 0 adds it
+  auto put = [&](int slot) {
 #pragma unroll
-      for (int g = 0; g < RG; ++g) sum += sR[g * E + t];
-      if (a0 < r && b0 < r) out[a0 * r + b0] = sum;
-    }
-  } else {
+    for (int q = 0; q < NT; ++q)
 #pragma unroll
-    for (int u = 0; u < BS; ++u)
+      for (int v = 0; v < 4; ++v) sacc[slot][q][v][lane] = acc[q][v];
+  };
+  auto add = [&](int slot) {
 #pragma unroll
-      for (int v = 0; v < BS; ++v) {
-        const int a = a0 + u, b = b0 + v;
-        if (a < r && b < r) out[a * r + b] = acc[u][v];
+    for (int q = 0; q < NT; ++q)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[q][v] += sacc[slot][q][v][lane];
+  };
+  if (wave & 1) put(wave >> 1);
+  __syncthreads();
+  if (!(wave & 1)) add(wave >> 1);
+  __syncthreads();
+  if (wave == 2) put(0);
+  __syncthreads();
+  if (wave == 0) {
+    add(0);
+#pragma unroll
+    for (int qa = 0; qa < NB; ++qa)
+#pragma unroll
+      for (int qb = qa; qb < NB; ++qb) {
+        const int tq = gram_tile<NB>(qa, qb);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int a = 16 * qa + kr + 4 * v, b = 16 * qb + c16;
+          if (a < r && b < r && (qa < qb || a <= b)) {
+            out[a * r + b] = acc[tq][v];
+            out[b * r + a] = acc[tq][v];
+          }
+        }
       }
   }
 }
