@@ -60,12 +60,16 @@ struct snmf_plan {
   int gram_blocks = 1;
   double normA2 = 0.0;
   KParams kp{};
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t gexec = nullptr;
+  // captured outer iterations: one, and kGraphRun of them back to back (one launch per
+  // run saves the per-launch gap between outer iterations)
+  hipGraph_t graph = nullptr, graph_run = nullptr;
+  hipGraphExec_t gexec = nullptr, gexec_run = nullptr;
 
   ~snmf_plan() {
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (graph) (void)hipGraphDestroy(graph);
+    if (gexec_run) (void)hipGraphExecDestroy(gexec_run);
+    if (graph_run) (void)hipGraphDestroy(graph_run);
     if (pool) (void)hipFree(pool);
     if (ev_in) (void)hipEventDestroy(ev_in);
     if (ev_out) (void)hipEventDestroy(ev_out);
@@ -193,6 +197,9 @@ snmf_status check_csr(snmf_plan* pl, const snmf_matrix* M, const char* what, boo
   if (sumsq) *sumsq = st3[0];
   return SNMF_OK;
 }
+
+// outer iterations per replay of the multi-iteration graph
+constexpr int kGraphRun = 8;
 
 // ------------------------------------------------------------------ one half-step
 // B = A P (partials in Bpart).  With rj.G set, rho = ||G||_2 as well: in one more
@@ -537,9 +544,10 @@ snmf_status plan_solve(snmf_plan* pl, const void* W0, void* W_out, void* Ht_out,
   launch_reset_state(pl->st, pl->normA2, pl->s);
   HIP_TRY(hipGetLastError());
   const int every = std::max(1, pl->p.check_every);
-  if (pl->p.use_graph && !pl->gexec) {
+  auto capture = [&](int iters, hipGraph_t* g, hipGraphExec_t* ge) -> snmf_status {
     HIP_TRY(hipStreamBeginCapture(pl->s, hipStreamCaptureModeThreadLocal));
-    snmf_status cs = outer_any(pl, pl->s);
+    snmf_status cs = SNMF_OK;
+    for (int u = 0; u < iters && cs == SNMF_OK; ++u) cs = outer_any(pl, pl->s);
     hipGraph_t gr = nullptr;
     hipError_t ce = hipStreamEndCapture(pl->s, &gr);
     if (cs != SNMF_OK) {
@@ -547,16 +555,30 @@ snmf_status plan_solve(snmf_plan* pl, const void* W0, void* W_out, void* Ht_out,
       return cs;
     }
     if (ce != hipSuccess) return fail(SNMF_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(ce));
-    pl->graph = gr;
-    HIP_TRY(hipGraphInstantiate(&pl->gexec, gr, nullptr, nullptr, 0));
-  }
-  for (int i = 0; i < pl->p.max_outer; ++i) {
-    if (pl->gexec) {
+    *g = gr;
+    HIP_TRY(hipGraphInstantiate(ge, gr, nullptr, nullptr, 0));
+    return SNMF_OK;
+  };
+  const int run = std::min(kGraphRun, every);
+  if (pl->p.use_graph && !pl->gexec) SNMF_TRY(capture(1, &pl->graph, &pl->gexec));
+  if (pl->p.use_graph && run > 1 && pl->p.max_outer >= run && !pl->gexec_run)
+    SNMF_TRY(capture(run, &pl->graph_run, &pl->gexec_run));
+  // outer iterations i .. : a captured run when it ends at or before the next check of the
+  // done flag and at or before max_outer, else single iterations
+  for (int i = 0; i < pl->p.max_outer;) {
+    const int next_check = (i / every + 1) * every;
+    const int room = std::min(pl->p.max_outer, next_check) - i;
+    if (pl->gexec_run && room >= run) {
+      HIP_TRY(hipGraphLaunch(pl->gexec_run, pl->s));
+      i += run;
+    } else if (pl->gexec) {
       HIP_TRY(hipGraphLaunch(pl->gexec, pl->s));
+      i += 1;
     } else {
       SNMF_TRY(outer_any(pl, pl->s));
+      i += 1;
     }
-    if ((i + 1) % every == 0 && i + 1 < pl->p.max_outer) {
+    if (i % every == 0 && i < pl->p.max_outer) {
       int32_t done = 0;
       HIP_TRY(hipMemcpyAsync(&done, &pl->st->done, sizeof(done), hipMemcpyDeviceToHost, pl->s));
       HIP_TRY(hipStreamSynchronize(pl->s));
