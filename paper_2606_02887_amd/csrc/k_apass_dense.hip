@@ -384,8 +384,8 @@ __global__ __launch_bounds__(256) void k_apass_bf16x3(const uint16_t* __restrict
   auto load_a = [&](u16x8 (&x)[2][4], int64_t k) {
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-      x[0][s] = jok ? __builtin_nontemporal_load((const u16x8*)(ah + k + 8 * s)) : zero;
-      x[1][s] = jok ? __builtin_nontemporal_load((const u16x8*)(al + k + 8 * s)) : zero;
+      x[0][s] = jok ? *(const u16x8*)(ah + k + 8 * s) : zero;
+      x[1][s] = jok ? *(const u16x8*)(al + k + 8 * s) : zero;
     }
   };
   int buf = 0;
