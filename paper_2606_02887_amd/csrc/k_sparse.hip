@@ -273,6 +273,10 @@ __global__ __launch_bounds__(256) void k_lai_ut(const T* __restrict__ U, int ell
 typedef float f32x4l __attribute__((ext_vector_type(4)));
 constexpr int kLaiRows = 64;                    // rows per LDS slab
 constexpr int kLaiMaxTiles = 8;                 // 16x16 output tiles per wave
+// Grids measured at n = 200000, ell = 64, r = 32 (A-pass time): B = U T with 1024
+// workgroups 63 us, 4096 76 us; T = U^T P with 256 partials beat 512.
+constexpr int kLaiUtGrid = 1024;   // workgroups of B = U T (pipelined slabs)
+constexpr int kLaiUtpGrid = 256;   // workgroups (partials) of T = U^T P
 // LDS pitches (dynamic shared memory sized to ell and r): a k-major read (16 consecutive
 // columns of 4 rows) is conflict-free with pitch == 16 mod 64, a row-major read (4
 // consecutive columns of 16 rows) with pitch == 4 mod 64.
@@ -461,14 +465,24 @@ __global__ __launch_bounds__(256) void k_lai_ut32(const float* __restrict__ U, i
   }
   const int TRr = (r + 15) / 16, nt = 4 * TRr;
   const int64_t ntiles = (n + kLaiRows - 1) / kLaiRows;
+  // pipelined when U takes 16-byte loads: the workgroup's next slab is in flight in
+  // registers while the MFMAs run on the current one
+  const bool vec = (ell & 3) == 0 && (reinterpret_cast<uintptr_t>(U) & 15) == 0;
+  SlabRegs<kLaiRows * kMaxEll / 4 / 256> ru;
+  if (vec && (int64_t)blockIdx.x < ntiles) ru.load(U, n, ell, (int64_t)blockIdx.x * kLaiRows);
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int64_t row0 = tile * kLaiRows;
     __syncthreads();
-    lai_stage(U, n, ell, row0, sU, PA);
-    if ((ell & 3) != 0)  // zero the K padding columns of the slab
-      for (int e = threadIdx.x; e < kLaiRows * (ellp - ell); e += 256)
-        sU[(e / (ellp - ell)) * PA + ell + e % (ellp - ell)] = 0.f;
+    if (vec) {
+      ru.store(sU, ell, PA);
+    } else {
+      lai_stage(U, n, ell, row0, sU, PA);
+      if ((ell & 3) != 0)  // zero the K padding columns of the slab
+        for (int e = threadIdx.x; e < kLaiRows * (ellp - ell); e += 256)
+          sU[(e / (ellp - ell)) * PA + ell + e % (ellp - ell)] = 0.f;
+    }
     __syncthreads();
+    if (vec && tile + gridDim.x < ntiles) ru.load(U, n, ell, (tile + gridDim.x) * kLaiRows);
     for (int t = w; t < nt; t += 4) {
       const int i0 = 16 * (t / TRr), j0 = 16 * (t % TRr);
       f32x4l d = {0.f, 0.f, 0.f, 0.f};
@@ -539,7 +553,7 @@ void launch_lai(const T* U, int ell, const double* lam, const T* P, int64_t n, i
   if constexpr (sizeof(T) == 4) {
     // FP32 partials, at most lai_blocks(n) of them (the FP64 partial buffer's count)
     int nb = lai_blocks(n);
-    if (nb > 256) nb = 256;
+    if (nb > kLaiUtpGrid) nb = kLaiUtpGrid;
     const int64_t rpb = ((n + nb - 1) / nb + kLaiRows - 1) / kLaiRows * kLaiRows;
     nb = (int)((n + rpb - 1) / rpb);
     static bool attr_set = false;  // allow up to 96 KB of dynamic LDS (ell 128, r 64: 75 KB)
@@ -556,7 +570,7 @@ void launch_lai(const T* U, int ell, const double* lam, const T* P, int64_t n, i
     hipLaunchKernelGGL(k_lai_reduce32, dim3((ell * r + 63) / 64), dim3(256), 0, s,
                        (const float*)part, nb, ell, r, lam, (float*)TT, gate);
     int64_t tiles = (n + kLaiRows - 1) / kLaiRows;
-    if (tiles > 4096) tiles = 4096;
+    if (tiles > kLaiUtGrid) tiles = kLaiUtGrid;
     const size_t lds2 =
         ((size_t)kLaiRows * lai_pitch_r(ell) + (size_t)((ell + 3) & ~3) * lai_pitch_k(r)) * 4;
     hipLaunchKernelGGL(k_lai_ut32, dim3((unsigned)tiles), dim3(256), lds2, s, (const float*)U,
