@@ -333,3 +333,30 @@ def mlp_init(r: int, hidden: int = 128, seed: int = SEED_BASE + 16):
             "b1": np.zeros(hidden),
             "M2": rng.standard_normal((r, hidden)) * (0.5 / np.sqrt(hidden)),
             "b2": np.full(r, np.log(np.e - 1.0))}
+
+
+# --------------------------------------------------------------------------- HBM-sized inputs
+def random_symmetric_csr(n: int, mean_degree: float, seed: int) -> sp.csr_matrix:
+    """A symmetric CSR with about n * mean_degree nonzeros at uniform random positions and
+    values uniform(0, 1] (both triangles stored, no self-loops): the shape of the graph
+    products at sizes that do not fit the caches, for timing the sparse A-pass."""
+    rng = np.random.default_rng(seed)
+    m = int(n * mean_degree / 2)
+    i = rng.integers(0, n, size=m, dtype=np.int64)
+    j = rng.integers(0, n, size=m, dtype=np.int64)
+    lo, hi = np.minimum(i, j), np.maximum(i, j)
+    key = np.unique(lo[lo != hi] * n + hi[lo != hi])   # each unordered pair once
+    i, j = key // n, key % n
+    v = 1.0 - rng.random(i.size)
+    a = sp.coo_matrix((np.concatenate([v, v]), (np.concatenate([i, j]), np.concatenate([j, i]))),
+                      shape=(n, n)).tocsr()
+    a.sort_indices()
+    return a
+
+
+def random_lowrank(n: int, ell: int, seed: int):
+    """(U, lam): a Gaussian n x ell factor and unit weights, for timing the LAI products at
+    sizes that do not fit the caches (the timing does not depend on U being orthonormal)."""
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((n, ell)).astype(np.float32), np.ones(ell)
+

@@ -71,3 +71,14 @@ def test_range_finder_orthonormal_and_near_optimal():
     best = np.sqrt(np.sort(ev ** 2)[:-k].sum())
     err = np.linalg.norm(Ad - (U * lam) @ U.T)
     assert best <= err <= 1.05 * best
+
+
+def test_random_symmetric_csr_and_lowrank():
+    a = gen.random_symmetric_csr(5000, 12.0, 7)
+    assert a.shape == (5000, 5000) and abs(a.nnz / 5000 - 12.0) < 1.0
+    assert (a - a.T).nnz == 0 and a.diagonal().max() == 0.0
+    assert a.data.min() > 0.0 and a.data.max() <= 1.0
+    b = gen.random_symmetric_csr(5000, 12.0, 7)
+    assert (a != b).nnz == 0
+    U, lam = gen.random_lowrank(100, 8, 3)
+    assert U.shape == (100, 8) and U.dtype == np.float32 and np.all(lam == 1.0)
