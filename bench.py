@@ -512,7 +512,7 @@ def main():
     roof = {"bound": "mfma", "achieved": ach32, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": ach32 / FP32_PEAK_TFLOPS,
             "traffic": _traffic("k_apass_dense.hip", "k_apass_f32w"),
-            "kernel": "k_apass_f32 (B = A P, FP32 MFMA)", "ms_per_launch": ms32,
+            "kernel": "k_apass_f32w (B = A P, FP32 MFMA)", "ms_per_launch": ms32,
             "algorithmic_per_launch": f"{flops:.4g} flop (2 n^2 r)"}
     forms["bf16x3"]["apass"] = {"bound": "hbm", "achieved": achbf, "peak": HBM_PEAK_GBS,
                                 "unit": "GB/s", "frac": achbf / HBM_PEAK_GBS,
