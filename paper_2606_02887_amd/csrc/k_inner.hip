@@ -488,7 +488,9 @@ __device__ __forceinline__ T second_dir(T z, T gz, T alpha) {  // max(0, Z - alp
 // f(Z) - f(X) = <g + grad f(Z), Z - X>/2 (exact for a quadratic).
 // phase 0: whole step.  Laplacian path: phase 1 writes Z and Z - X (into D); phase 2
 // reads them back together with L(Z - X).
-template <typename T, int RP>
+// V = 0: phase 0 only (a compile-time constant, so the Laplacian operands and their
+// registers drop out); V = 1: any phase.
+template <typename T, int RP, int V>
 __global__ __launch_bounds__(kThreads) void k_step1(
     const T* __restrict__ X, const T* __restrict__ g, T* __restrict__ Z, T* __restrict__ D,
     const T* __restrict__ LdZ, const T* __restrict__ GT, const double* __restrict__ Gcur,
@@ -496,6 +498,7 @@ __global__ __launch_bounds__(kThreads) void k_step1(
     KParams kp, State* __restrict__ st, const double* __restrict__ partsA,
     double* __restrict__ partsB, const double* __restrict__ partsC, double* __restrict__ trace,
     BMap bm) {
+  if constexpr (V == 0) phase = 0;
   const Loc lc = locate(bm, n, st, trace, kp.lam);
   st = lc.st;
   trace = lc.trace;
@@ -652,13 +655,19 @@ __device__ __forceinline__ double line_search(double delta, double q, double dZ,
 // <C, X+>, <P, X+>, ||X+ - P||^2, ||min(X+, g+)||^2 [and <X+, L X+>]; <S, L S> in slot 8.
 // phase 0: whole step.  Laplacian path: phase 1 writes X+ into Z and S into D; phase 2
 // reads them back with L S and keeps the buffer L X current (L X+ = L X + L S).
-template <typename T, int RP>
+// V = 0: phase 0 of a W-step, V = 1: phase 0 of an H-step (both compile-time, so the
+// unused operands and sums drop out of the registers); V = 2: any phase and step.
+template <typename T, int RP, int V>
 __global__ __launch_bounds__(kThreads) void k_step2(
     T* __restrict__ X, T* __restrict__ g, T* __restrict__ Z, T* __restrict__ D,
     const T* __restrict__ LS, const T* __restrict__ C, const T* __restrict__ P,
     T* __restrict__ LXb, const T* __restrict__ GT, int64_t n, int r, int k, int phase,
     int is_hstep, KParams kp, State* __restrict__ st, const double* __restrict__ partsB,
     const double* __restrict__ partsD, int nbD, double* __restrict__ partsC, BMap bm) {
+  if constexpr (V < 2) {
+    phase = 0;
+    is_hstep = V;
+  }
   const Loc lc = locate(bm, n, st, nullptr, kp.lam);
   st = lc.st;
   n = lc.n;
@@ -861,10 +870,17 @@ void launch_step1(const T* X, const T* g, T* Z, T* D, const T* LdZ, const T* GT,
                   double* partsB, const double* partsC, double* trace, hipStream_t s,
                   const BMap& bm, int grid) {
   if (grid <= 0) grid = inner_grid(n, r);
-  SNMF_DISPATCH_RP(rank_pad(r),
-                   hipLaunchKernelGGL((k_step1<T, RP>), dim3(grid), dim3(kThreads), 0, s, X, g,
-                                      Z, D, LdZ, GT, Gcur, Gprev, n, r, k, phase, is_hstep, kp, st,
-                                      partsA, partsB, partsC, trace, bm))
+  if (phase == 0) {
+    SNMF_DISPATCH_RP(rank_pad(r),
+                     hipLaunchKernelGGL((k_step1<T, RP, 0>), dim3(grid), dim3(kThreads), 0, s, X,
+                                        g, Z, D, LdZ, GT, Gcur, Gprev, n, r, k, phase, is_hstep,
+                                        kp, st, partsA, partsB, partsC, trace, bm))
+  } else {
+    SNMF_DISPATCH_RP(rank_pad(r),
+                     hipLaunchKernelGGL((k_step1<T, RP, 1>), dim3(grid), dim3(kThreads), 0, s, X,
+                                        g, Z, D, LdZ, GT, Gcur, Gprev, n, r, k, phase, is_hstep,
+                                        kp, st, partsA, partsB, partsC, trace, bm))
+  }
 }
 
 template <typename T>
@@ -873,10 +889,19 @@ void launch_step2(T* X, T* g, T* Z, T* D, const T* LS, const T* C, const T* P, T
                   const KParams& kp, State* st, const double* partsB, const double* partsD,
                   int nbD, double* partsC, hipStream_t s, const BMap& bm, int grid) {
   if (grid <= 0) grid = inner_grid(n, r);
-  SNMF_DISPATCH_RP(rank_pad(r),
-                   hipLaunchKernelGGL((k_step2<T, RP>), dim3(grid), dim3(kThreads), 0, s, X, g,
-                                      Z, D, LS, C, P, LXb, GT, n, r, k, phase, is_hstep, kp, st,
-                                      partsB, partsD, nbD, partsC, bm))
+#define SNMF_STEP2(V)                                                                          \
+  SNMF_DISPATCH_RP(rank_pad(r),                                                                \
+                   hipLaunchKernelGGL((k_step2<T, RP, V>), dim3(grid), dim3(kThreads), 0, s, X, \
+                                      g, Z, D, LS, C, P, LXb, GT, n, r, k, phase, is_hstep, kp, \
+                                      st, partsB, partsD, nbD, partsC, bm))
+  if (phase != 0) {
+    SNMF_STEP2(2)
+  } else if (is_hstep) {
+    SNMF_STEP2(1)
+  } else {
+    SNMF_STEP2(0)
+  }
+#undef SNMF_STEP2
 }
 
 #define SNMF_INST(T)                                                                            \
