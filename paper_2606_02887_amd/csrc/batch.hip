@@ -130,7 +130,7 @@ snmf_status binner(snmf_batch* b, T* X, const T* P, int is_hstep, hipStream_t s)
     for (const auto& c : b->cls)
       launch_step2<T>(X, (T*)b->g, (T*)b->Z, (T*)b->D, nullptr, (const T*)b->C, P, nullptr, GT, 0,
                       c.r, k, 0, is_hstep, b->kp, b->states, b->partsB, nullptr, 0, b->partsC, s,
-                      b->bmap(c), c.blocks);
+                      b->bmap(c), c.blocks, b->p.inner_iters - 1);
   }
   HIP_TRY(hipGetLastError());
   return SNMF_OK;

@@ -655,8 +655,12 @@ __device__ __forceinline__ double line_search(double delta, double q, double dZ,
 // <C, X+>, <P, X+>, ||X+ - P||^2, ||min(X+, g+)||^2 [and <X+, L X+>]; <S, L S> in slot 8.
 // phase 0: whole step.  Laplacian path: phase 1 writes X+ into Z and S into D; phase 2
 // reads them back with L S and keeps the buffer L X current (L X+ = L X + L S).
-// V = 0: phase 0 of a W-step, V = 1: phase 0 of an H-step (both compile-time, so the
-// unused operands and sums drop out of the registers); V = 2: any phase and step.
+// V = 0: phase 0 of a W-step; V = 1: phase 0 of the last inner iteration of an H-step,
+// which also forms the monitor sums; V = 3: phase 0 of an earlier H-step iteration, which
+// does not (their monitor sums would be overwritten unread); all three compile-time, so
+// unused operands and sums drop out of the registers.  V = 2: any phase and step.
+// An H-step that stops early (exact stationarity, stop[k]) forms the monitor sums in the
+// first skipped step 2 instead: X and g no longer change, so they are the final ones.
 template <typename T, int RP, int V>
 __global__ __launch_bounds__(kThreads) void k_step2(
     T* __restrict__ X, T* __restrict__ g, T* __restrict__ Z, T* __restrict__ D,
@@ -664,9 +668,9 @@ __global__ __launch_bounds__(kThreads) void k_step2(
     T* __restrict__ LXb, const T* __restrict__ GT, int64_t n, int r, int k, int phase,
     int is_hstep, KParams kp, State* __restrict__ st, const double* __restrict__ partsB,
     const double* __restrict__ partsD, int nbD, double* __restrict__ partsC, BMap bm) {
-  if constexpr (V < 2) {
+  if constexpr (V != 2) {
     phase = 0;
-    is_hstep = V;
+    is_hstep = V == 0 ? 0 : 1;
   }
   const Loc lc = locate(bm, n, st, nullptr, kp.lam);
   st = lc.st;
@@ -696,7 +700,8 @@ __global__ __launch_bounds__(kThreads) void k_step2(
   const bool w0 = lc.bid == 0 && threadIdx.x == 0;
   const int64_t ntiles = (n + TM - 1) / TM;
   // loads first: State scalars, partial sums of step 1 (and <D, L D>), G, the first tile
-  const int skip = st->done | st->stop[k];
+  const int done = st->done;
+  const int skip = done | st->stop[k];
   const double e_k = st->e[k], beta_k2 = st->beta[k];
   double pb[4] = {0.0, 0.0, 0.0, 0.0}, pd[1] = {0.0};
   if (phase != 2) {
@@ -705,7 +710,7 @@ __global__ __launch_bounds__(kThreads) void k_step2(
   }
   T gv[TileCfg<RP>::NG];
   if (phase != 1) load_G<T, RP>(GT, r, gv);
-  const bool mon = is_hstep && phase != 1;
+  const bool mon = V == 3 ? false : (is_hstep && phase != 1);
   const bool lap = phase == 2;
   T x[8], zz[8], dd[8], go[8], cv[8], pv[8], ls[8], lx[8];
   auto load_tile = [&](int64_t row0) {
@@ -724,7 +729,31 @@ __global__ __launch_bounds__(kThreads) void k_step2(
     }
   };
   if (lc.bid < ntiles) load_tile((int64_t)lc.bid * TM);
-  if (skip) return;
+  if (skip) {
+    if constexpr (V == 1 || V == 3) {
+      if (!done) {  // stopped H-step: monitor sums of the final X (S = 0, g unchanged)
+        double v[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        for (int64_t t = lc.bid; t < ntiles; t += lc.nb) {
+          const int64_t tb = t * TM * r;
+#pragma unroll
+          for (int p = 0; p < 8; ++p) {
+            if (t * TM + lr[p] < n && cl[p] < r) {
+              const T xv = ldo(tile_ptr(X, tb), bo[p]), gg = ldo(tile_ptr(g, tb), bo[p]);
+              const double xd = (double)xv, pd2 = (double)ldo(tile_ptr(P, tb), bo[p]);
+              v[3] += (double)ldo(tile_ptr(C, tb), bo[p]) * xd;
+              v[4] += pd2 * xd;
+              v[5] += (xd - pd2) * (xd - pd2);
+              const double mn = (double)(xv < gg ? xv : gg);
+              v[6] += mn * mn;
+            }
+          }
+        }
+        block_sum<9>(v, sm.red);
+        write_parts<9>(partsC, lc.bid, v);
+      }
+    }
+    return;
+  }
   double beta;
   if (phase != 2) {
     block_sum<4>(pb, sm.red);
@@ -797,7 +826,7 @@ __global__ __launch_bounds__(kThreads) void k_step2(
         v[1] += (double)sg[p] * (double)s;
         v[2] += (double)go[p] * (double)s;
         if (lap) v[8] += (double)s * (double)ls[p];
-        if (is_hstep) {
+        if (mon) {
           const double xv = (double)xn[p];
           v[3] += (double)cv[p] * xv;
           v[4] += (double)pv[p] * xv;
@@ -813,9 +842,9 @@ __global__ __launch_bounds__(kThreads) void k_step2(
       }
     }
   }
-  if (is_hstep || lap) {
+  if (mon || lap) {
     block_sum<9>(v, sm.red);
-  } else {  // a W-step without Laplacian produces only the first three sums
+  } else {  // a step without monitor sums or Laplacian produces only the first three
     double v3[3] = {v[0], v[1], v[2]};
     block_sum<3>(v3, sm.red);
     v[0] = v3[0];
@@ -887,7 +916,8 @@ template <typename T>
 void launch_step2(T* X, T* g, T* Z, T* D, const T* LS, const T* C, const T* P, T* LXb,
                   const T* GT, int64_t n, int r, int k, int phase, int is_hstep,
                   const KParams& kp, State* st, const double* partsB, const double* partsD,
-                  int nbD, double* partsC, hipStream_t s, const BMap& bm, int grid) {
+                  int nbD, double* partsC, hipStream_t s, const BMap& bm, int grid,
+                  int last_k) {
   if (grid <= 0) grid = inner_grid(n, r);
 #define SNMF_STEP2(V)                                                                          \
   SNMF_DISPATCH_RP(rank_pad(r),                                                                \
@@ -896,8 +926,10 @@ void launch_step2(T* X, T* g, T* Z, T* D, const T* LS, const T* C, const T* P, T
                                       st, partsB, partsD, nbD, partsC, bm))
   if (phase != 0) {
     SNMF_STEP2(2)
-  } else if (is_hstep) {
+  } else if (is_hstep && k >= last_k) {
     SNMF_STEP2(1)
+  } else if (is_hstep) {
+    SNMF_STEP2(3)
   } else {
     SNMF_STEP2(0)
   }
@@ -915,7 +947,7 @@ void launch_step2(T* X, T* g, T* Z, T* D, const T* LS, const T* C, const T* P, T
   template void launch_step2<T>(T*, T*, T*, T*, const T*, const T*, const T*, T*, const T*,    \
                                 int64_t, int, int, int, int, const KParams&, State*,            \
                                 const double*, const double*, int, double*, hipStream_t,        \
-                                const BMap&, int);
+                                const BMap&, int, int);
 SNMF_INST(float)
 SNMF_INST(double)
 

@@ -122,7 +122,8 @@ template <typename T>
 void launch_step2(T* X, T* g, T* Z, T* D, const T* LS, const T* C, const T* P, T* LXb,
                   const T* GT, int64_t n, int r, int k, int phase, int is_hstep,
                   const KParams& kp, State* st, const double* partsB, const double* partsD,
-                  int nbD, double* partsC, hipStream_t s, const BMap& bm = BMap{}, int grid = 0);
+                  int nbD, double* partsC, hipStream_t s, const BMap& bm = BMap{}, int grid = 0,
+                  int last_k = 0);  // last inner iteration (its H-step forms the monitor sums)
 
 template <typename T>
 void launch_stats2d(const T* x, int64_t rows, int64_t cols, int64_t ld, double* part, double* out,

@@ -291,7 +291,8 @@ snmf_status inner_step(snmf_plan* pl, T* X, const T* P, int is_hstep, int k, hip
     launch_step1<T>(X, g, Z, D, nullptr, GT, pl->G64[0], pl->G64[1], n, r, k, 0, is_hstep, pl->kp,
                     pl->st, pl->partsA, pl->partsB, pl->partsC, pl->trace, s);
     launch_step2<T>(X, g, Z, D, nullptr, (const T*)pl->C, P, nullptr, GT, n, r, k, 0, is_hstep,
-                    pl->kp, pl->st, pl->partsB, nullptr, 0, pl->partsC, s);
+                    pl->kp, pl->st, pl->partsB, nullptr, 0, pl->partsC, s, BMap{}, 0,
+                    pl->p.inner_iters - 1);
   } else {
     const int64_t* rp = pl->L.rowptr;
     const int32_t* ci = pl->L.col;

@@ -307,3 +307,24 @@ def test_error_codes(S):
     with pytest.raises(S.SnmfError) as e:
         S.solve(S.dense(_t(A, torch.float64)), _t(z, torch.float64), prm)
     assert e.value.name == "E_BREAKDOWN"
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_exact_stationary_start_stops_and_keeps_the_monitor(S, prec):
+    """Integer planted factors with lambda = 0 make every product exact, so W* is an exact
+    stationary point: the first inner iteration of each half-step gives S = 0 and the
+    later iterations stop (Algorithm 1 reaches <S,S> = 0).  The monitor record of the
+    stopped H-step must still be the final iterate's: zero residual and PG norm, and the
+    factors unchanged."""
+    rng = np.random.default_rng(5)
+    n, r = 70, 3
+    Wt = rng.integers(0, 3, size=(n, r)).astype(np.float64)
+    Wt[np.arange(r), np.arange(r)] = 2.0           # full column rank
+    A = Wt @ Wt.T
+    dt = torch.float32 if prec == "f32" else torch.float64
+    p = S.F32 if prec == "f32" else S.F64
+    W, Ht, info = S.solve(S.dense(_t(A, dt)), _t(Wt, dt), S.params(lam=0.0, prec=p, max_outer=3))
+    assert info["status"] == 0 and info["outer"] == 3
+    assert np.array_equal(W.double().cpu().numpy(), Wt)
+    assert np.array_equal(Ht.double().cpu().numpy(), Wt)
+    assert info["res_WH"] == 0.0 and info["pg_norm"] == 0.0
