@@ -602,7 +602,7 @@ __global__ __launch_bounds__(kThreads) void k_step1(
       const T dd = ok ? second_dir(z[p], gz, alpha) : T(0);
       d[p] = dd;
       if (ok) {
-        if (phase == 0) sto(tile_ptr(Z, tb), bo[p], z[p]);
+        // phase 0 keeps Z in registers only: step 2 recomputes it from X and g
         sto(tile_ptr(D, tb), bo[p], dd);
         v[0] += (double)gz * (double)dd;
         v[2] += (double)dd * (double)dd;
@@ -712,6 +712,9 @@ __global__ __launch_bounds__(kThreads) void k_step2(
   if (phase != 1) load_G<T, RP>(GT, r, gv);
   const bool mon = V == 3 ? false : (is_hstep && phase != 1);
   const bool lap = phase == 2;
+  // phase 0 (V != 2): Z = max(0, X - g / rho) is recomputed from X and g with step 1's
+  // arithmetic (the same bits), so Z is neither stored by step 1 nor read here
+  const T rinv = (T)(1.0 / st->rho);
   T x[8], zz[8], dd[8], go[8], cv[8], pv[8], ls[8], lx[8];
   auto load_tile = [&](int64_t row0) {
     const int64_t tb = row0 * r;
@@ -719,13 +722,14 @@ __global__ __launch_bounds__(kThreads) void k_step2(
     for (int p = 0; p < 8; ++p) {
       const bool ok = row0 + lr[p] < n && cl[p] < r;
       x[p] = ok ? ldo(tile_ptr(X, tb), bo[p]) : T(0);
-      zz[p] = ok ? ldo(tile_ptr(Z, tb), bo[p]) : T(0);
+      if constexpr (V == 2) zz[p] = ok ? ldo(tile_ptr(Z, tb), bo[p]) : T(0);
       dd[p] = (ok && phase != 2) ? ldo(tile_ptr(D, tb), bo[p]) : T(0);
       go[p] = (ok && phase != 1) ? ldo(tile_ptr(g, tb), bo[p]) : T(0);
       cv[p] = (ok && mon) ? ldo(tile_ptr(C, tb), bo[p]) : T(0);
       pv[p] = (ok && mon) ? ldo(tile_ptr(P, tb), bo[p]) : T(0);
       ls[p] = (ok && lap) ? ldo(tile_ptr(LS, tb), bo[p]) : T(0);
       lx[p] = (ok && lap && LXb) ? ldo(tile_ptr(LXb, tb), bo[p]) : T(0);
+      if constexpr (V != 2) zz[p] = first_proj(x[p], go[p], rinv);
     }
   };
   if (lc.bid < ntiles) load_tile((int64_t)lc.bid * TM);
