@@ -126,11 +126,11 @@ snmf_status binner(snmf_batch* b, T* X, const T* P, int is_hstep, hipStream_t s)
     for (const auto& c : b->cls)
       launch_step1<T>(X, (const T*)b->g, (T*)b->Z, (T*)b->D, nullptr, GT, b->G64[0], b->G64[1], 0,
                       c.r, k, 0, is_hstep, b->kp, b->states, b->partsA, b->partsB, b->partsC,
-                      b->traces, s, b->bmap(c), c.blocks);
+                      b->traces, s, b->bmap(c), c.blocks, 1);
     for (const auto& c : b->cls)
       launch_step2<T>(X, (T*)b->g, (T*)b->Z, (T*)b->D, nullptr, (const T*)b->C, P, nullptr, GT, 0,
                       c.r, k, 0, is_hstep, b->kp, b->states, b->partsB, nullptr, 0, b->partsC, s,
-                      b->bmap(c), c.blocks, b->p.inner_iters - 1);
+                      b->bmap(c), c.blocks, b->p.inner_iters - 1, 1);
   }
   HIP_TRY(hipGetLastError());
   return SNMF_OK;
@@ -157,7 +157,7 @@ snmf_status bfinalize(snmf_batch* b, hipStream_t s) {
   for (const auto& c : b->cls)
     launch_step1<T>(W, (const T*)b->g, (T*)b->Z, (T*)b->D, nullptr, (const T*)b->GT[0], b->G64[0],
                     b->G64[1], 0, c.r, 0, 0, 0, b->kp, b->states, b->partsA, b->partsB, b->partsC,
-                    b->traces, s, b->bmap(c), c.blocks);
+                    b->traces, s, b->bmap(c), c.blocks, 1);  // D is never read after it
   HIP_TRY(hipGetLastError());
   return SNMF_OK;
 }

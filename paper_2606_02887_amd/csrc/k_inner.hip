@@ -497,7 +497,7 @@ __global__ __launch_bounds__(kThreads) void k_step1(
     const double* __restrict__ Gprev, int64_t n, int r, int k, int phase, int is_hstep,
     KParams kp, State* __restrict__ st, const double* __restrict__ partsA,
     double* __restrict__ partsB, const double* __restrict__ partsC, double* __restrict__ trace,
-    BMap bm) {
+    BMap bm, int rd) {
   if constexpr (V == 0) phase = 0;
   const Loc lc = locate(bm, n, st, trace, kp.lam);
   st = lc.st;
@@ -602,8 +602,9 @@ __global__ __launch_bounds__(kThreads) void k_step1(
       const T dd = ok ? second_dir(z[p], gz, alpha) : T(0);
       d[p] = dd;
       if (ok) {
-        // phase 0 keeps Z in registers only: step 2 recomputes it from X and g
-        sto(tile_ptr(D, tb), bo[p], dd);
+        // phase 0 keeps Z in registers only, and D too when rd is set: step 2 recomputes
+        // them from X and g
+        if (phase != 0 || !rd) sto(tile_ptr(D, tb), bo[p], dd);
         v[0] += (double)gz * (double)dd;
         v[2] += (double)dd * (double)dd;
         v[3] += 0.5 * ((double)gvv[p] + (double)gz) * (double)dz;
@@ -661,13 +662,15 @@ __device__ __forceinline__ double line_search(double delta, double q, double dZ,
 // unused operands and sums drop out of the registers.  V = 2: any phase and step.
 // An H-step that stops early (exact stationarity, stop[k]) forms the monitor sums in the
 // first skipped step 2 instead: X and g no longer change, so they are the final ones.
+// rd (phase 0): step 1 stored no D; step 2 forms it again from X, g, G and alpha_k with
+// the same operations in the same order, so it holds the same bits.
 template <typename T, int RP, int V>
 __global__ __launch_bounds__(kThreads) void k_step2(
     T* __restrict__ X, T* __restrict__ g, T* __restrict__ Z, T* __restrict__ D,
     const T* __restrict__ LS, const T* __restrict__ C, const T* __restrict__ P,
     T* __restrict__ LXb, const T* __restrict__ GT, int64_t n, int r, int k, int phase,
     int is_hstep, KParams kp, State* __restrict__ st, const double* __restrict__ partsB,
-    const double* __restrict__ partsD, int nbD, double* __restrict__ partsC, BMap bm) {
+    const double* __restrict__ partsD, int nbD, double* __restrict__ partsC, BMap bm, int rd) {
   if constexpr (V != 2) {
     phase = 0;
     is_hstep = V == 0 ? 0 : 1;
@@ -712,9 +715,14 @@ __global__ __launch_bounds__(kThreads) void k_step2(
   if (phase != 1) load_G<T, RP>(GT, r, gv);
   const bool mon = V == 3 ? false : (is_hstep && phase != 1);
   const bool lap = phase == 2;
-  // phase 0 (V != 2): Z = max(0, X - g / rho) is recomputed from X and g with step 1's
-  // arithmetic (the same bits), so Z is neither stored by step 1 nor read here
+  // phase 0 (V != 2): Z = max(0, X - g / rho), and with rd also D = max(0, Z - alpha
+  // grad f(Z)) - Z, are recomputed from X and g with step 1's arithmetic (the same bits:
+  // the same operations on the same operands, the tile product on the same MFMA
+  // sequence), so step 1 does not store them.  rd trades a second tile product for two
+  // n x r transfers: set where the arrays stream from HBM, clear where the kernels are
+  // latency-bound.
   const T rinv = (T)(1.0 / st->rho);
+  const T alpha_r = (T)st->alpha[k];
   T x[8], zz[8], dd[8], go[8], cv[8], pv[8], ls[8], lx[8];
   auto load_tile = [&](int64_t row0) {
     const int64_t tb = row0 * r;
@@ -723,7 +731,7 @@ __global__ __launch_bounds__(kThreads) void k_step2(
       const bool ok = row0 + lr[p] < n && cl[p] < r;
       x[p] = ok ? ldo(tile_ptr(X, tb), bo[p]) : T(0);
       if constexpr (V == 2) zz[p] = ok ? ldo(tile_ptr(Z, tb), bo[p]) : T(0);
-      dd[p] = (ok && phase != 2) ? ldo(tile_ptr(D, tb), bo[p]) : T(0);
+      if (V == 2 || !rd) dd[p] = (ok && phase != 2) ? ldo(tile_ptr(D, tb), bo[p]) : T(0);
       go[p] = (ok && phase != 1) ? ldo(tile_ptr(g, tb), bo[p]) : T(0);
       cv[p] = (ok && mon) ? ldo(tile_ptr(C, tb), bo[p]) : T(0);
       pv[p] = (ok && mon) ? ldo(tile_ptr(P, tb), bo[p]) : T(0);
@@ -802,6 +810,23 @@ __global__ __launch_bounds__(kThreads) void k_step2(
     if (t != lc.bid) load_tile(row0);
     T xn[8];
     __syncthreads();
+    if (V != 2 && rd) {
+      // D as step 1 formed it: grad f(Z) = g + (Z - X)(G + lam I), then the projection
+#pragma unroll
+      for (int p = 0; p < 8; ++p) {
+        const bool ok = row0 + lr[p] < n && cl[p] < r;
+        sm.a[lr[p] * L::YP + cl[p]] = ok ? zz[p] - x[p] : T(0);
+      }
+      __syncthreads();
+      T dzg[8];
+      tile_gemm<T, RP>(sm.a, sm.G, dzg);
+#pragma unroll
+      for (int p = 0; p < 8; ++p) {
+        const bool ok = row0 + lr[p] < n && cl[p] < r;
+        const T gz = grad_at_z(go[p], dzg[p], lam, zz[p] - x[p]);
+        dd[p] = ok ? second_dir(zz[p], gz, alpha_r) : T(0);
+      }
+    }
 #pragma unroll
     for (int p = 0; p < 8; ++p) {
       const bool ok = row0 + lr[p] < n && cl[p] < r;
@@ -901,18 +926,18 @@ void launch_step1(const T* X, const T* g, T* Z, T* D, const T* LdZ, const T* GT,
                   const double* Gcur, const double* Gprev, int64_t n, int r, int k, int phase,
                   int is_hstep, const KParams& kp, State* st, const double* partsA,
                   double* partsB, const double* partsC, double* trace, hipStream_t s,
-                  const BMap& bm, int grid) {
+                  const BMap& bm, int grid, int rd) {
   if (grid <= 0) grid = inner_grid(n, r);
   if (phase == 0) {
     SNMF_DISPATCH_RP(rank_pad(r),
                      hipLaunchKernelGGL((k_step1<T, RP, 0>), dim3(grid), dim3(kThreads), 0, s, X,
                                         g, Z, D, LdZ, GT, Gcur, Gprev, n, r, k, phase, is_hstep,
-                                        kp, st, partsA, partsB, partsC, trace, bm))
+                                        kp, st, partsA, partsB, partsC, trace, bm, rd))
   } else {
     SNMF_DISPATCH_RP(rank_pad(r),
                      hipLaunchKernelGGL((k_step1<T, RP, 1>), dim3(grid), dim3(kThreads), 0, s, X,
                                         g, Z, D, LdZ, GT, Gcur, Gprev, n, r, k, phase, is_hstep,
-                                        kp, st, partsA, partsB, partsC, trace, bm))
+                                        kp, st, partsA, partsB, partsC, trace, bm, rd))
   }
 }
 
@@ -921,13 +946,13 @@ void launch_step2(T* X, T* g, T* Z, T* D, const T* LS, const T* C, const T* P, T
                   const T* GT, int64_t n, int r, int k, int phase, int is_hstep,
                   const KParams& kp, State* st, const double* partsB, const double* partsD,
                   int nbD, double* partsC, hipStream_t s, const BMap& bm, int grid,
-                  int last_k) {
+                  int last_k, int rd) {
   if (grid <= 0) grid = inner_grid(n, r);
 #define SNMF_STEP2(V)                                                                          \
   SNMF_DISPATCH_RP(rank_pad(r),                                                                \
                    hipLaunchKernelGGL((k_step2<T, RP, V>), dim3(grid), dim3(kThreads), 0, s, X, \
                                       g, Z, D, LS, C, P, LXb, GT, n, r, k, phase, is_hstep, kp, \
-                                      st, partsB, partsD, nbD, partsC, bm))
+                                      st, partsB, partsD, nbD, partsC, bm, rd))
   if (phase != 0) {
     SNMF_STEP2(2)
   } else if (is_hstep && k >= last_k) {
@@ -947,11 +972,11 @@ void launch_step2(T* X, T* g, T* Z, T* D, const T* LS, const T* C, const T* P, T
   template void launch_step1<T>(const T*, const T*, T*, T*, const T*, const T*, const double*, \
                                 const double*, int64_t, int, int, int, int, const KParams&,     \
                                 State*, const double*, double*, const double*, double*,         \
-                                hipStream_t, const BMap&, int);                                 \
+                                hipStream_t, const BMap&, int, int);                            \
   template void launch_step2<T>(T*, T*, T*, T*, const T*, const T*, const T*, T*, const T*,    \
                                 int64_t, int, int, int, int, const KParams&, State*,            \
                                 const double*, const double*, int, double*, hipStream_t,        \
-                                const BMap&, int, int);
+                                const BMap&, int, int, int);
 SNMF_INST(float)
 SNMF_INST(double)
 

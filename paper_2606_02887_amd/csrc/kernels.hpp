@@ -117,13 +117,14 @@ void launch_step1(const T* X, const T* g, T* Z, T* D, const T* LdZ, const T* GT,
                   const double* Gcur, const double* Gprev, int64_t n, int r, int k, int phase,
                   int is_hstep, const KParams& kp, State* st, const double* partsA,
                   double* partsB, const double* partsC, double* trace, hipStream_t s,
-                  const BMap& bm = BMap{}, int grid = 0);
+                  const BMap& bm = BMap{}, int grid = 0, int rd = 0);
 template <typename T>
 void launch_step2(T* X, T* g, T* Z, T* D, const T* LS, const T* C, const T* P, T* LXb,
                   const T* GT, int64_t n, int r, int k, int phase, int is_hstep,
                   const KParams& kp, State* st, const double* partsB, const double* partsD,
                   int nbD, double* partsC, hipStream_t s, const BMap& bm = BMap{}, int grid = 0,
-                  int last_k = 0);  // last inner iteration (its H-step forms the monitor sums)
+                  int last_k = 0,  // last inner iteration (its H-step forms the monitor sums)
+                  int rd = 0);     // phase 0: step 2 recomputes D (step 1 then stores none)
 
 template <typename T>
 void launch_stats2d(const T* x, int64_t rows, int64_t cols, int64_t ld, double* part, double* out,

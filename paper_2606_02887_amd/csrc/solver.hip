@@ -288,11 +288,14 @@ snmf_status inner_step(snmf_plan* pl, T* X, const T* P, int is_hstep, int k, hip
   T* g = (T*)pl->g;
   const bool lap = pl->lap && is_hstep;
   if (!lap) {
+    // D stored by step 1 and read back (measured faster here than recomputing it in
+    // step 2 at both the dense and the low-rank sizes; the batch recomputes it)
+    const int rd = 0;
     launch_step1<T>(X, g, Z, D, nullptr, GT, pl->G64[0], pl->G64[1], n, r, k, 0, is_hstep, pl->kp,
-                    pl->st, pl->partsA, pl->partsB, pl->partsC, pl->trace, s);
+                    pl->st, pl->partsA, pl->partsB, pl->partsC, pl->trace, s, BMap{}, 0, rd);
     launch_step2<T>(X, g, Z, D, nullptr, (const T*)pl->C, P, nullptr, GT, n, r, k, 0, is_hstep,
                     pl->kp, pl->st, pl->partsB, nullptr, 0, pl->partsC, s, BMap{}, 0,
-                    pl->p.inner_iters - 1);
+                    pl->p.inner_iters - 1, rd);
   } else {
     const int64_t* rp = pl->L.rowptr;
     const int32_t* ci = pl->L.col;
@@ -347,7 +350,8 @@ snmf_status finalize(snmf_plan* pl, hipStream_t s) {
   const int64_t n = pl->n;
   launch_step1<T>(W, (const T*)pl->g, (T*)pl->Z, (T*)pl->D, nullptr, (const T*)pl->GT[0],
                   pl->G64[0], pl->G64[1], n, pl->r, 0, 0, 0, pl->kp, pl->st,
-                  pl->partsA, pl->partsB, pl->partsC, pl->trace, s);
+                  pl->partsA, pl->partsB, pl->partsC, pl->trace, s, BMap{}, 0,
+                  1);  // D is never read after it
   HIP_TRY(hipGetLastError());
   return SNMF_OK;
 }
@@ -675,14 +679,14 @@ snmf_status snmf_plan_half_step(snmf_plan* pl, void* X, const void* P, int32_t i
     launch_step1<double>((const double*)X, (const double*)pl->g, (double*)pl->Z, (double*)pl->D,
                          nullptr, (const double*)pl->GT[is_hstep ? 1 : 0], pl->G64[0], pl->G64[1],
                          pl->n, pl->r, K, (pl->lap && is_hstep) ? 1 : 0, is_hstep, pl->kp, pl->st,
-                         pl->partsA, pl->partsB, pl->partsC, pl->trace, pl->s);
+                         pl->partsA, pl->partsB, pl->partsC, pl->trace, pl->s, BMap{}, 0, 1);
   } else {
     SNMF_TRY(half_start<float>(pl, (float*)X, (const float*)P, is_hstep, true, pl->s));
     SNMF_TRY(inner_steps<float>(pl, (float*)X, (const float*)P, is_hstep, pl->s));
     launch_step1<float>((const float*)X, (const float*)pl->g, (float*)pl->Z, (float*)pl->D,
                         nullptr, (const float*)pl->GT[is_hstep ? 1 : 0], pl->G64[0], pl->G64[1],
                         pl->n, pl->r, K, (pl->lap && is_hstep) ? 1 : 0, is_hstep, pl->kp, pl->st,
-                        pl->partsA, pl->partsB, pl->partsC, pl->trace, pl->s);
+                        pl->partsA, pl->partsB, pl->partsC, pl->trace, pl->s, BMap{}, 0, 1);
   }
   HIP_TRY(hipGetLastError());
   State hs;
