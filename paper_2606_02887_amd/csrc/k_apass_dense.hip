@@ -166,145 +166,169 @@ __global__ __launch_bounds__(256) void k_apass_f32(const float* __restrict__ A, 
     }
 }
 
-// FP32, wide loads (r in (32, 64], r even, lda % 4 == 0): each workgroup owns 128 output
-// rows j0..j0+127 and one K split; its four waves take contiguous quarters of that K
-// range.  Per k-pair a lane loads A[k+h][j0+4c .. +3] (one 16-byte vector) and
-// P[k+h][2c, 2c+1] (one 8-byte vector): MFMA N-block q covers the columns j0 + 4c + q,
-// M-block b the ranks m = 2c + b.  The four wave tiles are added in LDS in wave order
-// (deterministic) and written as coalesced rows of the partial product.
-// With rj.G set, the grid has one more row of workgroups: its first workgroup computes
-// rho = ||G||_2 (rho.hpp) beside the tiles and the rest of the row returns at once.  The
-// register bound of two waves per SIMD and the 64 KB of LDS leave room on a CU for that
-// workgroup next to a tile workgroup, so rho costs no time on the critical path.
+// FP32, wide loads (r in (32, 64], r even, lda % 4 == 0): a workgroup computes
+// 128-row output tiles over K ranges; its four waves take contiguous quarters of a range.
+// Per k-pair a lane loads A[k+h][j0+4c .. +3] (one 16-byte vector) and P[k+h][2c, 2c+1]
+// (one 8-byte vector): MFMA N-block q covers the columns j0 + 4c + q, M-block b the ranks
+// m = 2c + b.  The four wave tiles are added in LDS in wave order (deterministic) and
+// written as coalesced rows of a partial product.
+// Balanced split: the gx tiles x n rows of K, taken tile by tile, are cut into equal
+// chunks of `chunk` rows, one per workgroup, so every workgroup does the same MFMA work
+// and the grid fills the CUs evenly (two workgroups per CU).  A chunk covers one K range
+// of one tile or the end of one tile and the start of the next.  Tile t receives the
+// chunks of workgroups first(t) = floor(t n / chunk) .. last(t); workgroup w writes its
+// part of t to partial panel w - first(t), and last(t) writes zeros to the panels above
+// its own up to nslot - 1, so every tile has exactly nslot panels, added in panel order
+// by the consumer.
+// With rj.G set, the grid has one more workgroup (the last): it computes rho = ||G||_2
+// (rho.hpp) beside the tiles.  The register bound of two waves per SIMD and the 64 KB of
+// LDS leave room on a CU for it next to a tile workgroup (the tiles take one slot fewer
+// than two per CU), so rho costs no time on the critical path.
 __global__ __launch_bounds__(256, 2) void k_apass_f32w(const float* __restrict__ A, int64_t lda,
                                                        const float* __restrict__ P, int64_t n,
-                                                       int r, int64_t kchunk,
+                                                       int r, int64_t chunk, int nslot,
                                                        float* __restrict__ Bpart, int64_t pstride,
                                                        const State* __restrict__ st, RhoJob rj) {
   if (st->done) return;
-  if (rj.G && blockIdx.y == gridDim.y - 1) {
-    if (blockIdx.x == 0) rho_body(rj.G, rj.r, rj.st);
+  if (rj.G && blockIdx.x == gridDim.x - 1) {
+    rho_body(rj.G, rj.r, rj.st);
     return;
   }
   __shared__ float sacc[2 * 8 * 16 * 64];  // [slot][block(mb,nb)][v][lane], 64 KB
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // the wave index is uniform: K ranges, batch counts and loop control stay scalar
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int c = lane & 31, h = lane >> 5;
-  const int64_t j0 = (int64_t)blockIdx.x * 128;
-  const int64_t kb = (int64_t)blockIdx.y * kchunk;
-  const int64_t ke = kb + kchunk < n ? kb + kchunk : n;
-  const int64_t kq = ((ke - kb + 7) / 8) * 2;      // per-wave share, even
-  const int64_t wb = kb + wave * kq;
-  const int64_t we = wb + kq < ke ? wb + kq : ke;
-  f32x16 acc[2][4];
+  const int64_t w = blockIdx.x;
+  const int64_t gx = (n + 127) / 128;
+  const int64_t g0 = w * chunk;
+  const int64_t gend = g0 + chunk < gx * n ? g0 + chunk : gx * n;
+  for (int64_t gs = g0; gs < gend;) {
+    const int64_t t = gs / n;                        // tile
+    const int64_t kb = gs - t * n;                   // its K range [kb, ke)
+    const int64_t ke = kb + (gend - gs) < n ? kb + (gend - gs) : n;
+    const int slot = (int)(w - (t * n) / chunk);     // 0 .. nslot - 1
+    const bool last = (t * n + n - 1) / chunk == w;  // last contributor of tile t
+    const int64_t j0 = t * 128;
+    const int64_t kq = ((ke - kb + 7) / 8) * 2;      // per-wave share, even
+    const int64_t wb = kb + wave * kq < ke ? kb + wave * kq : ke;
+    const int64_t we = wb + kq < ke ? wb + kq : ke;  // wb <= we <= ke
+    f32x16 acc[2][4];
 #pragma unroll
-  for (int mb = 0; mb < 2; ++mb)
+    for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-    for (int nb = 0; nb < 4; ++nb)
+      for (int nb = 0; nb < 4; ++nb)
 #pragma unroll
-      for (int v = 0; v < 16; ++v) acc[mb][nb][v] = 0.0f;
-  const int64_t jc = j0 + 4 * c;
-  const bool jok = jc + 3 < n;                 // n % 4 == 0 on this path
-  const bool mok = 2 * c + 1 < r;              // r even on this path
-  // Out-of-range lanes read a clamped, valid address instead of being predicated: the
-  // loads stay unconditional (so the compiler keeps the prefetched batch in flight
-  // across the MFMAs), and a garbage column of A or rank of P only reaches an output
-  // column or rank that is never stored.
-  const float* arow = A + (jok ? jc : n - 4);
-  const float* prow = P + (mok ? 2 * c : 0);
-  constexpr int U = 8;  // k-pairs per batch of loads (two batches in flight; 16 measured no faster)
-  f32x4v xa[U], xb[U];
-  float2 ya[U], yb[U];
-  const f32x4v z4 = {0.f, 0.f, 0.f, 0.f};
-  const float2 z2 = {0.f, 0.f};
-  auto load = [&](f32x4v (&x)[U], float2 (&y)[U], int64_t k0) {
+        for (int v = 0; v < 16; ++v) acc[mb][nb][v] = 0.0f;
+    const int64_t jc = j0 + 4 * c;
+    const bool jok = jc + 3 < n;                 // n % 4 == 0 on this path
+    const bool mok = 2 * c + 1 < r;              // r even on this path
+    // Out-of-range lanes read a clamped, valid address instead of being predicated: the
+    // loads stay unconditional (so the compiler keeps the prefetched batch in flight
+    // across the MFMAs), and a garbage column of A or rank of P only reaches an output
+    // column or rank that is never stored.
+    const float* arow = A + (jok ? jc : n - 4);
+    const float* prow = P + (mok ? 2 * c : 0);
+    constexpr int U = 8;  // k-pairs per batch of loads (16 measured no faster)
+    f32x4v xa[U], xb[U];
+    float2 ya[U], yb[U];
+    const f32x4v z4 = {0.f, 0.f, 0.f, 0.f};
+    const float2 z2 = {0.f, 0.f};
+    auto load = [&](f32x4v (&x)[U], float2 (&y)[U], int64_t k0) {
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int64_t kk = k0 + 2 * u + h;
-      x[u] = __builtin_nontemporal_load((const f32x4v*)(arow + kk * lda));
-      y[u] = *(const float2*)(prow + kk * r);
+      for (int u = 0; u < U; ++u) {
+        const int64_t kk = k0 + 2 * u + h;
+        x[u] = __builtin_nontemporal_load((const f32x4v*)(arow + kk * lda));
+        y[u] = *(const float2*)(prow + kk * r);
+      }
+    };
+    auto mma = [&](const f32x4v (&x)[U], const float2 (&y)[U]) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const float av[4] = {x[u][0], x[u][1], x[u][2], x[u][3]};
+        const float pv[2] = {y[u].x, y[u].y};
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+          for (int mb = 0; mb < 2; ++mb)
+            acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(pv[mb], av[nb], acc[mb][nb], 0, 0, 0);
+      }
+    };
+    // full batches of U k-pairs; the prefetch of a batch beyond the last one re-reads
+    // the last batch (a valid address) and is never used, which keeps every load
+    // unconditional.  (Consuming the second batch conditionally lets the compiler sink
+    // its loads next to their MFMAs; a variant with both batches always in flight, 254
+    // registers, measured 10% slower.)
+    const int64_t nbat = (we - wb) / (2 * U);
+    const int64_t klast = wb + (nbat > 0 ? nbat - 1 : 0) * 2 * U;
+    int64_t k = wb;
+    if (nbat > 0) load(xa, ya, k);
+    for (int64_t b = 0; b < nbat; b += 2) {
+      load(xb, yb, k + 2 * U < klast ? k + 2 * U : klast);
+      mma(xa, ya);
+      load(xa, ya, k + 4 * U < klast ? k + 4 * U : klast);
+      if (b + 1 < nbat) mma(xb, yb);
+      k += 4 * U;
     }
-  };
-  auto mma = [&](const f32x4v (&x)[U], const float2 (&y)[U]) {
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const float av[4] = {x[u][0], x[u][1], x[u][2], x[u][3]};
-      const float pv[2] = {y[u].x, y[u].y};
+    k = wb + nbat * 2 * U;
+    for (; k < we; k += 2) {
+      const int64_t kk = k + h;
+      const bool kin = kk < we;
+      const f32x4v x = (kin && jok) ? *(const f32x4v*)(arow + kk * lda) : z4;
+      const float2 y = (kin && mok) ? *(const float2*)(prow + kk * r) : z2;
+      const float av[4] = {x[0], x[1], x[2], x[3]};
+      const float pv[2] = {y.x, y.y};
 #pragma unroll
       for (int nb = 0; nb < 4; ++nb)
 #pragma unroll
         for (int mb = 0; mb < 2; ++mb)
           acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(pv[mb], av[nb], acc[mb][nb], 0, 0, 0);
     }
-  };
-  // full batches of U k-pairs, two in flight; the prefetch of a batch beyond the last
-  // one re-reads the last batch (a valid address) and is never used, which keeps every
-  // load unconditional
-  const int64_t nbat = (we - wb) / (2 * U);
-  const int64_t klast = wb + (nbat > 0 ? nbat - 1 : 0) * 2 * U;
-  int64_t k = wb;
-  if (nbat > 0) load(xa, ya, k);
-  for (int64_t b = 0; b < nbat; b += 2) {
-    load(xb, yb, k + 2 * U < klast ? k + 2 * U : klast);
-    mma(xa, ya);
-    load(xa, ya, k + 4 * U < klast ? k + 4 * U : klast);
-    if (b + 1 < nbat) mma(xb, yb);
-    k += 4 * U;
-  }
-  k = wb + nbat * 2 * U;
-  for (; k < we; k += 2) {
-    const int64_t kk = k + h;
-    const bool kin = kk < we;
-    const f32x4v x = (kin && jok) ? *(const f32x4v*)(arow + kk * lda) : z4;
-    const float2 y = (kin && mok) ? *(const float2*)(prow + kk * r) : z2;
-    const float av[4] = {x[0], x[1], x[2], x[3]};
-    const float pv[2] = {y.x, y.y};
-#pragma unroll
-    for (int nb = 0; nb < 4; ++nb)
+    // the four K-quarter tiles, added pairwise in a fixed order in 64 KB of LDS:
+    // (w0 + w1) + (w2 + w3), the total in slot 0
+    auto put = [&](int sl) {
 #pragma unroll
       for (int mb = 0; mb < 2; ++mb)
-        acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(pv[mb], av[nb], acc[mb][nb], 0, 0, 0);
-  }
-  // the four K-quarter tiles, added pairwise in a fixed order in 64 KB of LDS:
-  // (w0 + w1) + (w2 + w3), the total in slot 0
-  auto put = [&](int slot) {
 #pragma unroll
-    for (int mb = 0; mb < 2; ++mb)
+        for (int nb = 0; nb < 4; ++nb)
 #pragma unroll
-      for (int nb = 0; nb < 4; ++nb)
+          for (int v = 0; v < 16; ++v) sacc[((sl * 8 + mb * 4 + nb) * 16 + v) * 64 + lane] = acc[mb][nb][v];
+    };
+    auto add = [&](int sl) {
 #pragma unroll
-        for (int v = 0; v < 16; ++v) sacc[((slot * 8 + mb * 4 + nb) * 16 + v) * 64 + lane] = acc[mb][nb][v];
-  };
-  auto add = [&](int slot) {
+      for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-    for (int mb = 0; mb < 2; ++mb)
+        for (int nb = 0; nb < 4; ++nb)
 #pragma unroll
-      for (int nb = 0; nb < 4; ++nb)
-#pragma unroll
-        for (int v = 0; v < 16; ++v) acc[mb][nb][v] += sacc[((slot * 8 + mb * 4 + nb) * 16 + v) * 64 + lane];
-  };
-  if (wave & 1) put(wave >> 1);
-  __syncthreads();
-  if (!(wave & 1)) add(wave >> 1);
-  __syncthreads();
-  if (wave == 2) put(0);
-  __syncthreads();
-  if (wave == 0) {
-    add(0);
-    put(0);
-  }
-  __syncthreads();
-  // element (jl, m) of the 128 x r tile: jl = 4c + nb, m = 2 mrow + mb with
-  // mrow = 8 (v/4) + 4 h + v%4
-  float* out = Bpart + (int64_t)blockIdx.y * pstride;
-  for (int e = threadIdx.x; e < 128 * 64; e += 256) {
-    const int jl = e >> 6, m = e & 63;
-    const int64_t jj = j0 + jl;
-    if (m < r && jj < n) {
-      const int cc = jl >> 2, nb = jl & 3, mb = m & 1, mrow = m >> 1;
-      const int hh = (mrow >> 2) & 1, v = 4 * (mrow >> 3) + (mrow & 3);
-      const int idx = ((mb * 4 + nb) * 16 + v) * 64 + 32 * hh + cc;
-      out[jj * r + m] = sacc[idx];
+          for (int v = 0; v < 16; ++v) acc[mb][nb][v] += sacc[((sl * 8 + mb * 4 + nb) * 16 + v) * 64 + lane];
+    };
+    if (wave & 1) put(wave >> 1);
+    __syncthreads();
+    if (!(wave & 1)) add(wave >> 1);
+    __syncthreads();
+    if (wave == 2) put(0);
+    __syncthreads();
+    if (wave == 0) {
+      add(0);
+      put(0);
     }
+    __syncthreads();
+    // element (jl, m) of the 128 x r tile: jl = 4c + nb, m = 2 mrow + mb with
+    // mrow = 8 (v/4) + 4 h + v%4
+    float* out = Bpart + (int64_t)slot * pstride;
+    const int zend = last ? nslot : slot + 1;  // panels slot + 1 .. zend - 1 get zeros
+    for (int e = threadIdx.x; e < 128 * 64; e += 256) {
+      const int jl = e >> 6, m = e & 63;
+      const int64_t jj = j0 + jl;
+      if (m < r && jj < n) {
+        const int cc = jl >> 2, nb = jl & 3, mb = m & 1, mrow = m >> 1;
+        const int hh = (mrow >> 2) & 1, v = 4 * (mrow >> 3) + (mrow & 3);
+        const int idx = ((mb * 4 + nb) * 16 + v) * 64 + 32 * hh + cc;
+        out[jj * r + m] = sacc[idx];
+        for (int z = slot + 1; z < zend; ++z) Bpart[(int64_t)z * pstride + jj * r + m] = 0.0f;
+      }
+    }
+    __syncthreads();  // sacc is reused by the next range
+    gs += ke - kb;
   }
 }
 
@@ -487,17 +511,26 @@ DenseSplit plan_dense_f32(int64_t n, int64_t lda, int r, const void* A) {
   if (dense_f32_wide(n, lda, r, A)) {
     d.wide = true;
     d.gx = (n + 127) / 128;
-    // as many K splits as keep every tile workgroup resident at two per CU with one slot
-    // to spare for the rho workgroup (measured at n = 8192: 7 splits beat 4, 6 and 8)
-    int64_t ks = (2 * device_cus() - 1) / d.gx;
-    const int64_t kmax = (n + 255) / 256;
-    if (ks > kmax) ks = kmax;
-    if (ks < 1) ks = 1;
-    if (ks > kMaxKSplit) ks = kMaxKSplit;
-    int64_t kc = (n + ks - 1) / ks;
-    kc = (kc + 63) / 64 * 64;
-    d.kchunk = kc;
-    d.ksplit = (int)((n + kc - 1) / kc);
+    // equal chunks of the gx x n (tile, K row) space, one per workgroup, for two tile
+    // workgroups per CU less one slot kept for the rho workgroup (at n = 8192: 511 chunks
+    // of 1028 rows; equal chunks measured 11% faster than 7 whole K splits per tile, which
+    // leave a quarter of the CUs with one workgroup); at least 256 rows each, and few
+    // enough contributors per tile for kMaxKSplit panels
+    const int64_t total = d.gx * n;
+    const int64_t nwg = 2 * device_cus() - 1;
+    int64_t chunk = (total + nwg - 1) / nwg;
+    const int64_t cmin = (n + kMaxKSplit - 2) / (kMaxKSplit - 1);
+    if (chunk < cmin) chunk = cmin;
+    if (chunk < 256) chunk = 256;
+    chunk = (chunk + 3) / 4 * 4;  // K ranges start on multiples of 4 rows (n % 4 == 0)
+    int nslot = 1;
+    for (int64_t t = 0; t < d.gx; ++t) {
+      const int64_t cnt = (t * n + n - 1) / chunk - (t * n) / chunk + 1;
+      if (cnt > nslot) nslot = (int)cnt;
+    }
+    d.kchunk = chunk;
+    d.ksplit = nslot;  // <= ceil(n / chunk) + 1 <= kMaxKSplit
+    d.nwg = (total + chunk - 1) / chunk;
     return d;
   }
   const int64_t gx = (n + 255) / 256;
@@ -519,9 +552,9 @@ void launch_apass_f32(const float* A, int64_t lda, const float* P, int64_t n, in
                       hipStream_t s, const RhoJob& rj) {
   dim3 grid((unsigned)d.gx, (unsigned)d.ksplit);
   if (d.wide) {
-    if (rj.G) grid.y += 1;
-    hipLaunchKernelGGL(k_apass_f32w, grid, dim3(256), 0, s, A, lda, P, n, r, d.kchunk, Bpart,
-                       pstride, st, rj);
+    const dim3 gw((unsigned)(d.nwg + (rj.G ? 1 : 0)));
+    hipLaunchKernelGGL(k_apass_f32w, gw, dim3(256), 0, s, A, lda, P, n, r, d.kchunk, d.ksplit,
+                       Bpart, pstride, st, rj);
     return;
   }
   if (rj.G) launch_rho(rj.G, rj.r, rj.st, s);

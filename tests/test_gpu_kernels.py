@@ -63,8 +63,10 @@ def test_rho_near_degenerate_spectrum(S):
 
 
 # ------------------------------------------------------------------ Gram and A-pass
-@pytest.mark.parametrize("n,r", [(1, 1), (37, 5), (500, 10), (1029, 33), (2048, 64), (4100, 34),
-                                 (4608, 64)])
+# (132, 34) and (260, 64): FP32 workgroup chunks longer than a tile's K (one workgroup
+# spans several tiles); (2048, 64), (4100, 34), (4608, 64): chunks that end inside tiles
+@pytest.mark.parametrize("n,r", [(1, 1), (37, 5), (132, 34), (260, 64), (500, 10), (1029, 33),
+                                 (2048, 64), (4100, 34), (4608, 64)])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_gram_and_dense_apass(S, n, r, prec):
     rng = np.random.default_rng(n * 100 + r)
