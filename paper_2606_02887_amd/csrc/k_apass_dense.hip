@@ -172,21 +172,28 @@ __global__ __launch_bounds__(256) void k_apass_f32(const float* __restrict__ A, 
 // (one 8-byte vector): MFMA N-block q covers the columns j0 + 4c + q, M-block b the ranks
 // m = 2c + b.  The four wave tiles are added in LDS in wave order (deterministic) and
 // written as coalesced rows of a partial product.
-// Balanced split: the gx tiles x n rows of K, taken tile by tile, are cut into equal
-// chunks of `chunk` rows, one per workgroup, so every workgroup does the same MFMA work
-// and the grid fills the CUs evenly (two workgroups per CU).  A chunk covers one K range
-// of one tile or the end of one tile and the start of the next.  Tile t receives the
-// chunks of workgroups first(t) = floor(t n / chunk) .. last(t); workgroup w writes its
-// part of t to partial panel w - first(t), and last(t) writes zeros to the panels above
-// its own up to nslot - 1, so every tile has exactly nslot panels, added in panel order
-// by the consumer.
+// Balanced split, every workgroup doing about the same MFMA work so the grid fills the CUs
+// evenly (two workgroups per CU):
+//  * nband full bands of `band` rows of K: workgroup w < nband gx takes rows
+//    [b band, (b + 1) band) of tile w % gx (b = w / gx) into partial panel b;
+//    consecutive workgroups take consecutive tiles of one band, so the workgroups in
+//    flight read the same rows of A at the same time;
+//  * the rows left, [nband band, n) of every tile, taken tile by tile, are cut into
+//    chunks of `rchunk` rows, one per remaining workgroup; a chunk covers one K range of
+//    one tile or the end of one tile and the start of the next.  Tile t receives the
+//    chunks of workgroups first(t) .. last(t) (counted from the first such workgroup,
+//    first(t) = floor(t lr / rchunk), lr the rows left per tile); workgroup w writes its
+//    part of t to panel nband + w - first(t), and last(t) writes zeros to the panels
+//    above its own up to nslot - 1.
+// So every tile has exactly nslot panels, added in panel order by the consumer.
 // With rj.G set, the grid has one more workgroup (the last): it computes rho = ||G||_2
 // (rho.hpp) beside the tiles.  The register bound of two waves per SIMD and the 64 KB of
 // LDS leave room on a CU for it next to a tile workgroup (the tiles take one slot fewer
 // than two per CU), so rho costs no time on the critical path.
 __global__ __launch_bounds__(256, 2) void k_apass_f32w(const float* __restrict__ A, int64_t lda,
                                                        const float* __restrict__ P, int64_t n,
-                                                       int r, int64_t chunk, int nslot,
+                                                       int r, int64_t band, int nband,
+                                                       int64_t rchunk, int nslot,
                                                        float* __restrict__ Bpart, int64_t pstride,
                                                        const State* __restrict__ st, RhoJob rj) {
   if (st->done) return;
@@ -200,14 +207,38 @@ __global__ __launch_bounds__(256, 2) void k_apass_f32w(const float* __restrict__
   const int c = lane & 31, h = lane >> 5;
   const int64_t w = blockIdx.x;
   const int64_t gx = (n + 127) / 128;
-  const int64_t g0 = w * chunk;
-  const int64_t gend = g0 + chunk < gx * n ? g0 + chunk : gx * n;
-  for (int64_t gs = g0; gs < gend;) {
-    const int64_t t = gs / n;                        // tile
-    const int64_t kb = gs - t * n;                   // its K range [kb, ke)
-    const int64_t ke = kb + (gend - gs) < n ? kb + (gend - gs) : n;
-    const int slot = (int)(w - (t * n) / chunk);     // 0 .. nslot - 1
-    const bool last = (t * n + n - 1) / chunk == w;  // last contributor of tile t
+  const int64_t nfull = (int64_t)nband * gx;
+  const int64_t r0 = (int64_t)nband * band;  // first row of K after the full bands
+  const int64_t lr = n > r0 ? n - r0 : 0;    // rows of K left per tile
+  const int64_t wp = w - nfull;
+  // segment cursor over this workgroup's share: one segment in a full band, else
+  // [gs, gend) of the tile-major space of the rows left
+  int64_t gs = 0, gend = 1;
+  if (w >= nfull) {
+    gs = wp * rchunk;
+    gend = gs + rchunk < gx * lr ? gs + rchunk : gx * lr;
+  }
+  while (gs < gend) {
+    int64_t t, kb, ke;  // tile and its K range [kb, ke)
+    int slot, zend;     // panel written; panels slot + 1 .. zend - 1 get zeros
+    if (w < nfull) {
+      const int64_t bd = w / gx;
+      t = w - bd * gx;
+      kb = bd * band;
+      ke = kb + band < n ? kb + band : n;
+      slot = (int)bd;
+      zend = slot + 1;
+      gs = gend;
+    } else {
+      t = gs / lr;
+      const int64_t o = gs - t * lr;
+      kb = r0 + o;
+      ke = r0 + (o + (gend - gs) < lr ? o + (gend - gs) : lr);
+      slot = nband + (int)(wp - (t * lr) / rchunk);
+      const bool last = (t * lr + lr - 1) / rchunk == wp;  // last contributor of tile t
+      zend = last ? nslot : slot + 1;
+      gs += ke - kb;
+    }
     const int64_t j0 = t * 128;
     const int64_t kq = ((ke - kb + 7) / 8) * 2;      // per-wave share, even
     const int64_t wb = kb + wave * kq < ke ? kb + wave * kq : ke;
@@ -269,19 +300,29 @@ __global__ __launch_bounds__(256, 2) void k_apass_f32w(const float* __restrict__
       if (b + 1 < nbat) mma(xb, yb);
       k += 4 * U;
     }
+    // the rows left (fewer than a batch): one batch of masked loads, all issued before
+    // the first wait, and MFMAs for the k-pairs present only
     k = wb + nbat * 2 * U;
-    for (; k < we; k += 2) {
-      const int64_t kk = k + h;
-      const bool kin = kk < we;
-      const f32x4v x = (kin && jok) ? *(const f32x4v*)(arow + kk * lda) : z4;
-      const float2 y = (kin && mok) ? *(const float2*)(prow + kk * r) : z2;
-      const float av[4] = {x[0], x[1], x[2], x[3]};
-      const float pv[2] = {y.x, y.y};
+    if (k < we) {
 #pragma unroll
-      for (int nb = 0; nb < 4; ++nb)
+      for (int u = 0; u < U; ++u) {
+        const int64_t kk = k + 2 * u + h;
+        const bool kin = kk < we;
+        xa[u] = (kin && jok) ? *(const f32x4v*)(arow + kk * lda) : z4;
+        ya[u] = (kin && mok) ? *(const float2*)(prow + kk * r) : z2;
+      }
 #pragma unroll
-        for (int mb = 0; mb < 2; ++mb)
-          acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(pv[mb], av[nb], acc[mb][nb], 0, 0, 0);
+      for (int u = 0; u < U; ++u) {
+        if (k + 2 * u < we) {
+          const float av[4] = {xa[u][0], xa[u][1], xa[u][2], xa[u][3]};
+          const float pv[2] = {ya[u].x, ya[u].y};
+#pragma unroll
+          for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+            for (int mb = 0; mb < 2; ++mb)
+              acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(pv[mb], av[nb], acc[mb][nb], 0, 0, 0);
+        }
+      }
     }
     // the four K-quarter tiles, added pairwise in a fixed order in 64 KB of LDS:
     // (w0 + w1) + (w2 + w3), the total in slot 0
@@ -315,7 +356,6 @@ __global__ __launch_bounds__(256, 2) void k_apass_f32w(const float* __restrict__
     // element (jl, m) of the 128 x r tile: jl = 4c + nb, m = 2 mrow + mb with
     // mrow = 8 (v/4) + 4 h + v%4
     float* out = Bpart + (int64_t)slot * pstride;
-    const int zend = last ? nslot : slot + 1;  // panels slot + 1 .. zend - 1 get zeros
     for (int e = threadIdx.x; e < 128 * 64; e += 256) {
       const int jl = e >> 6, m = e & 63;
       const int64_t jj = j0 + jl;
@@ -328,7 +368,6 @@ __global__ __launch_bounds__(256, 2) void k_apass_f32w(const float* __restrict__
       }
     }
     __syncthreads();  // sacc is reused by the next range
-    gs += ke - kb;
   }
 }
 
@@ -506,31 +545,62 @@ static int64_t device_cus() {
   return cus;
 }
 
+constexpr int64_t kDelta = 96;
 DenseSplit plan_dense_f32(int64_t n, int64_t lda, int r, const void* A) {
   DenseSplit d;
   if (dense_f32_wide(n, lda, r, A)) {
     d.wide = true;
     d.gx = (n + 127) / 128;
-    // equal chunks of the gx x n (tile, K row) space, one per workgroup, for two tile
-    // workgroups per CU less one slot kept for the rho workgroup (at n = 8192: 511 chunks
-    // of 1028 rows; equal chunks measured 11% faster than 7 whole K splits per tile, which
-    // leave a quarter of the CUs with one workgroup); at least 256 rows each, and few
-    // enough contributors per tile for kMaxKSplit panels
-    const int64_t total = d.gx * n;
+    // two tile workgroups per CU less one slot kept for the rho workgroup (511 at
+    // n = 8192): q full bands of one workgroup per tile, the m workgroups left sharing the
+    // rows after them.  Bands of at least 256 rows, and at most kMaxKSplit - 3 of them so
+    // that q plus the (at most 2) panels of the rows left fit in kMaxKSplit.  At n = 8192:
+    // 7 bands of 1040 rows and 63 chunks of 928 (whole K splits per tile, 7 per tile, 448
+    // workgroups: 115.6 us).
+    const int64_t gx = d.gx;
     const int64_t nwg = 2 * device_cus() - 1;
-    int64_t chunk = (total + nwg - 1) / nwg;
-    const int64_t cmin = (n + kMaxKSplit - 2) / (kMaxKSplit - 1);
-    if (chunk < cmin) chunk = cmin;
-    if (chunk < 256) chunk = 256;
-    chunk = (chunk + 3) / 4 * 4;  // K ranges start on multiples of 4 rows (n % 4 == 0)
-    int nslot = 1;
-    for (int64_t t = 0; t < d.gx; ++t) {
-      const int64_t cnt = (t * n + n - 1) / chunk - (t * n) / chunk + 1;
-      if (cnt > nslot) nslot = (int)cnt;
+    int64_t q = nwg / gx, m = nwg % gx;
+    int64_t qmax = n / 256 < kMaxKSplit - 3 ? n / 256 : kMaxKSplit - 3;
+    if (qmax < 1) qmax = 1;
+    if (q >= qmax) {
+      q = qmax;
+      m = 0;
     }
-    d.kchunk = chunk;
-    d.ksplit = nslot;  // <= ceil(n / chunk) + 1 <= kMaxKSplit
-    d.nwg = (total + chunk - 1) / chunk;
+    auto r4 = [](int64_t x) { return (x + 3) / 4 * 4; };
+    int64_t band = 0, lr = n, rchunk = 0;
+    if (q == 0) {
+      rchunk = r4((gx * n + m - 1) / m);
+    } else {
+      // with rows left over, the chunks of the rows left are about kDelta rows shorter
+      // than a band: a chunk that ends inside a tile pays a second pipeline start and
+      // epilogue (at n = 8192, kDelta 0 / 48 / 96 / 160: 110.7 / 112.9 / 107.8 / 108.0 us;
+      // one workgroup per (tile, band) at 8 bands and no rho slot: 106.0 us)
+      band = m ? r4((n * gx + m * kDelta + q * gx + m - 1) / (q * gx + m)) : r4((n + q - 1) / q);
+      if (m && q * band >= n) {
+        m = 0;
+        band = r4((n + q - 1) / q);
+      }
+      while (q > 1 && (q - 1) * band >= n) --q;
+      lr = n > q * band ? n - q * band : 0;
+      if (m && lr) rchunk = r4((gx * lr + m - 1) / m);
+    }
+    if (rchunk && rchunk < 4) rchunk = 4;
+    int nslot = (int)q;
+    int64_t npart = 0;
+    if (rchunk) {
+      npart = (gx * lr + rchunk - 1) / rchunk;
+      int64_t cnt = 0;
+      for (int64_t t = 0; t < gx; ++t) {
+        const int64_t c = (t * lr + lr - 1) / rchunk - (t * lr) / rchunk + 1;
+        if (c > cnt) cnt = c;
+      }
+      nslot += (int)cnt;
+    }
+    d.kchunk = band;
+    d.nband = (int)q;
+    d.rchunk = rchunk;
+    d.ksplit = nslot;  // <= kMaxKSplit
+    d.nwg = q * gx + npart;
     return d;
   }
   const int64_t gx = (n + 255) / 256;
@@ -553,8 +623,8 @@ void launch_apass_f32(const float* A, int64_t lda, const float* P, int64_t n, in
   dim3 grid((unsigned)d.gx, (unsigned)d.ksplit);
   if (d.wide) {
     const dim3 gw((unsigned)(d.nwg + (rj.G ? 1 : 0)));
-    hipLaunchKernelGGL(k_apass_f32w, gw, dim3(256), 0, s, A, lda, P, n, r, d.kchunk, d.ksplit,
-                       Bpart, pstride, st, rj);
+    hipLaunchKernelGGL(k_apass_f32w, gw, dim3(256), 0, s, A, lda, P, n, r, d.kchunk, d.nband,
+                       d.rchunk, d.ksplit, Bpart, pstride, st, rj);
     return;
   }
   if (rj.G) launch_rho(rj.G, rj.r, rj.st, s);

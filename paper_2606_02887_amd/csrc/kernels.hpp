@@ -13,7 +13,9 @@ constexpr int kMaxKSplit = 16;   // largest number of split-K partials of a dens
 struct DenseSplit {
   int64_t gx = 1;       // workgroups along the output rows
   int ksplit = 1;       // K splits (partial products)
-  int64_t kchunk = 0;   // rows of A per split (wide FP32: rows of the tile-major K space per workgroup)
+  int64_t kchunk = 0;   // rows of A per split (wide FP32: rows per full band)
+  int nband = 0;        // wide FP32: full bands of K
+  int64_t rchunk = 0;   // wide FP32: rows per workgroup over the rows after the bands (0: none)
   int64_t nwg = 0;      // wide FP32: tile workgroups of the balanced split
   bool wide = false;    // FP32: 16-byte A loads (r in (32, 64] even, n and lda multiples of 4)
 };
