@@ -29,6 +29,16 @@ namespace snmf {
 __device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
+// Workgroups per CU the row-tile kernels are built for: three for FP32 up to rank 32 (at
+// most 168 registers a lane, so three waves share a SIMD; the grid is then three per CU,
+// one pass over the tiles with no second round of workgroups), else whatever the
+// registers allow.  The general step 2 (V = 2, the Laplacian path) keeps its registers:
+// bounded to 168 it spills.
+template <typename T, int RP, int V = 0>
+__host__ __device__ constexpr int inner_occupancy() {
+  return (sizeof(T) == 4 && RP <= 32 && V != 2) ? 3 : 1;
+}
+
 template <int RP>
 struct TileCfg {
   static constexpr int RS = kThreads / RP;  // rows per pass (VALU layout)
@@ -235,7 +245,7 @@ __device__ __forceinline__ P tile_ptr(P base, int64_t tb) {
 // ----------------------------------------------------------------------------- init
 // C = (sum of the A-pass partials) + lam P;  g = X G + lam X - C [+ gam LX].
 template <typename T, int RP>
-__global__ __launch_bounds__(kThreads) void k_init(
+__global__ __launch_bounds__(kThreads, (inner_occupancy<T, RP>())) void k_init(
     const T* __restrict__ X, const T* __restrict__ P, const T* __restrict__ Bpart, int ksplit,
     int64_t bstride, T* __restrict__ Cout, T* __restrict__ g, const T* __restrict__ LX,
     const T* __restrict__ GT, int64_t n, int r, int is_hstep, KParams kp, State* __restrict__ st,
@@ -491,7 +501,7 @@ __device__ __forceinline__ T second_dir(T z, T gz, T alpha) {  // max(0, Z - alp
 // V = 0: phase 0 only (a compile-time constant, so the Laplacian operands and their
 // registers drop out); V = 1: any phase.
 template <typename T, int RP, int V>
-__global__ __launch_bounds__(kThreads) void k_step1(
+__global__ __launch_bounds__(kThreads, (inner_occupancy<T, RP>())) void k_step1(
     const T* __restrict__ X, const T* __restrict__ g, T* __restrict__ Z, T* __restrict__ D,
     const T* __restrict__ LdZ, const T* __restrict__ GT, const double* __restrict__ Gcur,
     const double* __restrict__ Gprev, int64_t n, int r, int k, int phase, int is_hstep,
@@ -665,7 +675,7 @@ __device__ __forceinline__ double line_search(double delta, double q, double dZ,
 // rd (phase 0): step 1 stored no D; step 2 forms it again from X, g, G and alpha_k with
 // the same operations in the same order, so it holds the same bits.
 template <typename T, int RP, int V>
-__global__ __launch_bounds__(kThreads) void k_step2(
+__global__ __launch_bounds__(kThreads, (inner_occupancy<T, RP, V>())) void k_step2(
     T* __restrict__ X, T* __restrict__ g, T* __restrict__ Z, T* __restrict__ D,
     const T* __restrict__ LS, const T* __restrict__ C, const T* __restrict__ P,
     T* __restrict__ LXb, const T* __restrict__ GT, int64_t n, int r, int k, int phase,
@@ -894,11 +904,31 @@ int rank_pad(int r) {
   return rp;
 }
 
-int inner_grid(int64_t n, int r) {
-  const int tm = 8 * kThreads / rank_pad(r);
+// Compute units of the current device (MI355X: 256).
+static int64_t inner_cus() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus < 1)
+    cus = 256;
+  return cus;
+}
+
+// One workgroup per tile up to what stays resident at once (FP32 up to rank 32: three per
+// CU), at most kInnerGrid (the partial-sum rows).  A grid larger than the resident
+// workgroups runs in two rounds, and the second round's workgroups start only when
+// first-round ones end.
+int inner_grid(int64_t n, int r, int esz) {
+  const int rp = rank_pad(r);
+  const int tm = 8 * kThreads / rp;
   int64_t nt = (n + tm - 1) / tm;
   if (nt < 1) nt = 1;
-  return (int)(nt < kInnerGrid ? nt : kInnerGrid);
+  int64_t cap = kInnerGrid;
+  if (esz == 4 && rp <= 32) {
+    const int64_t res = inner_occupancy<float, 32>() * inner_cus();
+    if (res < cap) cap = res;
+  }
+  return (int)(nt < cap ? nt : cap);
 }
 
 #define SNMF_DISPATCH_RP(rp, ...)                                   \
@@ -914,7 +944,7 @@ template <typename T>
 void launch_init(const T* X, const T* P, const T* Bpart, int ksplit, int64_t bstride, T* C, T* g,
                  const T* LX, const T* GT, int64_t n, int r, int is_hstep, const KParams& kp,
                  State* st, double* partsA, hipStream_t s, const BMap& bm, int grid) {
-  if (grid <= 0) grid = inner_grid(n, r);
+  if (grid <= 0) grid = inner_grid(n, r, (int)sizeof(T));
   SNMF_DISPATCH_RP(rank_pad(r),
                    hipLaunchKernelGGL((k_init<T, RP>), dim3(grid), dim3(kThreads), 0, s, X, P,
                                       Bpart, ksplit, bstride, C, g, LX, GT, n, r, is_hstep, kp, st,
@@ -927,7 +957,7 @@ void launch_step1(const T* X, const T* g, T* Z, T* D, const T* LdZ, const T* GT,
                   int is_hstep, const KParams& kp, State* st, const double* partsA,
                   double* partsB, const double* partsC, double* trace, hipStream_t s,
                   const BMap& bm, int grid, int rd) {
-  if (grid <= 0) grid = inner_grid(n, r);
+  if (grid <= 0) grid = inner_grid(n, r, (int)sizeof(T));
   if (phase == 0) {
     SNMF_DISPATCH_RP(rank_pad(r),
                      hipLaunchKernelGGL((k_step1<T, RP, 0>), dim3(grid), dim3(kThreads), 0, s, X,
@@ -947,7 +977,7 @@ void launch_step2(T* X, T* g, T* Z, T* D, const T* LS, const T* C, const T* P, T
                   const KParams& kp, State* st, const double* partsB, const double* partsD,
                   int nbD, double* partsC, hipStream_t s, const BMap& bm, int grid,
                   int last_k, int rd) {
-  if (grid <= 0) grid = inner_grid(n, r);
+  if (grid <= 0) grid = inner_grid(n, r, (int)sizeof(T));
 #define SNMF_STEP2(V)                                                                          \
   SNMF_DISPATCH_RP(rank_pad(r),                                                                \
                    hipLaunchKernelGGL((k_step2<T, RP, V>), dim3(grid), dim3(kThreads), 0, s, X, \
