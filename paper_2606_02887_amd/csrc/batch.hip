@@ -251,9 +251,8 @@ snmf_status batch_create(int32_t nprob, const snmf_matrix* A, const int32_t* r, 
   // row tiles per inner-kernel workgroup: more than one amortises each workgroup's fixed
   // cost (instance lookup, partial-sum reduction, line search, G staging).  4 measured
   // best on 256 graphs x 8 restarts (1: 114k, 2: 132k, 4: 138k, 8: 136k instance outer
-  // iterations/s); SNMF_BATCH_TILES_PER_WG overrides it.
-  int tpb = 4;
-  if (const char* e = std::getenv("SNMF_BATCH_TILES_PER_WG")) tpb = std::max(1, std::atoi(e));
+  // iterations/s).
+  constexpr int tpb = 4;
   for (auto& kv : by_r) {
     snmf_batch::Cls c;
     c.r = kv.first;
