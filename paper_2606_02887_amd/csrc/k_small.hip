@@ -80,17 +80,19 @@ __device__ __forceinline__ void gram_slab(const T* __restrict__ P, int r, int64_
         }
   };
   // wavefront `wave` takes k-steps wave, wave + 4, ...; batches of U of them, two in
-  // flight (the k-steps past the slab load clamped rows and contribute zeros)
+  // flight.  The k-steps past the slab load clamped rows and contribute exact zeros, so
+  // every load and MFMA of the loop is unconditional: a conditional consumer lets the
+  // compiler sink that batch's loads next to their MFMAs, where their latency is exposed.
   const int64_t mine = nst > wave ? (nst - wave + 3) / 4 : 0;
   const int64_t nbat = (mine + U - 1) / U;
   double xa[U][NB], xb[U][NB];
   if (nbat > 0) load(xa, wave);
   for (int64_t bt = 0; bt < nbat; bt += 2) {
     const int64_t j0 = wave + 4 * U * bt;
-    if (bt + 1 < nbat) load(xb, j0 + 4 * U);
+    load(xb, j0 + 4 * U);
     mma(xa);
-    if (bt + 2 < nbat) load(xa, j0 + 8 * U);
-    if (bt + 1 < nbat) mma(xb);
+    load(xa, j0 + 8 * U);
+    mma(xb);
   }
   // (w0 + w1) + (w2 + w3): odd waves park their sums, even waves add them; wave 2 parks
   // its pair sum and wave 0 adds it
