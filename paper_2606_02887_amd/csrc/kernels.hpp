@@ -128,6 +128,8 @@ void launch_step2(T* X, T* g, T* Z, T* D, const T* LS, const T* C, const T* P, T
                   int nbD, double* partsC, hipStream_t s, const BMap& bm = BMap{}, int grid = 0,
                   int last_k = 0,  // last inner iteration (its H-step forms the monitor sums)
                   int rd = 0);     // phase 0: step 2 recomputes D (step 1 then stores none)
+// Bytes of one n x r array from which a single solve recomputes D in step 2.
+constexpr int64_t kRecomputeDBytes = 4 << 20;
 
 template <typename T>
 void launch_stats2d(const T* x, int64_t rows, int64_t cols, int64_t ld, double* part, double* out,

@@ -129,6 +129,31 @@ def test_half_step_lockstep_lai(S, prec):
     _check_scalars(sc, log, 1e-10 if prec == "f64" else 1e-4)
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("is_hstep", [0, 1])
+def test_half_step_lockstep_lai_large_arrays(S, prec, is_hstep):
+    """n x r arrays of at least 4 MiB (n = 70000, r = 16): step 1 keeps D in registers
+    only and step 2 forms it again; several row tiles per workgroup.  FP64 is held to
+    1e-12; in FP32 the low-rank products T = U^T P sum 70000 terms each, whose rounding
+    (about sqrt(n) 2^-24 = 1.6e-5 relative) the five inner iterations carry into X, so
+    the FP32 bound is 1e-4 here (measured 2.2e-5, the same with D read back)."""
+    n, ell, r = 70000, 16, 16
+    a = gen.powerlaw_csr(n=n, seed=9)
+    U, lam_ = gen.range_finder(a, ell, 6, 2, 3)
+    rng = np.random.default_rng(6)
+    X = rng.random((n, r)) * 0.05
+    P = rng.random((n, r)) * 0.05
+    dt = DT[prec]
+    Ut = _t(U, dt)
+    lr_in = O.LowRank(Ut.double().cpu().numpy(), lam_)
+    lam = O.default_lambda(lr_in)
+    Xg, Xo, sc, log = _lockstep(S, S.lowrank(Ut, _t(lam_, torch.float64)), lr_in, X, P, prec,
+                                is_hstep, lam)
+    tol = 1e-12 if prec == "f64" else 1e-4
+    assert nrel(Xg, Xo) <= tol
+    _check_scalars(sc, log, 1e-10 if prec == "f64" else 1e-4)
+
+
 def test_half_step_ragged_rank_and_tail(S):
     """r = 1 and n not a multiple of any tile: exact FP64 agreement."""
     prob = gen.planted_dense(517, 1, 3)
