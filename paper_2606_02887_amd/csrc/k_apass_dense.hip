@@ -259,7 +259,7 @@ __global__ __launch_bounds__(256, 2) void k_apass_f32w(const float* __restrict__
     // column or rank that is never stored.
     const float* arow = A + (jok ? jc : n - 4);
     const float* prow = P + (mok ? 2 * c : 0);
-    constexpr int U = 8;  // k-pairs per batch of loads (16 measured no faster)
+    constexpr int U = 6;  // k-pairs per batch of loads (2: 91.3 us, 4: 90.7, 6: 89.0; 8 spills)
     f32x4v xa[U], xb[U];
     float2 ya[U], yb[U];
     const f32x4v z4 = {0.f, 0.f, 0.f, 0.f};
@@ -284,22 +284,32 @@ __global__ __launch_bounds__(256, 2) void k_apass_f32w(const float* __restrict__
             acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(pv[mb], av[nb], acc[mb][nb], 0, 0, 0);
       }
     };
-    // full batches of U k-pairs; the prefetch of a batch beyond the last one re-reads
-    // the last batch (a valid address) and is never used, which keeps every load
-    // unconditional.  (Consuming the second batch conditionally lets the compiler sink
-    // its loads next to their MFMAs; a variant with both batches always in flight, 254
-    // registers, measured 10% slower.)
+    // full batches of U k-pairs, two in flight: each loop step issues the loads of the
+    // next two batches among the MFMAs of the current two, one load per four MFMAs (the
+    // scheduling-group barriers below fix that order).  A wave issues in order and
+    // stalls on a load the memory pipeline cannot take yet, so loads issued in bursts
+    // held back MFMAs that were ready (at n = 8192: 106.5 us in bursts, 88-91 us
+    // interleaved, TCP stalled on pending data 65% of the cycles with MFMA 49% busy
+    // before).  The prefetch of a batch beyond the last one re-reads the last batch (a
+    // valid address) and is never used, which keeps every load unconditional.
     const int64_t nbat = (we - wb) / (2 * U);
     const int64_t klast = wb + (nbat > 0 ? nbat - 1 : 0) * 2 * U;
     int64_t k = wb;
     if (nbat > 0) load(xa, ya, k);
-    for (int64_t b = 0; b < nbat; b += 2) {
-      load(xb, yb, k + 2 * U < klast ? k + 2 * U : klast);
+    int64_t b = 0;
+    for (; b + 2 <= nbat; b += 2) {
+      load(xb, yb, k + 2 * U);
       mma(xa, ya);
       load(xa, ya, k + 4 * U < klast ? k + 4 * U : klast);
-      if (b + 1 < nbat) mma(xb, yb);
+      mma(xb, yb);
       k += 4 * U;
+#pragma unroll
+      for (int i = 0; i < 4 * U; ++i) {
+        __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);  // one global load
+        __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);  // four MFMAs
+      }
     }
+    if (b < nbat) mma(xa, ya);  // odd batch count: xa holds the last batch
     // the rows left (fewer than a batch): one batch of masked loads, all issued before
     // the first wait, and MFMAs for the k-pairs present only
     k = wb + nbat * 2 * U;
