@@ -55,29 +55,34 @@ __device__ __forceinline__ void gram_slab(const T* __restrict__ P, int r, int64_
     cok[q] = cc < r;
     ccl[q] = cc < r ? cc : r - 1;
   }
-  auto load = [&](double (&x)[U][NB], int64_t j0) {
+  // A batch holds the raw values of U k-steps (every address valid: rows past the slab
+  // clamped) and a row-in-range flag per k-step; the conversion to FP64 and the masking
+  // wait until the MFMAs.  (Masking at the load made the compiler branch around each
+  // load and wait for it inside the branch, one memory round trip per k-step.)
+  auto load = [&](T (&x)[U][NB], bool (&ok)[U], int64_t j0) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t row = rb + 4 * (j0 + 4 * u) + kr;
-      const bool rok = row < re;
-      const int64_t rc = rok ? row : re - 1;
+      ok[u] = row < re;
+      const int64_t rc = row < re ? row : re - 1;
 #pragma unroll
-      for (int q = 0; q < NB; ++q) {
-        const double v = (double)P[rc * r + ccl[q]];
-        x[u][q] = (rok && cok[q]) ? v : 0.0;
-      }
+      for (int q = 0; q < NB; ++q) x[u][q] = P[rc * r + ccl[q]];
     }
   };
-  auto mma = [&](const double (&x)[U][NB]) {
+  auto mma = [&](const T (&x)[U][NB], const bool (&ok)[U]) {
 #pragma unroll
-    for (int u = 0; u < U; ++u)
+    for (int u = 0; u < U; ++u) {
+      double xd[NB];
+#pragma unroll
+      for (int q = 0; q < NB; ++q) xd[q] = (ok[u] && cok[q]) ? (double)x[u][q] : 0.0;
 #pragma unroll
       for (int qa = 0; qa < NB; ++qa)
 #pragma unroll
         for (int qb = qa; qb < NB; ++qb) {
           const int tq = gram_tile<NB>(qa, qb);
-          acc[tq] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[u][qa], x[u][qb], acc[tq], 0, 0, 0);
+          acc[tq] = __builtin_amdgcn_mfma_f64_16x16x4f64(xd[qa], xd[qb], acc[tq], 0, 0, 0);
         }
+    }
   };
   // wavefront `wave` takes k-steps wave, wave + 4, ...; batches of U of them, two in
   // flight.  The k-steps past the slab load clamped rows and contribute exact zeros, so
@@ -85,14 +90,15 @@ __device__ __forceinline__ void gram_slab(const T* __restrict__ P, int r, int64_
   // compiler sink that batch's loads next to their MFMAs, where their latency is exposed.
   const int64_t mine = nst > wave ? (nst - wave + 3) / 4 : 0;
   const int64_t nbat = (mine + U - 1) / U;
-  double xa[U][NB], xb[U][NB];
-  if (nbat > 0) load(xa, wave);
+  T xa[U][NB], xb[U][NB];
+  bool oa[U], ob[U];
+  if (nbat > 0) load(xa, oa, wave);
   for (int64_t bt = 0; bt < nbat; bt += 2) {
     const int64_t j0 = wave + 4 * U * bt;
-    load(xb, j0 + 4 * U);
-    mma(xa);
-    load(xa, j0 + 8 * U);
-    mma(xb);
+    load(xb, ob, j0 + 4 * U);
+    mma(xa, oa);
+    load(xa, oa, j0 + 8 * U);
+    mma(xb, ob);
   }
   // (w0 + w1) + (w2 + w3): odd waves park their sums, even waves add them; wave 2 parks
   // its pair sum and wave 0 adds it
