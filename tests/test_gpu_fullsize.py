@@ -1,0 +1,124 @@
+"""Half-step parity at the benchmark sizes, in the launch configuration bench.py times.
+
+The dense planted problem at n = 8192, r = 64 (FP32 and split-BF16 A-pass with its
+balanced split over two workgroups per CU and the fused rho workgroup), the graph problem
+at n = 20000, r = 20 (CSR A-pass and the Laplacian products of the H-step) and the
+low-rank problem at n = 200000, ell = 64, r = 32 (the LAI products; the n x r arrays hold
+more than 4 MiB, so step 2 forms D again).  The oracle's half-step at these sizes costs a
+few dense or low-rank products on the CPU, so every entry of X+ is compared.
+
+Tolerances (normwise on X+ after one half-step of five inner iterations): FP32 sums of
+n = 8192 to 200000 terms carry about sqrt(n) 2^-24 = 5e-6 to 3e-5 relative rounding into
+B, which the inner iterations pass on to X, so FP32 is held to 3e-5; split BF16 adds the
+2^-17 element error of A_hi + A_lo, 5e-5.  Measured: 1.9e-6 (dense FP32), 2.5e-6 (split
+BF16), 1.9e-7 (graph), 5.3e-7 (low rank).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2606_02887_amd import gen
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+@pytest.fixture(scope="module")
+def S():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2606_02887_amd import snmf
+    return snmf
+
+
+def nrel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    d = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (d if d > 0 else 1.0)
+
+
+def _t(x, dtype):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV, dtype)
+
+
+def _half_step(S, Aop_gpu, Aop_oracle, X, P, prec, is_hstep, lam, gamma=0.0, L_gpu=None,
+               L_or=None):
+    Xt, Pt = _t(X, torch.float32), _t(P, torch.float32)
+    X_in, P_in = Xt.double().cpu().numpy(), Pt.double().cpu().numpy()
+    prm = S.params(lam=lam, gamma=gamma, prec=prec, inner_iters=5, max_outer=1, validate=0)
+    pl = S.Plan(Aop_gpu, X.shape[1], prm, L_gpu)
+    sc = pl.half_step(Xt, Pt, bool(is_hstep))
+    pl.close()
+    log = []
+    Xo = O.half_step(Aop_oracle, X_in, P_in, O.Params(lam=lam, gamma=gamma, inner_iters=5),
+                     laplacian=L_or is not None, L=L_or, log=log)
+    return Xt.double().cpu().numpy(), Xo, sc, log
+
+
+def _scalars(sc, log, tol):
+    assert abs(sc["rho"] - log[0]["rho"]) <= 1e-10 * log[0]["rho"]
+    assert abs(sc["beta"] - log[-1]["beta"]) <= tol
+    assert abs(sc["ss"] - log[-1]["ss"]) <= tol * log[-1]["ss"]
+    assert int(sc["ls_evals"]) == sum(e["evals"] for e in log)
+
+
+@pytest.fixture(scope="module")
+def dense_c1():
+    p = gen.config(1)                                   # planted dense n = 8192, r = 64
+    A = p["A"]
+    At = _t(A, torch.float32)
+    A_in = At.double().cpu().numpy()                    # the FP32-rounded input both sides see
+    lam = 0.01 * float(np.sqrt(np.sum(A_in * A_in)))    # bench.py's lambda
+    P = gen.start_factor(np.random.default_rng(3), A.shape[0], 64, float(A.mean()))
+    return At, A_in, p["W0"], P, lam
+
+
+@pytest.mark.parametrize("form,tol", [("f32", 3e-5), ("bf16x3", 5e-5)])
+@pytest.mark.parametrize("is_hstep", [0, 1])
+def test_dense_n8192_r64_half_step(S, dense_c1, form, tol, is_hstep):
+    At, A_in, X, P, lam = dense_c1
+    prec = S.F32 if form == "f32" else S.BF16X3
+    Xg, Xo, sc, log = _half_step(S, S.dense(At), A_in, X, P, prec, is_hstep, lam)
+    err = nrel(Xg, Xo)
+    print(f"dense n=8192 r=64 {form} is_hstep={is_hstep}: nrel {err:.3e}")
+    assert err <= tol
+    _scalars(sc, log, 1e-3)
+    assert (Xg >= 0).all()
+
+
+def test_graph_n20000_r20_hstep(S):
+    p = gen.config(2)                                   # SBM n = 20000, 10-NN Laplacian
+    A, L = p["A"], p["L"]
+    r = 20
+    Ag, Lg = S.csr_from_scipy(A, torch.float32), S.csr_from_scipy(L, torch.float32)
+    import scipy.sparse as sp
+    A_in = sp.csr_matrix((Ag.keep[2].double().cpu().numpy(), A.indices, A.indptr), A.shape)
+    L_in = sp.csr_matrix((Lg.keep[2].double().cpu().numpy(), L.indices, L.indptr), L.shape)
+    lam = 0.01 * float(np.sqrt(np.sum(A_in.data ** 2)))
+    X = p["W0"]
+    P = gen.start_factor(np.random.default_rng(4), A.shape[0], r, float(A_in.mean()))
+    Xg, Xo, sc, log = _half_step(S, Ag, A_in, X, P, S.F32, 1, lam, gamma=0.2, L_gpu=Lg,
+                                 L_or=L_in)
+    err = nrel(Xg, Xo)
+    print(f"graph n=20000 r=20 H-step: nrel {err:.3e}")
+    assert err <= 3e-5
+    _scalars(sc, log, 1e-3)
+
+
+def test_lowrank_n200000_r32_half_step(S):
+    q = gen.config(3)                                   # LAI n = 200000, ell = 64
+    U, lamv = q["U"], q["lam"]
+    r = 32
+    Ut = _t(U, torch.float32)
+    lr_in = O.LowRank(Ut.double().cpu().numpy(), lamv)
+    lam = 0.01 * float(np.sqrt(np.sum(lamv ** 2)))     # bench.py's lambda
+    X = q["W0"]
+    P = np.random.default_rng(5).random(X.shape) * float(X.mean())
+    Xg, Xo, sc, log = _half_step(S, S.lowrank(Ut, _t(lamv, torch.float64)), lr_in, X, P,
+                                 S.F32, 0, lam)
+    err = nrel(Xg, Xo)
+    print(f"low rank n=200000 r=32: nrel {err:.3e}")
+    assert err <= 3e-5
+    _scalars(sc, log, 1e-3)
