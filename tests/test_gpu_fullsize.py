@@ -1,7 +1,8 @@
 """Half-step parity at the benchmark sizes, in the launch configuration bench.py times.
 
-The dense planted problem at n = 8192, r = 64 (FP32 and split-BF16 A-pass with its
-balanced split over two workgroups per CU and the fused rho workgroup), the graph problem
+The dense planted problem at n = 8192, r = 64 (the FP32 A-pass with its balanced split
+over two workgroups per CU, and the split-BF16 A-pass, each with the fused rho workgroup),
+the graph problem
 at n = 20000, r = 20 (CSR A-pass and the Laplacian products of the H-step) and the
 low-rank problem at n = 200000, ell = 64, r = 32 (the LAI products; the n x r arrays hold
 more than 4 MiB, so step 2 forms D again).  The oracle's half-step at these sizes costs a
