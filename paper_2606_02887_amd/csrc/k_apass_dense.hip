@@ -189,7 +189,8 @@ __global__ __launch_bounds__(256) void k_apass_f32(const float* __restrict__ A, 
 // With rj.G set, the grid has one more workgroup (the last): it computes rho = ||G||_2
 // (rho.hpp) beside the tiles.  The register bound of two waves per SIMD and the 64 KB of
 // LDS leave room on a CU for it next to a tile workgroup (the tiles take one slot fewer
-// than two per CU), so rho costs no time on the critical path.
+// than two per CU), so rho (56 us alone at r = 64) adds only the slowdown of the tile
+// workgroup that shares its CU: about 6 us at n = 8192.
 __global__ __launch_bounds__(256, 2) void k_apass_f32w(const float* __restrict__ A, int64_t lda,
                                                        const float* __restrict__ P, int64_t n,
                                                        int r, int64_t band, int nband,
@@ -565,8 +566,9 @@ DenseSplit plan_dense_f32(int64_t n, int64_t lda, int r, const void* A) {
     // n = 8192): q full bands of one workgroup per tile, the m workgroups left sharing the
     // rows after them.  Bands of at least 256 rows, and at most kMaxKSplit - 3 of them so
     // that q plus the (at most 2) panels of the rows left fit in kMaxKSplit.  At n = 8192:
-    // 7 bands of 1040 rows and 63 chunks of 928 (whole K splits per tile, 7 per tile, 448
-    // workgroups: 115.6 us).
+    // 7 bands of 1040 rows and 63 chunks of 928.  Measured with loads issued in bursts:
+    // whole K splits (7 per tile, 448 workgroups) 115.6 us, equal chunks without bands
+    // 113.3 us, these bands 107.8 us.
     const int64_t gx = d.gx;
     const int64_t nwg = 2 * device_cus() - 1;
     int64_t q = nwg / gx, m = nwg % gx;
