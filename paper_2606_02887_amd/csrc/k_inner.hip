@@ -223,13 +223,18 @@ __device__ __forceinline__ Loc locate(const BMap& bm, int64_t n, State* st, doub
 // Element access inside a tile: a uniform base pointer (the tile's first row, held in
 // scalar registers) plus this thread's fixed byte offset, so the loads take the
 // scalar-base + 32-bit vector-offset form and one offset register serves every array.
+// The access goes through a global-address-space pointer: the opaque tile pointer (below)
+// hides where the array lives, and a generic pointer would give flat instructions, which
+// also count against the LDS wait counter, so every wait on LDS would wait for them too.
 template <typename T>
 __device__ __forceinline__ T ldo(const T* __restrict__ base, uint32_t bo) {
-  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + bo);
+  typedef const __attribute__((address_space(1))) T* GP;
+  return *(GP)(reinterpret_cast<const char*>(base) + bo);
 }
 template <typename T>
 __device__ __forceinline__ void sto(T* __restrict__ base, uint32_t bo, T v) {
-  *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + bo) = v;
+  typedef __attribute__((address_space(1))) T* GP;
+  *(GP)(reinterpret_cast<char*>(base) + bo) = v;
 }
 // A tile's pointer into one array, pinned as an opaque uniform (scalar-register) value:
 // the empty asm emits nothing, but it stops the compiler from re-associating
@@ -289,27 +294,43 @@ __global__ __launch_bounds__(kThreads, (inner_occupancy<T, RP>())) void k_init(
   for (int64_t t = lc.bid; t < ntiles; t += lc.nb) {
     const int64_t row0 = t * TM, tb = row0 * r;
     const T* __restrict__ Bt = tile_ptr(Bpart, tb);
-    T x[8], cv[8], pv[8];
+    T x[8], cv[8], pv[8], lx[8];
+    bool ok[8];
+    // X, P (and L X) of the tile and the split-K partials of B, the loads of four
+    // partials for all eight elements in flight before any is added; each element adds
+    // its partials in panel order
 #pragma unroll
     for (int p = 0; p < 8; ++p) {
-      const bool ok = row0 + lr[p] < n && cl[p] < r;
-      T b = T(0);
-      if (ok) {
-        int s = 0;
-        for (; s + 4 <= ksplit; s += 4) {  // four split-K partials in flight, added in order
-          const T b0 = ldo(Bt + s * bstride, bo[p]), b1 = ldo(Bt + (s + 1) * bstride, bo[p]);
-          const T b2 = ldo(Bt + (s + 2) * bstride, bo[p]), b3 = ldo(Bt + (s + 3) * bstride, bo[p]);
-          b += b0;
-          b += b1;
-          b += b2;
-          b += b3;
-        }
-        for (; s < ksplit; ++s) b += ldo(Bt + s * bstride, bo[p]);
-      }
-      x[p] = ok ? ldo(tile_ptr(X, tb), bo[p]) : T(0);
-      pv[p] = ok ? ldo(tile_ptr(P, tb), bo[p]) : T(0);
-      cv[p] = b + lam * pv[p];
+      ok[p] = row0 + lr[p] < n && cl[p] < r;
+      x[p] = ok[p] ? ldo(tile_ptr(X, tb), bo[p]) : T(0);
+      pv[p] = ok[p] ? ldo(tile_ptr(P, tb), bo[p]) : T(0);
+      lx[p] = (ok[p] && LX) ? ldo(tile_ptr(LX, tb), bo[p]) : T(0);
     }
+    T b[8];
+#pragma unroll
+    for (int p = 0; p < 8; ++p) b[p] = T(0);
+    int s = 0;
+    for (; s + 4 <= ksplit; s += 4) {
+      T bq[4][8];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int p = 0; p < 8; ++p)
+          bq[u][p] = ok[p] ? ldo(Bt + (s + u) * bstride, bo[p]) : T(0);
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int p = 0; p < 8; ++p) b[p] += bq[u][p];
+    }
+    for (; s < ksplit; ++s) {
+      T bs[8];
+#pragma unroll
+      for (int p = 0; p < 8; ++p) bs[p] = ok[p] ? ldo(Bt + s * bstride, bo[p]) : T(0);
+#pragma unroll
+      for (int p = 0; p < 8; ++p) b[p] += bs[p];
+    }
+#pragma unroll
+    for (int p = 0; p < 8; ++p) cv[p] = b[p] + lam * pv[p];
     if (first) store_G<T, RP>(sm.G, gv);
     first = false;
     __syncthreads();
@@ -320,10 +341,10 @@ __global__ __launch_bounds__(kThreads, (inner_occupancy<T, RP>())) void k_init(
     tile_gemm<T, RP>(sm.a, sm.G, xg);
 #pragma unroll
     for (int p = 0; p < 8; ++p) {
-      if (row0 + lr[p] < n && cl[p] < r) {
+      if (ok[p]) {
         sto(tile_ptr(Cout, tb), bo[p], cv[p]);
         T gvv = xg[p] + lam * x[p] - cv[p];
-        if (LX) gvv += gam * ldo(tile_ptr(LX, tb), bo[p]);
+        if (LX) gvv += gam * lx[p];
         sto(tile_ptr(g, tb), bo[p], gvv);
         if (is_hstep) {
           v[0] += (double)cv[p] * (double)pv[p];
