@@ -113,9 +113,15 @@ __global__ __launch_bounds__(256) void k_bspmm(const BGraph* __restrict__ graphs
   const int c = lane % cw, slot = lane / cw;
   const int64_t wave = ((int64_t)blockIdx.x - G->blk0) * (kThreads / kWave) + threadIdx.x / kWave;
   const int64_t nw = (int64_t)G->nblk * (kThreads / kWave);
-  const int64_t* __restrict__ rowptr = G->rowptr;
-  const int32_t* __restrict__ col = G->col;
-  const T* __restrict__ val = (const T*)G->val;
+  // the CSR arrays come from the graph table, so the compiler cannot see that they are
+  // global memory: without the address space it would emit flat loads, which also count
+  // against the LDS wait counter
+  typedef const __attribute__((address_space(1))) int64_t* GI64;
+  typedef const __attribute__((address_space(1))) int32_t* GI32;
+  typedef const __attribute__((address_space(1))) T* GT_;
+  const GI64 __restrict__ rowptr = (GI64)G->rowptr;
+  const GI32 __restrict__ col = (GI32)G->col;
+  const GT_ __restrict__ val = (GT_)G->val;
   const int64_t nr = n * r;
   const T* __restrict__ Pg = P + G->off0;
   T* __restrict__ Bg = B + G->off0;

@@ -80,8 +80,11 @@ __global__ __launch_bounds__(kThreads) void k_ws_frame(const BInst* __restrict__
   const int64_t n = d.n;
   const T* __restrict__ Y = Ybuf + d.off;
   double* __restrict__ R = Rbuf + d.off;
-  const int64_t* __restrict__ rowptr = G.rowptr;
-  const T* __restrict__ val = (const T*)G.val;
+  // table pointers: cast to global memory so the loads are not flat instructions
+  typedef const __attribute__((address_space(1))) int64_t* GI64;
+  typedef const __attribute__((address_space(1))) T* GT_;
+  const GI64 __restrict__ rowptr = (GI64)G.rowptr;
+  const GT_ __restrict__ val = (GT_)G.val;
   // R_i = Y_i / d_i and the first squared norms
   double best = -1.0;
   int bidx = 0;
