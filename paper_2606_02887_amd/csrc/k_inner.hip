@@ -925,13 +925,17 @@ int rank_pad(int r) {
   return rp;
 }
 
-// Compute units of the current device (MI355X: 256).
+// Compute units of the current device (MI355X: 256), looked up once per device: the
+// launchers ask on every launch.
 static int64_t inner_cus() {
+  static int cached[64] = {0};  // concurrent first lookups store the same value
   int dev = 0, cus = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (dev >= 0 && dev < 64 && cached[dev] > 0) return cached[dev];
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
       cus < 1)
     cus = 256;
+  if (dev >= 0 && dev < 64) cached[dev] = cus;
   return cus;
 }
 
