@@ -173,6 +173,14 @@ __device__ __forceinline__ double gram_sum4(const double* __restrict__ part, int
                                            int q) {
   double s = 0.0;
   int b = q;
+  // sixteen of this thread's slabs per round trip, added in slab order
+  for (; b + 60 < nb; b += 64) {
+    double v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) v[u] = part[(size_t)(b + 4 * u) * rr + e];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) s += v[u];
+  }
   for (; b + 12 < nb; b += 16) {
     const double v0 = part[(size_t)b * rr + e], v1 = part[(size_t)(b + 4) * rr + e];
     const double v2 = part[(size_t)(b + 8) * rr + e], v3 = part[(size_t)(b + 12) * rr + e];

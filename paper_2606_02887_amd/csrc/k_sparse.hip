@@ -434,6 +434,14 @@ __global__ __launch_bounds__(256) void k_lai_reduce32(const float* __restrict__ 
   double s = 0.0;
   if (e < ne) {
     int b = q;
+    // sixteen of this thread's blocks per round trip, added in block order
+    for (; b + 60 < nb; b += 64) {
+      float v[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) v[u] = part[(size_t)(b + 4 * u) * ne + e];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) s += v[u];
+    }
     for (; b + 12 < nb; b += 16) {
       const float v0 = part[(size_t)b * ne + e], v1 = part[(size_t)(b + 4) * ne + e];
       const float v2 = part[(size_t)(b + 8) * ne + e], v3 = part[(size_t)(b + 12) * ne + e];
