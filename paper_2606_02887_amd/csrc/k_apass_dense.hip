@@ -515,12 +515,18 @@ __global__ __launch_bounds__(256) void k_apass_bf16x3(const uint16_t* __restrict
 
 // ----------------------------------------------------------------------------- partial sum
 // out = part[0] + part[1] + ... (left to right, the order the init kernel uses).
+// ks <= kMaxKSplit: an element's partials are all loaded before the first is added.
 template <typename T>
 __global__ __launch_bounds__(256) void k_sum_parts(const T* __restrict__ part, int ks,
                                                    int64_t stride, T* __restrict__ out, int64_t N) {
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < N; e += (int64_t)gridDim.x * 256) {
+    T v[kMaxKSplit];
+#pragma unroll
+    for (int s = 0; s < kMaxKSplit; ++s) v[s] = s < ks ? part[s * stride + e] : T(0);
     T b = T(0);
-    for (int s = 0; s < ks; ++s) b += part[s * stride + e];
+#pragma unroll
+    for (int s = 0; s < kMaxKSplit; ++s)
+      if (s < ks) b += v[s];
     out[e] = b;
   }
 }
