@@ -247,6 +247,21 @@ __device__ __forceinline__ P tile_ptr(P base, int64_t tb) {
   return q;
 }
 
+// ----------------------------------------------------------------------------- Z and D
+// The two projections of Algorithm 1 and the gradient at Z.
+template <typename T>
+__device__ __forceinline__ T first_proj(T x, T g, T rinv) {  // max(0, X - g / rho)
+  return relu(fmaT(-g, rinv, x));
+}
+template <typename T>
+__device__ __forceinline__ T grad_at_z(T g, T dzg, T lam, T dz) {  // g + (Z-X)(G + lam I)
+  return fmaT(lam, dz, g + dzg);
+}
+template <typename T>
+__device__ __forceinline__ T second_dir(T z, T gz, T alpha) {  // max(0, Z - alpha gZ) - Z
+  return relu(fmaT(-alpha, gz, z)) - z;
+}
+
 // ----------------------------------------------------------------------------- init
 // C = (sum of the A-pass partials) + lam P;  g = X G + lam X - C [+ gam LX].
 template <typename T, int RP>
@@ -254,7 +269,7 @@ __global__ __launch_bounds__(kThreads, (inner_occupancy<T, RP>())) void k_init(
     const T* __restrict__ X, const T* __restrict__ P, const T* __restrict__ Bpart, int ksplit,
     int64_t bstride, T* __restrict__ Cout, T* __restrict__ g, const T* __restrict__ LX,
     const T* __restrict__ GT, int64_t n, int r, int is_hstep, KParams kp, State* __restrict__ st,
-    double* __restrict__ partsA, BMap bm) {
+    double* __restrict__ partsA, BMap bm, T* __restrict__ Zn, T* __restrict__ Dn) {
   const Loc lc = locate(bm, n, st, nullptr, kp.lam);
   st = lc.st;
   if (st->done) return;
@@ -288,6 +303,7 @@ __global__ __launch_bounds__(kThreads, (inner_occupancy<T, RP>())) void k_init(
   T gv[TileCfg<RP>::NG];
   load_G<T, RP>(GT, r, gv);
   const T lam = (T)kp.lam, gam = (T)kp.gamma;
+  const T rinv = Zn ? (T)(1.0 / st->rho) : T(0);
   double v[1] = {0.0};
   const int64_t ntiles = (n + TM - 1) / TM;
   bool first = true;
@@ -346,6 +362,11 @@ __global__ __launch_bounds__(kThreads, (inner_occupancy<T, RP>())) void k_init(
         T gvv = xg[p] + lam * x[p] - cv[p];
         if (LX) gvv += gam * lx[p];
         sto(tile_ptr(g, tb), bo[p], gvv);
+        if (Zn) {  // Laplacian H-step: Z and Z - X of the first inner iteration
+          const T zz = first_proj(x[p], gvv, rinv);
+          sto(tile_ptr(Zn, tb), bo[p], zz);
+          sto(tile_ptr(Dn, tb), bo[p], zz - x[p]);
+        }
         if (is_hstep) {
           v[0] += (double)cv[p] * (double)pv[p];
         } else {
@@ -498,21 +519,6 @@ __device__ bool inner_entry(int k, int is_hstep, int r, const KParams& kp, State
   return true;
 }
 
-// ----------------------------------------------------------------------------- Z and D
-// The two projections of Algorithm 1 and the gradient at Z.
-template <typename T>
-__device__ __forceinline__ T first_proj(T x, T g, T rinv) {  // max(0, X - g / rho)
-  return relu(fmaT(-g, rinv, x));
-}
-template <typename T>
-__device__ __forceinline__ T grad_at_z(T g, T dzg, T lam, T dz) {  // g + (Z-X)(G + lam I)
-  return fmaT(lam, dz, g + dzg);
-}
-template <typename T>
-__device__ __forceinline__ T second_dir(T z, T gz, T alpha) {  // max(0, Z - alpha gZ) - Z
-  return relu(fmaT(-alpha, gz, z)) - z;
-}
-
 // ----------------------------------------------------------------------------- step 1
 // Z = max(0, X - g/rho);  grad f(Z) = g + (Z - X)(G + lam I) [+ gam L(Z-X)];
 // D = max(0, Z - alpha grad f(Z)) - Z.  Partials: <grad f(Z), D>, <D G, D>, ||D||^2 and
@@ -560,10 +566,10 @@ __global__ __launch_bounds__(kThreads, (inner_occupancy<T, RP>())) void k_step1(
   // loads first: State scalars, partial sums of the previous kernel, G, the first tile
   const int done = st->done;
   const int km = k > 0 ? k - 1 : 0;
-  const int stop_prev = st->stop[km], stop_k = st->stop[k];
-  const double e_prev = st->e[km], alpha_k2 = st->alpha[k], rho = st->rho;
+  const int stop_prev = st->stop[km];
+  const double e_prev = st->e[km], rho = st->rho;
   double pe[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  if (phase != 2) entry_loads(k, is_hstep, partsA, partsC, lc.nb, pe);
+  entry_loads(k, is_hstep, partsA, partsC, lc.nb, pe);
   T gv[TileCfg<RP>::NG];
   if (phase != 1) load_G<T, RP>(GT, r, gv);
   T x[8], gvv[8], z[8], lz[8];
@@ -580,15 +586,13 @@ __global__ __launch_bounds__(kThreads, (inner_occupancy<T, RP>())) void k_step1(
   };
   if (lc.bid < ntiles) load_tile((int64_t)lc.bid * TM);
   if (done) return;
+  // every phase opens the inner iteration: the Laplacian path launches phase 2 only (its
+  // Z and Z - X come from the previous step 2 or from init), phase 1 only as the closing
+  // entry of the half-step API
   double alpha_d = 0.0;
-  if (phase != 2) {
-    if (!inner_entry(k, is_hstep, r, kp, st, pe, stop_prev, e_prev, rho, Gcur, Gprev, trace,
-                     sm.red, lc.bid == 0 && threadIdx.x == 0, alpha_d))
-      return;
-  } else {
-    if (stop_k) return;
-    alpha_d = alpha_k2;
-  }
+  if (!inner_entry(k, is_hstep, r, kp, st, pe, stop_prev, e_prev, rho, Gcur, Gprev, trace,
+                   sm.red, lc.bid == 0 && threadIdx.x == 0, alpha_d))
+    return;
   const T rinv = (T)(1.0 / rho);
   const T alpha = (T)alpha_d;
   const T lam = (T)kp.lam, gam = (T)kp.gamma;
@@ -899,6 +903,11 @@ __global__ __launch_bounds__(kThreads, (inner_occupancy<T, RP, V>())) void k_ste
           sto(tile_ptr(LXb, tb), bo[p], lxn);
           if (is_hstep) v[7] += (double)xn[p] * (double)lxn;
         }
+        if (lap) {  // Z and Z - X of the next inner iteration, from the final X and g
+          const T zn = first_proj(xn[p], gn, rinv);
+          sto(tile_ptr(Z, tb), bo[p], zn);
+          sto(tile_ptr(D, tb), bo[p], zn - xn[p]);
+        }
       }
     }
   }
@@ -968,12 +977,13 @@ int inner_grid(int64_t n, int r, int esz) {
 template <typename T>
 void launch_init(const T* X, const T* P, const T* Bpart, int ksplit, int64_t bstride, T* C, T* g,
                  const T* LX, const T* GT, int64_t n, int r, int is_hstep, const KParams& kp,
-                 State* st, double* partsA, hipStream_t s, const BMap& bm, int grid) {
+                 State* st, double* partsA, hipStream_t s, const BMap& bm, int grid, T* Zn,
+                 T* Dn) {
   if (grid <= 0) grid = inner_grid(n, r, (int)sizeof(T));
   SNMF_DISPATCH_RP(rank_pad(r),
                    hipLaunchKernelGGL((k_init<T, RP>), dim3(grid), dim3(kThreads), 0, s, X, P,
                                       Bpart, ksplit, bstride, C, g, LX, GT, n, r, is_hstep, kp, st,
-                                      partsA, bm))
+                                      partsA, bm, Zn, Dn))
 }
 
 template <typename T>
@@ -1023,7 +1033,7 @@ void launch_step2(T* X, T* g, T* Z, T* D, const T* LS, const T* C, const T* P, T
 #define SNMF_INST(T)                                                                            \
   template void launch_init<T>(const T*, const T*, const T*, int, int64_t, T*, T*, const T*,   \
                                const T*, int64_t, int, int, const KParams&, State*, double*,   \
-                               hipStream_t, const BMap&, int);                                  \
+                               hipStream_t, const BMap&, int, T*, T*);                          \
   template void launch_step1<T>(const T*, const T*, T*, T*, const T*, const T*, const double*, \
                                 const double*, int64_t, int, int, int, int, const KParams&,     \
                                 State*, const double*, double*, const double*, double*,         \

@@ -114,7 +114,8 @@ void launch_lai(const T* U, int ell, const double* lam, const T* P, int64_t n, i
 template <typename T>
 void launch_init(const T* X, const T* P, const T* Bpart, int ksplit, int64_t bstride, T* C, T* g,
                  const T* LX, const T* GT, int64_t n, int r, int is_hstep, const KParams& kp,
-                 State* st, double* partsA, hipStream_t s, const BMap& bm = BMap{}, int grid = 0);
+                 State* st, double* partsA, hipStream_t s, const BMap& bm = BMap{}, int grid = 0,
+                 T* Zn = nullptr, T* Dn = nullptr);  // Laplacian H-step: Z, Z - X of iteration 0
 template <typename T>
 void launch_step1(const T* X, const T* g, T* Z, T* D, const T* LdZ, const T* GT,
                   const double* Gcur, const double* Gprev, int64_t n, int r, int k, int phase,

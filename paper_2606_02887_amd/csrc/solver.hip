@@ -269,7 +269,8 @@ snmf_status half_start(snmf_plan* pl, T* X, const T* P, int is_hstep, bool with_
   }
   launch_init<T>(X, P, (const T*)pl->Bpart, ksplit_of(pl), n * r, (T*)pl->C, (T*)pl->g,
                  lap ? (const T*)pl->LX : nullptr, (const T*)pl->GT[gi], n, r, is_hstep, pl->kp,
-                 pl->st, pl->partsA, s);
+                 pl->st, pl->partsA, s, BMap{}, 0, lap ? (T*)pl->Z : nullptr,
+                 lap ? (T*)pl->D : nullptr);
   HIP_TRY(hipGetLastError());
   return SNMF_OK;
 }
@@ -304,9 +305,11 @@ snmf_status inner_step(snmf_plan* pl, T* X, const T* P, int is_hstep, int k, hip
     T* LT = (T*)pl->LT;
     const int32_t* g1 = &pl->st->done;
     const int32_t* g2 = &pl->st->stop[k];
-    launch_step1<T>(X, g, Z, D, nullptr, GT, pl->G64[0], pl->G64[1], n, r, k, 1, is_hstep, pl->kp,
-                    pl->st, pl->partsA, pl->partsB, pl->partsC, pl->trace, s);
-    launch_spmm<T>(rp, ci, lv, D, n, r, LT, nullptr, nullptr, g1, g2, s);
+    // Z and D = Z - X of this iteration come from init (k = 0) or the previous step 2, so
+    // the first product runs at once, before this iteration's stop test (made by its
+    // phase-2 step 1): it is gated on the solve only, since stop[k] still holds the
+    // previous half-step's flag, and a stopped iteration's product is never read
+    launch_spmm<T>(rp, ci, lv, D, n, r, LT, nullptr, nullptr, g1, nullptr, s);
     launch_step1<T>(X, g, Z, D, LT, GT, pl->G64[0], pl->G64[1], n, r, k, 2, is_hstep, pl->kp,
                     pl->st, pl->partsA, pl->partsB, pl->partsC, pl->trace, s);
     launch_spmm<T>(rp, ci, lv, D, n, r, nullptr, D, pl->partsD, g1, g2, s);
