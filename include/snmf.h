@@ -191,16 +191,20 @@ snmf_status snmf_split_bf16(const float* x, int64_t count, uint16_t* hi, uint16_
  * instance keeps its own scalars (rho, BB steps, line search, nonmonotone reference,
  * monitor, stop flag), so instance (g, s) follows exactly the iteration of a single
  * solve of problem g from its start; the restarts of a problem share one sweep over its
- * CSR matrix in the A-pass (B_s = A P_s for all s at once).  This form is not in the
- * paper: it serves many-small-graph workloads and multi-start runs.
+ * CSR matrix in the A-pass (B_s = A P_s for all s at once); with dense A in BF16X3 the
+ * restarts share one stream of A_hi and A_lo (one stacked split-BF16 product of S r
+ * columns).  This form is not in the paper: it serves many-small-graph workloads and
+ * multi-start runs.
  *
  * A:        nprob matrices, all CSR or all DENSE, symmetric, n_g >= 1 (LOWRANK and a
  *           Laplacian term are not supported: E_UNSUPPORTED).
  * r:        nprob ranks, 1 <= r_g <= min(64, n_g).
  * lam:      nprob penalties lambda_g (host), or NULL to use p->lambda for every problem.
  * restarts: S >= 1 starts per problem.
- * p:        shared parameters (precision F64 or F32; max_outer, target_res and
- *           check_every apply per instance; gamma and L are ignored).
+ * p:        shared parameters (precision F64 or F32, or BF16X3 for dense A: the A-pass
+ *           in split BF16 as for the single solve, everything else in FP32; max_outer,
+ *           target_res and check_every apply per instance; gamma and L are ignored).
+ *           BF16X3 with CSR A: E_UNSUPPORTED.
  * W0[g]:    device array of S * n_g * r_g values: restart s is the n_g x r_g row-major
  *           block at offset s * n_g * r_g.  W_out[g], Ht_out[g] have the same layout.
  * infos:    host array of nprob * S records, instance g * S + s.
@@ -226,6 +230,11 @@ snmf_status snmf_solve_batched(int32_t nprob, const snmf_matrix* A, const int32_
 /* The batch's A-pass alone: P and B are device arrays holding every instance's n_g x r_g
  * block one after another in instance order (g * S + s), B = A_g P for each. */
 snmf_status snmf_batch_apass(snmf_batch* b, const void* P, void* B, void* stream);
+/* Average duration (ms) of the batch's A-pass (every launch of snmf_batch_apass: for
+ * BF16X3 the stacked partner split and the stacked product of each problem) over `reps`
+ * back-to-back runs on the batch's stream, measured with HIP events after one untimed
+ * run.  P is a batch buffer (device); the products land in batch scratch. */
+snmf_status snmf_batch_time_apass(snmf_batch* b, const void* P, int32_t reps, double* ms);
 /* Number of instances and the total element count sum_g S n_g r_g of a batch buffer. */
 snmf_status snmf_batch_size(const snmf_batch* b, int32_t* ninst, int64_t* elements);
 

@@ -72,11 +72,37 @@ snmf_status bcheck_csr(snmf_batch* b, const snmf_matrix* M, const std::string& w
   return SNMF_OK;
 }
 
+// G64 set (dense BF16X3 only): rho of every instance inside the stacked A-pass launches,
+// from its Gram in G64
 template <typename T>
-snmf_status bapass(snmf_batch* b, const T* P, T* B, hipStream_t s) {
+snmf_status bapass(snmf_batch* b, const T* P, T* B, hipStream_t s,
+                   const double* G64 = nullptr) {
   if (!b->dense) {
     launch_bspmm<T>(b->dgraph, b->sblk_tab, b->sblocks, b->states, P, B, s);
     HIP_TRY(hipGetLastError());
+    return SNMF_OK;
+  }
+  if (b->prec == SNMF_BF16X3) {
+    // one stacked split-BF16 product per problem: its S restarts are consecutive blocks
+    for (int g = 0; g < b->nprob; ++g) {
+      const BInst& d = b->hinst[(size_t)g * b->S];
+      const DenseSplit& sp = b->ds[g];
+      const int64_t snr = (int64_t)b->S * d.n * d.r;
+      State* st = b->states + (size_t)g * b->S;
+      const double* Grho = G64 ? G64 + d.goff : nullptr;
+      launch_split_pt_stack((const float*)(P + d.off), d.n, d.r, b->S, b->ldb[g], b->Pthi,
+                            b->Ptlo, st, s);
+      if (sp.ksplit == 1) {
+        launch_apass_bf16x3_stack(b->Ahi[g], b->Alo[g], b->ldb[g], b->Pthi, b->Ptlo, d.n, d.r,
+                                  b->S, sp, (float*)(B + d.off), 0, st, Grho, s);
+      } else {
+        launch_apass_bf16x3_stack(b->Ahi[g], b->Alo[g], b->ldb[g], b->Pthi, b->Ptlo, d.n, d.r,
+                                  b->S, sp, (float*)b->Bpart, snr, st, Grho, s);
+        launch_sum_parts<float>((const float*)b->Bpart, sp.ksplit, snr, (float*)(B + d.off), snr,
+                                s);
+      }
+      HIP_TRY(hipGetLastError());
+    }
     return SNMF_OK;
   }
   for (int i = 0; i < b->ninst; ++i) {
@@ -103,13 +129,16 @@ snmf_status bhalf_start(snmf_batch* b, T* X, const T* P, int is_hstep, bool with
   const int gi = is_hstep ? 1 : 0;
   for (const auto& c : b->cls)
     launch_bgram<T>(P, c.r, b->gblk_tab + c.gtab_off, c.gblocks, b->dinst, b->states, b->gpart, s);
-  launch_bgram_reduce<T>(b->dinst, b->ninst, b->states, b->gpart, b->G64[gi], (T*)b->GT[gi], s);
+  launch_bgram_reduce<T>(b->dinst, b->ninst, b->max_r, b->states, b->gpart, b->G64[gi],
+                         (T*)b->GT[gi], s);
   HIP_TRY(hipGetLastError());
-  if (with_rho) {
+  // dense BF16X3 (when the slots allow): rho runs inside the stacked A-pass launches
+  const bool rho_in_apass = b->dense && b->prec == SNMF_BF16X3 && b->rho_in_apass;
+  if (with_rho && !rho_in_apass) {
     launch_brho(b->dinst, b->ninst, b->states, b->G64[gi], s);
     HIP_TRY(hipGetLastError());
   }
-  SNMF_TRY(bapass<T>(b, P, (T*)b->B, s));
+  SNMF_TRY(bapass<T>(b, P, (T*)b->B, s, with_rho && rho_in_apass ? b->G64[gi] : nullptr));
   for (const auto& c : b->cls) {
     launch_init<T>(X, P, (const T*)b->B, 1, 0, (T*)b->C, (T*)b->g, nullptr, (const T*)b->GT[gi], 0,
                    c.r, is_hstep, b->kp, b->states, b->partsA, s, b->bmap(c), c.blocks);
@@ -171,8 +200,9 @@ snmf_status batch_create(int32_t nprob, const snmf_matrix* A, const int32_t* r, 
   if (nprob < 1) return fail(SNMF_E_ARG, "nprob must be >= 1");
   if (restarts < 1) return fail(SNMF_E_ARG, "restarts must be >= 1");
   if (!A || !r) return fail(SNMF_E_ARG, "A and r are required");
-  if (p->prec == SNMF_BF16X3) return fail(SNMF_E_UNSUPPORTED, "batched solves run in F64 or F32");
   const bool dense = A[0].fmt == SNMF_DENSE;
+  if (p->prec == SNMF_BF16X3 && !dense)
+    return fail(SNMF_E_UNSUPPORTED, "batched BF16X3 solves take dense A");
   for (int g = 0; g < nprob; ++g) {
     const std::string what = "A[" + std::to_string(g) + "]";
     SNMF_TRY(check_matrix(&A[g], what.c_str()));
@@ -309,6 +339,30 @@ snmf_status batch_create(int32_t nprob, const snmf_matrix* A, const int32_t* r, 
       b->ksplit_max = std::max(b->ksplit_max, b->ds[g].ksplit);
     }
   }
+  // BF16X3: one stacked product per problem over its S r columns
+  int64_t pt_max = 0, bpart_max = 0;
+  if (dense && b->prec == SNMF_BF16X3) {
+    b->ds.resize(nprob);
+    b->ldb.resize(nprob);
+    b->Ahi.assign(nprob, nullptr);
+    b->Alo.assign(nprob, nullptr);
+    // rho runs inside the A-pass launch when its S workgroups find free slots beside the
+    // product's (two per CU): a rho workgroup that waits for a slot, or holds one a tile
+    // workgroup waits for, lengthens the launch by a whole rho (about 55 us at r = 64)
+    int dev = 0, cus = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    b->rho_in_apass = true;
+    for (int g = 0; g < nprob; ++g) {
+      const int64_t R = (int64_t)restarts * b->r[g];
+      b->ds[g] = plan_dense_bf16_stack(b->n[g], R);
+      if (b->ds[g].nwg + restarts > 2 * (int64_t)cus) b->rho_in_apass = false;
+      b->ldb[g] = (b->n[g] + 63) / 64 * 64;
+      pt_max = std::max(pt_max, R * b->ldb[g]);
+      if (b->ds[g].ksplit > 1)
+        bpart_max = std::max(bpart_max, (int64_t)b->ds[g].ksplit * R * b->n[g]);
+    }
+  }
   b->trace_stride = (int64_t)p->max_outer * kTraceFields;
 
   // ---- one allocation, carved
@@ -325,6 +379,15 @@ snmf_status batch_create(int32_t nprob, const snmf_matrix* A, const int32_t* r, 
   add(&b->D, tb);
   add(&b->B, tb);
   if (dense && b->prec == SNMF_F32) add(&b->Bpart, (size_t)b->ksplit_max * b->max_nr * b->esz);
+  if (dense && b->prec == SNMF_BF16X3) {
+    for (int g = 0; g < nprob; ++g) {
+      add((void**)&b->Ahi[g], (size_t)b->n[g] * b->ldb[g] * 2);
+      add((void**)&b->Alo[g], (size_t)b->n[g] * b->ldb[g] * 2);
+    }
+    add((void**)&b->Pthi, (size_t)pt_max * 2);
+    add((void**)&b->Ptlo, (size_t)pt_max * 2);
+    if (bpart_max > 0) add(&b->Bpart, (size_t)bpart_max * 4);
+  }
   add(&b->GT[0], (size_t)b->gsum * b->esz);
   add(&b->GT[1], (size_t)b->gsum * b->esz);
   add((void**)&b->G64[0], (size_t)b->gsum * 8);
@@ -374,6 +437,12 @@ snmf_status batch_create(int32_t nprob, const snmf_matrix* A, const int32_t* r, 
     if (!(b->normA2[g] > 0.0)) return fail(SNMF_E_ARG, what + " is zero");
   }
   for (int i = 0; i < b->ninst; ++i) b->hinst[i].normA2 = b->normA2[b->hinst[i].prob];
+  if (dense && b->prec == SNMF_BF16X3) {
+    for (int g = 0; g < nprob; ++g)
+      launch_split_rows((const float*)A[g].dense, b->n[g], A[g].ld, b->ldb[g], b->Ahi[g],
+                        b->Alo[g], b->s);
+    HIP_TRY(hipGetLastError());
+  }
   HIP_TRY(hipMemcpyAsync(b->dinst, b->hinst.data(), b->hinst.size() * sizeof(BInst),
                          hipMemcpyHostToDevice, b->s));
   HIP_TRY(hipMemcpyAsync(b->blk_tab, btab.data(), btab.size() * 4, hipMemcpyHostToDevice, b->s));
@@ -554,6 +623,30 @@ snmf_status snmf_batch_apass(snmf_batch* b, const void* P, void* B, void* stream
     HIP_TRY(hipEventRecord(b->ev_out, b->s));
     HIP_TRY(hipStreamWaitEvent(user, b->ev_out, 0));
   }
+  return SNMF_OK;
+}
+
+snmf_status snmf_batch_time_apass(snmf_batch* b, const void* P, int32_t reps, double* ms) {
+  if (!b || !P || !ms) return fail(SNMF_E_ARG, "batch, P and ms are required");
+  if (reps < 1) return fail(SNMF_E_ARG, "reps must be >= 1");
+  launch_breset(b->states, b->dinst, b->ninst, b->s);
+  auto run = [&]() -> snmf_status {
+    if (b->prec == SNMF_F64) return bapass<double>(b, (const double*)P, (double*)b->B, b->s);
+    return bapass<float>(b, (const float*)P, (float*)b->B, b->s);
+  };
+  SNMF_TRY(run());
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  HIP_TRY(hipEventRecord(e0, b->s));
+  for (int i = 0; i < reps; ++i) SNMF_TRY(run());
+  HIP_TRY(hipEventRecord(e1, b->s));
+  HIP_TRY(hipEventSynchronize(e1));
+  float tot = 0.0f;
+  HIP_TRY(hipEventElapsedTime(&tot, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *ms = (double)tot / reps;
   return SNMF_OK;
 }
 

@@ -1,0 +1,258 @@
+// The split-BF16 A-pass of a batched dense solve, stacked over restarts: B_s = A P_s for
+// the S restarts of one problem in one launch.  All S products share their left operand
+// (the per-iteration A-pass of Section 4.1, once per restart), so A_hi and A_lo are
+// streamed once for the S right operands: at r = 64 and S = 8 the three BF16 products
+// (A_hi P_hi + A_hi P_lo + A_lo P_hi, FP32 accumulation, the split of the single solve)
+// become bound by the matrix cores instead of HBM.
+//
+// Operands: A_hi, A_lo (n x ldb BF16, columns n.. zero); Pt_hi, Pt_lo ((S r) x ldb BF16,
+// row s r + m holds column m of P_s, columns n.. zero; k_split_pt_stack writes them).
+// The S r stacked columns are cut into blocks of 64.  A workgroup (4 waves x 32 output
+// rows) computes 128 rows x one column block over one K slice; with one slice it writes
+// B directly, else split-K partials that k_sum_parts adds in slice order.  The spectral
+// norms rho_s of the restarts' Grams can run in the same launch.
+#include <type_traits>
+
+#include "common.hpp"
+#include "kernels.hpp"
+#include "rho.hpp"
+
+namespace snmf {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+
+namespace {
+
+__device__ __forceinline__ bool stack_done(const State* st, int S) {
+  for (int i = 0; i < S; ++i)
+    if (!st[i].done) return false;
+  return true;
+}
+
+// Workgroup id -> (unit, column block), unit = K slice * gx + row tile.  Workgroups go to
+// the 8 XCDs in turn (id mod 8).  The G column blocks of one unit get ids of one residue
+// mod 8 that are dispatched one after another on that XCD, so they read the same rows of
+// A at about the same time through that XCD's L2.  Ids past the last whole group of 8 G
+// map in order.
+struct StackMap {
+  int64_t unit;
+  int cb;
+};
+__device__ __forceinline__ StackMap stack_map(int64_t id, int64_t nwg, int G) {
+  const int64_t grp = 8 * (int64_t)G;
+  const int64_t full = nwg / grp * grp;
+  StackMap m;
+  if (id < full) {
+    const int64_t x = id & 7, j = id >> 3;
+    const int64_t jg = j / G;
+    m.unit = jg * 8 + x;
+    m.cb = (int)(j - jg * G);
+  } else {
+    m.unit = id / G;
+    m.cb = (int)(id - m.unit * G);
+  }
+  return m;
+}
+
+}  // namespace
+
+template <int V>
+using IC = std::integral_constant<int, V>;
+
+// Per 64-column slab of A a lane loads 32 consecutive BF16 of its row from A_hi and A_lo
+// (four 16-byte vectors each; lanes l and l + 32 cover 128 contiguous bytes); the slab of
+// the block's 64 rows of Pt_hi / Pt_lo is staged in LDS (two buffers) and shared by the
+// four waves.  Loads run two slabs ahead: one slab's MFMAs (24 per wave) are shorter than
+// a memory round trip, so with one slab ahead every slab waited on its loads.  The A
+// vectors go to a ring of three register sets and the Pt vectors to a ring of two; the
+// loop is unrolled six slabs deep so every ring index is static.  Past the last slab the
+// prefetch re-reads the last slab (in bounds, unused).
+//
+// Workgroups past the first ntile (one per restart, launched when Grho is set) compute
+// rho = ||G_s||_2 of restart s (r x r FP64 Grams r^2 apart) beside the products.
+__global__ __launch_bounds__(256, 2) void k_apass_bf16x3s(
+    const uint16_t* __restrict__ Ahi, const uint16_t* __restrict__ Alo, int64_t ldb,
+    const uint16_t* __restrict__ Pthi, const uint16_t* __restrict__ Ptlo, int64_t n, int r,
+    int S, int64_t gx, int ncb, int64_t kchunk, int64_t ntile, float* __restrict__ Bout,
+    int64_t pstride, State* __restrict__ st, const double* __restrict__ Grho) {
+  if ((int64_t)blockIdx.x >= ntile) {
+    const int s = (int)((int64_t)blockIdx.x - ntile);
+    if (!st[s].done) rho_body(Grho + (int64_t)s * r * r, r, st + s);
+    return;
+  }
+  if (stack_done(st, S)) return;
+  constexpr int NNB = 2;                    // 32-column MFMA blocks per workgroup
+  constexpr int KS = 64;                    // k per slab
+  constexpr int PROW = KS + 8;              // LDS row pitch (bf16), keeps 16-byte alignment
+  __shared__ __attribute__((aligned(16))) uint16_t sP[2][2][32 * NNB * PROW];  // [buf][hi/lo]
+  const StackMap sm = stack_map((int64_t)blockIdx.x, ntile, ncb);
+  const int64_t tile = sm.unit % gx, ksl = sm.unit / gx;
+  const int64_t R = (int64_t)S * r;
+  const int64_t mb = (int64_t)sm.cb * (32 * NNB);  // first stacked column of the block
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int c = lane & 31, h = lane >> 5;
+  const int64_t j0 = (tile * 4 + wave) * 32;
+  const int64_t kb = ksl * kchunk;
+  int64_t ke = kb + kchunk;
+  if (ke > ldb) ke = ldb;
+  const int64_t nk = (ke - kb) / KS;        // slabs, >= 1
+  const int64_t klast = kb + (nk - 1) * KS;
+  f32x16 acc[NNB];
+#pragma unroll
+  for (int nb = 0; nb < NNB; ++nb)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[nb][v] = 0.0f;
+  const int64_t j = j0 + c;
+  const bool jok = j < n;
+  const uint16_t* ah = Ahi + (jok ? j : 0) * ldb + 32 * h;
+  const uint16_t* al = Alo + (jok ? j : 0) * ldb + 32 * h;
+  const u16x8 zero = {0, 0, 0, 0, 0, 0, 0, 0};
+  // Pt staging: 2 (hi, lo) x 64 rows x 64 bf16 = 1024 16-byte vectors, 4 per thread
+  constexpr int VPR = KS / 8;               // vectors per row
+  constexpr int NVEC = 2 * 32 * NNB * VPR;
+  constexpr int NPT = NVEC / 256;
+  u16x8 xr[3][2][4];                        // A ring
+  u16x8 pr[2][NPT];                         // Pt ring
+  auto stage_load = [&](u16x8 (&p)[NPT], int64_t k) {
+#pragma unroll
+    for (int q = 0; q < NPT; ++q) {
+      const int e = tid + 256 * q;
+      const int which = e / (32 * NNB * VPR);
+      const int rem = e - which * (32 * NNB * VPR);
+      const int m = rem / VPR, qq = rem - m * VPR;
+      const int64_t M = mb + m;
+      p[q] = M < R ? *(const u16x8*)((which ? Ptlo : Pthi) + M * ldb + k + 8 * qq) : zero;
+    }
+  };
+  auto stage_store = [&](const u16x8 (&p)[NPT], int b) {
+#pragma unroll
+    for (int q = 0; q < NPT; ++q) {
+      const int e = tid + 256 * q;
+      const int which = e / (32 * NNB * VPR);
+      const int rem = e - which * (32 * NNB * VPR);
+      const int m = rem / VPR, qq = rem - m * VPR;
+      *(u16x8*)&sP[b][which][m * PROW + 8 * qq] = p[q];
+    }
+  };
+  auto load_a = [&](u16x8 (&x)[2][4], int64_t k) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      x[0][s] = jok ? *(const u16x8*)(ah + k + 8 * s) : zero;
+      x[1][s] = jok ? *(const u16x8*)(al + k + 8 * s) : zero;
+    }
+  };
+  auto mma = [&](const u16x8 (&x)[2][4], int b) {
+#pragma unroll
+    for (int nb = 0; nb < NNB; ++nb) {
+      const int m = 32 * nb + c;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const u16x8 bh = *(const u16x8*)&sP[b][0][m * PROW + 32 * h + 8 * s];
+        const u16x8 bl = *(const u16x8*)&sP[b][1][m * PROW + 32 * h + 8 * s];
+        acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, x[0][s]),
+                                                          __builtin_bit_cast(bf16x8, bh), acc[nb], 0, 0, 0);
+        acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, x[0][s]),
+                                                          __builtin_bit_cast(bf16x8, bl), acc[nb], 0, 0, 0);
+        acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, x[1][s]),
+                                                          __builtin_bit_cast(bf16x8, bh), acc[nb], 0, 0, 0);
+      }
+    }
+  };
+  // slab i (ring phase I = i mod 6): prefetch slab i + 2 into the ring slots that held
+  // slab i's Pt (already in LDS) and slab i - 1's A (consumed), multiply slab i, stage
+  // slab i + 1's Pt (loaded one step earlier) into the other LDS buffer
+  auto step = [&](auto I, int64_t i) {
+    constexpr int ia = decltype(I)::value % 3, ip = decltype(I)::value % 2;
+    const int64_t kn = i + 2 < nk ? kb + (i + 2) * KS : klast;
+    stage_load(pr[ip], kn);
+    load_a(xr[(ia + 2) % 3], kn);
+    mma(xr[ia], ip);
+    stage_store(pr[ip ^ 1], ip ^ 1);
+    __syncthreads();
+  };
+  stage_load(pr[0], kb);
+  load_a(xr[0], kb);
+  const int64_t k1 = nk > 1 ? kb + KS : klast;
+  stage_load(pr[1], k1);
+  load_a(xr[1], k1);
+  stage_store(pr[0], 0);
+  __syncthreads();
+  int64_t i = 0;
+  for (; i + 6 <= nk; i += 6) {
+    step(IC<0>{}, i);
+    step(IC<1>{}, i + 1);
+    step(IC<2>{}, i + 2);
+    step(IC<3>{}, i + 3);
+    step(IC<4>{}, i + 4);
+    step(IC<5>{}, i + 5);
+  }
+  if (i < nk) step(IC<0>{}, i);
+  if (i + 1 < nk) step(IC<1>{}, i + 1);
+  if (i + 2 < nk) step(IC<2>{}, i + 2);
+  if (i + 3 < nk) step(IC<3>{}, i + 3);
+  if (i + 4 < nk) step(IC<4>{}, i + 4);
+  // D[row][col]: row = 8 (v/4) + 4 h + v%4 (output row j0 + row), col = lane%32.  Stacked
+  // column M is column M mod r of restart M / r, whose n x r block starts at (M / r) n r.
+  float* out = Bout + ksl * pstride;
+#pragma unroll
+  for (int nb = 0; nb < NNB; ++nb) {
+    const int64_t M = mb + 32 * nb + c;
+    if (M < R) {
+      const int64_t s = M / r, m = M - s * r;
+      float* o = out + s * n * r + m;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int64_t jj = j0 + 8 * (v >> 2) + 4 * h + (v & 3);
+        if (jj < n) o[jj * r] = acc[nb][v];
+      }
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------- launchers
+static int64_t stack_cus() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus < 1)
+    cus = 256;
+  return cus;
+}
+
+// Two workgroups per CU: the (row tile, column block) pairs, times K slices of whole
+// 64-column slabs while there are fewer pairs than that (at most kMaxKSplit slices).
+// n = 8192, S r = 512: 64 x 8 pairs, one slice.
+DenseSplit plan_dense_bf16_stack(int64_t n, int64_t R) {
+  DenseSplit d;
+  const int64_t ldb = (n + 63) / 64 * 64;
+  d.gx = (n + 127) / 128;
+  const int64_t ncb = (R + 63) / 64;
+  const int64_t pairs = d.gx * ncb;
+  int64_t ks = (2 * stack_cus() + pairs - 1) / pairs;
+  const int64_t kmax = ldb / 64;
+  if (ks > kmax) ks = kmax;
+  if (ks > kMaxKSplit) ks = kMaxKSplit;
+  if (ks < 1) ks = 1;
+  int64_t kc = (ldb + ks - 1) / ks;
+  kc = (kc + 63) / 64 * 64;
+  d.kchunk = kc;
+  d.ksplit = (int)((ldb + kc - 1) / kc);
+  d.nwg = pairs * d.ksplit;
+  return d;
+}
+
+void launch_apass_bf16x3_stack(const uint16_t* Ahi, const uint16_t* Alo, int64_t ldb,
+                               const uint16_t* Pthi, const uint16_t* Ptlo, int64_t n, int r,
+                               int S, const DenseSplit& d, float* Bout, int64_t pstride,
+                               State* st, const double* Grho, hipStream_t s) {
+  const int ncb = (int)(((int64_t)S * r + 63) / 64);
+  const int64_t nrho = Grho ? S : 0;
+  hipLaunchKernelGGL(k_apass_bf16x3s, dim3((unsigned)(d.nwg + nrho)), dim3(256), 0, s, Ahi, Alo,
+                     ldb, Pthi, Ptlo, n, r, S, d.gx, ncb, d.kchunk, d.nwg, Bout, pstride, st,
+                     Grho);
+}
+
+}  // namespace snmf

@@ -212,7 +212,8 @@ __global__ __launch_bounds__(kThreads) void k_gram_reduce(const double* __restri
   }
 }
 
-// Batched: one workgroup per instance adds its Gram slabs in the order above.
+// Batched: workgroups (instance, y) add the Gram slabs of elements y kThreads + t (stride
+// gridDim.y kThreads) in the order above.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_bgram_reduce(const BInst* __restrict__ inst,
                                                            const State* __restrict__ states,
@@ -224,7 +225,7 @@ __global__ __launch_bounds__(kThreads) void k_bgram_reduce(const BInst* __restri
   if (states[i].done) return;
   const int rr = d->r * d->r;
   const double* part = gpart + d->gpoff;
-  for (int e = threadIdx.x; e < rr; e += kThreads) {
+  for (int e = blockIdx.y * kThreads + threadIdx.x; e < rr; e += gridDim.y * kThreads) {
     const double s = ((gram_sum4(part, d->gnb, rr, e, 0) + gram_sum4(part, d->gnb, rr, e, 1)) +
                       gram_sum4(part, d->gnb, rr, e, 2)) +
                      gram_sum4(part, d->gnb, rr, e, 3);
@@ -324,6 +325,59 @@ __global__ __launch_bounds__(kThreads) void k_split_pt(const float* __restrict__
   }
 }
 
+typedef unsigned short u16x8s __attribute__((ext_vector_type(8)));
+
+// The P factors of S restarts (S consecutive n x r FP32 blocks) -> Pt_hi, Pt_lo
+// ((S r) x ldp BF16, row s r + m = column m of block s, zero beyond n).  A workgroup
+// transposes a 64 (k) x 64 (stacked column) tile through LDS, so the reads (rows of P)
+// and the writes (rows of Pt) are both contiguous.  Grid: ldp / 64 x ceil(S r / 64).
+__global__ __launch_bounds__(kThreads) void k_split_pt_stack(const float* __restrict__ P,
+                                                             int64_t n, int r, int S, int64_t ldp,
+                                                             uint16_t* __restrict__ hi,
+                                                             uint16_t* __restrict__ lo,
+                                                             const State* __restrict__ st) {
+  bool all = true;
+  for (int i = 0; i < S; ++i)
+    if (!st[i].done) all = false;
+  if (all) return;
+  __shared__ float tile[64][65];
+  const int64_t R = (int64_t)S * r;
+  const int64_t k0 = (int64_t)blockIdx.x * 64, m0 = (int64_t)blockIdx.y * 64;
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < 64 * 64 / kThreads; ++q) {
+    const int e = tid + kThreads * q;
+    const int kk = e >> 6, mm = e & 63;
+    const int64_t k = k0 + kk, M = m0 + mm;
+    float a = 0.0f;
+    if (k < n && M < R) {
+      const int64_t s = M / r, m = M - s * r;
+      a = P[(s * n + k) * r + m];
+    }
+    tile[kk][mm] = a;
+  }
+  __syncthreads();
+  // eight consecutive k of one stacked column per thread: 16-byte stores
+#pragma unroll
+  for (int q = 0; q < 64 * 64 / 8 / kThreads; ++q) {
+    const int e = tid + kThreads * q;
+    const int mm = e >> 3, kk0 = (e & 7) * 8;
+    const int64_t M = m0 + mm;
+    if (M < R) {
+      u16x8s vh, vl;
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const float a = tile[kk0 + t][mm];
+        const uint16_t h = bf16_rne(a);
+        vh[t] = h;
+        vl[t] = bf16_rne(a - bf16_to_f32(h));
+      }
+      *(u16x8s*)(hi + M * ldp + k0 + kk0) = vh;
+      *(u16x8s*)(lo + M * ldp + k0 + kk0) = vl;
+    }
+  }
+}
+
 // ----------------------------------------------------------------------------- launchers
 int gram_blocks(int64_t n) {
   int64_t g = (n + 127) / 128;
@@ -368,18 +422,19 @@ void launch_bgram(const T* P, int r, const int32_t* gblk_inst, int gblocks, cons
                                        gblk_inst, inst, states, gpart))
 }
 template <typename T>
-void launch_bgram_reduce(const BInst* inst, int ninst, const State* states, const double* gpart,
-                         double* G64, T* GT, hipStream_t s) {
-  hipLaunchKernelGGL(k_bgram_reduce<T>, dim3(ninst), dim3(kThreads), 0, s, inst, states, gpart,
-                     G64, GT);
+void launch_bgram_reduce(const BInst* inst, int ninst, int max_r, const State* states,
+                         const double* gpart, double* G64, T* GT, hipStream_t s) {
+  const int ny = (max_r * max_r + kThreads - 1) / kThreads;
+  hipLaunchKernelGGL(k_bgram_reduce<T>, dim3(ninst, ny), dim3(kThreads), 0, s, inst, states,
+                     gpart, G64, GT);
 }
 template void launch_bgram<float>(const float*, int, const int32_t*, int, const BInst*,
                                   const State*, double*, hipStream_t);
 template void launch_bgram<double>(const double*, int, const int32_t*, int, const BInst*,
                                    const State*, double*, hipStream_t);
-template void launch_bgram_reduce<float>(const BInst*, int, const State*, const double*, double*,
-                                         float*, hipStream_t);
-template void launch_bgram_reduce<double>(const BInst*, int, const State*, const double*,
+template void launch_bgram_reduce<float>(const BInst*, int, int, const State*, const double*,
+                                         double*, float*, hipStream_t);
+template void launch_bgram_reduce<double>(const BInst*, int, int, const State*, const double*,
                                           double*, double*, hipStream_t);
 
 void launch_brho(const BInst* inst, int ninst, State* states, const double* G64, hipStream_t s) {
@@ -405,6 +460,13 @@ void launch_split_rows(const float* A, int64_t n, int64_t lda, int64_t ldb, uint
   if (nb > 65536) nb = 65536;
   hipLaunchKernelGGL(k_split_rows, dim3((unsigned)nb), dim3(kThreads), 0, s, A, n, lda, ldb, hi,
                      lo);
+}
+
+void launch_split_pt_stack(const float* P, int64_t n, int r, int S, int64_t ldp, uint16_t* hi,
+                           uint16_t* lo, const State* st, hipStream_t s) {
+  const int64_t R = (int64_t)S * r;
+  hipLaunchKernelGGL(k_split_pt_stack, dim3((unsigned)(ldp / 64), (unsigned)((R + 63) / 64)),
+                     dim3(kThreads), 0, s, P, n, r, S, ldp, hi, lo, st);
 }
 
 void launch_split_pt(const float* P, int64_t n, int r, int64_t ldp, uint16_t* hi, uint16_t* lo,

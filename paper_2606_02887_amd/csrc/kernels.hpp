@@ -70,8 +70,8 @@ template <typename T>
 void launch_bgram(const T* P, int r, const int32_t* gblk_inst, int gblocks, const BInst* inst,
                   const State* states, double* gpart, hipStream_t s);
 template <typename T>
-void launch_bgram_reduce(const BInst* inst, int ninst, const State* states, const double* gpart,
-                         double* G64, T* GT, hipStream_t s);
+void launch_bgram_reduce(const BInst* inst, int ninst, int max_r, const State* states,
+                         const double* gpart, double* G64, T* GT, hipStream_t s);
 void launch_brho(const BInst* inst, int ninst, State* states, const double* G64, hipStream_t s);
 template <typename T>
 void launch_norm2(const T* x, int64_t N, double* part, double* out, unsigned* counter,
@@ -80,6 +80,11 @@ void launch_split_rows(const float* A, int64_t n, int64_t lda, int64_t ldb, uint
                        uint16_t* lo, hipStream_t s);
 void launch_split_pt(const float* P, int64_t n, int r, int64_t ldp, uint16_t* hi, uint16_t* lo,
                      const State* st, hipStream_t s);
+
+// S consecutive n x r blocks -> (S r) x ldp transposed BF16 hi/lo (ldp a multiple of 64);
+// skipped when all S states are done.
+void launch_split_pt_stack(const float* P, int64_t n, int r, int S, int64_t ldp, uint16_t* hi,
+                           uint16_t* lo, const State* st, hipStream_t s);
 
 template <typename T>
 void launch_sum_parts(const T* part, int ks, int64_t stride, T* out, int64_t N, hipStream_t s);
@@ -95,6 +100,15 @@ void launch_apass_bf16x3(const uint16_t* Ahi, const uint16_t* Alo, int64_t ldb,
                          const uint16_t* Pthi, const uint16_t* Ptlo, int64_t ldp, int64_t n, int r,
                          const DenseSplit& d, float* Bpart, int64_t pstride, const State* st,
                          hipStream_t s, const RhoJob& rj = RhoJob{});
+
+// Stacked split-BF16 A-pass of S restarts of one problem (R = S r columns): B_s = A P_s,
+// written to Bout + s n r (one K slice) or as d.ksplit partials pstride apart.  With Grho
+// set, rho of restart s (st[s].rho) from the FP64 Gram at Grho + s r^2 in the same launch.
+DenseSplit plan_dense_bf16_stack(int64_t n, int64_t R);
+void launch_apass_bf16x3_stack(const uint16_t* Ahi, const uint16_t* Alo, int64_t ldb,
+                               const uint16_t* Pthi, const uint16_t* Ptlo, int64_t n, int r,
+                               int S, const DenseSplit& d, float* Bout, int64_t pstride,
+                               State* st, const double* Grho, hipStream_t s);
 
 template <typename T>
 void launch_spmm(const int64_t* rowptr, const int32_t* col, const T* val, const T* X, int64_t n,

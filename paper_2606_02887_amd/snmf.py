@@ -68,8 +68,8 @@ EXPORTS = ("snmf_params_default", "snmf_solve", "snmf_plan_create", "snmf_plan_s
            "snmf_plan_destroy", "snmf_plan_half_step", "snmf_plan_apass", "snmf_plan_gram",
            "snmf_plan_time_apass", "snmf_rho", "snmf_spmm", "snmf_split_bf16",
            "snmf_batch_create", "snmf_batch_solve", "snmf_batch_destroy", "snmf_solve_batched",
-           "snmf_batch_apass", "snmf_batch_size", "snmf_mlp_sync", "snmf_mlp_forward",
-           "snmf_mlp_workspace_bytes", "snmf_mlp_train_step", "snmf_batch_frame",
+           "snmf_batch_apass", "snmf_batch_time_apass", "snmf_batch_size", "snmf_mlp_sync",
+           "snmf_mlp_forward", "snmf_mlp_workspace_bytes", "snmf_mlp_train_step", "snmf_batch_frame",
            "snmf_batch_targets", "snmf_batch_warmstart", "snmf_clock_rate_hz",
            "snmf_last_error", "snmf_abi_version")
 
@@ -102,6 +102,7 @@ def load_library(path: str = LIB_PATH):
                                 c_int32, POINTER(vp), POINTER(Params), POINTER(vp), POINTER(vp),
                                 POINTER(Info), vp, POINTER(c_double)], c_int32),
         "snmf_batch_apass": ([vp, vp, vp, vp], c_int32),
+        "snmf_batch_time_apass": ([vp, vp, c_int32, POINTER(c_double)], c_int32),
         "snmf_batch_size": ([vp, POINTER(c_int32), POINTER(c_int64)], c_int32),
         "snmf_mlp_sync": ([POINTER(MlpC), vp], c_int32),
         "snmf_mlp_forward": ([POINTER(MlpC), c_int64, vp, vp, vp, vp], c_int32),
@@ -315,6 +316,14 @@ class Batch:
     def apass(self, P, B):
         _check(_lib.snmf_batch_apass(self._h, _ptr(P), _ptr(B), _stream()))
         return B
+
+    def time_apass(self, P, reps: int = 20) -> float:
+        """Average time in ms of the batch's A-pass launches (HIP events on its stream)."""
+        import torch
+        torch.cuda.synchronize()
+        ms = c_double()
+        _check(_lib.snmf_batch_time_apass(self._h, _ptr(P), int(reps), ctypes.byref(ms)))
+        return ms.value
 
     def offsets(self):
         """Element offset of every problem's block (restart 0) in a batch buffer."""

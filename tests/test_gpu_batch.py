@@ -193,6 +193,75 @@ def test_batch_graph_replay_equals_direct(S):
         assert torch.equal(out[0][0][g], out[1][0][g]) and torch.equal(out[0][1][g], out[1][1][g])
 
 
+def _dense_sym(rng, n):
+    a = rng.random((n, n))
+    return 0.5 * (a + a.T)
+
+
+@pytest.mark.parametrize("shapes,restarts", [
+    ([(260, 64), (197, 20), (70, 3)], 3),   # few (row tile, column block) pairs: K slices
+    ([(1100, 64)], 57),                      # 9 x 57 pairs: one slice, written directly
+])
+def test_batch_bf16x3_stacked_apass(S, shapes, restarts):
+    """BF16X3 batches run one stacked split-BF16 product per problem over its S r columns
+    (A_hi P_hi + A_hi P_lo + A_lo P_hi); every instance's block must be A_g P_s to the
+    split's accuracy (operands exact to ~2^-16 relative, FP32 accumulation), as for the
+    single solve's split A-pass."""
+    rng = np.random.default_rng(1300 + restarts)
+    As = [torch.from_numpy(_dense_sym(rng, n)).to(DEV, torch.float32) for n, _ in shapes]
+    a_in = [a.double().cpu().numpy() for a in As]
+    prm = S.params(prec=S.BF16X3, max_outer=1)
+    with S.Batch([S.dense(a) for a in As], [r for _, r in shapes], prm, restarts=restarts) as b:
+        P = torch.from_numpy(rng.random(b.elements)).to(DEV, torch.float32)
+        B = torch.full_like(P, float("nan"))
+        b.apass(P, B)
+        Pn, Bn = P.double().cpu().numpy(), B.double().cpu().numpy()
+    off = 0
+    for g, (n, r) in enumerate(shapes):
+        for s in range(restarts):
+            p_s = Pn[off: off + n * r].reshape(n, r)
+            b_s = Bn[off: off + n * r].reshape(n, r)
+            err = nrel(b_s, O.apply_A(a_in[g], p_s))
+            assert err <= 2e-5, (g, s, err)
+            off += n * r
+    assert off == Bn.size
+
+
+def test_batch_bf16x3_instances_follow_the_oracle(S):
+    """A dense BF16X3 batch of config 0 (planted n = 500, r = 10) for 20 outer iterations,
+    the budget of the single solve's config-0 test: restarts 0 and 2 start from config 0's
+    W0 and must match the oracle's residual and PG norm to 1e-3, as the single solve does,
+    and each other bitwise; restart 1 starts at random: residual to 1e-3, PG norm (the
+    quantity most sensitive to rounding after 20 iterations; 1.4e-3 measured from another
+    random start) to 1e-2."""
+    prob = gen.config(0)
+    At = torch.from_numpy(prob["A"]).to(DEV, torch.float32)
+    a_in = At.double().cpu().numpy()
+    lam = O.default_lambda(a_in)
+    n, r = prob["W0"].shape
+    w0 = [prob["W0"], gen.start_factor(np.random.default_rng(5), n, r, float(a_in.mean())),
+          prob["W0"]]
+    W0 = torch.from_numpy(np.stack(w0)).to(DEV, torch.float32).contiguous()
+    w_in = W0.double().cpu().numpy()
+    prm = S.params(lam=lam, prec=S.BF16X3, max_outer=20)
+    with S.Batch([S.dense(At)], [r], prm, restarts=3) as b:
+        Ws, Hs, infos, _ = b.solve([W0])
+    for s in range(2):
+        _, _, hist = O.snmpbb(a_in, w_in[s], O.Params(lam=lam), 20)
+        ref = hist[-1]
+        info = infos[s]
+        assert info["status"] == 0 and info["outer"] == 20
+        assert abs(info["res_WH"] - ref["res_WH"]) <= 1e-3 * ref["res_WH"], s
+        assert abs(info["pg_norm"] - ref["pg"]) <= (1e-3 if s == 0 else 1e-2) * ref["pg"], s
+        W = Ws[0][s].double().cpu().numpy()
+        Ht = Hs[0][s].double().cpu().numpy()
+        assert (W >= 0).all() and (Ht >= 0).all()
+        # the monitor against A_hi + A_lo (2^-17 elementwise) vs the FP64 residual
+        assert abs(info["res_WH"] - O.residual_WH(a_in, W, Ht)) <= 5e-4 * info["res_WH"]
+    assert torch.equal(Ws[0][2], Ws[0][0]) and torch.equal(Hs[0][2], Hs[0][0])
+    assert infos[2]["res_WH"] == infos[0]["res_WH"]
+
+
 def test_batch_error_codes(S):
     graphs = _graphs(2100, [(60, 3), (80, 4)], restarts=1)
     As, _, W0s, _ = _batch_inputs(S, graphs, torch.float64)

@@ -123,3 +123,22 @@ def test_lowrank_n200000_r32_half_step(S):
     print(f"low rank n=200000 r=32: nrel {err:.3e}")
     assert err <= 3e-5
     _scalars(sc, log, 1e-3)
+
+
+def test_dense_n8192_batched8_bf16x3_stacked_apass(S, dense_c1):
+    """The stacked split-BF16 A-pass of bench.py's 8 batched restarts (8192 x 8192 times
+    8 x (8192 x 64), one launch of 64 x 8 (row tile, column block) workgroups): every
+    instance's block against the FP64 product, to the split's accuracy (3e-5: the
+    single-solve split bound with FP32 sums over 8192 terms)."""
+    At, A_in, _, _, _ = dense_c1
+    rng = np.random.default_rng(1101)
+    with S.Batch([S.dense(At)], [64], S.params(prec=S.BF16X3, max_outer=1), restarts=8) as b:
+        P = torch.from_numpy(rng.random(b.elements)).to(DEV, torch.float32)
+        B = torch.full_like(P, float("nan"))
+        b.apass(P, B)
+        Pn = P.double().cpu().numpy().reshape(8, 8192, 64)
+        Bn = B.double().cpu().numpy().reshape(8, 8192, 64)
+    for s in range(8):
+        err = nrel(Bn[s], A_in @ Pn[s])
+        print(f"batched8 bf16x3 restart {s}: nrel {err:.3e}")
+        assert err <= 3e-5, (s, err)
