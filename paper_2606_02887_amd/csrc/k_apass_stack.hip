@@ -105,11 +105,14 @@ __global__ __launch_bounds__(256, 2) void k_apass_bf16x3s(
   for (int nb = 0; nb < NNB; ++nb)
 #pragma unroll
     for (int v = 0; v < 16; ++v) acc[nb][v] = 0.0f;
-  const int64_t j = j0 + c;
-  const bool jok = j < n;
-  const uint16_t* ah = Ahi + (jok ? j : 0) * ldb + 32 * h;
-  const uint16_t* al = Alo + (jok ? j : 0) * ldb + 32 * h;
-  const u16x8 zero = {0, 0, 0, 0, 0, 0, 0, 0};
+  // Rows past n and stacked columns past S r read the last valid row of A or Pt instead:
+  // they feed only output rows and columns that are never stored, and loads without a
+  // condition keep the loop free of branches (the compiler counts loads in flight
+  // exactly only in straight-line code; behind a branch it waited for all of them,
+  // the prefetch included, before every LDS stage).
+  const int64_t j = j0 + c < n ? j0 + c : n - 1;
+  const uint16_t* ah = Ahi + j * ldb + 32 * h;
+  const uint16_t* al = Alo + j * ldb + 32 * h;
   // Pt staging: 2 (hi, lo) x 64 rows x 64 bf16 = 1024 16-byte vectors, 4 per thread
   constexpr int VPR = KS / 8;               // vectors per row
   constexpr int NVEC = 2 * 32 * NNB * VPR;
@@ -123,8 +126,8 @@ __global__ __launch_bounds__(256, 2) void k_apass_bf16x3s(
       const int which = e / (32 * NNB * VPR);
       const int rem = e - which * (32 * NNB * VPR);
       const int m = rem / VPR, qq = rem - m * VPR;
-      const int64_t M = mb + m;
-      p[q] = M < R ? *(const u16x8*)((which ? Ptlo : Pthi) + M * ldb + k + 8 * qq) : zero;
+      const int64_t M = mb + m < R ? mb + m : R - 1;
+      p[q] = *(const u16x8*)((which ? Ptlo : Pthi) + M * ldb + k + 8 * qq);
     }
   };
   auto stage_store = [&](const u16x8 (&p)[NPT], int b) {
@@ -140,8 +143,8 @@ __global__ __launch_bounds__(256, 2) void k_apass_bf16x3s(
   auto load_a = [&](u16x8 (&x)[2][4], int64_t k) {
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-      x[0][s] = jok ? *(const u16x8*)(ah + k + 8 * s) : zero;
-      x[1][s] = jok ? *(const u16x8*)(al + k + 8 * s) : zero;
+      x[0][s] = *(const u16x8*)(ah + k + 8 * s);
+      x[1][s] = *(const u16x8*)(al + k + 8 * s);
     }
   };
   auto mma = [&](const u16x8 (&x)[2][4], int b) {
