@@ -344,17 +344,24 @@ __global__ __launch_bounds__(kThreads) void k_split_pt_stack(const float* __rest
   const int64_t R = (int64_t)S * r;
   const int64_t k0 = (int64_t)blockIdx.x * 64, m0 = (int64_t)blockIdx.y * 64;
   const int tid = threadIdx.x;
+  // every load is issued (clamped to a valid element) before the first is used, and the
+  // padding (k >= n, M >= R) is zeroed afterwards: a load behind a branch would be
+  // waited for on its own
+  float a[64 * 64 / kThreads];
 #pragma unroll
   for (int q = 0; q < 64 * 64 / kThreads; ++q) {
     const int e = tid + kThreads * q;
     const int kk = e >> 6, mm = e & 63;
-    const int64_t k = k0 + kk, M = m0 + mm;
-    float a = 0.0f;
-    if (k < n && M < R) {
-      const int64_t s = M / r, m = M - s * r;
-      a = P[(s * n + k) * r + m];
-    }
-    tile[kk][mm] = a;
+    const int64_t k = k0 + kk < n ? k0 + kk : n - 1;
+    const int64_t M = m0 + mm < R ? m0 + mm : R - 1;
+    const int64_t s = M / r, m = M - s * r;
+    a[q] = P[(s * n + k) * r + m];
+  }
+#pragma unroll
+  for (int q = 0; q < 64 * 64 / kThreads; ++q) {
+    const int e = tid + kThreads * q;
+    const int kk = e >> 6, mm = e & 63;
+    tile[kk][mm] = (k0 + kk < n && m0 + mm < R) ? a[q] : 0.0f;
   }
   __syncthreads();
   // eight consecutive k of one stacked column per thread: 16-byte stores
