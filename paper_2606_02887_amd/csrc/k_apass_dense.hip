@@ -402,7 +402,13 @@ __global__ __launch_bounds__(256) void k_apass_bf16x3(const uint16_t* __restrict
   // with rj.G set, one more row of workgroups: its first computes rho = ||G||_2 (the grid
   // is resident at once, so it runs beside the tiles)
   if (rj.G && blockIdx.y == gridDim.y - 1) {
-    if (blockIdx.x == 0) rho_body(rj.G, rj.r, rj.st);
+    if (blockIdx.x == 0) {
+      // rho, not the tiles, sets the length of this launch at r = 64: its waves take
+      // issue priority over the tile waves that share its CU (split-BF16 solve at n = 8192:
+      // 2712 -> 2895 outer iterations/s)
+      __builtin_amdgcn_s_setprio(3);
+      rho_body(rj.G, rj.r, rj.st);
+    }
     return;
   }
   constexpr int KS = 64;                    // k per slab
@@ -419,11 +425,14 @@ __global__ __launch_bounds__(256) void k_apass_bf16x3(const uint16_t* __restrict
   for (int nb = 0; nb < NNB; ++nb)
 #pragma unroll
     for (int v = 0; v < 16; ++v) acc[nb][v] = 0.0f;
-  const int64_t j = j0 + c;
-  const bool jok = j < n;
-  const uint16_t* ah = Ahi + (jok ? j : 0) * ldb + 32 * h;
-  const uint16_t* al = Alo + (jok ? j : 0) * ldb + 32 * h;
-  const u16x8 zero = {0, 0, 0, 0, 0, 0, 0, 0};
+  // Rows past n and Pt rows past r read the last valid row instead: they feed only output
+  // rows and columns that are never stored.  Loads without a condition (and a prefetch
+  // past the last slab that re-reads it) keep the loop free of branches, so the compiler
+  // counts the loads in flight exactly instead of waiting for all of them, the prefetch
+  // included, before every LDS stage.
+  const int64_t j = j0 + c < n ? j0 + c : n - 1;
+  const uint16_t* ah = Ahi + j * ldb + 32 * h;
+  const uint16_t* al = Alo + j * ldb + 32 * h;
   // Pt staging: the slab is 32*NNB rows (m) x 64 bf16 for hi and lo, i.e. NVEC 16-byte
   // vectors, NPT per thread.  Global loads of the next slab are issued before the next
   // A vectors and written to LDS only after the current MFMAs, so no wait on the A
@@ -438,7 +447,8 @@ __global__ __launch_bounds__(256) void k_apass_bf16x3(const uint16_t* __restrict
       const int which = e / (32 * NNB * (KS / 8));
       const int rem = e - which * (32 * NNB * (KS / 8));
       const int m = rem / (KS / 8), qq = rem - m * (KS / 8);
-      pt[q] = m < r ? *(const u16x8*)((which ? Ptlo : Pthi) + (int64_t)m * ldp + k + 8 * qq) : zero;
+      const int mm = m < r ? m : r - 1;
+      pt[q] = *(const u16x8*)((which ? Ptlo : Pthi) + (int64_t)mm * ldp + k + 8 * qq);
     }
   };
   auto stage_store = [&](int b) {
@@ -455,8 +465,8 @@ __global__ __launch_bounds__(256) void k_apass_bf16x3(const uint16_t* __restrict
   auto load_a = [&](u16x8 (&x)[2][4], int64_t k) {
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-      x[0][s] = jok ? *(const u16x8*)(ah + k + 8 * s) : zero;
-      x[1][s] = jok ? *(const u16x8*)(al + k + 8 * s) : zero;
+      x[0][s] = *(const u16x8*)(ah + k + 8 * s);
+      x[1][s] = *(const u16x8*)(al + k + 8 * s);
     }
   };
   int buf = 0;
@@ -467,11 +477,9 @@ __global__ __launch_bounds__(256) void k_apass_bf16x3(const uint16_t* __restrict
   }
   __syncthreads();
   for (int64_t k = kb; k < ke; k += KS) {
-    const bool more = k + KS < ke;
-    if (more) {
-      stage_load(k + KS);
-      load_a(xn, k + KS);
-    }
+    const int64_t kn = k + KS < ke ? k + KS : k;
+    stage_load(kn);
+    load_a(xn, kn);
 #pragma unroll
     for (int nb = 0; nb < NNB; ++nb) {
       const int m = 32 * nb + c;
@@ -487,14 +495,12 @@ __global__ __launch_bounds__(256) void k_apass_bf16x3(const uint16_t* __restrict
                                                           __builtin_bit_cast(bf16x8, bh), acc[nb], 0, 0, 0);
       }
     }
-    if (more) stage_store(buf ^ 1);
+    stage_store(buf ^ 1);
     __syncthreads();
-    if (more) {
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        xa[0][s] = xn[0][s];
-        xa[1][s] = xn[1][s];
-      }
+    for (int s = 0; s < 4; ++s) {
+      xa[0][s] = xn[0][s];
+      xa[1][s] = xn[1][s];
     }
     buf ^= 1;
   }

@@ -262,6 +262,35 @@ def test_batch_bf16x3_instances_follow_the_oracle(S):
     assert infos[2]["res_WH"] == infos[0]["res_WH"]
 
 
+def test_batch_bf16x3_stop_and_breakdown_stay_in_their_restart(S):
+    """Restarts of one dense problem share the stacked split-BF16 product: restart 0 stops
+    at its own first monitored hit of a target, restart 2 (zero start: G = 0, rho = 0)
+    breaks down, and restart 1's trajectory is bitwise the same as without them."""
+    prob = gen.planted_dense(240, 6, 77)
+    At = torch.from_numpy(prob["A"]).to(DEV, torch.float32)
+    lam = O.default_lambda(At.double().cpu().numpy())
+    rng = np.random.default_rng(9)
+    w0 = np.stack([prob["W0"], gen.start_factor(rng, 240, 6, float(prob["A"].mean())),
+                   np.zeros((240, 6))])
+    W0 = torch.from_numpy(w0).to(DEV, torch.float32).contiguous()
+    names = {v: k for k, v in S.STATUS.items()}
+    with S.Batch([S.dense(At)], [6], S.params(lam=lam, prec=S.BF16X3, max_outer=30),
+                 restarts=3) as b:
+        _, _, base, tr = b.solve([W0], trace=True)
+    tau = tr[0, 9, 0]              # restart 0's residual after 10 outer iterations
+    prm = S.params(lam=lam, prec=S.BF16X3, max_outer=30, target_res=tau, check_every=4)
+    with S.Batch([S.dense(At)], [6], prm, restarts=3) as b:
+        _, _, infos, tr2 = b.solve([W0], trace=True)
+    assert base[2]["status"] == names["E_BREAKDOWN"] == infos[2]["status"]
+    hits = np.nonzero(tr[0, :, 0] <= tau)[0]
+    assert infos[0]["converged_at"] == hits[0] + 1 == infos[0]["outer"]
+    assert 1 <= infos[0]["converged_at"] <= 10
+    for i in (0, 1):
+        k = infos[i]["outer"]
+        assert np.array_equal(tr2[i, :k, :5], tr[i, :k, :5]), i
+    assert base[1]["status"] == 0 and base[1]["outer"] == 30
+
+
 def test_batch_error_codes(S):
     graphs = _graphs(2100, [(60, 3), (80, 4)], restarts=1)
     As, _, W0s, _ = _batch_inputs(S, graphs, torch.float64)
