@@ -19,7 +19,7 @@
 
 namespace snmf {
 
-typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4s __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
@@ -61,8 +61,12 @@ __device__ __forceinline__ StackMap stack_map(int64_t id, int64_t nwg, int G) {
 template <int V>
 using IC = std::integral_constant<int, V>;
 
-// Per 64-column slab of A a lane loads 32 consecutive BF16 of its row from A_hi and A_lo
-// (four 16-byte vectors each; lanes l and l + 32 cover 128 contiguous bytes); the slab of
+// A wave computes 32 rows x 64 columns as 2 x 4 blocks of v_mfma_f32_16x16x32_bf16: a
+// lane (l mod 16, l / 16) holds 8 consecutive k of row l mod 16 (A) or of stacked column
+// l mod 16 (Pt), so the four lanes of a row read 64 contiguous bytes and one A load
+// instruction touches 16 rows (the 32x32x16 shape touched 32 rows with 32 bytes each, and
+// the vector cache's per-line work, not the bytes, set the pace).  Per 64-column slab a
+// lane loads two 16-byte vectors of each of its two rows from A_hi and A_lo; the slab of
 // the block's 64 rows of Pt_hi / Pt_lo is staged in LDS (two buffers) and shared by the
 // four waves.  Loads run two slabs ahead: one slab's MFMAs (24 per wave) are shorter than
 // a memory round trip, so with one slab ahead every slab waited on its loads.  The A
@@ -83,7 +87,7 @@ __global__ __launch_bounds__(256, 2) void k_apass_bf16x3s(
     return;
   }
   if (stack_done(st, S)) return;
-  constexpr int NNB = 2;                    // 32-column MFMA blocks per workgroup
+  constexpr int NNB = 2;                    // the workgroup's 64 stacked columns, in units of 32
   constexpr int KS = 64;                    // k per slab
   constexpr int PROW = KS + 8;              // LDS row pitch (bf16), keeps 16-byte alignment
   __shared__ __attribute__((aligned(16))) uint16_t sP[2][2][32 * NNB * PROW];  // [buf][hi/lo]
@@ -93,31 +97,34 @@ __global__ __launch_bounds__(256, 2) void k_apass_bf16x3s(
   const int64_t mb = (int64_t)sm.cb * (32 * NNB);  // first stacked column of the block
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int c = lane & 31, h = lane >> 5;
+  const int ri = lane & 15, g = lane >> 4;
   const int64_t j0 = (tile * 4 + wave) * 32;
   const int64_t kb = ksl * kchunk;
   int64_t ke = kb + kchunk;
   if (ke > ldb) ke = ldb;
   const int64_t nk = (ke - kb) / KS;        // slabs, >= 1
   const int64_t klast = kb + (nk - 1) * KS;
-  f32x16 acc[NNB];
+  f32x4s acc[2][4];                         // [row block][16-column block]
 #pragma unroll
-  for (int nb = 0; nb < NNB; ++nb)
+  for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-    for (int v = 0; v < 16; ++v) acc[nb][v] = 0.0f;
+    for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = f32x4s{0.0f, 0.0f, 0.0f, 0.0f};
   // Rows past n and stacked columns past S r read the last valid row of A or Pt instead:
   // they feed only output rows and columns that are never stored, and loads without a
   // condition keep the loop free of branches (the compiler counts loads in flight
   // exactly only in straight-line code; behind a branch it waited for all of them,
   // the prefetch included, before every LDS stage).
-  const int64_t j = j0 + c < n ? j0 + c : n - 1;
-  const uint16_t* ah = Ahi + j * ldb + 32 * h;
-  const uint16_t* al = Alo + j * ldb + 32 * h;
+  const int64_t ja = j0 + ri < n ? j0 + ri : n - 1;
+  const int64_t jb = j0 + 16 + ri < n ? j0 + 16 + ri : n - 1;
+  const uint16_t* ah0 = Ahi + ja * ldb + 8 * g;
+  const uint16_t* al0 = Alo + ja * ldb + 8 * g;
+  const uint16_t* ah1 = Ahi + jb * ldb + 8 * g;
+  const uint16_t* al1 = Alo + jb * ldb + 8 * g;
   // Pt staging: 2 (hi, lo) x 64 rows x 64 bf16 = 1024 16-byte vectors, 4 per thread
   constexpr int VPR = KS / 8;               // vectors per row
   constexpr int NVEC = 2 * 32 * NNB * VPR;
   constexpr int NPT = NVEC / 256;
-  u16x8 xr[3][2][4];                        // A ring
+  u16x8 xr[3][2][4];                        // A ring: [slot][hi/lo][row block x k half]
   u16x8 pr[2][NPT];                         // Pt ring
   auto stage_load = [&](u16x8 (&p)[NPT], int64_t k) {
 #pragma unroll
@@ -142,25 +149,31 @@ __global__ __launch_bounds__(256, 2) void k_apass_bf16x3s(
   };
   auto load_a = [&](u16x8 (&x)[2][4], int64_t k) {
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      x[0][s] = *(const u16x8*)(ah + k + 8 * s);
-      x[1][s] = *(const u16x8*)(al + k + 8 * s);
+    for (int kh = 0; kh < 2; ++kh) {
+      x[0][kh] = *(const u16x8*)(ah0 + k + 32 * kh);
+      x[0][2 + kh] = *(const u16x8*)(ah1 + k + 32 * kh);
+      x[1][kh] = *(const u16x8*)(al0 + k + 32 * kh);
+      x[1][2 + kh] = *(const u16x8*)(al1 + k + 32 * kh);
     }
   };
   auto mma = [&](const u16x8 (&x)[2][4], int b) {
 #pragma unroll
-    for (int nb = 0; nb < NNB; ++nb) {
-      const int m = 32 * nb + c;
+    for (int kh = 0; kh < 2; ++kh) {
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const u16x8 bh = *(const u16x8*)&sP[b][0][m * PROW + 32 * h + 8 * s];
-        const u16x8 bl = *(const u16x8*)&sP[b][1][m * PROW + 32 * h + 8 * s];
-        acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, x[0][s]),
-                                                          __builtin_bit_cast(bf16x8, bh), acc[nb], 0, 0, 0);
-        acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, x[0][s]),
-                                                          __builtin_bit_cast(bf16x8, bl), acc[nb], 0, 0, 0);
-        acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, x[1][s]),
-                                                          __builtin_bit_cast(bf16x8, bh), acc[nb], 0, 0, 0);
+      for (int cb = 0; cb < 4; ++cb) {
+        const int m = 16 * cb + ri;
+        const u16x8 bh = *(const u16x8*)&sP[b][0][m * PROW + 32 * kh + 8 * g];
+        const u16x8 bl = *(const u16x8*)&sP[b][1][m * PROW + 32 * kh + 8 * g];
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb) {
+          const bf16x8 xh = __builtin_bit_cast(bf16x8, x[0][2 * rb + kh]);
+          const bf16x8 xl = __builtin_bit_cast(bf16x8, x[1][2 * rb + kh]);
+          f32x4s d = acc[rb][cb];
+          d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, __builtin_bit_cast(bf16x8, bh), d, 0, 0, 0);
+          d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, __builtin_bit_cast(bf16x8, bl), d, 0, 0, 0);
+          d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl, __builtin_bit_cast(bf16x8, bh), d, 0, 0, 0);
+          acc[rb][cb] = d;
+        }
       }
     }
   };
@@ -197,20 +210,23 @@ __global__ __launch_bounds__(256, 2) void k_apass_bf16x3s(
   if (i + 2 < nk) step(IC<2>{}, i + 2);
   if (i + 3 < nk) step(IC<3>{}, i + 3);
   if (i + 4 < nk) step(IC<4>{}, i + 4);
-  // D[row][col]: row = 8 (v/4) + 4 h + v%4 (output row j0 + row), col = lane%32.  Stacked
-  // column M is column M mod r of restart M / r, whose n x r block starts at (M / r) n r.
+  // D of block (rb, cb): row 4 (l / 16) + v (output row j0 + 16 rb + row), column l mod 16
+  // (stacked column mb + 16 cb + column).  Stacked column M is column M mod r of restart
+  // M / r, whose n x r block starts at (M / r) n r.
   float* out = Bout + ksl * pstride;
 #pragma unroll
-  for (int nb = 0; nb < NNB; ++nb) {
-    const int64_t M = mb + 32 * nb + c;
+  for (int cb = 0; cb < 4; ++cb) {
+    const int64_t M = mb + 16 * cb + ri;
     if (M < R) {
       const int64_t s = M / r, m = M - s * r;
       float* o = out + s * n * r + m;
 #pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int64_t jj = j0 + 8 * (v >> 2) + 4 * h + (v & 3);
-        if (jj < n) o[jj * r] = acc[nb][v];
-      }
+      for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t jj = j0 + 16 * rb + 4 * g + v;
+          if (jj < n) o[jj * r] = acc[rb][cb][v];
+        }
     }
   }
 }
