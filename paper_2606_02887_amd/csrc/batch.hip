@@ -635,17 +635,15 @@ snmf_status snmf_batch_time_apass(snmf_batch* b, const void* P, int32_t reps, do
     return bapass<float>(b, (const float*)P, (float*)b->B, b->s);
   };
   SNMF_TRY(run());
-  hipEvent_t e0, e1;
-  HIP_TRY(hipEventCreate(&e0));
-  HIP_TRY(hipEventCreate(&e1));
-  HIP_TRY(hipEventRecord(e0, b->s));
+  ScopedEvent e0, e1;
+  HIP_TRY(hipEventCreate(&e0.e));
+  HIP_TRY(hipEventCreate(&e1.e));
+  HIP_TRY(hipEventRecord(e0.e, b->s));
   for (int i = 0; i < reps; ++i) SNMF_TRY(run());
-  HIP_TRY(hipEventRecord(e1, b->s));
-  HIP_TRY(hipEventSynchronize(e1));
+  HIP_TRY(hipEventRecord(e1.e, b->s));
+  HIP_TRY(hipEventSynchronize(e1.e));
   float tot = 0.0f;
-  HIP_TRY(hipEventElapsedTime(&tot, e0, e1));
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  HIP_TRY(hipEventElapsedTime(&tot, e0.e, e1.e));
   *ms = (double)tot / reps;
   return SNMF_OK;
 }

@@ -42,6 +42,14 @@ struct DevBuf {
   }
 };
 
+// A HIP event destroyed with its scope (the timing entry points return early on errors).
+struct ScopedEvent {
+  hipEvent_t e = nullptr;
+  ~ScopedEvent() {
+    if (e) (void)hipEventDestroy(e);
+  }
+};
+
 snmf_status check_params(const snmf_params* p);
 snmf_status check_matrix(const snmf_matrix* A, const char* what);
 KParams kparams_of(const snmf_params& p, bool lap);

@@ -765,17 +765,15 @@ snmf_status snmf_plan_time_apass(snmf_plan* pl, const void* P, int32_t reps, dou
     HIP_TRY(hipGetLastError());
   }
   SNMF_TRY(launch());
-  hipEvent_t e0, e1;
-  HIP_TRY(hipEventCreate(&e0));
-  HIP_TRY(hipEventCreate(&e1));
-  HIP_TRY(hipEventRecord(e0, pl->s));
+  ScopedEvent e0, e1;
+  HIP_TRY(hipEventCreate(&e0.e));
+  HIP_TRY(hipEventCreate(&e1.e));
+  HIP_TRY(hipEventRecord(e0.e, pl->s));
   for (int i = 0; i < reps; ++i) SNMF_TRY(launch());
-  HIP_TRY(hipEventRecord(e1, pl->s));
-  HIP_TRY(hipEventSynchronize(e1));
+  HIP_TRY(hipEventRecord(e1.e, pl->s));
+  HIP_TRY(hipEventSynchronize(e1.e));
   float tot = 0.0f;
-  HIP_TRY(hipEventElapsedTime(&tot, e0, e1));
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  HIP_TRY(hipEventElapsedTime(&tot, e0.e, e1.e));
   *ms = (double)tot / reps;
   return SNMF_OK;
 }
