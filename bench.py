@@ -50,6 +50,9 @@ def _args():
     ap.add_argument("--train-graphs", type=int, default=2048)
     ap.add_argument("--train-outer", type=int, default=300)
     ap.add_argument("--epochs", type=int, default=4)
+    ap.add_argument("--batch-apass-only", action="store_true",
+                    help="only the stacked split-BF16 A-pass of 8 batched restarts, 20 times "
+                         "(for hardware counters)")
     ap.add_argument("--apass-only", action="store_true",
                     help="only a 256 MiB device copy (the counter scale reference) and 20 "
                          "A-pass launches of each form; for hardware-counter runs")
@@ -96,6 +99,22 @@ def _apass_only(torch, S, A, W0, lam):
                 pl.apass(W0, B)
             torch.cuda.synchronize()
     print(json.dumps({"apass_only": True, "copy_bytes": COPY_BYTES}))
+
+
+def _batch_apass_only(torch, np, S, gen, A, A64):
+    """A plain copy of COPY_BYTES (the counter calibration) and 21 launches of the stacked
+    split-BF16 A-pass of 8 restarts (one untimed), nothing else."""
+    src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=A.device)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    rng = np.random.default_rng(1101)
+    W0b = torch.from_numpy(np.stack([gen.start_factor(rng, N, R, float(A64.mean()))
+                                     for _ in range(8)])).to(A.device, torch.float32)
+    with S.Batch([S.dense(A)], [R], S.params(prec=S.BF16X3, max_outer=1), 8) as bt:
+        ms = bt.time_apass(W0b.reshape(-1), 20)
+    torch.cuda.synchronize()
+    print(json.dumps({"batch_apass_only": True, "copy_bytes": COPY_BYTES,
+                      "ms_split_and_product": ms}))
 
 
 def _traffic(kernel_src, name):
@@ -466,6 +485,9 @@ def main():
 
     if a.apass_only:
         _apass_only(torch, S, A, W0, lam)
+        return
+    if a.batch_apass_only:
+        _batch_apass_only(torch, np, S, gen, A, A64)
         return
 
     forms = {}
