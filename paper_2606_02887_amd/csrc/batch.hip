@@ -72,8 +72,8 @@ snmf_status bcheck_csr(snmf_batch* b, const snmf_matrix* M, const std::string& w
   return SNMF_OK;
 }
 
-// G64 set (dense BF16X3 only): rho of every instance inside the stacked A-pass launches,
-// from its Gram in G64
+// G64 set (dense BF16X3 only): rho of every instance inside the stacked A-pass launches
+// (the product's when its workgroups fit, else the split's), from its Gram in G64
 template <typename T>
 snmf_status bapass(snmf_batch* b, const T* P, T* B, hipStream_t s,
                    const double* G64 = nullptr) {
@@ -90,14 +90,17 @@ snmf_status bapass(snmf_batch* b, const T* P, T* B, hipStream_t s,
       const int64_t snr = (int64_t)b->S * d.n * d.r;
       State* st = b->states + (size_t)g * b->S;
       const double* Grho = G64 ? G64 + d.goff : nullptr;
+      // rho rides in the product launch when its workgroups find free slots there, else
+      // in the split launch (its tiles are short, so rho sets that launch's length)
       launch_split_pt_stack((const float*)(P + d.off), d.n, d.r, b->S, b->ldb[g], b->Pthi,
-                            b->Ptlo, st, s);
+                            b->Ptlo, st, b->rho_in_apass ? nullptr : Grho, s);
+      const double* Grho_ap = b->rho_in_apass ? Grho : nullptr;
       if (sp.ksplit == 1) {
         launch_apass_bf16x3_stack(b->Ahi[g], b->Alo[g], b->ldb[g], b->Pthi, b->Ptlo, d.n, d.r,
-                                  b->S, sp, (float*)(B + d.off), 0, st, Grho, s);
+                                  b->S, sp, (float*)(B + d.off), 0, st, Grho_ap, s);
       } else {
         launch_apass_bf16x3_stack(b->Ahi[g], b->Alo[g], b->ldb[g], b->Pthi, b->Ptlo, d.n, d.r,
-                                  b->S, sp, (float*)b->Bpart, snr, st, Grho, s);
+                                  b->S, sp, (float*)b->Bpart, snr, st, Grho_ap, s);
         launch_sum_parts<float>((const float*)b->Bpart, sp.ksplit, snr, (float*)(B + d.off), snr,
                                 s);
       }
@@ -132,8 +135,8 @@ snmf_status bhalf_start(snmf_batch* b, T* X, const T* P, int is_hstep, bool with
   launch_bgram_reduce<T>(b->dinst, b->ninst, b->max_r, b->states, b->gpart, b->G64[gi],
                          (T*)b->GT[gi], s);
   HIP_TRY(hipGetLastError());
-  // dense BF16X3 (when the slots allow): rho runs inside the stacked A-pass launches
-  const bool rho_in_apass = b->dense && b->prec == SNMF_BF16X3 && b->rho_in_apass;
+  // dense BF16X3: rho runs inside the stacked A-pass launches (product or split)
+  const bool rho_in_apass = b->dense && b->prec == SNMF_BF16X3;
   if (with_rho && !rho_in_apass) {
     launch_brho(b->dinst, b->ninst, b->states, b->G64[gi], s);
     HIP_TRY(hipGetLastError());
@@ -346,9 +349,10 @@ snmf_status batch_create(int32_t nprob, const snmf_matrix* A, const int32_t* r, 
     b->ldb.resize(nprob);
     b->Ahi.assign(nprob, nullptr);
     b->Alo.assign(nprob, nullptr);
-    // rho runs inside the A-pass launch when its S workgroups find free slots beside the
+    // rho runs inside the product launch when its S workgroups find free slots beside the
     // product's (two per CU): a rho workgroup that waits for a slot, or holds one a tile
-    // workgroup waits for, lengthens the launch by a whole rho (about 55 us at r = 64)
+    // workgroup waits for, lengthens the launch by a whole rho (about 55 us at r = 64).
+    // Otherwise it runs inside the partner split's launch, whose tiles are short.
     int dev = 0, cus = 0;
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));

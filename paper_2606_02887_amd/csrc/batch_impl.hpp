@@ -32,7 +32,7 @@ struct snmf_batch {
   std::vector<int64_t> ldb;                  // BF16X3: row pitch of A_hi, A_lo, Pt (n up to 64)
   std::vector<uint16_t*> Ahi, Alo;           // BF16X3: split A of every problem
   uint16_t *Pthi = nullptr, *Ptlo = nullptr; // BF16X3: stacked split P of one problem
-  bool rho_in_apass = false;                 // BF16X3: rho inside the stacked A-pass launches
+  bool rho_in_apass = false;                 // BF16X3: rho in the product (else split) launch
   struct Cls {
     int r = 0;
     int blocks = 0;        // inner-kernel workgroups

@@ -330,19 +330,31 @@ typedef unsigned short u16x8s __attribute__((ext_vector_type(8)));
 // The P factors of S restarts (S consecutive n x r FP32 blocks) -> Pt_hi, Pt_lo
 // ((S r) x ldp BF16, row s r + m = column m of block s, zero beyond n).  A workgroup
 // transposes a 64 (k) x 64 (stacked column) tile through LDS, so the reads (rows of P)
-// and the writes (rows of Pt) are both contiguous.  Grid: ldp / 64 x ceil(S r / 64).
+// and the writes (rows of Pt) are both contiguous.
+//
+// Grid: ntile = (ldp / 64) x ceil(S r / 64) tile workgroups, then (Grho set) S more that
+// compute rho of restart s from its FP64 Gram at Grho + s r^2 beside the short tiles.
 __global__ __launch_bounds__(kThreads) void k_split_pt_stack(const float* __restrict__ P,
                                                              int64_t n, int r, int S, int64_t ldp,
                                                              uint16_t* __restrict__ hi,
                                                              uint16_t* __restrict__ lo,
-                                                             const State* __restrict__ st) {
+                                                             State* __restrict__ st,
+                                                             const double* __restrict__ Grho) {
+  const int64_t nkx = ldp / 64, ntile = nkx * (((int64_t)S * r + 63) / 64);
+  if ((int64_t)blockIdx.x >= ntile) {
+    const int s = (int)((int64_t)blockIdx.x - ntile);
+    __builtin_amdgcn_s_setprio(3);  // rho sets this launch's length: issue priority
+    if (!st[s].done) rho_body(Grho + (int64_t)s * r * r, r, st + s);
+    return;
+  }
   bool all = true;
   for (int i = 0; i < S; ++i)
     if (!st[i].done) all = false;
   if (all) return;
   __shared__ float tile[64][65];
   const int64_t R = (int64_t)S * r;
-  const int64_t k0 = (int64_t)blockIdx.x * 64, m0 = (int64_t)blockIdx.y * 64;
+  const int64_t by = (int64_t)blockIdx.x / nkx;
+  const int64_t k0 = ((int64_t)blockIdx.x - by * nkx) * 64, m0 = by * 64;
   const int tid = threadIdx.x;
   // every load is issued (clamped to a valid element) before the first is used, and the
   // padding (k >= n, M >= R) is zeroed afterwards: a load behind a branch would be
@@ -470,10 +482,11 @@ void launch_split_rows(const float* A, int64_t n, int64_t lda, int64_t ldb, uint
 }
 
 void launch_split_pt_stack(const float* P, int64_t n, int r, int S, int64_t ldp, uint16_t* hi,
-                           uint16_t* lo, const State* st, hipStream_t s) {
+                           uint16_t* lo, State* st, const double* Grho, hipStream_t s) {
   const int64_t R = (int64_t)S * r;
-  hipLaunchKernelGGL(k_split_pt_stack, dim3((unsigned)(ldp / 64), (unsigned)((R + 63) / 64)),
-                     dim3(kThreads), 0, s, P, n, r, S, ldp, hi, lo, st);
+  const int64_t ntile = (ldp / 64) * ((R + 63) / 64);
+  hipLaunchKernelGGL(k_split_pt_stack, dim3((unsigned)(ntile + (Grho ? S : 0))), dim3(kThreads),
+                     0, s, P, n, r, S, ldp, hi, lo, st, Grho);
 }
 
 void launch_split_pt(const float* P, int64_t n, int r, int64_t ldp, uint16_t* hi, uint16_t* lo,

@@ -82,9 +82,10 @@ void launch_split_pt(const float* P, int64_t n, int r, int64_t ldp, uint16_t* hi
                      const State* st, hipStream_t s);
 
 // S consecutive n x r blocks -> (S r) x ldp transposed BF16 hi/lo (ldp a multiple of 64);
-// skipped when all S states are done.
+// skipped when all S states are done.  With Grho set, rho of restart s (st[s].rho) from
+// the FP64 Gram at Grho + s r^2 in the same launch.
 void launch_split_pt_stack(const float* P, int64_t n, int r, int S, int64_t ldp, uint16_t* hi,
-                           uint16_t* lo, const State* st, hipStream_t s);
+                           uint16_t* lo, State* st, const double* Grho, hipStream_t s);
 
 template <typename T>
 void launch_sum_parts(const T* part, int ks, int64_t stride, T* out, int64_t N, hipStream_t s);

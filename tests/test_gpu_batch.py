@@ -262,6 +262,27 @@ def test_batch_bf16x3_instances_follow_the_oracle(S):
     assert infos[2]["res_WH"] == infos[0]["res_WH"]
 
 
+def test_batch_bf16x3_rho_beside_the_split(S):
+    """57 restarts of rank 64 at n = 1100 fill every workgroup slot of the stacked product
+    (9 x 57 pairs), so rho runs in the partner split's launch instead: restarts 0 and 56
+    must follow the oracle's solve from their starts for 5 outer iterations."""
+    prob = gen.planted_dense(1100, 64, 57)
+    At = torch.from_numpy(prob["A"]).to(DEV, torch.float32)
+    a_in = At.double().cpu().numpy()
+    lam = O.default_lambda(a_in)
+    rng = np.random.default_rng(57)
+    w0 = np.stack([gen.start_factor(rng, 1100, 64, float(a_in.mean())) for _ in range(57)])
+    W0 = torch.from_numpy(w0).to(DEV, torch.float32).contiguous()
+    w_in = W0.double().cpu().numpy()
+    with S.Batch([S.dense(At)], [64], S.params(lam=lam, prec=S.BF16X3, max_outer=5),
+                 restarts=57) as b:
+        _, _, infos, _ = b.solve([W0])
+    for s in (0, 56):
+        _, _, hist = O.snmpbb(a_in, w_in[s], O.Params(lam=lam), 5)
+        assert infos[s]["status"] == 0 and infos[s]["outer"] == 5
+        assert abs(infos[s]["res_WH"] - hist[-1]["res_WH"]) <= 1e-3 * hist[-1]["res_WH"], s
+
+
 def test_batch_bf16x3_stop_and_breakdown_stay_in_their_restart(S):
     """Restarts of one dense problem share the stacked split-BF16 product: restart 0 stops
     at its own first monitored hit of a target, restart 2 (zero start: G = 0, rho = 0)
