@@ -235,12 +235,28 @@ def pg_norm(A, W, Ht, prm: Params, L=None) -> float:
     return float(np.sqrt(np.sum(np.minimum(W, gw) ** 2) + np.sum(np.minimum(Ht, gh) ** 2)))
 
 
+def objective(A, W, Ht, prm: Params, L=None, normA2=None) -> float:
+    """f(W, H) of eq. (1.3), plus gam/2 tr(H L H^T) of eq. (2.3) when L is given, in the
+    trace form 1/2||A||^2 - <A Ht, W> + 1/2<W^T W, Ht^T Ht> + lam/2||W - Ht||^2
+    [+ gam/2 <Ht, L Ht>] (for LowRank input ||A||^2 is the surrogate's sum(lam^2))."""
+    nA2 = norm2_A(A) if normA2 is None else normA2
+    v = (0.5 * nA2 - np.sum(apply_A(A, Ht) * W) + 0.5 * np.sum((W.T @ W) * (Ht.T @ Ht))
+         + 0.5 * prm.lam * np.sum((W - Ht) ** 2))
+    if L is not None and prm.gamma:
+        v += 0.5 * prm.gamma * np.sum(Ht * np.asarray(L @ Ht))
+    return float(v)
+
+
 def monitor(A, W, Ht, prm: Params, L=None, normA2=None):
+    """The per-outer-iteration record: residuals ||A - W H||/||A|| and ||A - W W^T||/||A||
+    (Section 4), the symmetry gap ||W - H^T||/||W||, the projected-gradient norm and the
+    objective f(W, H)."""
     nA2 = norm2_A(A) if normA2 is None else normA2
     out = dict(res_WH=residual_WH(A, W, Ht, nA2),
                res_WWt=residual_WH(A, W, W, nA2),
                sym_gap=float(np.linalg.norm(W - Ht) / max(np.linalg.norm(W), 1e-300)),
-               pg=pg_norm(A, W, Ht, prm, L))
+               pg=pg_norm(A, W, Ht, prm, L),
+               objective=objective(A, W, Ht, prm, L, nA2))
     return out
 
 
