@@ -43,7 +43,8 @@ typedef enum snmf_status {
   SNMF_OK = 0,
   SNMF_E_ARG = 1,           /* invalid argument (null pointer, bad parameter value) */
   SNMF_E_SHAPE = 2,         /* inconsistent sizes (r > n, r > 64, bad leading dimension) */
-  SNMF_E_NOT_SYMMETRIC = 3, /* CSR pattern/values not symmetric */
+  SNMF_E_NOT_SYMMETRIC = 3, /* CSR pattern/values not symmetric, or a dense A that fails the
+                               opt-in check of params.check_symmetry */
   SNMF_E_NEGATIVE = 4,      /* negative entry in A or W0 (A >= 0 and W0 >= 0 are required) */
   SNMF_E_NONFINITE = 5,     /* NaN or Inf in A or W0 */
   SNMF_E_OOM = 6,           /* device allocation failed */
@@ -64,7 +65,10 @@ typedef enum snmf_precision { SNMF_F64 = 0, SNMF_F32 = 1, SNMF_BF16X3 = 2 } snmf
 
 /* The symmetric nonnegative input A (n x n), or a graph Laplacian L.  Element type of
  * `dense`, `val` and `U` follows the solve precision (double for F64, float otherwise).
- *  DENSE:   dense[i*ld + j], ld >= n; symmetry is the caller's promise (not checked).
+ *  DENSE:   dense[i*ld + j], ld >= n; symmetric: checked only when the solve's
+ *           params.check_symmetry is set (O(n^2)), else the caller's promise.  The FP32
+ *           A-pass forms A^T P (equal to A P for symmetric A) while the FP64 and split-BF16
+ *           forms multiply A P, so an unchecked asymmetric A makes the forms disagree.
  *  CSR:     rowptr[n+1] (int64, device), col[nnz] (int32, device), val[nnz]; both
  *           triangles stored; rows need not be sorted.
  *  LOWRANK: U[i*ell + a] (n x ell, orthonormal columns) and lam[ell] (double, device):
@@ -107,7 +111,10 @@ typedef struct snmf_params {
   int32_t project_update;    /* 1: W_{k+1} = max(0, Z + phi beta D); 0: no projection     [1] */
   int32_t validate;    /* 1: check A >= 0, finite, W0 >= 0 finite, CSR structure        [1] */
   int32_t use_graph;   /* 1: replay one outer iteration as a captured hipGraph           [1] */
-  int32_t reserved;
+  int32_t check_symmetry; /* 1: dense A must satisfy |a_ij - a_ji| <= 2^-20 max(|a_ij|, |a_ji|)
+                          for all i, j, else SNMF_E_NOT_SYMMETRIC (one O(n^2) pass over A at
+                          plan or batch creation); 0: not checked (CSR symmetry is checked
+                          whenever validate is set)                                      [0] */
 } snmf_params;
 
 /* Per-solve results (host struct written on return). */
@@ -286,9 +293,23 @@ snmf_status snmf_batch_targets(snmf_batch* b, const void* C, const void* Ht, voi
                                int32_t* perm, void* stream);
 /* W0 (batch buffer) for every instance: frame of Omega, then the network whose r matches
  * the instance's rank (E_ARG if none; FP32 batches only).  nmodels = 0: the frame alone,
- * W0 = s relu(C) / rms(relu(C)) per instance (the ablation without the network). */
+ * W0 = s relu(C) / rms(relu(C)) per instance (the ablation without the network).  Dense
+ * batches take the degrees d = A 1 from a row sum on the device (BF16X3 dense batches:
+ * E_UNSUPPORTED). */
 snmf_status snmf_batch_warmstart(snmf_batch* b, int32_t nmodels, const snmf_mlp* models,
                                  const void* Omega, void* W0, void* stream);
+
+/* The warm start of one problem (dense or CSR A, F32 or F64), without a batch: the same
+ * sketch, frame and network as snmf_batch_warmstart for a batch of one problem with one
+ * start.  Omega (n x r, device, of the precision's type) is the Gaussian sketch matrix,
+ * drawn by the caller; W0_out (n x r) receives the start.  mlp = NULL gives the start of
+ * the frame alone, W0 = s relu(C) / rms(relu(C)); otherwise mlp->r must equal r and prec
+ * must be F32.  Dense A is read in place (its degrees d = A 1 are summed on the device in
+ * FP64).  Scratch memory is allocated and freed inside the call.  Errors: E_ARG (null
+ * pointers, prec not F32/F64), E_SHAPE (r outside [1, min(64, n)], network rank != r),
+ * E_UNSUPPORTED (LOWRANK A, a network with F64), and the input checks of a solve. */
+snmf_status snmf_warmstart(const snmf_mlp* mlp, const snmf_matrix* A, int32_t r, int32_t prec,
+                           const void* Omega, void* W0_out, void* stream);
 
 /* Device clock rate (Hz) of the trace ticks and info.seconds. */
 double snmf_clock_rate_hz(void);

@@ -170,6 +170,18 @@ def match_columns(C, Ht):
     return p
 
 
+def frame_start(A, Omega, normA):
+    """The start of the frame alone (the ablation without the network):
+    W0 = s relu(C) / rms(relu(C)), rms over all n r entries (W0 = s everywhere if
+    relu(C) = 0)."""
+    C, K, _ = frame(A, Omega)
+    n, r = C.shape
+    s = scale(normA, n, r)
+    pos = np.maximum(C, 0.0)
+    rms = float(np.sqrt(np.mean(pos * pos)))
+    return (s * pos / rms if rms > 0 else np.full_like(C, s)), C, K
+
+
 def warm_start(params, A, Omega, normA):
     """W0 = s * MLP(C) for one problem."""
     C, K, _ = frame(A, Omega)

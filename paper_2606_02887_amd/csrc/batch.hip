@@ -434,6 +434,8 @@ snmf_status batch_create(int32_t nprob, const snmf_matrix* A, const int32_t* r, 
       SNMF_TRY(bstats(b, A[g].dense, A[g].n, A[g].n, A[g].ld, st3));
       if (p->validate && st3[2] > 0) return fail(SNMF_E_NONFINITE, what + " has NaN/Inf entries");
       if (p->validate && st3[1] > 0) return fail(SNMF_E_NEGATIVE, what + " has negative entries");
+      if (p->check_symmetry)
+        SNMF_TRY(check_dense_symmetry(&A[g], b->prec, b->flags, b->s, what.c_str()));
       b->normA2[g] = st3[0];
     } else {
       SNMF_TRY(bcheck_csr(b, &A[g], what, &b->normA2[g]));

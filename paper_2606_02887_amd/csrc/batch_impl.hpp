@@ -61,6 +61,8 @@ struct snmf_batch {
   BGraph* dgraph = nullptr;
   double* wsR = nullptr;       // warm start: FP64 scratch of the frame (allocated on first use)
   int32_t* wsI = nullptr;      // warm start: anchors / permutations, kMaxRank per instance
+  double* wsDeg = nullptr;     // warm start of dense problems: row sums of every A_g
+  BGraph* wsG = nullptr;       // warm start of dense problems: their table (deg, n)
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
 
@@ -80,6 +82,8 @@ struct snmf_batch {
     if (pool) (void)hipFree(pool);
     if (wsR) (void)hipFree(wsR);
     if (wsI) (void)hipFree(wsI);
+    if (wsDeg) (void)hipFree(wsDeg);
+    if (wsG) (void)hipFree(wsG);
     if (ev_in) (void)hipEventDestroy(ev_in);
     if (ev_out) (void)hipEventDestroy(ev_out);
     if (s) (void)hipStreamDestroy(s);

@@ -82,6 +82,7 @@ struct BGraph {
   const int64_t* rowptr;
   const int32_t* col;
   const void* val;
+  const double* deg;  // warm start of dense problems: row sums A 1 (CSR: nullptr)
   int64_t n;
   int64_t off0;
   int32_t r, S;

@@ -52,6 +52,11 @@ struct ScopedEvent {
 
 snmf_status check_params(const snmf_params* p);
 snmf_status check_matrix(const snmf_matrix* A, const char* what);
+// relative tolerance of the dense symmetry check: about eight FP32 ulps, far above the
+// rounding a product such as X X^T leaves between mirrored entries
+constexpr double kSymTol = 0x1p-20;
+snmf_status check_dense_symmetry(const snmf_matrix* M, int prec, unsigned* flags, hipStream_t s,
+                                 const char* what);
 KParams kparams_of(const snmf_params& p, bool lap);
 
 }  // namespace snmf

@@ -480,6 +480,15 @@ __device__ bool inner_entry(int k, int is_hstep, int r, const KParams& kp, State
       block_sum<1>(a1, sred);                        // <C, P> with P = W
       if (w0) st->m_CP = a1[0];
     }
+    // the partner block vanished (rho = 0) or overflowed: breakdown, reported here so
+    // that the record of the last completed outer iteration (above) is kept
+    if (!(rho > 0.0) || !(rho < 1e308)) {
+      if (w0) {
+        st->status = 9;
+        st->done = 1;
+      }
+      return false;
+    }
     e_k = 0.0;
     alpha_k = 1.0 / rho;
   } else {

@@ -97,6 +97,48 @@ __global__ __launch_bounds__(kThreads) void k_csr_symmetry(const int64_t* __rest
   if (bad) atomicAdd(&flags[3], bad);
 }
 
+// Symmetry of a dense n x n matrix (leading dimension ld): workgroup (bx, by), by <= bx,
+// stages the 32 x 32 tile at (block row by, block column bx) in LDS and compares it with
+// the mirrored tile read row by row.  flags[3] += entries with
+// |a_ij - a_ji| > tol max(|a_ij|, |a_ji|) (NaN entries count as mismatches).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_dense_symmetry(const T* __restrict__ A, int64_t n,
+                                                             int64_t ld, double tol,
+                                                             unsigned* __restrict__ flags) {
+  if (blockIdx.y > blockIdx.x) return;
+  __shared__ T tile[32][33];
+  const int64_t i0 = (int64_t)blockIdx.y * 32, j0 = (int64_t)blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8 threads
+  for (int q = ty; q < 32; q += 8) {
+    const int64_t i = i0 + q, j = j0 + tx;
+    tile[q][tx] = (i < n && j < n) ? A[i * ld + j] : T(0);
+  }
+  __syncthreads();
+  unsigned bad = 0;
+  for (int q = ty; q < 32; q += 8) {
+    const int64_t j = j0 + q, i = i0 + tx;                    // entry (j, i) of the mirror
+    if (i < n && j < n) {
+      const double a = (double)A[j * ld + i];
+      const double b = (double)tile[tx][q];                    // entry (i, j)
+      const double m = fmax(fabs(a), fabs(b));
+      if (!(fabs(a - b) <= tol * m)) ++bad;
+    }
+  }
+  if (bad) atomicAdd(&flags[3], bad);
+}
+
+template <typename T>
+void launch_dense_symmetry(const T* A, int64_t n, int64_t ld, double tol, unsigned* flags,
+                           hipStream_t s) {
+  const int64_t nt = (n + 31) / 32;
+  hipLaunchKernelGGL(k_dense_symmetry<T>, dim3((unsigned)nt, (unsigned)nt), dim3(kThreads), 0, s,
+                     A, n, ld, tol, flags);
+}
+template void launch_dense_symmetry<float>(const float*, int64_t, int64_t, double, unsigned*,
+                                           hipStream_t);
+template void launch_dense_symmetry<double>(const double*, int64_t, int64_t, double, unsigned*,
+                                            hipStream_t);
+
 template <typename T>
 void launch_stats2d(const T* x, int64_t rows, int64_t cols, int64_t ld, double* part, double* out,
                     unsigned* counter, hipStream_t s) {

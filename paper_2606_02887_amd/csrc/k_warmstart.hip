@@ -88,9 +88,14 @@ __global__ __launch_bounds__(kThreads) void k_ws_frame(const BInst* __restrict__
   // R_i = Y_i / d_i and the first squared norms
   double best = -1.0;
   int bidx = 0;
+  const double* __restrict__ degd = G.deg;
   for (int64_t row = threadIdx.x; row < n; row += kThreads) {
     double deg = 0.0;
-    for (int64_t z = rowptr[row]; z < rowptr[row + 1]; ++z) deg += (double)val[z];
+    if (degd) {
+      deg = degd[row];
+    } else {
+      for (int64_t z = rowptr[row]; z < rowptr[row + 1]; ++z) deg += (double)val[z];
+    }
     const double inv = deg > 0.0 ? 1.0 / deg : 0.0;
     double nrm = 0.0;
 #pragma unroll
@@ -223,6 +228,31 @@ __global__ __launch_bounds__(kThreads) void k_ws_frame(const BInst* __restrict__
     case 32: { constexpr int RP = 32; __VA_ARGS__; } break;          \
     default: { constexpr int RP = 64; __VA_ARGS__; } break;          \
   }
+
+// Row sums deg[i] = sum_j A[i][j] of a dense matrix in FP64: one wavefront per row, each
+// lane adds every 64th entry in order, then a fixed shuffle tree.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_dense_rowsum(const T* __restrict__ A, int64_t n,
+                                                           int64_t ld, double* __restrict__ deg) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * (kThreads / kWave) + (threadIdx.x >> 6);
+  if (row >= n) return;
+  const T* __restrict__ a = A + row * ld;
+  double s = 0.0;
+  for (int64_t j = lane; j < n; j += kWave) s += (double)a[j];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if (lane == 0) deg[row] = s;
+}
+
+template <typename T>
+void launch_dense_rowsum(const T* A, int64_t n, int64_t ld, double* deg, hipStream_t s) {
+  const int64_t rows_per = kThreads / kWave;
+  hipLaunchKernelGGL(k_dense_rowsum<T>, dim3((unsigned)((n + rows_per - 1) / rows_per)),
+                     dim3(kThreads), 0, s, A, n, ld, deg);
+}
+template void launch_dense_rowsum<float>(const float*, int64_t, int64_t, double*, hipStream_t);
+template void launch_dense_rowsum<double>(const double*, int64_t, int64_t, double*, hipStream_t);
 
 template <typename T>
 void launch_ws_frame(const BInst* inst, int ninst, int max_r, const BGraph* graphs, const T* Y,

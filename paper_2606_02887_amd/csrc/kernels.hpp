@@ -52,6 +52,8 @@ void launch_mlp_train_step(const MlpDev& m, int64_t pool, int64_t B, const float
                            const float* T, const int32_t* idx, float mu, float lr, int step,
                            const MlpWork& w, hipStream_t s);
 template <typename T>
+void launch_dense_rowsum(const T* A, int64_t n, int64_t ld, double* deg, hipStream_t s);
+template <typename T>
 void launch_ws_frame(const BInst* inst, int ninst, int max_r, const BGraph* graphs, const T* Y,
                      double* R, T* C, int32_t* anchors, hipStream_t s);
 template <typename T>
@@ -150,6 +152,9 @@ constexpr int64_t kRecomputeDBytes = 4 << 20;
 template <typename T>
 void launch_stats2d(const T* x, int64_t rows, int64_t cols, int64_t ld, double* part, double* out,
                     unsigned* counter, hipStream_t s);
+template <typename T>
+void launch_dense_symmetry(const T* A, int64_t n, int64_t ld, double tol, unsigned* flags,
+                           hipStream_t s);
 void launch_csr_structure(const int64_t* rowptr, const int32_t* col, int64_t n, int64_t nnz,
                           unsigned* flags, hipStream_t s);
 template <typename T>

@@ -191,12 +191,10 @@ __device__ __forceinline__ void rho_body(const double* __restrict__ G, int r,
     H = nhi;
   }
   if (t == 0) {
+    // rho = 0 (the partner block vanished) is reported by the first inner kernel of the
+    // half-step, after the monitor record of the outer iteration that produced it
     const double rho = m > 0 ? ldexp(0.5 * (L + H), ex) : 0.0;
     st->rho = rho;
-    if (!(rho > 0.0) || !(rho < 1e308)) {
-      st->status = 9;  // SNMF_E_BREAKDOWN
-      st->done = 1;
-    }
   }
 }
 

@@ -171,6 +171,30 @@ snmf_status check_values(const double* st3, const char* what) {
   return SNMF_OK;
 }
 
+}  // namespace
+
+namespace snmf {
+// Opt-in symmetry check of a dense matrix (params.check_symmetry): E_NOT_SYMMETRIC when an
+// entry and its mirror differ by more than kSymTol of the larger.
+snmf_status check_dense_symmetry(const snmf_matrix* M, int prec, unsigned* flags, hipStream_t s,
+                                 const char* what) {
+  HIP_TRY(hipMemsetAsync(flags, 0, 4 * sizeof(unsigned), s));
+  if (prec == SNMF_F64)
+    launch_dense_symmetry<double>((const double*)M->dense, M->n, M->ld, kSymTol, flags, s);
+  else
+    launch_dense_symmetry<float>((const float*)M->dense, M->n, M->ld, kSymTol, flags, s);
+  HIP_TRY(hipGetLastError());
+  unsigned f[4];
+  HIP_TRY(hipMemcpyAsync(f, flags, sizeof(f), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (f[3]) return fail(SNMF_E_NOT_SYMMETRIC, std::string(what) + " is not symmetric (" +
+                                                  std::to_string(f[3]) + " mismatched entries)");
+  return SNMF_OK;
+}
+}  // namespace snmf
+
+namespace {
+
 snmf_status check_csr(snmf_plan* pl, const snmf_matrix* M, const char* what, bool need_nonneg,
                       double* sumsq) {
   HIP_TRY(hipMemsetAsync(pl->flags, 0, 4 * sizeof(unsigned), pl->s));
@@ -468,6 +492,7 @@ snmf_status plan_create(const snmf_matrix* A, int32_t r, const snmf_params* p, h
   if (A->fmt == SNMF_DENSE) {
     SNMF_TRY(stats_any(pl, A->dense, n, n, A->ld, st3));
     if (p->validate) SNMF_TRY(check_values(st3, "A"));
+    if (p->check_symmetry) SNMF_TRY(check_dense_symmetry(A, pl->prec, pl->flags, pl->s, "A"));
     pl->normA2 = st3[0];
   } else if (A->fmt == SNMF_CSR) {
     SNMF_TRY(check_csr(pl, A, "A", p->validate != 0, &pl->normA2));

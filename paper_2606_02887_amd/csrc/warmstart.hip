@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "../../include/snmf.h"
 #include "batch_impl.hpp"
@@ -89,18 +90,58 @@ snmf_status ws_scratch(snmf_batch* b) {
   return SNMF_OK;
 }
 
+// Dense problems: the degrees d = A 1 of every problem and a table that hands them to the
+// frame kernel (CSR problems sum their rows inside it).
+snmf_status dense_degrees(snmf_batch* b) {
+  if (!b->wsDeg) {
+    int64_t tot = 0;
+    for (int g = 0; g < b->nprob; ++g) tot += b->n[g];
+    HIP_TRY(hipMalloc((void**)&b->wsDeg, (size_t)tot * 8));
+    HIP_TRY(hipMalloc((void**)&b->wsG, (size_t)b->nprob * sizeof(BGraph)));
+    std::vector<BGraph> tab(b->nprob);
+    int64_t at = 0;
+    for (int g = 0; g < b->nprob; ++g) {
+      std::memset(&tab[g], 0, sizeof(BGraph));
+      tab[g].val = b->A[g].dense;
+      tab[g].deg = b->wsDeg + at;
+      tab[g].n = b->n[g];
+      tab[g].r = b->r[g];
+      tab[g].S = b->S;
+      at += b->n[g];
+    }
+    HIP_TRY(hipMemcpyAsync(b->wsG, tab.data(), tab.size() * sizeof(BGraph), hipMemcpyHostToDevice,
+                           b->s));
+    HIP_TRY(hipStreamSynchronize(b->s));
+  }
+  int64_t at = 0;
+  for (int g = 0; g < b->nprob; ++g) {
+    if (b->prec == SNMF_F64)
+      launch_dense_rowsum<double>((const double*)b->A[g].dense, b->n[g], b->A[g].ld, b->wsDeg + at,
+                                  b->s);
+    else
+      launch_dense_rowsum<float>((const float*)b->A[g].dense, b->n[g], b->A[g].ld, b->wsDeg + at,
+                                 b->s);
+    at += b->n[g];
+  }
+  HIP_TRY(hipGetLastError());
+  return SNMF_OK;
+}
+
 // Y = A Omega, then the frame of every instance into C (stream b->s).
 snmf_status frame_async(snmf_batch* b, const void* Omega, void* Y, void* C, int32_t* anchors) {
-  if (b->dense) return fail(SNMF_E_UNSUPPORTED, "the warm start takes CSR batches");
+  if (b->dense && b->prec == SNMF_BF16X3)
+    return fail(SNMF_E_UNSUPPORTED, "the warm start of dense problems runs in F32 or F64");
   SNMF_TRY(ws_scratch(b));
+  if (b->dense) SNMF_TRY(dense_degrees(b));
+  const BGraph* graphs = b->dense ? b->wsG : b->dgraph;
   launch_breset(b->states, b->dinst, b->ninst, b->s);  // clears the done flags the A-pass reads
   SNMF_TRY(batch_apass_async(b, Omega, Y, b->s));
   int32_t* anc = anchors ? anchors : b->wsI;
   if (b->prec == SNMF_F64)
-    launch_ws_frame<double>(b->dinst, b->ninst, b->max_r, b->dgraph, (const double*)Y, b->wsR,
+    launch_ws_frame<double>(b->dinst, b->ninst, b->max_r, graphs, (const double*)Y, b->wsR,
                             (double*)C, anc, b->s);
   else
-    launch_ws_frame<float>(b->dinst, b->ninst, b->max_r, b->dgraph, (const float*)Y, b->wsR,
+    launch_ws_frame<float>(b->dinst, b->ninst, b->max_r, graphs, (const float*)Y, b->wsR,
                            (float*)C, anc, b->s);
   HIP_TRY(hipGetLastError());
   return SNMF_OK;
@@ -227,6 +268,29 @@ snmf_status snmf_batch_warmstart(snmf_batch* b, int32_t nmodels, const snmf_mlp*
   }
   HIP_TRY(hipStreamSynchronize(b->s));
   return finish(b, user);
+}
+
+snmf_status snmf_warmstart(const snmf_mlp* mlp, const snmf_matrix* A, int32_t r, int32_t prec,
+                           const void* Omega, void* W0_out, void* stream) {
+  if (!A || !Omega || !W0_out) return fail(SNMF_E_ARG, "A, Omega and W0_out are required");
+  if (A->fmt == SNMF_LOWRANK) return fail(SNMF_E_UNSUPPORTED, "the warm start takes dense or CSR A");
+  if (prec != SNMF_F32 && prec != SNMF_F64) return fail(SNMF_E_ARG, "prec must be F32 or F64");
+  if (mlp) {
+    SNMF_TRY(check_mlp(mlp, false));
+    if (mlp->r != r) return fail(SNMF_E_SHAPE, "the network's rank differs from r");
+    if (prec != SNMF_F32) return fail(SNMF_E_UNSUPPORTED, "the warm start network runs in FP32");
+  }
+  snmf_params p;
+  SNMF_TRY(snmf_params_default(&p));
+  p.prec = prec;
+  p.max_outer = 1;
+  snmf_batch* b = nullptr;
+  SNMF_TRY(snmf_batch_create(1, A, &r, nullptr, 1, &p, stream, &b));
+  snmf_status s = snmf_batch_warmstart(b, mlp ? 1 : 0, mlp, Omega, W0_out, stream);
+  std::string keep = err_ref();
+  snmf_batch_destroy(b);
+  err_ref() = keep;
+  return s;
 }
 
 }  // extern "C"

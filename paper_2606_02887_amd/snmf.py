@@ -44,7 +44,7 @@ class Params(ctypes.Structure):
                 ("max_ls", c_int32), ("inner_iters", c_int32), ("max_outer", c_int32),
                 ("check_every", c_int32), ("target_res", c_double), ("prec", c_int32),
                 ("accept_at_relaxed", c_int32), ("project_update", c_int32),
-                ("validate", c_int32), ("use_graph", c_int32), ("reserved", c_int32)]
+                ("validate", c_int32), ("use_graph", c_int32), ("check_symmetry", c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -70,7 +70,7 @@ EXPORTS = ("snmf_params_default", "snmf_solve", "snmf_plan_create", "snmf_plan_s
            "snmf_batch_create", "snmf_batch_solve", "snmf_batch_destroy", "snmf_solve_batched",
            "snmf_batch_apass", "snmf_batch_time_apass", "snmf_batch_size", "snmf_mlp_sync",
            "snmf_mlp_forward", "snmf_mlp_workspace_bytes", "snmf_mlp_train_step", "snmf_batch_frame",
-           "snmf_batch_targets", "snmf_batch_warmstart", "snmf_clock_rate_hz",
+           "snmf_batch_targets", "snmf_batch_warmstart", "snmf_warmstart", "snmf_clock_rate_hz",
            "snmf_last_error", "snmf_abi_version")
 
 
@@ -113,6 +113,7 @@ def load_library(path: str = LIB_PATH):
         "snmf_batch_frame": ([vp, vp, vp, vp, vp, vp], c_int32),
         "snmf_batch_targets": ([vp, vp, vp, vp, vp, vp], c_int32),
         "snmf_batch_warmstart": ([vp, c_int32, POINTER(MlpC), vp, vp, vp], c_int32),
+        "snmf_warmstart": ([POINTER(MlpC), POINTER(Matrix), c_int32, c_int32, vp, vp, vp], c_int32),
         "snmf_clock_rate_hz": ([], c_double),
         "snmf_last_error": ([], ctypes.c_char_p),
         "snmf_abi_version": ([], c_int32),
@@ -434,6 +435,17 @@ class Mlp:
 def solve(A: MatrixRef, W0, prm: Params, L: MatrixRef | None = None, trace: bool = True):
     with Plan(A, W0.shape[1], prm, L) as pl:
         return pl.solve(W0, trace=trace)
+
+
+def warmstart(A: MatrixRef, Omega, mlp: "Mlp | None" = None):
+    """The warm start of one problem (snmf_warmstart): W0 from the sketch matrix Omega
+    (n x r, float32 or float64) through the frame and, if given, the network."""
+    import torch
+    W0 = torch.empty_like(Omega)
+    _check(_lib.snmf_warmstart(ctypes.byref(mlp.desc) if mlp is not None else None,
+                               ctypes.byref(A.desc), Omega.shape[1], prec_of(Omega.dtype),
+                               _ptr(Omega), _ptr(W0), _stream()))
+    return W0
 
 
 def rho(G) -> float:

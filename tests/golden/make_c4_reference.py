@@ -1,0 +1,84 @@
+"""Writes c4_reference.json: the FP64 oracle's solve of every instance of the batched
+workload (256 SBM graphs, n ~ U[500, 5000], k = r in {8, 16, 32}, 8 random starts each,
+seed 1004 + g) for 20 outer iterations.  For each instance: whether the iteration broke
+down (a factor collapsed to zero, so rho = ||P^T P||_2 = 0 for the next half-step), the
+number of completed outer iterations, and the monitor record after the last of them; and
+the same from the start changed at rounding level (every entry of W0 times 1 + 2^-24 u,
+u = +-1 from default_rng(7919 g + s)), which measures how far that instance's iteration
+itself carries a rounding difference within 20 outer iterations.  Calls only the CPU
+reference and the seeded input generators.
+
+    python tests/golden/make_c4_reference.py [workers]
+"""
+import json
+import multiprocessing as mp
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+os.environ.setdefault("OPENBLAS_NUM_THREADS", "1")
+
+import numpy as np  # noqa: E402
+
+OUTER = 20
+_GRAPHS = None
+
+
+def _run(A, W0, lam):
+    import oracle as O
+    prm = O.Params(lam=lam)
+    W = np.array(W0, dtype=np.float64)
+    Ht = W.copy()
+    rec, done, broke = None, 0, False
+    for _ in range(OUTER):
+        try:
+            W = O.half_step(A, W, Ht, prm)
+            Ht = O.half_step(A, Ht, W, prm)
+        except FloatingPointError:
+            broke = True
+            break
+        done += 1
+        rec = O.monitor(A, W, Ht, prm)
+    out = {"breakdown": broke, "outer": done}
+    if rec is not None:
+        out.update({k: rec[k] for k in ("res_WH", "res_WWt", "pg", "sym_gap", "objective")})
+    return out
+
+
+def _solve(job):
+    g, s = job
+    gr = _GRAPHS[g]
+    A = gr["A"]
+    lam = 0.01 * float(np.sqrt(np.sum(np.asarray(A.data, dtype=np.float64) ** 2)))
+    W0 = np.asarray(gr["W0"][s], dtype=np.float64)
+    out = {"g": g, "s": s, "n": int(gr["n"]), "r": int(gr["r"])}
+    out.update(_run(A, W0, lam))
+    u = np.random.default_rng(7919 * g + s).choice([-1.0, 1.0], size=W0.shape)
+    out["perturbed"] = _run(A, W0 * (1.0 + 2.0 ** -24 * u), lam)
+    return out
+
+
+def _init():
+    global _GRAPHS
+    from paper_2606_02887_amd import gen
+    _GRAPHS = gen.config(4)
+
+
+def main(workers=4):
+    from paper_2606_02887_amd import gen
+    graphs = gen.config(4)
+    S = len(graphs[0]["W0"])
+    jobs = [(g, s) for g in range(len(graphs)) for s in range(S)]
+    with mp.Pool(workers, initializer=_init) as pool:
+        res = pool.map(_solve, jobs, chunksize=8)
+    out = {"workload": "256 SBM graphs, n ~ U[500,5000], k = r in {8,16,32}, 8 starts, seed 1004",
+           "outer": OUTER, "lambda": "0.01 ||A_g||_F per graph", "instances": res}
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "c4_reference.json")
+    with open(path, "w") as f:
+        json.dump(out, f)
+    print(path, sum(r["breakdown"] for r in res), "breakdowns")
+
+
+if __name__ == "__main__":
+    main(int(sys.argv[1]) if len(sys.argv) > 1 else 4)

@@ -10,6 +10,7 @@ import scipy.sparse as sp
 
 import oracle as O
 from paper_2606_02887_amd import gen
+from parity_util import comp_rel, nrel
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -24,13 +25,6 @@ def S():
 
 
 DEV = "cuda"
-
-
-def nrel(a, b):
-    a = np.asarray(a, dtype=np.float64)
-    b = np.asarray(b, dtype=np.float64)
-    den = np.linalg.norm(b)
-    return np.linalg.norm(a - b) / (den if den > 0 else 1.0)
 
 
 def _t(x, dtype):
@@ -83,7 +77,10 @@ def test_gram_and_dense_apass(S, n, r, prec):
     B = torch.empty_like(Pt)
     pl.apass(Pt, B)
     tol = 1e-12 if prec == "f64" else 1e-5
-    assert nrel(B.cpu().numpy(), O.apply_A(A_in, P_in)) <= tol
+    ref = O.apply_A(A_in, P_in)
+    assert nrel(B.cpu().numpy(), ref) <= tol
+    # A, P >= 0: every entry is a sum of nonnegative terms, |A||P| = A P
+    assert comp_rel(B.cpu().numpy(), ref, ref) <= tol
     pl.close()
 
 
@@ -99,9 +96,13 @@ def test_split_bf16_apass(S, n, r):
     pl = S.Plan(S.dense(At), r, S.params(prec=S.BF16X3, max_outer=1))
     B = torch.empty_like(Pt)
     pl.apass(Pt, B)
-    err = nrel(B.cpu().numpy(), O.apply_A(A_in, P_in))
+    ref = O.apply_A(A_in, P_in)
+    err = nrel(B.cpu().numpy(), ref)
     # three-product split: operands exact to ~2^-16 relative, FP32 accumulation
     assert err <= 2e-5, err
+    # entrywise: each operand's hi + lo is within 2^-17 of it, so every (nonnegative)
+    # term is within ~2^-16 of its value, plus the FP32 sum: 3e-5 of A P per entry
+    assert comp_rel(B.cpu().numpy(), ref, ref) <= 3e-5
     pl.close()
 
 
@@ -150,11 +151,14 @@ def test_csr_spmm(S, prec, r):
     ref = a_in @ X.double().cpu().numpy()
     tol = 1e-13 if prec == "f64" else 1e-6
     assert nrel(Y.cpu().numpy(), ref) <= tol
+    mag = abs(a_in) @ np.abs(X.double().cpu().numpy())
+    assert comp_rel(Y.cpu().numpy(), ref, mag) <= (1e-13 if prec == "f64" else 2e-6)
 
 
 # ------------------------------------------------------------------ LAI product
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-@pytest.mark.parametrize("n,ell,r", [(997, 16, 5), (20000, 74, 32), (5000, 128, 64)])
+@pytest.mark.parametrize("n,ell,r", [(997, 16, 5), (20000, 74, 32), (5000, 128, 64),
+                                    (70000, 16, 16)])
 def test_lai_apass(S, prec, n, ell, r):
     rng = np.random.default_rng(n + ell)
     U, _ = np.linalg.qr(rng.standard_normal((n, ell)))
@@ -170,4 +174,8 @@ def test_lai_apass(S, prec, n, ell, r):
     ref = O.apply_A(O.LowRank(Ut.double().cpu().numpy(), lam), Pt.double().cpu().numpy())
     tol = 1e-12 if prec == "f64" else 2e-6
     assert nrel(B.cpu().numpy(), ref) <= tol
+    # entrywise against |U| |lam| |U|^T |P| (U has mixed signs: the products cancel)
+    Ua = np.abs(Ut.double().cpu().numpy())
+    mag = Ua @ (np.abs(lam)[:, None] * (Ua.T @ np.abs(Pt.double().cpu().numpy())))
+    assert comp_rel(B.cpu().numpy(), ref, mag) <= (1e-13 if prec == "f64" else 2e-6)
     pl.close()

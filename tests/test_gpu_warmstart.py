@@ -208,10 +208,68 @@ def test_warmstart_error_codes(S):
             b.warmstart([S.Mlp(_rand_init(4, 1))], Om64)
         assert e.value.name == "E_UNSUPPORTED"
     A = torch.eye(40, dtype=torch.float32, device=DEV)
-    with S.Batch([S.dense(A)], [4], S.params(prec=S.F32), restarts=1) as b:
+    with S.Batch([S.dense(A)], [4], S.params(prec=S.BF16X3), restarts=1) as b:
         with pytest.raises(S.SnmfError) as e:
             b.frame(torch.ones(160, dtype=torch.float32, device=DEV))
         assert e.value.name == "E_UNSUPPORTED"
+    with pytest.raises(S.SnmfError) as e:                       # network rank != r
+        S.warmstart(S.dense(A), torch.ones((40, 4), dtype=torch.float32, device=DEV),
+                    S.Mlp(_rand_init(5, 1)))
+    assert e.value.name == "E_SHAPE"
+    with pytest.raises(S.SnmfError) as e:                       # network in F64
+        S.warmstart(S.dense(A.double()), torch.ones((40, 4), dtype=torch.float64, device=DEV),
+                    S.Mlp(_rand_init(4, 1)))
+    assert e.value.name == "E_UNSUPPORTED"
+
+
+def _single_problem(kind, dt, n=260, r=6, seed=5):
+    """A planted symmetric nonnegative problem, dense or as CSR (an SBM graph), with its
+    FP64 copy as the device holds it and a Gaussian sketch matrix."""
+    rng = np.random.default_rng(seed)
+    if kind == "dense":
+        W = rng.random((n, r))
+        a = W @ W.T
+        At = torch.from_numpy(a).to(DEV, dt)
+        ref = At.double().cpu().numpy()
+        M = S_mod().dense(At)
+    else:
+        adj, _ = gen.sbm_adjacency(n, r, 0.3, 0.02, rng)
+        a = gen.normalized_adjacency(adj)
+        M = S_mod().csr_from_scipy(a, dt)
+        ref = a.copy()
+        ref.data = M.keep[2].double().cpu().numpy()
+    Om = gen.sketch_matrix(n, r, 600 + seed)
+    return M, ref, torch.from_numpy(Om).to(DEV, dt)
+
+
+def S_mod():
+    from paper_2606_02887_amd import snmf
+    return snmf
+
+
+@pytest.mark.parametrize("kind", ["dense", "csr"])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_single_problem_frame_start_matches_oracle(S, kind, prec):
+    """snmf_warmstart without a network (the frame alone) for one dense or CSR problem:
+    the oracle's frame_start on the same inputs (anchors are integer decisions taken in
+    FP64 on both sides; the coordinates carry the FP32 sketch's rounding in F32)."""
+    M, ref, Om = _single_problem(kind, DT[prec])
+    W0 = S.warmstart(M, Om).double().cpu().numpy()
+    Wo, _, _ = WS.frame_start(ref, Om.double().cpu().numpy(), np.sqrt(O.norm2_A(ref)))
+    tol = 1e-10 if prec == "f64" else 2e-5
+    assert nrel(W0, Wo) <= tol, nrel(W0, Wo)
+    assert (W0 >= 0).all()
+
+
+@pytest.mark.parametrize("kind", ["dense", "csr"])
+def test_single_problem_learned_start_matches_oracle(S, kind):
+    M, ref, Om = _single_problem(kind, torch.float32, r=8, seed=9)
+    mlp = S.Mlp(_rand_init(8, 77))
+    W0 = S.warmstart(M, Om, mlp).double().cpu().numpy()
+    Wo, _, _ = WS.warm_start(mlp.params(), ref, Om.double().cpu().numpy(),
+                             np.sqrt(O.norm2_A(ref)))
+    assert nrel(W0, Wo) <= 2e-5, nrel(W0, Wo)
+    assert (W0 > 0).all()
 
 
 def test_warm_start_gain_on_detectable_graphs(S):

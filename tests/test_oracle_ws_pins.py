@@ -134,3 +134,19 @@ def test_softplus_and_scale():
         W[j * 25:(j + 1) * 25, j] = s * np.sqrt(n / 25)
     assert np.isclose(np.sqrt(np.mean(W * W)), s)
     assert np.isclose(np.linalg.norm(W @ W.T), normA)
+
+
+def test_frame_start_scale_and_sign():
+    """The frame-only start is nonnegative, zero exactly where the coordinate is negative,
+    and its entry RMS is the scale s = (sqrt(r) ||A||_F / (n r))^(1/2) (closed form)."""
+    rng = np.random.default_rng(77)
+    n, r = 120, 5
+    W = rng.random((n, r))
+    A = W @ W.T
+    Om = rng.standard_normal((n, r))
+    nA = float(np.linalg.norm(A))
+    W0, C, K = WS.frame_start(A, Om, nA)
+    s = np.sqrt(np.sqrt(r) * nA / (n * r))
+    assert (W0 >= 0).all()
+    assert np.array_equal(W0 == 0, C <= 0)
+    assert abs(np.sqrt(np.mean(W0 ** 2)) - s) <= 1e-13 * s
