@@ -17,8 +17,8 @@ Recipes (all seeds go through numpy's PCG64 ``default_rng``):
   K-nearest-neighbour graph over Gaussian node features with cluster-shifted means
   (the Laplacian of eq. (2.3) built over a feature graph).
 * a power-law CSR matrix (Chung-Lu-like sampling of row degrees with exponent 2.1).
-* the randomized range finder of Section 2.3 (sketch, thin QR, small symmetric
-  eigendecomposition) that turns a CSR matrix into the low-rank input ``U diag(lam) U^T``.
+* Gaussian sketch matrices (the random input of the range finder of Section 2.3 and of
+  the warm start; the range finder itself is method arithmetic and lives with the solver).
 * ``W0 = U[0,1] * sqrt(mean(A) / r)`` (Section 4.1 item (4) uses ``2*sqrt(mean/r)``;
   the workloads here use the factor 1).
 """
@@ -245,39 +245,16 @@ def powerlaw_csr(n: int = 200000, exponent: float = 2.1, mean_degree: float = 10
     return best
 
 
-def range_finder(a, rank: int, oversample: int, power_iters: int, seed: int):
-    """Randomized eigen-sketch of a symmetric matrix (Section 2.3 of the paper).
-
-    ``Y = A Omega`` with Gaussian ``Omega`` (n x (rank+oversample)), orthonormalised
-    by thin QR; each power iteration multiplies by A twice with a QR after every
-    product; then the small matrix ``Q^T A Q`` is diagonalised and the ``rank``
-    eigenpairs of largest magnitude are kept: ``U = Q P``, ``lam = E``.
-    Returns ``U`` (n x rank, float64, orthonormal columns) and ``lam`` (rank,).
-    """
-    rng = np.random.default_rng(seed)
-    n = a.shape[0]
-    ell = rank + oversample
-    omega = rng.standard_normal((n, ell))
-    q, _ = np.linalg.qr(a @ omega)
-    for _ in range(power_iters):
-        q, _ = np.linalg.qr(a @ q)
-        q, _ = np.linalg.qr(a @ q)
-    t = q.T @ (a @ q)
-    t = 0.5 * (t + t.T)
-    ev, p = np.linalg.eigh(t)
-    order = np.argsort(-np.abs(ev), kind="stable")[:rank]
-    u = q @ p[:, order]
-    return np.ascontiguousarray(u), ev[order].copy()
-
-
 def lai_problem(n: int = 200000, rank: int = 64, oversample: int = 10, power_iters: int = 2,
                 r: int = 32, seed: int = SEED_BASE + 3):
-    """Low-rank input workload: power-law CSR A, its sketch (U, lam) and W0."""
+    """Low-rank input workload: the power-law CSR A, the Gaussian sketch matrix Omega
+    (n x (rank + oversample)) from which the range finder builds the surrogate
+    U diag(lam) U^T, the sketch sizes, and W0."""
     a = powerlaw_csr(n=n, seed=seed)
-    u, lam = range_finder(a, rank, oversample, power_iters, seed + 17)
+    omega = sketch_matrix(n, rank + oversample, seed + 17)
     rng = np.random.default_rng(seed + 29)
     w0 = start_factor(rng, n, r, mean_of_sparse(a))
-    return {"A": a, "U": u, "lam": lam, "W0": w0}
+    return {"A": a, "Omega": omega, "rank": rank, "power_iters": power_iters, "W0": w0}
 
 
 # --------------------------------------------------------------------------- batches
@@ -320,7 +297,8 @@ def config(c: int, **over):
 
 # --------------------------------------------------------------------------- warm start
 def sketch_matrix(n: int, r: int, seed: int):
-    """Gaussian sketch Omega (n x r, float64) for the warm start's Y = A Omega."""
+    """Gaussian sketch matrix Omega (n x r, float64): the random input of Y = A Omega in
+    the range finder and the warm start."""
     return np.random.default_rng(seed).standard_normal((n, r))
 
 

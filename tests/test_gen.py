@@ -59,20 +59,6 @@ def test_powerlaw_mean_degree_and_symmetry():
     assert a.diagonal().sum() == 0
 
 
-def test_range_finder_orthonormal_and_near_optimal():
-    rng = np.random.default_rng(2)
-    n, k = 400, 10
-    w = rng.random((n, k))
-    A = sp.csr_matrix(w @ w.T + 0.01 * (lambda e: e + e.T)(rng.standard_normal((n, n))))
-    U, lam = gen.range_finder(A, k, 10, 2, 7)
-    assert np.abs(U.T @ U - np.eye(k)).max() < 1e-12
-    Ad = A.toarray()
-    ev = np.linalg.eigvalsh(Ad)
-    best = np.sqrt(np.sort(ev ** 2)[:-k].sum())
-    err = np.linalg.norm(Ad - (U * lam) @ U.T)
-    assert best <= err <= 1.05 * best
-
-
 def test_random_symmetric_csr_and_lowrank():
     a = gen.random_symmetric_csr(5000, 12.0, 7)
     assert a.shape == (5000, 5000) and abs(a.nnz / 5000 - 12.0) < 1.0

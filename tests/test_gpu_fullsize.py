@@ -124,7 +124,7 @@ def test_graph_n20000_r20_hstep(S):
 
 def test_lowrank_n200000_r32_half_step(S):
     q = gen.config(3)                                   # LAI n = 200000, ell = 64
-    U, lamv = q["U"], q["lam"]
+    U, lamv = O.range_finder(q["A"], q["rank"], q["power_iters"], q["Omega"])
     r = 32
     Ut = _t(U, torch.float32)
     lr_in = O.LowRank(Ut.double().cpu().numpy(), lamv)

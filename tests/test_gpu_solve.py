@@ -143,7 +143,7 @@ def test_half_step_lockstep_graph_laplacian(S, prec):
 def test_half_step_lockstep_lai(S, prec):
     n, ell, r = 3000, 24, 6
     a = gen.powerlaw_csr(n=n, seed=9)
-    U, lam_ = gen.range_finder(a, ell, 6, 2, 3)
+    U, lam_ = O.range_finder(a, ell, 2, gen.sketch_matrix(n, ell + 6, 3))
     rng = np.random.default_rng(4)
     X = rng.random((n, r)) * 0.05
     P = rng.random((n, r)) * 0.05
@@ -172,7 +172,7 @@ def test_half_step_lockstep_lai_large_arrays(S, prec, is_hstep):
     from 3000 to 70000), hence the bound of fp32_bounds."""
     n, ell, r = 70000, 16, 16
     a = gen.powerlaw_csr(n=n, seed=9)
-    U, lam_ = gen.range_finder(a, ell, 6, 2, 3)
+    U, lam_ = O.range_finder(a, ell, 2, gen.sketch_matrix(n, ell + 6, 3))
     rng = np.random.default_rng(6)
     X = rng.random((n, r)) * 0.05
     P = rng.random((n, r)) * 0.05
@@ -328,7 +328,7 @@ def test_whole_solve_graph(S):
 def test_whole_solve_lai(S):
     n = 5000
     a = gen.powerlaw_csr(n=n, seed=31)
-    U, lam_ = gen.range_finder(a, 32, 10, 2, 5)
+    U, lam_ = O.range_finder(a, 32, 2, gen.sketch_matrix(n, 42, 5))
     lr = O.LowRank(U, lam_)
     rng = np.random.default_rng(8)
     W0 = gen.start_factor(rng, n, 8, gen.mean_of_sparse(a))
