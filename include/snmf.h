@@ -191,6 +191,38 @@ snmf_status snmf_plan_time_apass(snmf_plan* plan, const void* P, int32_t reps, d
 snmf_status snmf_split_bf16(const float* x, int64_t count, uint16_t* hi, uint16_t* lo,
                             void* stream);
 
+/* ---------------------------------------------------------------- LAI sketch, SVD start
+ * The randomized range finder that builds the low-rank surrogate A ~= U diag(lam) U^T of
+ * LAI-SNMPBB (Section 2.3: a random sketch A S = Q R, Q^T A Q = P E P^T, U = Q P).  The
+ * paper leaves the sketch open; this library takes S = Omega, a Gaussian n x ell matrix
+ * with ell = rank + oversample drawn by the caller, and power_iters rounds of subspace
+ * iteration with an orthonormalisation after every product:
+ *   Y = A Omega, Q = orth(Y); power_iters times { Q = orth(A Q), Q = orth(A Q) };
+ *   T = Q^T A Q = P E P^T; the rank eigenpairs of largest |E| (ties: lower index first):
+ *   U = Q P_rank (n x rank, orthonormal columns), lam = E_rank (decreasing |lam|).
+ * orth() is a shifted Cholesky QR followed by two plain ones, the Gram products in FP64;
+ * the small eigenproblem is solved by Jacobi rotations in FP64.  All on the device.
+ * A: dense (read in place; symmetry is the caller's promise) or CSR (structure and
+ *    symmetry checked: E_SHAPE, E_NOT_SYMMETRIC); LOWRANK: E_UNSUPPORTED.
+ * prec: SNMF_F32 or SNMF_F64, the type of A's values, Omega and U_out.
+ * Omega: n x (rank + oversample) device array; U_out: n x rank device array; lam_out:
+ *    rank doubles (device).  1 <= rank, 0 <= oversample, rank + oversample <= min(128, n),
+ *    0 <= power_iters <= 16 (else E_SHAPE / E_ARG).  E_BREAKDOWN if the sketch has lost
+ *    rank beyond what the shifted factorisation absorbs.  Scratch memory is allocated and
+ *    freed inside the call; the stream is synchronised before it returns. */
+snmf_status snmf_lai_sketch(const snmf_matrix* A, int32_t rank, int32_t oversample,
+                            int32_t power_iters, int32_t prec, const void* Omega, void* U_out,
+                            double* lam_out, void* stream);
+/* The SVD-based start of the numerical experiments (Section 4.2): with the leading r
+ * singular triplets A ~= U E V^T, W0 = |U E^(1/2)| (and H0 = |E^(1/2) V^T|, which for a
+ * symmetric A is W0^T: the singular triplets are eigenpairs, E = |lam|, V = U sign(lam)).
+ * The triplets come from the range finder above with rank = r; W0_out is n x r (device,
+ * of the precision's type), ready to be passed as W0 to snmf_solve.  Omega is
+ * n x (r + oversample).  Errors as snmf_lai_sketch, and E_SHAPE for r > 64. */
+snmf_status snmf_svd_start(const snmf_matrix* A, int32_t r, int32_t oversample,
+                           int32_t power_iters, int32_t prec, const void* Omega, void* W0_out,
+                           void* stream);
+
 /* ---------------------------------------------------------------- batched solves
  * The batching form: many independent SNMPBB solves (problem g, restart s) run together,
  * every kernel of a half-step covering all of them in one launch (one per distinct rank

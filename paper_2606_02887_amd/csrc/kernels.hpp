@@ -164,4 +164,25 @@ void launch_reset_state(State* st, double normA2, hipStream_t s);
 void launch_split_flat(const float* x, int64_t count, uint16_t* hi, uint16_t* lo, hipStream_t s);
 
 
+
+// ---- range finder and SVD start (k_sketch.hip)
+template <typename T>
+void launch_sketch_spmm(const int64_t* rowptr, const int32_t* col, const T* val, const T* X,
+                        int64_t n, int w, T* Y, hipStream_t s);
+template <typename T>
+void launch_sketch_dense(const T* A, int64_t ld, const T* X, int64_t n, int w, T* Y,
+                         hipStream_t s);
+int sketch_slabs(int64_t n, int64_t* rows_per);
+template <typename T>
+void launch_tsgram(const T* X, const T* Y, int64_t n, int w, double* part, double* C,
+                   hipStream_t s);
+void launch_chol_inv(const double* G, int w, double shift_rel, double* R, double* Rinv,
+                     int32_t* flag, hipStream_t s);
+template <typename T>
+void launch_tsmm(const T* Y, int64_t n, int w, const double* M, int c, int absval, T* Q,
+                 hipStream_t s);
+void launch_jacobi(const double* Tin, int w, double* A, double* V, double* ev, hipStream_t s);
+void launch_sketch_select(const double* ev, const double* V, int w, int k, int sqrt_scale,
+                          double* lam, double* M, hipStream_t s);
+
 }  // namespace snmf

@@ -70,7 +70,8 @@ EXPORTS = ("snmf_params_default", "snmf_solve", "snmf_plan_create", "snmf_plan_s
            "snmf_batch_create", "snmf_batch_solve", "snmf_batch_destroy", "snmf_solve_batched",
            "snmf_batch_apass", "snmf_batch_time_apass", "snmf_batch_size", "snmf_mlp_sync",
            "snmf_mlp_forward", "snmf_mlp_workspace_bytes", "snmf_mlp_train_step", "snmf_batch_frame",
-           "snmf_batch_targets", "snmf_batch_warmstart", "snmf_warmstart", "snmf_clock_rate_hz",
+           "snmf_batch_targets", "snmf_batch_warmstart", "snmf_warmstart", "snmf_lai_sketch",
+           "snmf_svd_start", "snmf_clock_rate_hz",
            "snmf_last_error", "snmf_abi_version")
 
 
@@ -114,6 +115,10 @@ def load_library(path: str = LIB_PATH):
         "snmf_batch_targets": ([vp, vp, vp, vp, vp, vp], c_int32),
         "snmf_batch_warmstart": ([vp, c_int32, POINTER(MlpC), vp, vp, vp], c_int32),
         "snmf_warmstart": ([POINTER(MlpC), POINTER(Matrix), c_int32, c_int32, vp, vp, vp], c_int32),
+        "snmf_lai_sketch": ([POINTER(Matrix), c_int32, c_int32, c_int32, c_int32, vp, vp, vp, vp],
+                            c_int32),
+        "snmf_svd_start": ([POINTER(Matrix), c_int32, c_int32, c_int32, c_int32, vp, vp, vp],
+                           c_int32),
         "snmf_clock_rate_hz": ([], c_double),
         "snmf_last_error": ([], ctypes.c_char_p),
         "snmf_abi_version": ([], c_int32),
@@ -445,6 +450,28 @@ def warmstart(A: MatrixRef, Omega, mlp: "Mlp | None" = None):
     _check(_lib.snmf_warmstart(ctypes.byref(mlp.desc) if mlp is not None else None,
                                ctypes.byref(A.desc), Omega.shape[1], prec_of(Omega.dtype),
                                _ptr(Omega), _ptr(W0), _stream()))
+    return W0
+
+
+def lai_sketch(A: MatrixRef, rank: int, power_iters: int, Omega):
+    """Range finder (snmf_lai_sketch): U (n x rank) and lam (rank, float64) from the
+    Gaussian sketch matrix Omega (n x (rank + oversample), float32 or float64)."""
+    import torch
+    U = torch.empty((Omega.shape[0], rank), dtype=Omega.dtype, device=Omega.device)
+    lam = torch.empty(rank, dtype=torch.float64, device=Omega.device)
+    _check(_lib.snmf_lai_sketch(ctypes.byref(A.desc), int(rank), Omega.shape[1] - int(rank),
+                                int(power_iters), prec_of(Omega.dtype), _ptr(Omega), _ptr(U),
+                                _ptr(lam), _stream()))
+    return U, lam
+
+
+def svd_start(A: MatrixRef, r: int, power_iters: int, Omega):
+    """SVD-based start W0 = |U E^(1/2)| (snmf_svd_start); Omega is n x (r + oversample)."""
+    import torch
+    W0 = torch.empty((Omega.shape[0], r), dtype=Omega.dtype, device=Omega.device)
+    _check(_lib.snmf_svd_start(ctypes.byref(A.desc), int(r), Omega.shape[1] - int(r),
+                               int(power_iters), prec_of(Omega.dtype), _ptr(Omega), _ptr(W0),
+                               _stream()))
     return W0
 
 
