@@ -158,3 +158,28 @@ def test_dense_n8192_batched8_bf16x3_stacked_apass(S, dense_c1):
         err = nrel(Bn[s], A_in @ Pn[s])
         print(f"batched8 bf16x3 restart {s}: nrel {err:.3e}")
         assert err <= 3e-5, (s, err)
+
+
+def test_lowrank_n200000_device_sketch(S):
+    """The surrogate of the LAI workload built on the device (snmf_lai_sketch: the
+    power-law graph n = 200000, rank 64 + 10, two power iterations, FP32) against the
+    oracle's range finder from the same Omega: eigenvalues within 1e-5 of |lam_1| and the
+    subspaces within a sine of 1e-5 (as far as the oracle's own gap between the 64th and
+    65th Ritz values allows: Davis-Kahan with 100 x 2^-24 |lam_1| / gap)."""
+    q = gen.config(3)
+    M = S.csr_from_scipy(q["A"], torch.float32)
+    Om = _t(q["Omega"], torch.float32)
+    U, lam = S.lai_sketch(M, q["rank"], q["power_iters"], Om)
+    ref = q["A"].copy().astype(np.float64)
+    ref.data = M.keep[2].double().cpu().numpy()
+    om = Om.double().cpu().numpy()
+    Uo, lo = O.range_finder(ref, q["rank"], q["power_iters"], om)
+    _, ritz = O.range_finder(ref, om.shape[1], q["power_iters"], om)
+    Ug, lg = U.double().cpu().numpy(), lam.cpu().numpy()
+    lerr = np.abs(lg - lo).max() / abs(lo[0])
+    ang = float(np.linalg.norm(Ug - Uo @ (Uo.T @ Ug), 2))
+    gap = abs(ritz[q["rank"] - 1]) - abs(ritz[q["rank"]])
+    bound = max(1e-5, 100 * 2.0 ** -24 * abs(ritz[0]) / gap)
+    print(f"device sketch n=200000: eigenvalues {lerr:.2e}, sin angle {ang:.2e} (bound {bound:.1e})")
+    assert lerr <= 1e-5
+    assert ang <= bound
