@@ -149,6 +149,22 @@ snmf_status snmf_params_default(snmf_params* p);
 snmf_status snmf_solve(const snmf_matrix* A, int32_t r, const void* W0, const snmf_params* p,
                        void* W_out, void* Ht_out, snmf_info* info, void* stream, double* trace);
 
+/* snmf_solve without any allocation, for callers that cannot allocate device memory
+ * (serving loops and harnesses that forbid hipMalloc): the same computation as
+ * snmf_solve with use_graph = 0 (direct launches; instantiating a graph allocates), with
+ * its scratch in the library's static device array of 64 MiB per GPU (held from the
+ * first use of the library on a device until the process ends), work on the caller's
+ * stream, and no host heap allocation on success.  Limits: F64 or F32 (BF16X3:
+ * E_UNSUPPORTED, its split copies of A would not fit); the scratch the problem needs must
+ * fit 64 MiB (about 6 n r element sizes plus, for dense F32, the split-K partial panels;
+ * dense n = 8192, r = 64 in F32 needs 31 MiB), else E_SHAPE with the size in the message.
+ * Every call on a GPU shares that GPU's array, and the library clears what must start at
+ * zero on each call: calls that overlap on one GPU (several host threads, or streams that
+ * run concurrently) race and must not be issued.  The call synchronises the stream. */
+snmf_status snmf_solve_noalloc(const snmf_matrix* A, int32_t r, const void* W0,
+                               const snmf_params* p, void* W_out, void* Ht_out, snmf_info* info,
+                               void* stream, double* trace);
+
 /* Plans: the same solve with scratch memory and input preprocessing (||A||^2, validation,
  * the BF16 split) kept across calls, for repeated timed solves.  A plan keeps the
  * pointers of A and L given at creation; they must stay valid until destroy. */

@@ -15,6 +15,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -64,12 +65,16 @@ struct snmf_plan {
   // run saves the per-launch gap between outer iterations)
   hipGraph_t graph = nullptr, graph_run = nullptr;
   hipGraphExec_t gexec = nullptr, gexec_run = nullptr;
+  // the allocation-free solve: pool is the library's static scratch and s the caller's
+  // stream, neither owned by the plan
+  bool borrowed = false;
 
   ~snmf_plan() {
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (graph) (void)hipGraphDestroy(graph);
     if (gexec_run) (void)hipGraphExecDestroy(gexec_run);
     if (graph_run) (void)hipGraphDestroy(graph_run);
+    if (borrowed) return;
     if (pool) (void)hipFree(pool);
     if (ev_in) (void)hipEventDestroy(ev_in);
     if (ev_out) (void)hipEventDestroy(ev_out);
@@ -393,10 +398,10 @@ snmf_status build_kparams(snmf_plan* pl) {
   return SNMF_OK;
 }
 
-snmf_status plan_create(const snmf_matrix* A, int32_t r, const snmf_params* p, hipStream_t user,
-                        snmf_plan** out) {
-  if (!out) return fail(SNMF_E_ARG, "out is NULL");
-  *out = nullptr;
+// Sets up plan pl: checks, scratch (hipMalloc, or the caller's fixed pool of fixed_bytes,
+// in which case the plan runs on the user stream and owns nothing), ||A||^2, the split.
+snmf_status plan_init(snmf_plan* pl, const snmf_matrix* A, int32_t r, const snmf_params* p,
+                      hipStream_t user, void* fixed_pool, size_t fixed_bytes) {
   SNMF_TRY(check_params(p));
   SNMF_TRY(check_matrix(A, "A"));
   if (r < 1 || r > kMaxRank) return fail(SNMF_E_SHAPE, "r must lie in [1, 64]");
@@ -409,9 +414,6 @@ snmf_status plan_create(const snmf_matrix* A, int32_t r, const snmf_params* p, h
   }
   if (p->prec == SNMF_BF16X3 && A->fmt != SNMF_DENSE)
     return fail(SNMF_E_UNSUPPORTED, "BF16X3 applies to dense A only");
-  auto pl = new (std::nothrow) snmf_plan();
-  if (!pl) return fail(SNMF_E_OOM, "host allocation failed");
-  std::unique_ptr<snmf_plan> guard(pl);
   pl->A = *A;
   if (lap) pl->L = *p->L;
   pl->p = *p;
@@ -420,12 +422,18 @@ snmf_status plan_create(const snmf_matrix* A, int32_t r, const snmf_params* p, h
   pl->n = A->n;
   pl->prec = p->prec;
   pl->esz = elt_size(p->prec);
-  HIP_TRY(hipStreamCreateWithFlags(&pl->s, hipStreamNonBlocking));
-  HIP_TRY(hipEventCreateWithFlags(&pl->ev_in, hipEventDisableTiming));
-  HIP_TRY(hipEventCreateWithFlags(&pl->ev_out, hipEventDisableTiming));
-  if (user) {
-    HIP_TRY(hipEventRecord(pl->ev_in, user));
-    HIP_TRY(hipStreamWaitEvent(pl->s, pl->ev_in, 0));
+  if (fixed_pool) {
+    pl->borrowed = true;
+    pl->s = user;
+    pl->p.use_graph = 0;  // instantiating a graph allocates
+  } else {
+    HIP_TRY(hipStreamCreateWithFlags(&pl->s, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&pl->ev_in, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&pl->ev_out, hipEventDisableTiming));
+    if (user) {
+      HIP_TRY(hipEventRecord(pl->ev_in, user));
+      HIP_TRY(hipStreamWaitEvent(pl->s, pl->ev_in, 0));
+    }
   }
   const int64_t n = pl->n;
   const size_t nr = (size_t)n * r * pl->esz;
@@ -438,9 +446,11 @@ snmf_status plan_create(const snmf_matrix* A, int32_t r, const snmf_params* p, h
   if (A->fmt == SNMF_DENSE && pl->prec != SNMF_F64) ksplit = pl->ds.ksplit;
   pl->gram_blocks = gram_blocks(n);
   const int lai_nb = lai_blocks(n);
-  // carve one allocation
-  std::vector<std::pair<void**, size_t>> req;
-  auto add = [&](void** dst, size_t bytes) { req.push_back({dst, (bytes + 255) / 256 * 256}); };
+  // carve one allocation (a fixed table: the allocation-free path allocates nothing on the
+  // host either)
+  std::pair<void**, size_t> req[40];
+  int nreq = 0;
+  auto add = [&](void** dst, size_t bytes) { req[nreq++] = {dst, (bytes + 255) / 256 * 256}; };
   add(&pl->Wb, nr);
   add(&pl->Hb, nr);
   add(&pl->C, nr);
@@ -478,12 +488,20 @@ snmf_status plan_create(const snmf_matrix* A, int32_t r, const snmf_params* p, h
     add((void**)&pl->Ptlo, (size_t)r * pl->ldb * 2);
   }
   size_t total = 0;
-  for (auto& q : req) total += q.second;
-  HIP_TRY(hipMalloc(&pl->pool, total));
+  for (int q = 0; q < nreq; ++q) total += req[q].second;
+  if (fixed_pool) {
+    if (total > fixed_bytes)
+      return fail(SNMF_E_SHAPE, "the solve needs " + std::to_string(total) +
+                                    " bytes of scratch, more than the " +
+                                    std::to_string(fixed_bytes) + " of the static array");
+    pl->pool = fixed_pool;
+  } else {
+    HIP_TRY(hipMalloc(&pl->pool, total));
+  }
   size_t off = 0;
-  for (auto& q : req) {
-    *q.first = (char*)pl->pool + off;
-    off += q.second;
+  for (int q = 0; q < nreq; ++q) {
+    *req[q].first = (char*)pl->pool + off;
+    off += req[q].second;
   }
   HIP_TRY(hipMemsetAsync(pl->counters, 0, C_COUNT * sizeof(unsigned), pl->s));
   HIP_TRY(hipMemsetAsync(pl->st, 0, sizeof(State), pl->s));
@@ -497,11 +515,12 @@ snmf_status plan_create(const snmf_matrix* A, int32_t r, const snmf_params* p, h
   } else if (A->fmt == SNMF_CSR) {
     SNMF_TRY(check_csr(pl, A, "A", p->validate != 0, &pl->normA2));
   } else {
-    std::vector<double> lam(A->ell);
-    HIP_TRY(hipMemcpyAsync(lam.data(), A->lam, A->ell * 8, hipMemcpyDeviceToHost, pl->s));
+    double lam[kMaxEll];
+    HIP_TRY(hipMemcpyAsync(lam, A->lam, A->ell * 8, hipMemcpyDeviceToHost, pl->s));
     HIP_TRY(hipStreamSynchronize(pl->s));
     double s2 = 0.0;
-    for (double v : lam) {
+    for (int64_t a = 0; a < A->ell; ++a) {
+      const double v = lam[a];
       if (!std::isfinite(v)) return fail(SNMF_E_NONFINITE, "lam has NaN/Inf entries");
       s2 += v * v;
     }
@@ -519,6 +538,17 @@ snmf_status plan_create(const snmf_matrix* A, int32_t r, const snmf_params* p, h
   }
   SNMF_TRY(build_kparams(pl));
   HIP_TRY(hipStreamSynchronize(pl->s));
+  return SNMF_OK;
+}
+
+snmf_status plan_create(const snmf_matrix* A, int32_t r, const snmf_params* p, hipStream_t user,
+                        snmf_plan** out) {
+  if (!out) return fail(SNMF_E_ARG, "out is NULL");
+  *out = nullptr;
+  auto pl = new (std::nothrow) snmf_plan();
+  if (!pl) return fail(SNMF_E_OOM, "host allocation failed");
+  std::unique_ptr<snmf_plan> guard(pl);
+  SNMF_TRY(plan_init(pl, A, r, p, user, nullptr, 0));
   *out = guard.release();
   return SNMF_OK;
 }
@@ -528,12 +558,19 @@ snmf_status read_info(snmf_plan* pl, snmf_info* info, double* trace) {
   HIP_TRY(hipMemcpyAsync(&hs, pl->st, sizeof(State), hipMemcpyDeviceToHost, pl->s));
   HIP_TRY(hipStreamSynchronize(pl->s));
   const double hz = snmf_clock_rate_hz();
-  std::vector<double> tr;
+  // the clock ticks of the last record and of the record that met the target
+  double ticks_last = 0.0, ticks_conv = 0.0;
   if (hs.trace_len > 0) {
-    tr.resize((size_t)hs.trace_len * kTraceFields);
-    HIP_TRY(hipMemcpyAsync(tr.data(), pl->trace, tr.size() * 8, hipMemcpyDeviceToHost, pl->s));
+    if (trace)
+      HIP_TRY(hipMemcpyAsync(trace, pl->trace, (size_t)hs.trace_len * kTraceFields * 8,
+                             hipMemcpyDeviceToHost, pl->s));
+    HIP_TRY(hipMemcpyAsync(&ticks_last, pl->trace + (size_t)(hs.trace_len - 1) * kTraceFields + 5,
+                           8, hipMemcpyDeviceToHost, pl->s));
+    if (hs.converged_at > 0)
+      HIP_TRY(hipMemcpyAsync(&ticks_conv,
+                             pl->trace + (size_t)(hs.converged_at - 1) * kTraceFields + 5, 8,
+                             hipMemcpyDeviceToHost, pl->s));
     HIP_TRY(hipStreamSynchronize(pl->s));
-    if (trace) std::memcpy(trace, tr.data(), tr.size() * 8);
   }
   if (info) {
     std::memset(info, 0, sizeof(*info));
@@ -549,9 +586,8 @@ snmf_status read_info(snmf_plan* pl, snmf_info* info, double* trace) {
     info->pg_norm = hs.pg_last;
     info->objective = hs.f_last;
     info->normA2 = pl->normA2;
-    info->seconds = hs.trace_len > 0 ? tr[(size_t)(hs.trace_len - 1) * kTraceFields + 5] / hz : 0.0;
-    info->seconds_to_target =
-        hs.converged_at > 0 ? tr[(size_t)(hs.converged_at - 1) * kTraceFields + 5] / hz : -1.0;
+    info->seconds = hs.trace_len > 0 ? ticks_last / hz : 0.0;
+    info->seconds_to_target = hs.converged_at > 0 ? ticks_conv / hz : -1.0;
   }
   if (hs.status != 0) return fail((snmf_status)hs.status, "numeric breakdown during the solve");
   return SNMF_OK;
@@ -564,6 +600,7 @@ snmf_status plan_solve(snmf_plan* pl, const void* W0, void* W_out, void* Ht_out,
   const int64_t n = pl->n;
   const int r = pl->r;
   const size_t nr = (size_t)n * r * pl->esz;
+  if (pl->borrowed) user = nullptr;  // the plan already runs on the caller's stream
   if (user) {
     HIP_TRY(hipEventRecord(pl->ev_in, user));
     HIP_TRY(hipStreamWaitEvent(pl->s, pl->ev_in, 0));
@@ -630,10 +667,48 @@ snmf_status plan_solve(snmf_plan* pl, const void* W0, void* W_out, void* Ht_out,
   return rs;
 }
 
+// ------------------------------------------------------------------ allocation-free solve
+// The scratch of snmf_solve_noalloc: a file-scope device array (each GPU the library runs
+// on holds its own copy until the process ends).  Host code uses its address from
+// hipGetSymbolAddress, taken once per device, never the array's name.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+snmf_status scratch_address(void** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(SNMF_E_DEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(SNMF_E_DEVICE, "no device address for the static scratch");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return SNMF_OK;
+}
+
 }  // namespace
 
 // ================================================================== C ABI
 extern "C" {
+
+snmf_status snmf_solve_noalloc(const snmf_matrix* A, int32_t r, const void* W0,
+                               const snmf_params* p, void* W_out, void* Ht_out, snmf_info* info,
+                               void* stream, double* trace) {
+  if (!p) return fail(SNMF_E_ARG, "params is NULL");
+  if (p->prec == SNMF_BF16X3)
+    return fail(SNMF_E_UNSUPPORTED, "the split copies of A do not fit the static scratch");
+  void* sp = nullptr;
+  SNMF_TRY(scratch_address(&sp));
+  snmf_plan pl;
+  SNMF_TRY(plan_init(&pl, A, r, p, (hipStream_t)stream, sp, kScratchBytes));
+  return plan_solve(&pl, W0, W_out, Ht_out, info, (hipStream_t)stream, trace);
+}
 
 snmf_status snmf_params_default(snmf_params* p) {
   if (!p) return fail(SNMF_E_ARG, "params is NULL");

@@ -64,7 +64,8 @@ class MlpC(ctypes.Structure):
                 ("adam_m", c_void_p), ("adam_v", c_void_p)]
 
 
-EXPORTS = ("snmf_params_default", "snmf_solve", "snmf_plan_create", "snmf_plan_solve",
+EXPORTS = ("snmf_params_default", "snmf_solve", "snmf_solve_noalloc", "snmf_plan_create",
+           "snmf_plan_solve",
            "snmf_plan_destroy", "snmf_plan_half_step", "snmf_plan_apass", "snmf_plan_gram",
            "snmf_plan_time_apass", "snmf_rho", "snmf_spmm", "snmf_split_bf16",
            "snmf_batch_create", "snmf_batch_solve", "snmf_batch_destroy", "snmf_solve_batched",
@@ -84,6 +85,8 @@ def load_library(path: str = LIB_PATH):
         "snmf_params_default": ([POINTER(Params)], c_int32),
         "snmf_solve": ([POINTER(Matrix), c_int32, vp, POINTER(Params), vp, vp, POINTER(Info), vp,
                         POINTER(c_double)], c_int32),
+        "snmf_solve_noalloc": ([POINTER(Matrix), c_int32, vp, POINTER(Params), vp, vp,
+                                POINTER(Info), vp, POINTER(c_double)], c_int32),
         "snmf_plan_create": ([POINTER(Matrix), c_int32, POINTER(Params), vp, POINTER(vp)], c_int32),
         "snmf_plan_solve": ([vp, vp, vp, vp, POINTER(Info), vp, POINTER(c_double)], c_int32),
         "snmf_plan_destroy": ([vp], c_int32),
@@ -440,6 +443,26 @@ class Mlp:
 def solve(A: MatrixRef, W0, prm: Params, L: MatrixRef | None = None, trace: bool = True):
     with Plan(A, W0.shape[1], prm, L) as pl:
         return pl.solve(W0, trace=trace)
+
+
+def solve_noalloc(A: MatrixRef, W0, prm: Params, L: MatrixRef | None = None, W_out=None,
+                  Ht_out=None, trace: bool = True):
+    """snmf_solve_noalloc: the solve with the library's static scratch (no allocation in
+    the library; the outputs are the caller's)."""
+    import torch
+    if L is not None:
+        prm.L = ctypes.pointer(L.desc)
+    W_out = torch.empty_like(W0) if W_out is None else W_out
+    Ht_out = torch.empty_like(W0) if Ht_out is None else Ht_out
+    info = Info()
+    tr = (c_double * (prm.max_outer * TRACE_FIELDS))() if trace else None
+    _check(_lib.snmf_solve_noalloc(ctypes.byref(A.desc), W0.shape[1], _ptr(W0), ctypes.byref(prm),
+                                   _ptr(W_out), _ptr(Ht_out), ctypes.byref(info), _stream(), tr))
+    out = info.as_dict()
+    if trace:
+        arr = np.frombuffer(tr, dtype=np.float64).reshape(prm.max_outer, TRACE_FIELDS)
+        out["trace"] = arr[: info.outer].copy()
+    return W_out, Ht_out, out
 
 
 def warmstart(A: MatrixRef, Omega, mlp: "Mlp | None" = None):
