@@ -7,3 +7,4 @@ from .snmpbb import (Params, LowRank, HalfStep, apply_A, norm2_A, spectral_norm_
                      objective_direct, nmpbb, half_step, residual_WH, pg_norm, monitor,
                      snmpbb, default_lambda)
 from .lai import range_finder, svd_start  # noqa: E402,F401
+from .graph import knn, similarity, normalized_laplacian, knn_laplacian  # noqa: E402,F401

@@ -1,8 +1,7 @@
 """Seeded synthetic inputs for the SNMPBB workloads.
 
-This module builds inputs only: the symmetric nonnegative matrix A (dense, CSR or
-low-rank U diag(lam) U^T), the graph Laplacian L, cluster labels and the starting
-factor W0.  It contains none of the solver's arithmetic, so both the HIP path and the
+This module builds inputs only: the symmetric nonnegative matrix A (dense or CSR), node
+features, cluster labels, Gaussian sketch matrices and the starting factor W0.  It contains none of the solver's arithmetic, so both the HIP path and the
 CPU reference consume identical bytes from it without sharing any solver code.
 
 Recipes (all seeds go through numpy's PCG64 ``default_rng``):
@@ -13,9 +12,8 @@ Recipes (all seeds go through numpy's PCG64 ``default_rng``):
   the synthetic experiment of the paper's Section 4 (there ``V = W W^T`` without noise).
 * stochastic block model graphs with equal clusters, normalised as
   ``D^{-1/2} Adj D^{-1/2}`` (isolated nodes get a zero scale).
-* a normalised Laplacian ``I - D^{-1/2} K D^{-1/2}`` of the symmetrised, unweighted
-  K-nearest-neighbour graph over Gaussian node features with cluster-shifted means
-  (the Laplacian of eq. (2.3) built over a feature graph).
+* Gaussian node features with cluster-shifted means, over which the graph workload's
+  K-nearest-neighbour Laplacian (eq. (2.3)) is built by the method's preprocessing.
 * a power-law CSR matrix (Chung-Lu-like sampling of row degrees with exponent 2.1).
 * Gaussian sketch matrices (the random input of the range finder of Section 2.3 and of
   the warm start; the range finder itself is method arithmetic and lives with the solver).
@@ -149,31 +147,6 @@ def normalized_adjacency(adj: sp.csr_matrix) -> sp.csr_matrix:
     return out
 
 
-def knn_laplacian(x: np.ndarray, knn: int) -> sp.csr_matrix:
-    """Normalised Laplacian ``I - D^{-1/2} K D^{-1/2}`` of the symmetrised (union),
-    unweighted ``knn``-nearest-neighbour graph over the rows of ``x`` (Euclidean)."""
-    from scipy.spatial import cKDTree
-
-    n = x.shape[0]
-    tree = cKDTree(x)
-    _, nb = tree.query(x, k=knn + 1)
-    rows = np.repeat(np.arange(n), knn)
-    cols = nb[:, 1:].reshape(-1)
-    keep = rows != cols
-    rows, cols = rows[keep], cols[keep]
-    k = sp.coo_matrix((np.ones(rows.size), (rows, cols)), shape=(n, n)).tocsr()
-    k = k + k.T
-    k.data[:] = 1.0
-    d = np.asarray(k.sum(axis=1)).ravel()
-    s = np.zeros_like(d)
-    s[d > 0] = 1.0 / np.sqrt(d[d > 0])
-    lap = sp.identity(n, format="csr") - sp.diags(s) @ k @ sp.diags(s)
-    lap = sp.csr_matrix(lap)
-    lap.sum_duplicates()
-    lap.sort_indices()
-    return lap
-
-
 def cluster_features(labels: np.ndarray, k: int, dim: int, rng, spread: float = 2.0):
     """Gaussian node features ``x_i ~ N(mu_{c(i)}, I)`` with ``mu_c ~ N(0, spread^2 I)``."""
     mu = rng.standard_normal((k, dim)) * spread
@@ -182,17 +155,15 @@ def cluster_features(labels: np.ndarray, k: int, dim: int, rng, spread: float = 
 
 def sbm_problem(n: int = 20000, k: int = 20, r: int = 20, p_in: float = 0.02,
                 p_out: float = 0.0005, seed: int = SEED_BASE + 2, knn: int = 10,
-                feat_dim: int = 16, with_laplacian: bool = True):
-    """Graph workload: normalised SBM adjacency, optional kNN-feature Laplacian, W0."""
+                feat_dim: int = 16):
+    """Graph workload: normalised SBM adjacency, the node features over which the
+    K-nearest-neighbour Laplacian is built (K = ``knn``), labels and W0."""
     rng = np.random.default_rng(seed)
     adj, labels = sbm_adjacency(n, k, p_in, p_out, rng)
     a = normalized_adjacency(adj)
-    lap = None
-    if with_laplacian:
-        x = cluster_features(labels, k, feat_dim, rng)
-        lap = knn_laplacian(x, knn)
+    x = cluster_features(labels, k, feat_dim, rng)
     w0 = start_factor(rng, n, r, mean_of_sparse(a))
-    return {"A": a, "L": lap, "labels": labels, "W0": w0, "k": k}
+    return {"A": a, "X": x, "knn": knn, "labels": labels, "W0": w0, "k": k}
 
 
 # --------------------------------------------------------------------------- power law

@@ -41,16 +41,6 @@ def test_tri_unrank_enumerates_all_pairs():
     assert list(zip(i.tolist(), j.tolist())) == ref
 
 
-def test_knn_laplacian_is_normalised_laplacian():
-    rng = np.random.default_rng(1)
-    x = rng.standard_normal((200, 3))
-    L = gen.knn_laplacian(x, 5)
-    Ld = L.toarray()
-    assert np.allclose(Ld, Ld.T) and np.allclose(np.diag(Ld), 1.0)
-    ev = np.linalg.eigvalsh(Ld)
-    assert ev.min() > -1e-12 and ev.max() < 2 + 1e-12
-
-
 def test_powerlaw_mean_degree_and_symmetry():
     a = gen.powerlaw_csr(n=20000, seed=5)
     assert abs(a.nnz / a.shape[0] - 10) <= 0.2 + 1e-9

@@ -123,7 +123,7 @@ def test_half_step_lockstep_dense(S, prec, is_hstep, n, r):
 def test_half_step_lockstep_graph_laplacian(S, prec):
     """H-step of Graph-SNMPBB: gradient term gam L Ht and the <D, L D> curvature."""
     p = gen.sbm_problem(n=600, k=4, r=4, p_in=0.1, p_out=0.01, seed=17)
-    A, L = p["A"], p["L"]
+    A, L = p["A"], O.knn_laplacian(p["X"], p["knn"])
     rng = np.random.default_rng(2)
     X = p["W0"]
     P = rng.random(X.shape) * X.mean()
@@ -316,7 +316,7 @@ def test_whole_solve_trace_matches_oracle_history(S):
 
 def test_whole_solve_graph(S):
     p = gen.sbm_problem(n=1000, k=5, r=5, p_in=0.08, p_out=0.004, seed=23)
-    A, L = p["A"], p["L"]
+    A, L = p["A"], O.knn_laplacian(p["X"], p["knn"])
     Ag, Lg = S.csr_from_scipy(A, torch.float64), S.csr_from_scipy(L, torch.float64)
     lam = O.default_lambda(A)
     W, Ht, info, hist = _whole(S, Ag, A, p["W0"], "f64", 60, lam, gamma=0.2, L_gpu=Lg, L_or=L)

@@ -25,7 +25,7 @@ def _sym_nonneg(n, rng, rank=None):
 
 def _small_laplacian(n, rng, knn=3):
     x = rng.standard_normal((n, 2))
-    return gen.knn_laplacian(x, knn)
+    return O.knn_laplacian(x, knn)
 
 
 # ------------------------------------------------------------------ gradients vs FD

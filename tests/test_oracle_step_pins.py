@@ -219,7 +219,7 @@ def test_monitor_by_explicit_loops():
     A = 0.5 * (a + a.T)
     x = rng.standard_normal((n, 2))
     from paper_2606_02887_amd import gen
-    L = gen.knn_laplacian(x, 2)
+    L = O.knn_laplacian(x, 2)
     Ld = L.toarray()
     W, Ht = rng.random((n, r)), rng.random((n, r))
     m = O.monitor(A, W, Ht, O.Params(lam=lam, gamma=gam), L)

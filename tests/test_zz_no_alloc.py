@@ -49,7 +49,8 @@ def test_noalloc_equals_solve_on_consecutive_calls(S):
     _same(S, S.dense(A1), torch.from_numpy(p1["W0"]).to(DEV, torch.float64),
           dict(lam=O.default_lambda(p1["A"]), max_outer=12, prec=S.F64))
     g = gen.sbm_problem(n=1000, k=5, r=5, p_in=0.08, p_out=0.004, seed=23)
-    Ag, Lg = S.csr_from_scipy(g["A"], torch.float32), S.csr_from_scipy(g["L"], torch.float32)
+    Ag = S.csr_from_scipy(g["A"], torch.float32)
+    Lg = S.csr_from_scipy(O.knn_laplacian(g["X"], g["knn"]), torch.float32)
     _same(S, Ag, torch.from_numpy(g["W0"]).to(DEV, torch.float32),
           dict(lam=O.default_lambda(g["A"]), gamma=0.2, max_outer=10), Lg)
 
