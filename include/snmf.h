@@ -239,6 +239,32 @@ snmf_status snmf_svd_start(const snmf_matrix* A, int32_t r, int32_t oversample,
                            int32_t power_iters, int32_t prec, const void* Omega, void* W0_out,
                            void* stream);
 
+/* ---------------------------------------------------------------- graph preprocessing
+ * The similarity matrix of data points that Graph-SNMPBB factors, and the Laplacian of
+ * its regulariser (Section 2.2, after Kuang et al.: a Gaussian kernel with parameter sigma,
+ * keeping each point's K nearest neighbours; eq. (2.3): L = I - D^{-1/2} V D^{-1/2},
+ * d_i = sum_j V_ij).  Readings: Euclidean neighbours, the point itself excluded, ties to
+ * the lower index (distances in FP64 on the device); the kernel exp(-||x_i - x_j||^2 /
+ * (2 sigma^2)), sigma = 0 for the unweighted graph (kept entries 1); the pattern is
+ * symmetrised by union (kept when either point lists the other); an isolated point has
+ * L_ii = 1.
+ * X: n x dim row-major device array (float for F32, double for F64), 1 <= dim <= 64,
+ * 1 <= K <= min(64, n - 1), 2 <= n < 2^31.
+ * snmf_knn: nbr_out (n x K int32, device): the neighbours of every point by increasing
+ *   distance.
+ * snmf_knn_graph: the CSR matrix V (laplacian = 0) or L (laplacian = 1, with the diagonal)
+ *   with sorted columns: rowptr_out (n + 1 int64), col_out (int32) and val_out (float or
+ *   double) device arrays of `capacity` >= n (2 K + laplacian) entries (the largest
+ *   possible union; E_SHAPE otherwise, nothing written); *nnz_out (host) receives the
+ *   number of entries.  Scratch memory is allocated and freed inside the call; the stream
+ *   is synchronised before it returns. */
+snmf_status snmf_knn(const void* X, int64_t n, int32_t dim, int32_t K, int32_t prec,
+                     int32_t* nbr_out, void* stream);
+snmf_status snmf_knn_graph(const void* X, int64_t n, int32_t dim, int32_t K, double sigma,
+                           int32_t laplacian, int32_t prec, int64_t* rowptr_out,
+                           int32_t* col_out, void* val_out, int64_t capacity, int64_t* nnz_out,
+                           void* stream);
+
 /* ---------------------------------------------------------------- batched solves
  * The batching form: many independent SNMPBB solves (problem g, restart s) run together,
  * every kernel of a half-step covering all of them in one launch (one per distinct rank

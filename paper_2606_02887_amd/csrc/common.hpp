@@ -15,6 +15,8 @@ constexpr int kTraceFields = 10;       // doubles per outer-iteration trace reco
 constexpr int kMaxInner = 64;         // largest number of inner iterations per half-step
 constexpr int kInnerGrid = 1024;       // workgroups of the row-tile kernels (re-reduced)
 constexpr int kSketchMaxW = 128;     // widest sketch (rank + oversampling) of the range finder
+constexpr int kKnnMaxDim = 64;       // largest point dimension of the K-nearest-neighbour search
+constexpr int kKnnMaxK = 64;         // largest K of the K-nearest-neighbour search
 
 // Counters of the setup kernels that finish a reduction in their last workgroup.
 enum Counter { C_GRAM = 0, C_INIT, C_STEP1, C_STEP2, C_NORM, C_LAI, C_LAPRED, C_MISC, C_COUNT };

@@ -185,4 +185,20 @@ void launch_jacobi(const double* Tin, int w, double* A, double* V, double* ev, h
 void launch_sketch_select(const double* ev, const double* V, int w, int k, int sqrt_scale,
                           double* lam, double* M, hipStream_t s);
 
+
+// ---- graph preprocessing (k_graph.hip)
+template <typename T>
+void launch_count_nonfinite(const T* X, int64_t count, unsigned* flag, hipStream_t s);
+template <typename T>
+void launch_knn(const T* X, int64_t n, int dim, int K, int32_t* nbr, hipStream_t s);
+void launch_knn_pattern_count(const int32_t* nbr, int64_t n, int K, int diag, unsigned* cnt,
+                              int64_t* rowptr, hipStream_t s);
+void launch_knn_pattern_fill(const int32_t* nbr, int64_t n, int K, int diag,
+                             const int64_t* rowptr, int32_t* col, unsigned long long* cursor,
+                             hipStream_t s);
+template <typename T>
+void launch_knn_values(const T* X, int64_t n, int dim, double sigma, int laplacian,
+                       const int64_t* rowptr, const int32_t* col, double* v, double* deg, T* val,
+                       hipStream_t s);
+
 }  // namespace snmf

@@ -72,7 +72,7 @@ EXPORTS = ("snmf_params_default", "snmf_solve", "snmf_solve_noalloc", "snmf_plan
            "snmf_batch_apass", "snmf_batch_time_apass", "snmf_batch_size", "snmf_mlp_sync",
            "snmf_mlp_forward", "snmf_mlp_workspace_bytes", "snmf_mlp_train_step", "snmf_batch_frame",
            "snmf_batch_targets", "snmf_batch_warmstart", "snmf_warmstart", "snmf_lai_sketch",
-           "snmf_svd_start", "snmf_clock_rate_hz",
+           "snmf_svd_start", "snmf_knn", "snmf_knn_graph", "snmf_clock_rate_hz",
            "snmf_last_error", "snmf_abi_version")
 
 
@@ -122,6 +122,9 @@ def load_library(path: str = LIB_PATH):
                             c_int32),
         "snmf_svd_start": ([POINTER(Matrix), c_int32, c_int32, c_int32, c_int32, vp, vp, vp],
                            c_int32),
+        "snmf_knn": ([vp, c_int64, c_int32, c_int32, c_int32, vp, vp], c_int32),
+        "snmf_knn_graph": ([vp, c_int64, c_int32, c_int32, c_double, c_int32, c_int32, vp, vp, vp,
+                            c_int64, POINTER(c_int64), vp], c_int32),
         "snmf_clock_rate_hz": ([], c_double),
         "snmf_last_error": ([], ctypes.c_char_p),
         "snmf_abi_version": ([], c_int32),
@@ -496,6 +499,31 @@ def svd_start(A: MatrixRef, r: int, power_iters: int, Omega):
                                int(power_iters), prec_of(Omega.dtype), _ptr(Omega), _ptr(W0),
                                _stream()))
     return W0
+
+
+def knn(X, K: int):
+    """Neighbour lists (n x K int32) of the rows of X (snmf_knn)."""
+    import torch
+    nbr = torch.empty((X.shape[0], K), dtype=torch.int32, device=X.device)
+    _check(_lib.snmf_knn(_ptr(X), X.shape[0], X.shape[1], int(K), prec_of(X.dtype), _ptr(nbr),
+                         _stream()))
+    return nbr
+
+
+def knn_graph(X, K: int, sigma: float = 0.0, laplacian: bool = True) -> MatrixRef:
+    """The K-nearest-neighbour similarity (or its normalised Laplacian) of the rows of X
+    as a CSR MatrixRef (snmf_knn_graph)."""
+    import torch
+    n, dim = X.shape
+    cap = n * (2 * int(K) + (1 if laplacian else 0))
+    rowptr = torch.empty(n + 1, dtype=torch.int64, device=X.device)
+    col = torch.empty(cap, dtype=torch.int32, device=X.device)
+    val = torch.empty(cap, dtype=X.dtype, device=X.device)
+    nnz = c_int64()
+    _check(_lib.snmf_knn_graph(_ptr(X), n, dim, int(K), float(sigma), int(bool(laplacian)),
+                               prec_of(X.dtype), _ptr(rowptr), _ptr(col), _ptr(val), cap,
+                               ctypes.byref(nnz), _stream()))
+    return csr(rowptr, col[: nnz.value], val[: nnz.value], n)
 
 
 def rho(G) -> float:

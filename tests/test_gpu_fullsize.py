@@ -226,3 +226,15 @@ def test_dense_n8192_r64_whole_solve_2000_outer(S, form):
     assert abs(gres[0] - res_ref) <= 1e-3 * res_ref
     assert np.all(np.abs(gres - ores.mean()) <= 1e-3 * ores.mean())
     assert z <= 4.0
+
+
+def test_graph_n20000_device_laplacian(S):
+    """The graph workload's Laplacian (10-NN over 16-dim features, n = 20000) built on the
+    device: pattern identical to the oracle's, values within FP32 rounding."""
+    p = gen.config(2)
+    X = _t(p["X"], torch.float32)
+    M = S.knn_graph(X, p["knn"])
+    rowptr, col, val = (t.cpu().numpy() for t in M.keep)
+    ref = O.knn_laplacian(X.double().cpu().numpy(), p["knn"])
+    assert np.array_equal(rowptr, ref.indptr) and np.array_equal(col, ref.indices)
+    assert np.abs(val.astype(np.float64) - ref.data).max() <= 2e-7
