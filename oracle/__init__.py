@@ -8,3 +8,4 @@ from .snmpbb import (Params, LowRank, HalfStep, apply_A, norm2_A, spectral_norm_
                      snmpbb, default_lambda)
 from .lai import range_finder, svd_start  # noqa: E402,F401
 from .graph import knn, similarity, normalized_laplacian, knn_laplacian  # noqa: E402,F401
+from .nmf import nmf as nmf_solve  # noqa: E402,F401

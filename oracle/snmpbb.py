@@ -131,14 +131,17 @@ class HalfStep:
         self.rho = spectral_norm_psd(self.G)              # rho0 = ||H0 H0^T||_2
 
     def grad(self, X):
-        g = X @ self.G - self.B + self.lam * (X - self.P)
+        g = X @ self.G - self.B
+        if self.lam:                     # (the penalty needs X and P of one shape)
+            g = g + self.lam * (X - self.P)
         if self.L is not None:
             g = g + self.gamma * np.asarray(self.L @ X)
         return g
 
     def f(self, X):
-        v = (0.5 * self.normA2 - np.sum(self.B * X) + 0.5 * np.sum((X.T @ X) * self.G)
-             + 0.5 * self.lam * np.sum((X - self.P) ** 2))
+        v = 0.5 * self.normA2 - np.sum(self.B * X) + 0.5 * np.sum((X.T @ X) * self.G)
+        if self.lam:
+            v += 0.5 * self.lam * np.sum((X - self.P) ** 2)
         if self.L is not None:
             v += 0.5 * self.gamma * np.sum(X * np.asarray(self.L @ X))
         return float(v)
