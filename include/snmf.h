@@ -385,6 +385,31 @@ snmf_status snmf_batch_warmstart(snmf_batch* b, int32_t nmodels, const snmf_mlp*
 snmf_status snmf_warmstart(const snmf_mlp* mlp, const snmf_matrix* A, int32_t r, int32_t prec,
                            const void* Omega, void* W0_out, void* stream);
 
+/* NMPBB for rectangular NMF, min ||V - W Ht^T||_F^2 / 2 over W, Ht >= 0 (eq. (1.1)), with
+ * the alternating scheme of Section 2.1: each outer iteration runs inner_iters iterations
+ * of Algorithm 1 on W (the partner Ht, gradient W Ht^T Ht - V Ht), then on Ht (partner W,
+ * gradient Ht W^T W - V^T W), with the same first projection, BB steps, nonmonotone line
+ * search and stopping tests as the symmetric solve but no penalty term.
+ * V: m x n_cols, dense (row-major, ld >= n_cols, read in place) or CSR (m rows, columns in
+ *    [0, n_cols) strictly increasing per row; its transpose is formed once on the device
+ *    in deterministic order); entries >= 0.  LOWRANK is E_UNSUPPORTED.
+ * W0 (m x r), Ht0 (n_cols x r): device, row-major, of the precision's type, >= 0; not
+ *    modified.  W_out, Ht_out: device, same shapes, caller-owned.
+ * p: prec F32 or F64 (else E_UNSUPPORTED); lambda must be 0 (E_ARG otherwise) and L NULL;
+ *    max_outer, inner_iters, line-search and stopping fields as for snmf_solve.
+ * info: res_WH = ||V - W Ht^T||_F / ||V||_F, pg_norm the projected gradient of the pair,
+ *    objective = res^2 ||V||^2 / 2; res_WWt and sym_gap are NaN.  trace (host, optional,
+ *    max_outer x 10 doubles): the per-outer records of snmf_solve, fields 1 and 2 NaN.
+ * Scratch memory (about 8 max(m, n_cols) r elements, plus the transpose of a CSR V) is
+ * allocated and freed inside the call; the call synchronises the stream.
+ * Errors: E_ARG (null pointers, lambda != 0, V zero), E_SHAPE (r outside [1, min(64, m,
+ * n_cols)], malformed CSR, ld < n_cols), E_NEGATIVE / E_NONFINITE (inputs), E_BREAKDOWN
+ * (a factor collapsed to zero or a scalar overflowed: the outputs hold the last iterate,
+ * info the last completed record, as in snmf_solve). */
+snmf_status snmf_nmf_solve(const snmf_matrix* V, int64_t n_cols, int32_t r, const void* W0,
+                           const void* Ht0, const snmf_params* p, void* W_out, void* Ht_out,
+                           snmf_info* info, void* stream, double* trace);
+
 /* Device clock rate (Hz) of the trace ticks and info.seconds. */
 double snmf_clock_rate_hz(void);
 const char* snmf_last_error(void);

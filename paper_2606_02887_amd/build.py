@@ -12,7 +12,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 SOURCES = ["k_small.hip", "k_inner.hip", "k_apass_dense.hip", "k_apass_stack.hip", "k_sparse.hip",
            "k_validate.hip", "solver.hip", "batch.hip", "k_warmstart.hip", "warmstart.hip",
-           "k_sketch.hip", "sketch.hip", "k_graph.hip", "graph.hip"]
+           "k_sketch.hip", "sketch.hip", "k_graph.hip", "graph.hip", "k_nmf.hip", "nmf.hip"]
 LIB = os.path.join(HERE, "libsnmf.so")
 ARCH = os.environ.get("SNMF_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",

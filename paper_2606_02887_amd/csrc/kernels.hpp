@@ -201,4 +201,16 @@ void launch_knn_values(const T* X, int64_t n, int dim, double sigma, int laplaci
                        const int64_t* rowptr, const int32_t* col, double* v, double* deg, T* val,
                        hipStream_t s);
 
+
+// ---- NMPBB for rectangular NMF (k_nmf.hip)
+template <typename T>
+void launch_rect_apass(const T* V, int64_t ld, int64_t rows, int64_t K, int trans, const T* P,
+                       int r, T* B, const State* st, hipStream_t s);
+void launch_csr_check_rect(const int64_t* rowptr, const int32_t* col, int64_t m, int64_t ncols,
+                           int64_t nnz, unsigned* flags, hipStream_t s);
+template <typename T>
+void launch_csr_transpose(const int64_t* rowptr, const int32_t* col, const T* val, int64_t m,
+                          int64_t ncols, int64_t nnz, unsigned* cnt, unsigned long long* cursor,
+                          int64_t* rowptrT, int32_t* colT, T* valT, hipStream_t s);
+
 }  // namespace snmf

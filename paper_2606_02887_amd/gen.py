@@ -309,3 +309,34 @@ def random_lowrank(n: int, ell: int, seed: int):
     rng = np.random.default_rng(seed)
     return rng.standard_normal((n, ell)).astype(np.float32), np.ones(ell)
 
+
+
+# --------------------------------------------------------------------------- rectangular NMF
+def planted_rect(m: int, n: int, r: int, seed: int, noise: float = 0.01):
+    """Planted rectangular problem ``V = max(W* Ht*^T + E, 0)`` (m x n, float64) for NMF
+    (eq. (1.1)): ``W*`` and ``Ht*`` uniform on [0, 1), E Gaussian with standard deviation
+    ``noise * mean(W* Ht*^T)``.  Returns ``V``, ``W0`` (m x r) and ``Ht0`` (n x r), the
+    starts drawn as ``start_factor`` from the mean of V."""
+    rng = np.random.default_rng(seed)
+    wstar, hstar = rng.random((m, r)), rng.random((n, r))
+    v = wstar @ hstar.T
+    if noise > 0.0:
+        v += (noise * float(v.mean())) * rng.standard_normal((m, n))
+    np.maximum(v, 0.0, out=v)
+    mv = float(v.mean())
+    return {"V": np.ascontiguousarray(v), "W0": start_factor(rng, m, r, mv),
+            "Ht0": start_factor(rng, n, r, mv)}
+
+
+def random_rect_csr(m: int, n: int, density: float, r: int, seed: int):
+    """A sparse m x n nonnegative matrix with about density*m*n entries at uniform random
+    positions, values uniform(0, 1] (a document-term-like count surrogate), and starts
+    W0, Ht0 from its mean."""
+    rng = np.random.default_rng(seed)
+    nnz = int(density * m * n)
+    key = np.unique(rng.integers(0, m * n, size=nnz, dtype=np.int64))
+    v = 1.0 - rng.random(key.size)
+    a = sp.csr_matrix((v, (key // n, key % n)), shape=(m, n))
+    a.sort_indices()
+    mv = float(a.data.sum()) / m / n
+    return {"V": a, "W0": start_factor(rng, m, r, mv), "Ht0": start_factor(rng, n, r, mv)}

@@ -72,7 +72,7 @@ EXPORTS = ("snmf_params_default", "snmf_solve", "snmf_solve_noalloc", "snmf_plan
            "snmf_batch_apass", "snmf_batch_time_apass", "snmf_batch_size", "snmf_mlp_sync",
            "snmf_mlp_forward", "snmf_mlp_workspace_bytes", "snmf_mlp_train_step", "snmf_batch_frame",
            "snmf_batch_targets", "snmf_batch_warmstart", "snmf_warmstart", "snmf_lai_sketch",
-           "snmf_svd_start", "snmf_knn", "snmf_knn_graph", "snmf_clock_rate_hz",
+           "snmf_svd_start", "snmf_knn", "snmf_knn_graph", "snmf_nmf_solve", "snmf_clock_rate_hz",
            "snmf_last_error", "snmf_abi_version")
 
 
@@ -125,6 +125,8 @@ def load_library(path: str = LIB_PATH):
         "snmf_knn": ([vp, c_int64, c_int32, c_int32, c_int32, vp, vp], c_int32),
         "snmf_knn_graph": ([vp, c_int64, c_int32, c_int32, c_double, c_int32, c_int32, vp, vp, vp,
                             c_int64, POINTER(c_int64), vp], c_int32),
+        "snmf_nmf_solve": ([POINTER(Matrix), c_int64, c_int32, vp, vp, POINTER(Params), vp, vp,
+                            POINTER(Info), vp, POINTER(c_double)], c_int32),
         "snmf_clock_rate_hz": ([], c_double),
         "snmf_last_error": ([], ctypes.c_char_p),
         "snmf_abi_version": ([], c_int32),
@@ -554,3 +556,20 @@ def clock_rate_hz() -> float:
 
 def abi_version() -> int:
     return _lib.snmf_abi_version()
+
+
+def nmf_solve(V: MatrixRef, n_cols: int, W0, Ht0, prm: Params, trace: bool = True):
+    """NMPBB for rectangular NMF (snmf_nmf_solve): V is m x n_cols (dense or CSR), W0 is
+    m x r, Ht0 n_cols x r; returns W, Ht and the info dict (with the trace)."""
+    import torch
+    W_out, Ht_out = torch.empty_like(W0), torch.empty_like(Ht0)
+    info = Info()
+    tr = (c_double * (prm.max_outer * TRACE_FIELDS))() if trace else None
+    _check(_lib.snmf_nmf_solve(ctypes.byref(V.desc), int(n_cols), W0.shape[1], _ptr(W0),
+                               _ptr(Ht0), ctypes.byref(prm), _ptr(W_out), _ptr(Ht_out),
+                               ctypes.byref(info), _stream(), tr))
+    out = info.as_dict()
+    if trace:
+        arr = np.frombuffer(tr, dtype=np.float64).reshape(prm.max_outer, TRACE_FIELDS)
+        out["trace"] = arr[: info.outer].copy()
+    return W_out, Ht_out, out

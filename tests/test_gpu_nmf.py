@@ -1,0 +1,116 @@
+"""GPU parity of NMPBB for rectangular NMF (snmf_nmf_solve, eq. (1.1) with the
+alternating scheme of Section 2.1) against the oracle (oracle/nmf.py) from the same V, W0
+and Ht0.
+
+Tolerances: FP64 runs the oracle's arithmetic in another summation order, so a few outer
+iterations agree to 1e-9 relative (factors and residual trace).  FP32 sums in FP32 with
+FP64 scalars: the factors after 10 outer iterations agree to 2e-3 normwise and the
+residual trace to 1e-4 relative, the bounds the symmetric solve meets at these sizes (the
+BB steps amplify the FP32 rounding of the gradient, about 1e-6, by at most a few hundred
+over ten outer iterations of three inner steps).
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle as O
+from paper_2606_02887_amd import gen
+from parity_util import nrel
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+DT = {"f64": torch.float64, "f32": torch.float32}
+TOL = {"f64": (1e-9, 1e-9), "f32": (2e-3, 1e-4)}   # (factors, residual trace)
+
+
+@pytest.fixture(scope="module")
+def S():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2606_02887_amd import snmf
+    return snmf
+
+
+def _run(S, kind, prec, m, n, r, seed, outer):
+    dt = DT[prec]
+    if kind == "dense":
+        prob = gen.planted_rect(m, n, r, seed)
+        Vt = torch.from_numpy(prob["V"]).to(DEV, dt)
+        M = S.dense(Vt)
+        Vref = Vt.double().cpu().numpy()
+    else:
+        prob = gen.random_rect_csr(m, n, 0.02, r, seed)
+        M = S.csr_from_scipy(prob["V"], dt)
+        Vref = prob["V"].copy().astype(np.float64)
+        Vref.data = M.keep[2].double().cpu().numpy()
+    W0 = torch.from_numpy(prob["W0"]).to(DEV, dt)
+    H0 = torch.from_numpy(prob["Ht0"]).to(DEV, dt)
+    W, Ht, info = S.nmf_solve(M, n, W0, H0, S.params(prec=S.prec_of(dt), lam=0.0, max_outer=outer))
+    Wo, Ho, hist = O.nmf_solve(Vref, W0.double().cpu().numpy(), H0.double().cpu().numpy(),
+                               O.Params(), outer)
+    return W, Ht, info, Wo, Ho, hist
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("kind,m,n,r", [("dense", 700, 450, 12), ("dense", 130, 1029, 5),
+                                        ("csr", 3000, 1700, 16), ("csr", 517, 2048, 33)])
+def test_nmf_matches_oracle(S, prec, kind, m, n, r):
+    outer = 10
+    W, Ht, info, Wo, Ho, hist = _run(S, kind, prec, m, n, r, 11 + m, outer)
+    ftol, rtol = TOL[prec]
+    Wg, Hg = W.double().cpu().numpy(), Ht.double().cpu().numpy()
+    ew, eh = nrel(Wg, Wo), nrel(Hg, Ho)
+    tr = info["trace"]
+    res_o = np.array([h["res_WH"] for h in hist])
+    pg_o = np.array([h["pg"] for h in hist])
+    eres = np.abs(tr[:, 0] - res_o).max() / res_o.max()
+    epg = abs(info["pg_norm"] - pg_o[-1]) / pg_o[-1]
+    print(f"{kind} {m}x{n} r={r} {prec}: W {ew:.1e}, Ht {eh:.1e}, residual trace {eres:.1e}, "
+          f"pg {epg:.1e}; residual {res_o[0]:.4f} -> {res_o[-1]:.4f}")
+    assert info["status"] == 0 and info["outer"] == outer and tr.shape[0] == outer
+    assert ew <= ftol and eh <= ftol
+    assert eres <= rtol
+    # the objective is res^2 ||V||^2 / 2 on both sides: its relative error is twice the
+    # residual's at the last record, where the trace tolerance (relative to the largest
+    # residual) is res_max / res_last times larger
+    obj_o = hist[-1]["objective"]
+    assert abs(info["objective"] - obj_o) <= 2.5 * rtol * res_o.max() / res_o[-1] * obj_o
+    assert epg <= (1e-7 if prec == "f64" else 0.05)
+    assert np.isnan(info["res_WWt"]) and np.isnan(tr[:, 1]).all()
+    assert (Wg >= 0).all() and (Hg >= 0).all()
+
+
+def test_nmf_reaches_planted_fit(S):
+    """200 outer iterations on the planted dense problem (m = 700, n = 450, r = 12, noise
+    1%) in FP32 bring the residual to the noise level, as the oracle's 200 iterations do
+    (both below 0.02, within 5% of each other)."""
+    W, Ht, info, Wo, Ho, hist = _run(S, "dense", "f32", 700, 450, 12, 711, 200)
+    print(f"200 outer: gpu {info['res_WH']:.5f}, oracle {hist[-1]['res_WH']:.5f}")
+    assert info["res_WH"] < 0.02 and hist[-1]["res_WH"] < 0.02
+    assert abs(info["res_WH"] - hist[-1]["res_WH"]) <= 0.05 * hist[-1]["res_WH"]
+
+
+def test_nmf_error_codes(S):
+    V = torch.rand((40, 30), dtype=torch.float64, device=DEV)
+    W0 = torch.rand((40, 4), dtype=torch.float64, device=DEV)
+    H0 = torch.rand((30, 4), dtype=torch.float64, device=DEV)
+
+    def code(M, ncols, W, H, **kw):
+        kw.setdefault("prec", S.prec_of(torch.float64))
+        with pytest.raises(S.SnmfError) as e:
+            S.nmf_solve(M, ncols, W, H, S.params(max_outer=3, **kw))
+        return e.value.name
+
+    assert code(S.dense(V), 30, W0, H0, lam=0.5) == "E_ARG"
+    assert code(S.dense(V), 31, W0, torch.rand((31, 4), dtype=torch.float64, device=DEV),
+                lam=0.0) == "E_SHAPE"                                  # ld 30 < n_cols
+    assert code(S.dense(V), 30, W0, H0, lam=0.0, prec=S.BF16X3) == "E_UNSUPPORTED"
+    Vn = V.clone()
+    Vn[3, 4] = -1.0
+    assert code(S.dense(Vn), 30, W0, H0, lam=0.0) == "E_NEGATIVE"
+    a = sp.random(40, 30, density=0.2, random_state=3, format="csr")
+    M = S.csr_from_scipy(a, torch.float64)
+    assert code(M, 20, W0, H0[:20].contiguous(), lam=0.0) == "E_SHAPE"   # columns >= n_cols
+    lr = S.lowrank(W0, torch.ones(4, dtype=torch.float64, device=DEV))
+    assert code(lr, 30, W0, H0, lam=0.0) == "E_UNSUPPORTED"
