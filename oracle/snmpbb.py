@@ -294,6 +294,28 @@ def snmpbb(A, W0, prm: Params, max_outer: int, L=None, target_res: float = 0.0,
     return W, Ht, hist
 
 
+def naive(A, W0, prm: Params, max_outer: int, target_res: float = 0.0):
+    """The naive symmetric variant that Section 2.1 describes before the penalty method
+    (and reports to perform poorly): every outer iteration runs Algorithm 1 on W alone for
+    min ||A - W W_i^T||_F^2 / 2, the partner held at the current iterate W_i and no
+    penalty, then sets H <- W^T.  prm.lam must be 0.  Returns (W, Ht, history) as snmpbb
+    does, with Ht = W after every outer iteration."""
+    if prm.lam != 0.0:
+        raise ValueError("the naive variant has no penalty term (lam must be 0)")
+    nA2 = norm2_A(A)
+    W = np.array(W0, dtype=np.float64, copy=True)
+    hist = []
+    for i in range(max_outer):
+        W = half_step(A, W, W.copy(), prm, False, None, nA2)
+        Ht = W.copy()                                  # H <- W^T
+        m = monitor(A, W, Ht, prm, None, nA2)
+        m["outer"] = i + 1
+        hist.append(m)
+        if target_res > 0 and m["res_WH"] <= target_res:
+            break
+    return W, W.copy(), hist
+
+
 def default_lambda(A) -> float:
     """lambda ~= 0.01 ||A||_F (Section 4.1, guideline (1))."""
     return 0.01 * float(np.sqrt(norm2_A(A)))
