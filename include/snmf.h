@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define SNMF_ABI_VERSION 1
+#define SNMF_ABI_VERSION 2
 #define SNMF_TRACE_FIELDS 10
 
 typedef enum snmf_status {
@@ -115,6 +115,11 @@ typedef struct snmf_params {
                           for all i, j, else SNMF_E_NOT_SYMMETRIC (one O(n^2) pass over A at
                           plan or batch creation); 0: not checked (CSR symmetry is checked
                           whenever validate is set)                                      [0] */
+  int32_t naive;       /* 1: the naive symmetric variant of Section 2.1 in place of the
+                          penalty method: each outer iteration runs Algorithm 1 on W with
+                          the partner held at the current W and no penalty, then sets
+                          H <- W^T (an ablation).  Needs lambda = 0 (E_ARG) and no Laplacian
+                          (E_UNSUPPORTED); single solves only (batches: E_UNSUPPORTED)     [0] */
 } snmf_params;
 
 /* Per-solve results (host struct written on return). */

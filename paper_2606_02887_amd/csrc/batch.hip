@@ -200,6 +200,7 @@ snmf_status batch_create(int32_t nprob, const snmf_matrix* A, const int32_t* r, 
   if (!out) return fail(SNMF_E_ARG, "out is NULL");
   *out = nullptr;
   SNMF_TRY(check_params(p));
+  if (p->naive) return fail(SNMF_E_UNSUPPORTED, "the naive variant runs as single solves only");
   if (nprob < 1) return fail(SNMF_E_ARG, "nprob must be >= 1");
   if (restarts < 1) return fail(SNMF_E_ARG, "restarts must be >= 1");
   if (!A || !r) return fail(SNMF_E_ARG, "A and r are required");

@@ -806,6 +806,10 @@ __global__ __launch_bounds__(kThreads, (inner_occupancy<T, RP, V>())) void k_ste
         }
         block_sum<9>(v, sm.red);
         write_parts<9>(partsC, lc.bid, v);
+        if (w0) {  // (set already when an earlier step 2 of this H-step ran)
+          st->pending = 1;
+          st->t_hstep = wall_clock64();
+        }
       }
     }
     return;
@@ -934,6 +938,28 @@ __global__ __launch_bounds__(kThreads, (inner_occupancy<T, RP, V>())) void k_ste
     st->pending = 1;
     st->t_hstep = wall_clock64();
   }
+}
+
+// ----------------------------------------------------------------------------- naive variant
+// H-step of the naive symmetric variant (H <- W^T after each W-step): after H was set to
+// W and the H-step's init ran at H = W, this keeps <C, P> for the monitor (as the first
+// inner kernel of an H-step does) and marks the half-step stopped before inner iteration
+// 0, so that its one step 2 forms the monitor sums of H = W without moving it.
+__global__ __launch_bounds__(kThreads) void k_naive_hentry(const double* __restrict__ partsA,
+                                                           int nb, State* __restrict__ st) {
+  __shared__ double sred[kThreads / kWave];
+  if (st->done) return;
+  double a1[1];
+  load_slots<1>(partsA, nb, 0, a1);
+  block_sum<1>(a1, sred);
+  if (threadIdx.x == 0) {
+    st->m_CP = a1[0];
+    st->stop[0] = 1;
+  }
+}
+
+void launch_naive_hentry(const double* partsA, int nb, State* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_naive_hentry, dim3(1), dim3(kThreads), 0, s, partsA, nb, st);
 }
 
 // ----------------------------------------------------------------------------- launchers

@@ -146,6 +146,8 @@ void launch_step2(T* X, T* g, T* Z, T* D, const T* LS, const T* C, const T* P, T
                   int nbD, double* partsC, hipStream_t s, const BMap& bm = BMap{}, int grid = 0,
                   int last_k = 0,  // last inner iteration (its H-step forms the monitor sums)
                   int rd = 0);     // phase 0: step 2 recomputes D (step 1 then stores none)
+// Naive variant: the H-step's entry at H = W (<C, P> kept, half-step stopped before k = 0).
+void launch_naive_hentry(const double* partsA, int nb, State* st, hipStream_t s);
 // Bytes of one n x r array from which a single solve recomputes D in step 2.
 constexpr int64_t kRecomputeDBytes = 4 << 20;
 

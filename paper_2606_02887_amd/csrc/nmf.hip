@@ -197,6 +197,7 @@ snmf_status nmf_solve(const snmf_matrix* V, int64_t ncols, int32_t r, const void
     return fail(SNMF_E_UNSUPPORTED, "NMF runs in F32 or F64");
   if (p->lambda != 0.0) return fail(SNMF_E_ARG, "NMF has no symmetric penalty: lambda must be 0");
   if (p->L) return fail(SNMF_E_UNSUPPORTED, "NMF takes no Laplacian");
+  if (p->naive) return fail(SNMF_E_UNSUPPORTED, "the naive variant is a symmetric one");
   const int64_t m = V->n;
   if (ncols < 1 || ncols >= ((int64_t)1 << 31)) return fail(SNMF_E_SHAPE, "n_cols must lie in [1, 2^31)");
   if (V->fmt == SNMF_DENSE && V->ld < ncols) return fail(SNMF_E_SHAPE, "V: ld < n_cols");

@@ -364,6 +364,18 @@ snmf_status outer_iteration(snmf_plan* pl, hipStream_t s) {
   T* H = (T*)pl->Hb;
   SNMF_TRY(half_start<T>(pl, W, H, 0, true, s));
   SNMF_TRY(inner_steps<T>(pl, W, H, 0, s));
+  if (pl->p.naive) {
+    // H <- W^T, then an H-step that stops before its first inner iteration: its init
+    // (at H = W) and its one step 2 supply the monitor sums of the pair (W, W)
+    HIP_TRY(hipMemcpyAsync(H, W, (size_t)pl->n * pl->r * sizeof(T), hipMemcpyDeviceToDevice, s));
+    SNMF_TRY(half_start<T>(pl, H, W, 1, false, s));
+    launch_naive_hentry(pl->partsA, inner_grid(pl->n, pl->r, (int)sizeof(T)), pl->st, s);
+    launch_step2<T>(H, (T*)pl->g, (T*)pl->Z, (T*)pl->D, nullptr, (const T*)pl->C, W, nullptr,
+                    (const T*)pl->GT[1], pl->n, pl->r, 0, 0, 1, pl->kp, pl->st, pl->partsB,
+                    nullptr, 0, pl->partsC, s, BMap{}, 0, 0, 0);
+    HIP_TRY(hipGetLastError());
+    return SNMF_OK;
+  }
   SNMF_TRY(half_start<T>(pl, H, W, 1, true, s));
   SNMF_TRY(inner_steps<T>(pl, H, W, 1, s));
   return SNMF_OK;
@@ -414,6 +426,9 @@ snmf_status plan_init(snmf_plan* pl, const snmf_matrix* A, int32_t r, const snmf
   }
   if (p->prec == SNMF_BF16X3 && A->fmt != SNMF_DENSE)
     return fail(SNMF_E_UNSUPPORTED, "BF16X3 applies to dense A only");
+  if (p->naive && p->lambda != 0.0)
+    return fail(SNMF_E_ARG, "the naive variant has no penalty: lambda must be 0");
+  if (p->naive && lap) return fail(SNMF_E_UNSUPPORTED, "the naive variant takes no Laplacian");
   pl->A = *A;
   if (lap) pl->L = *p->L;
   pl->p = *p;

@@ -44,7 +44,8 @@ class Params(ctypes.Structure):
                 ("max_ls", c_int32), ("inner_iters", c_int32), ("max_outer", c_int32),
                 ("check_every", c_int32), ("target_res", c_double), ("prec", c_int32),
                 ("accept_at_relaxed", c_int32), ("project_update", c_int32),
-                ("validate", c_int32), ("use_graph", c_int32), ("check_symmetry", c_int32)]
+                ("validate", c_int32), ("use_graph", c_int32), ("check_symmetry", c_int32),
+                ("naive", c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -64,6 +65,7 @@ class MlpC(ctypes.Structure):
                 ("adam_m", c_void_p), ("adam_v", c_void_p)]
 
 
+ABI_VERSION = 2
 EXPORTS = ("snmf_params_default", "snmf_solve", "snmf_solve_noalloc", "snmf_plan_create",
            "snmf_plan_solve",
            "snmf_plan_destroy", "snmf_plan_half_step", "snmf_plan_apass", "snmf_plan_gram",
@@ -135,6 +137,9 @@ def load_library(path: str = LIB_PATH):
         fn = getattr(lib, name)
         fn.argtypes = args
         fn.restype = res
+    if lib.snmf_abi_version() != ABI_VERSION:   # the structs above follow this version
+        raise ImportError(f"{path} has ABI {lib.snmf_abi_version()}, the binding {ABI_VERSION}:"
+                          " rebuild it with __graft_entry__.build()")
     return lib
 
 
