@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define SNMF_ABI_VERSION 2
+#define SNMF_ABI_VERSION 3
 #define SNMF_TRACE_FIELDS 10
 
 typedef enum snmf_status {
@@ -88,6 +88,17 @@ typedef struct snmf_matrix {
   const double* lam;
 } snmf_matrix;
 
+/* Launch shape of a batched solve (snmf_batch_create), chosen by timing on the batch's
+ * own shapes (the package's autotuner caches the choice per device and workload).  Class q
+ * holds the instances of rank r with rank padding 8, 16, 32, 64 (q = 0..3: r <= 8,
+ * r <= 16, r <= 32, r <= 64).  Any value in range gives the same iteration; only the
+ * grouping of the FP64 partial sums, and so their rounding, changes with it. */
+typedef struct snmf_batch_tuning {
+  int32_t tiles_per_wg[4];  /* row tiles per inner-kernel workgroup of class q, 1..64   [4] */
+  int32_t spmm_rows_per_wg; /* rows per workgroup of the batched SpMM (CSR A), 1..4096 [16] */
+  int32_t reserved[3];      /* must be 0 */
+} snmf_batch_tuning;
+
 /* Solver parameters.  snmf_params_default() fills the values in brackets. */
 typedef struct snmf_params {
   double lambda;       /* symmetric penalty lam >= 0 (eq. (1.3))                         [0] */
@@ -120,6 +131,9 @@ typedef struct snmf_params {
                           the partner held at the current W and no penalty, then sets
                           H <- W^T (an ablation).  Needs lambda = 0 (E_ARG) and no Laplacian
                           (E_UNSUPPORTED); single solves only (batches: E_UNSUPPORTED)     [0] */
+  const snmf_batch_tuning* tuning; /* batched solves: launch shape, or NULL for the
+                          defaults (read at snmf_batch_create; values out of range: E_ARG)
+                          [NULL] */
 } snmf_params;
 
 /* Per-solve results (host struct written on return). */

@@ -201,6 +201,21 @@ snmf_status batch_create(int32_t nprob, const snmf_matrix* A, const int32_t* r, 
   *out = nullptr;
   SNMF_TRY(check_params(p));
   if (p->naive) return fail(SNMF_E_UNSUPPORTED, "the naive variant runs as single solves only");
+  int tpb_cls[4] = {4, 4, 4, 4};  // row tiles per inner-kernel workgroup, per rank class
+  int spmm_rows = 16;              // rows per workgroup of the batched SpMM
+  if (p->tuning) {
+    const snmf_batch_tuning& t = *p->tuning;
+    for (int q = 0; q < 4; ++q) {
+      if (t.tiles_per_wg[q] < 1 || t.tiles_per_wg[q] > 64)
+        return fail(SNMF_E_ARG, "tuning: tiles_per_wg must lie in [1, 64]");
+      tpb_cls[q] = t.tiles_per_wg[q];
+    }
+    if (t.spmm_rows_per_wg < 1 || t.spmm_rows_per_wg > 4096)
+      return fail(SNMF_E_ARG, "tuning: spmm_rows_per_wg must lie in [1, 4096]");
+    if (t.reserved[0] || t.reserved[1] || t.reserved[2])
+      return fail(SNMF_E_ARG, "tuning: reserved fields must be 0");
+    spmm_rows = t.spmm_rows_per_wg;
+  }
   if (nprob < 1) return fail(SNMF_E_ARG, "nprob must be >= 1");
   if (restarts < 1) return fail(SNMF_E_ARG, "restarts must be >= 1");
   if (!A || !r) return fail(SNMF_E_ARG, "A and r are required");
@@ -283,13 +298,14 @@ snmf_status batch_create(int32_t nprob, const snmf_matrix* A, const int32_t* r, 
   std::vector<int32_t> btab;
   int part_row = 0;
   // row tiles per inner-kernel workgroup: more than one amortises each workgroup's fixed
-  // cost (instance lookup, partial-sum reduction, line search, G staging).  4 measured
-  // best on 256 graphs x 8 restarts (1: 114k, 2: 132k, 4: 138k, 8: 136k instance outer
-  // iterations/s).
-  constexpr int tpb = 4;
+  // cost (instance lookup, partial-sum reduction, line search, G staging).  The default 4
+  // measured best on 256 graphs x 8 restarts (1: 114k, 2: 132k, 4: 138k, 8: 136k instance
+  // outer iterations/s); a tuning picks it per rank class.
   for (auto& kv : by_r) {
     snmf_batch::Cls c;
     c.r = kv.first;
+    const int rp = rank_pad(c.r);
+    const int tpb = tpb_cls[rp <= 8 ? 0 : rp <= 16 ? 1 : rp <= 32 ? 2 : 3];
     c.tab_off = (int64_t)btab.size();
     c.gtab_off = (int64_t)gtab.size();
     int blk = 0, gb = 0;
@@ -330,7 +346,7 @@ snmf_status batch_create(int32_t nprob, const snmf_matrix* A, const int32_t* r, 
       G.r = b->r[g];
       G.S = restarts;
       G.blk0 = sblk;
-      G.nblk = (int)std::min<int64_t>(4096, std::max<int64_t>(1, (G.n + 15) / 16));
+      G.nblk = (int)std::min<int64_t>(4096, std::max<int64_t>(1, (G.n + spmm_rows - 1) / spmm_rows));
       G.inst0 = g * restarts;
       for (int j = 0; j < G.nblk; ++j) stab.push_back(g);
       sblk += G.nblk;

@@ -37,6 +37,11 @@ class Matrix(ctypes.Structure):
                 ("nnz", c_int64), ("U", c_void_p), ("ell", c_int64), ("lam", c_void_p)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("tiles_per_wg", c_int32 * 4), ("spmm_rows_per_wg", c_int32),
+                ("reserved", c_int32 * 3)]
+
+
 class Params(ctypes.Structure):
     _fields_ = [("lambda_", c_double), ("gamma", c_double), ("L", POINTER(Matrix)),
                 ("eta", c_double), ("theta", c_double), ("phi", c_double),
@@ -45,7 +50,7 @@ class Params(ctypes.Structure):
                 ("check_every", c_int32), ("target_res", c_double), ("prec", c_int32),
                 ("accept_at_relaxed", c_int32), ("project_update", c_int32),
                 ("validate", c_int32), ("use_graph", c_int32), ("check_symmetry", c_int32),
-                ("naive", c_int32)]
+                ("naive", c_int32), ("tuning", POINTER(Tuning))]
 
 
 class Info(ctypes.Structure):
@@ -65,7 +70,7 @@ class MlpC(ctypes.Structure):
                 ("adam_m", c_void_p), ("adam_v", c_void_p)]
 
 
-ABI_VERSION = 2
+ABI_VERSION = 3
 EXPORTS = ("snmf_params_default", "snmf_solve", "snmf_solve_noalloc", "snmf_plan_create",
            "snmf_plan_solve",
            "snmf_plan_destroy", "snmf_plan_half_step", "snmf_plan_apass", "snmf_plan_gram",
@@ -204,6 +209,15 @@ def csr_from_scipy(a, dtype, device="cuda"):
 
 
 # ------------------------------------------------------------------ parameters
+def tuning(tiles_per_wg=(4, 4, 4, 4), spmm_rows_per_wg: int = 16) -> Tuning:
+    """Launch shape of a batched solve (rank classes r <= 8, 16, 32, 64)."""
+    t = Tuning()
+    for q, v in enumerate(tiles_per_wg):
+        t.tiles_per_wg[q] = int(v)
+    t.spmm_rows_per_wg = int(spmm_rows_per_wg)
+    return t
+
+
 def params(**kw) -> Params:
     p = Params()
     _check(_lib.snmf_params_default(ctypes.byref(p)))
@@ -211,6 +225,11 @@ def params(**kw) -> Params:
         if k == "lam":
             k = "lambda_"
         if k == "L":
+            continue
+        if k == "tuning":                 # a Tuning, a dict of its fields, or None
+            if isinstance(v, dict):
+                v = tuning(**v)
+            p.tuning = ctypes.pointer(v) if v is not None else None
             continue
         if not hasattr(p, k):
             raise KeyError(k)
