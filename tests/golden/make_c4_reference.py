@@ -3,10 +3,17 @@ workload (256 SBM graphs, n ~ U[500, 5000], k = r in {8, 16, 32}, 8 random start
 seed 1004 + g) for 20 outer iterations.  For each instance: whether the iteration broke
 down (a factor collapsed to zero, so rho = ||P^T P||_2 = 0 for the next half-step), the
 number of completed outer iterations, and the monitor record after the last of them; and
-the same from the start changed at rounding level (every entry of W0 times 1 + 2^-24 u,
-u = +-1 from default_rng(7919 g + s)), which measures how far that instance's iteration
-itself carries a rounding difference within 20 outer iterations.  Calls only the CPU
-reference and the seeded input generators.
+the same twice more with rounding-size changes of both factors after every outer
+iteration: every entry of X in {W, Ht} plus eps max|X| u, u standard normal from
+default_rng(7919 g + s), projected to >= 0, with eps = 2^-52 ("perturbed", the absolute
+size of FP64 rounding in a sum) and eps = 2^-24 ("perturbed32", FP32).  These measure how
+far each instance's own iteration carries rounding differences within 20 outer
+iterations.  The change is additive on purpose: at the saddle points that these
+instances approach (graphs below the detection threshold), whole columns of W and Ht are
+exactly zero and their gradient columns vanish, so a relative change (x (1 + eps u))
+leaves them dead, while a rounding-size entry revives them and the iteration leaves the
+saddle, a thousandfold per outer iteration.  Calls only the CPU reference and the seeded
+input generators.
 
     python tests/golden/make_c4_reference.py [workers]
 """
@@ -25,7 +32,7 @@ OUTER = 20
 _GRAPHS = None
 
 
-def _run(A, W0, lam):
+def _run(A, W0, lam, rng=None, eps=0.0):
     import oracle as O
     prm = O.Params(lam=lam)
     W = np.array(W0, dtype=np.float64)
@@ -40,6 +47,9 @@ def _run(A, W0, lam):
             break
         done += 1
         rec = O.monitor(A, W, Ht, prm)
+        if rng is not None:
+            W = np.maximum(W + eps * np.abs(W).max() * rng.standard_normal(W.shape), 0.0)
+            Ht = np.maximum(Ht + eps * np.abs(Ht).max() * rng.standard_normal(Ht.shape), 0.0)
     out = {"breakdown": broke, "outer": done}
     if rec is not None:
         out.update({k: rec[k] for k in ("res_WH", "res_WWt", "pg", "sym_gap", "objective")})
@@ -54,8 +64,8 @@ def _solve(job):
     W0 = np.asarray(gr["W0"][s], dtype=np.float64)
     out = {"g": g, "s": s, "n": int(gr["n"]), "r": int(gr["r"])}
     out.update(_run(A, W0, lam))
-    u = np.random.default_rng(7919 * g + s).choice([-1.0, 1.0], size=W0.shape)
-    out["perturbed"] = _run(A, W0 * (1.0 + 2.0 ** -24 * u), lam)
+    out["perturbed"] = _run(A, W0, lam, np.random.default_rng(7919 * g + s), 2.0 ** -52)
+    out["perturbed32"] = _run(A, W0, lam, np.random.default_rng(7919 * g + s), 2.0 ** -24)
     return out
 
 
