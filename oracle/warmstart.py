@@ -15,16 +15,20 @@ SNMPBB in three steps, each written here plainly in numpy float64:
                every row in the anchor frame are C = Y Y_K^{-1}, computed as
                C = Y Y_K^T (Y_K Y_K^T + eps I)^{-1} with eps = 1e-12 tr(Y_K Y_K^T) / r.
                If Y = W M for some r x r M (as for A = W W^T), C = W W_K^{-1}: the frame
-               removes the random mixing M that a row-wise map could not undo.
-3. network     W0_i = s softplus(M2 relu(M1 c_i + b1) + b2), a row-wise MLP r -> H -> r
-               with BF16 weights M1, M2 (FP32 biases), and the scale
+               removes the random mixing M that a row-wise map could not undo.  C is then
+               divided by the entry RMS of relu(C), so that every problem's coordinates
+               have the same scale (a row-wise map cannot see a per-problem scale).
+3. network     W0_i = s relu(c_i + M2 relu(M1 c_i + b1) + b2), a row-wise residual MLP
+               r -> H -> r with BF16 weights M1, M2 (FP32 biases), and the scale
                s = (sqrt(r) ||A||_F / (n r))^(1/2), the entry RMS of a W with
-               ||W W^T||_F = ||A||_F and r equal orthogonal columns.
+               ||W W^T||_F = ||A||_F and r equal orthogonal columns.  With M2 = 0 and
+               b2 = 0 it is the start of the frame alone, s relu(c_i).
 
-Training: targets are converged SNMPBB factors Ht / s whose columns are permuted to the
+Training: targets are converged SNMPBB factors Ht whose columns are permuted to the
 anchor order by a linear assignment (scipy's Hungarian solver) on the cosine similarity
-of columns; the loss is the mean squared error plus a scale term
-mu (mean(y^2) - mean(t^2))^2; the optimiser is Adam (Kingma & Ba, 2015).
+of columns, divided by their entry RMS (the shape of the factor; s sets the scale); the
+loss is the mean squared error plus a scale term mu (mean(y^2) - mean(t^2))^2; the
+optimiser is Adam (Kingma & Ba, 2015).
 """
 from __future__ import annotations
 
@@ -83,11 +87,20 @@ def coords(Y, K):
     return np.linalg.solve(Gk + eps * np.eye(r), (Y @ YK.T).T).T
 
 
+def rms_pos(C) -> float:
+    """Entry RMS of relu(C)."""
+    pos = np.maximum(C, 0.0)
+    return float(np.sqrt(np.mean(pos * pos)))
+
+
 def frame(A, Omega):
-    """(C, K, Y): coordinates of every row in the SPA anchor frame of the sketch."""
+    """(C, K, Y): coordinates of every row in the SPA anchor frame of the sketch, divided
+    by rms(relu(C)) (left as they are if relu(C) = 0)."""
     Y = sketch(A, Omega)
     K = spa(row_normalise(Y, row_sums(A)), Omega.shape[1])
-    return coords(Y, K), K, Y
+    C = coords(Y, K)
+    rms = rms_pos(C)
+    return (C / rms if rms > 0 else C), K, Y
 
 
 def scale(normA, n, r):
@@ -105,24 +118,16 @@ def bf16_round(x):
 
 
 # --------------------------------------------------------------------------- network
-def softplus(o):
-    return np.maximum(o, 0.0) + np.log1p(np.exp(-np.abs(o)))
-
-
-def sigmoid(o):
-    return 0.5 * (1.0 + np.tanh(0.5 * o))
-
-
 def forward(params, C, quantize=True):
-    """Rows of C (N x r) -> (y, cache): y = softplus(M2 relu(M1 c + b1) + b2)."""
+    """Rows of C (N x r) -> (y, cache): y = relu(c + M2 relu(M1 c + b1) + b2)."""
     M1 = bf16_round(params["M1"]) if quantize else np.asarray(params["M1"], np.float64)
     M2 = bf16_round(params["M2"]) if quantize else np.asarray(params["M2"], np.float64)
     b1 = np.asarray(params["b1"], np.float64)
     b2 = np.asarray(params["b2"], np.float64)
     a = C @ M1.T + b1
     h = np.maximum(a, 0.0)
-    o = h @ M2.T + b2
-    return softplus(o), (C, a, h, o, M1, M2)
+    o = C + h @ M2.T + b2
+    return np.maximum(o, 0.0), (C, a, h, o, M1, M2)
 
 
 def loss(y, T, mu):
@@ -138,7 +143,7 @@ def loss_and_grad(params, C, T, mu, quantize=True):
     N = y.size
     d = np.mean(y * y) - np.mean(T * T)
     dy = 2.0 * (y - T) / N + mu * 2.0 * d * (2.0 * y / N)
-    do = dy * sigmoid(o)
+    do = dy * (o > 0)
     gM2 = do.T @ h
     gb2 = do.sum(axis=0)
     dh = do @ M2
@@ -170,15 +175,24 @@ def match_columns(C, Ht):
     return p
 
 
+def targets(C, Ht):
+    """Training targets of one problem: the columns of Ht in the anchor order
+    (match_columns) divided by their entry RMS (zero if Ht = 0); and the permutation."""
+    p = match_columns(C, Ht)
+    T = np.asarray(Ht, dtype=np.float64)[:, p]
+    rms = float(np.sqrt(np.mean(T * T)))
+    return (T / rms if rms > 0 else T), p
+
+
 def frame_start(A, Omega, normA):
     """The start of the frame alone (the ablation without the network):
     W0 = s relu(C) / rms(relu(C)), rms over all n r entries (W0 = s everywhere if
-    relu(C) = 0)."""
+    relu(C) = 0; the frame's C has rms(relu(C)) = 1 already, up to rounding)."""
     C, K, _ = frame(A, Omega)
     n, r = C.shape
     s = scale(normA, n, r)
     pos = np.maximum(C, 0.0)
-    rms = float(np.sqrt(np.mean(pos * pos)))
+    rms = rms_pos(C)
     return (s * pos / rms if rms > 0 else np.full_like(C, s)), C, K
 
 

@@ -274,14 +274,14 @@ def sketch_matrix(n: int, r: int, seed: int):
 
 
 def mlp_init(r: int, hidden: int = 128, seed: int = SEED_BASE + 16):
-    """Initial weights of the warm-start network r -> hidden -> r: He-normal M1, M2 scaled
-    by 1/sqrt(fan_in) x 0.5, zero b1 and b2 = log(e - 1) (softplus(b2) = 1 for zero input:
-    the untrained net returns the unit-scale start)."""
+    """Initial weights of the residual warm-start network r -> hidden -> r: He-normal M1,
+    zero b1, and zero M2 and b2, so that the untrained network returns its input's
+    positive part (the start of the frame alone)."""
     rng = np.random.default_rng(seed)
     return {"M1": rng.standard_normal((hidden, r)) * np.sqrt(2.0 / r),
             "b1": np.zeros(hidden),
-            "M2": rng.standard_normal((r, hidden)) * (0.5 / np.sqrt(hidden)),
-            "b2": np.full(r, np.log(np.e - 1.0))}
+            "M2": np.zeros((r, hidden)),
+            "b2": np.zeros(r)}
 
 
 # --------------------------------------------------------------------------- HBM-sized inputs

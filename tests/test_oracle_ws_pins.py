@@ -37,7 +37,8 @@ def test_coords_reproduce_planted_mixing():
 
 
 def test_frame_undoes_sketch_mixing_for_exact_low_rank():
-    """A = W W^T with W separable: Y = W (W^T Omega) and C = W W_K^{-1} for any Omega."""
+    """A = W W^T with W separable: Y = W (W^T Omega) and C = W W_K^{-1} for any Omega, up
+    to the frame's scaling to rms(relu(C)) = 1."""
     rng = np.random.default_rng(5)
     n, r = 150, 4
     W = rng.random((n, r)) * 0.2
@@ -47,7 +48,10 @@ def test_frame_undoes_sketch_mixing_for_exact_low_rank():
     for s in range(3):
         Om = gen.sketch_matrix(n, r, 100 + s)
         C, K, _ = WS.frame(A, Om)
-        assert np.max(np.abs(C - W @ np.linalg.inv(W[K]))) <= 1e-7
+        E = W @ np.linalg.inv(W[K])
+        E /= np.sqrt(np.mean(np.maximum(E, 0.0) ** 2))
+        assert np.max(np.abs(C - E)) <= 1e-7
+        assert abs(np.sqrt(np.mean(np.maximum(C, 0.0) ** 2)) - 1.0) <= 1e-12
 
 
 def _fd(fun, x, h=1e-6):
@@ -83,16 +87,39 @@ def test_mlp_gradient_matches_finite_differences(mu):
 
 
 def test_planted_gradient_mistake_is_caught():
-    """A dropped sigmoid factor (a plausible slip) is visible to the FD check."""
+    """A dropped output mask [o > 0] (a plausible slip) is visible to the FD check."""
     rng = np.random.default_rng(4)
     prm = {"M1": rng.standard_normal((5, 3)), "b1": np.zeros(5),
            "M2": rng.standard_normal((3, 5)), "b2": np.zeros(3)}
     C = rng.standard_normal((7, 3))
     T = rng.random((7, 3))
     y, (C_, a, h, o, M1, M2) = WS.forward(prm, C, quantize=False)
-    wrong = (2.0 * (y - T) / y.size).T @ h            # gM2 without the sigmoid
+    assert (o < 0).any() and (o > 0).any()
+    wrong = (2.0 * (y - T) / y.size).T @ h            # gM2 without the mask
     right = WS.loss_and_grad(prm, C, T, 0.0, quantize=False)[1]["M2"]
     assert np.max(np.abs(wrong - right)) > 1e-3
+
+
+def test_residual_network_starts_at_the_frame():
+    """With M2 = 0 and b2 = 0 the network is the frame's own start relu(c)."""
+    rng = np.random.default_rng(8)
+    r = 5
+    prm = gen.mlp_init(r, 16, 3)
+    assert not prm["M2"].any() and not prm["b2"].any()
+    C = rng.standard_normal((40, r))
+    y, _ = WS.forward(prm, C)
+    assert np.array_equal(y, np.maximum(C, 0.0))
+
+
+def test_targets_are_matched_and_unit_rms():
+    rng = np.random.default_rng(12)
+    C = rng.random((60, 4)) ** 3
+    perm = rng.permutation(4)
+    Ht = 7.0 * C[:, perm] + 1e-3 * rng.random((60, 4))
+    T, p = WS.targets(C, Ht)
+    assert np.array_equal(perm[p], np.arange(4))
+    assert abs(np.sqrt(np.mean(T * T)) - 1.0) <= 1e-14
+    assert np.allclose(T * np.sqrt(np.mean(Ht * Ht)), Ht[:, p], rtol=1e-14)
 
 
 def test_adam_first_step_closed_form():
@@ -122,10 +149,7 @@ def test_match_columns_recovers_permutation():
     assert np.array_equal(perm[p], np.arange(6))
 
 
-def test_softplus_and_scale():
-    o = np.array([-800.0, -5.0, 0.0, 3.0, 800.0])
-    ref = np.array([0.0, np.log1p(np.exp(-5.0)), np.log(2.0), np.log1p(np.exp(3.0)), 800.0])
-    assert np.allclose(WS.softplus(o), ref, rtol=1e-15, atol=1e-300)
+def test_scale():
     # r orthogonal columns with entry RMS s have ||W W^T||_F = sqrt(r) n s^2 = ||A||_F
     n, r, normA = 100, 4, 7.0
     s = WS.scale(normA, n, r)
