@@ -51,7 +51,7 @@ def _args():
                     help="c4: JSON cache of the batch autotuner (default: the user cache)")
     ap.add_argument("--train-graphs", type=int, default=2048)
     ap.add_argument("--train-outer", type=int, default=300)
-    ap.add_argument("--epochs", type=int, default=4)
+    ap.add_argument("--epochs", type=int, default=8)
     ap.add_argument("--batch-apass-only", action="store_true",
                     help="only the stacked split-BF16 A-pass of 8 batched restarts, 20 times "
                          "(for hardware counters)")
@@ -318,8 +318,9 @@ def _bench_c4ws(a, torch, np, S, gen):
            "arms": out_arms,
            "training": {"generate_s": t_gen, "solve_frame_targets_s": t_pool,
                         "train_s": t_train, "log": log,
-                        "target_solves_ok": {str(r): v[2] for r, v in pools.items()},
-                        "pool_rows": {str(r): int(v[0].shape[0]) for r, v in pools.items()}}}
+                        "target_solves_ok": {str(r): v[4] for r, v in pools.items()},
+                        "pool_rows": {str(r): int(v[0].shape[0]) for r, v in pools.items()},
+                        "held_rows": {str(r): int(v[2].shape[0]) for r, v in pools.items()}}}
     print(json.dumps(out))
 
 

@@ -343,10 +343,13 @@ snmf_status snmf_batch_size(const snmf_batch* b, int32_t* ninst, int64_t* elemen
  * W0 for each instance of a batch (CSR problems) from a Gaussian sketch Omega:
  *   Y = A Omega; SPA (successive projection, Gillis & Vavasis 2014) on the rows Y_i / d_i,
  *   d = A 1, gives r anchor rows K; C = Y Y_K^T (Y_K Y_K^T + eps I)^{-1},
- *   eps = 1e-12 tr(Y_K Y_K^T) / r (the coordinates in the anchor frame);
- *   W0_i = s softplus(M2 relu(M1 c_i + b1) + b2), s = (sqrt(r) ||A||_F / (n r))^(1/2).
+ *   eps = 1e-12 tr(Y_K Y_K^T) / r (the coordinates in the anchor frame), divided by the
+ *   entry RMS of relu(C) (so that every problem's coordinates have one scale);
+ *   W0_i = s relu(c_i + M2 relu(M1 c_i + b1) + b2), s = (sqrt(r) ||A||_F / (n r))^(1/2),
+ *   a residual network that is the frame's own start s relu(c_i) while M2 = 0, b2 = 0.
  * The network (one per rank r) is trained on converged factors whose columns are matched
- * to the anchor order (linear assignment on column cosines) and divided by s; the loss is
+ * to the anchor order (linear assignment on column cosines) and divided by their entry
+ * RMS (the factor's shape; s sets its scale); the loss is
  * mean((y - t)^2) + mu (mean(y^2) - mean(t^2))^2, the optimiser Adam (beta1 0.9, beta2
  * 0.999, eps 1e-8).  All arrays below are device arrays; the caller owns them. */
 typedef struct snmf_mlp {
@@ -377,10 +380,11 @@ snmf_status snmf_mlp_train_step(const snmf_mlp* m, int64_t pool_rows, const floa
                                 float lr, int32_t step, void* work, size_t work_bytes,
                                 void* stream, double* loss);
 /* The frame of every instance of a CSR batch: Omega, Y, C are batch buffers (the
- * instance-major layout of snmf_batch_apass); anchors (optional): 64 ints per instance. */
+ * instance-major layout of snmf_batch_apass), C scaled to rms(relu(C)) = 1 per instance;
+ * anchors (optional): 64 ints per instance. */
 snmf_status snmf_batch_frame(snmf_batch* b, const void* Omega, void* Y, void* C,
                              int32_t* anchors, void* stream);
-/* Training targets: T[:, j] = Ht[:, p[j]] / s per instance, p the column assignment
+/* Training targets: T[:, j] = Ht[:, p[j]] / rms(Ht) per instance, p the column assignment
  * maximising sum_j cos(C_j, Ht_p[j]); perm (optional): 64 ints per instance. */
 snmf_status snmf_batch_targets(snmf_batch* b, const void* C, const void* Ht, void* T,
                                int32_t* perm, void* stream);

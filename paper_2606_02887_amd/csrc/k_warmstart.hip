@@ -3,10 +3,12 @@
 //   frame   for every instance (one workgroup each): d = A 1, the sketch rows Y_i / d_i,
 //           successive projection (SPA, Gillis & Vavasis 2014) for r anchor rows K, and
 //           the coordinates C = Y Y_K^T (Y_K Y_K^T + eps I)^{-1}, eps = 1e-12 tr / r;
-//   network W0_i = s softplus(M2 relu(M1 c_i + b1) + b2), r -> H -> r, BF16 weights and
-//           FP32 arithmetic, s = (sqrt(r) ||A||_F / (n r))^(1/2);
+//           divided by the entry RMS of relu(C);
+//   network W0_i = s relu(c_i + M2 relu(M1 c_i + b1) + b2), r -> H -> r (residual: with
+//           M2 = 0, b2 = 0 the frame's own start s relu(c_i)), BF16 weights and FP32
+//           arithmetic, s = (sqrt(r) ||A||_F / (n r))^(1/2);
 //   targets converged factor columns matched to the anchor order (linear assignment on
-//           column cosines, Hungarian method) and divided by s;
+//           column cosines, Hungarian method) and divided by their entry RMS;
 //   training forward / backward over a minibatch of rows, gradients reduced in a fixed
 //           order, Adam (Kingma & Ba 2015), BF16 copies refreshed after every step.
 #include "common.hpp"
@@ -205,6 +207,7 @@ __global__ __launch_bounds__(kThreads) void k_ws_frame(const BInst* __restrict__
   }
   __syncthreads();
   T* __restrict__ Cout = Cbuf + d.off;
+  double pos2[1] = {0.0};  // sum of relu(C)^2 of the stored values
   for (int64_t row = threadIdx.x; row < n; row += kThreads) {
     double y[RP];
 #pragma unroll
@@ -214,8 +217,20 @@ __global__ __launch_bounds__(kThreads) void k_ws_frame(const BInst* __restrict__
 #pragma unroll
       for (int c = 0; c < RP; ++c)
         if (c < r) s = __builtin_fma(y[c], sG[c * kMaxRank + b], s);
-      Cout[row * r + b] = (T)s;
+      const T cv = (T)s;
+      Cout[row * r + b] = cv;
+      const double p = fmax((double)cv, 0.0);
+      pos2[0] = __builtin_fma(p, p, pos2[0]);
     }
+  }
+  // C divided by the entry RMS of relu(C) (kept if relu(C) = 0): every thread rescales
+  // the rows it wrote
+  block_sum<1>(pos2, sv);
+  const double rms = sqrt(pos2[0] / ((double)n * r));
+  if (rms > 0.0) {
+    const double kap = 1.0 / rms;
+    for (int64_t row = threadIdx.x; row < n; row += kThreads)
+      for (int b = 0; b < r; ++b) Cout[row * r + b] = (T)((double)Cout[row * r + b] * kap);
   }
   if ((int)threadIdx.x < r) anchors[(size_t)i * kMaxRank + threadIdx.x] = sK[threadIdx.x];
 }
@@ -269,7 +284,7 @@ template void launch_ws_frame<double>(const BInst*, int, int, const BGraph*, con
 // ----------------------------------------------------------------------------- targets
 // One workgroup per instance: cosines of the columns of C and Ht (FP64), the assignment
 // p maximising sum_j cos(C_j, Ht_p[j]) (Hungarian method with potentials on the cost
-// -cos, one thread), then Tout[:, j] = Ht[:, p[j]] / s.
+// -cos, one thread), then Tout[:, j] = Ht[:, p[j]] / rms(Ht).
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_ws_match(const BInst* __restrict__ inst,
                                                        const T* __restrict__ Cbuf,
@@ -362,8 +377,12 @@ __global__ __launch_bounds__(kThreads) void k_ws_match(const BInst* __restrict__
     for (int j = 1; j <= r; ++j) sp[p[j] - 1] = j - 1;  // anchor p[j]-1 <- column j-1
   }
   __syncthreads();
-  const double s = sqrt(sqrt((double)r) * sqrt(d.normA2) / ((double)n * r));
-  const double inv = s > 0.0 ? 1.0 / s : 0.0;
+  // the matched columns divided by their entry RMS (||Ht||_F^2 = sum of the squared
+  // column norms, added in column order)
+  double h2 = 0.0;
+  for (int b = 0; b < r; ++b) h2 = __builtin_fma(hn[b], hn[b], h2);
+  const double rms = sqrt(h2 / ((double)n * r));
+  const double inv = rms > 0.0 ? 1.0 / rms : 1.0;
   T* __restrict__ Tout = Tbuf + d.off;
   for (int64_t e = threadIdx.x; e < n * r; e += kThreads) {
     const int64_t row = e / r;
@@ -417,8 +436,8 @@ template void launch_ws_spa_only<double>(const BInst*, int, const double*, doubl
 
 // ----------------------------------------------------------------------------- network
 // Weights staged in LDS as FP32 (dequantised BF16): M1 (H x r) and M2^T (H x r), so row
-// k of each is contiguous.  One thread per row: a_k = M1_k c + b1_k, h_k = relu(a_k),
-// o += h_k M2[:, k]; y = softplus(o) (the stable form max(o, 0) + log1p(exp(-|o|))).
+// k of each is contiguous.  One thread per row: o = c + b2, then for every hidden unit
+// a_k = M1_k c + b1_k, h_k = relu(a_k), o += h_k M2[:, k]; y = relu(o).
 template <int RP>
 struct MlpSmem {
   float M1[kMlpHidden * RP];
@@ -438,10 +457,6 @@ __device__ __forceinline__ void mlp_stage(const MlpDev& m, MlpSmem<RP>& sm) {
   for (int e = threadIdx.x; e < kMlpHidden; e += kThreads) sm.b1[e] = m.b1[e];
   for (int e = threadIdx.x; e < RP; e += kThreads) sm.b2[e] = e < r ? m.b2[e] : 0.f;
   __syncthreads();
-}
-
-__device__ __forceinline__ float softplusf(float o) {
-  return fmaxf(o, 0.f) + log1pf(expf(-fabsf(o)));
 }
 
 // Forward over rows of a plain N x r array, or (bm.blk_inst != null) over the rows of the
@@ -478,7 +493,7 @@ __global__ __launch_bounds__(kThreads) void k_mlp_fwd(MlpDev m, int64_t N,
 #pragma unroll
     for (int j = 0; j < RP; ++j) {
       c[j] = j < r ? C[off + row * r + j] : 0.f;
-      o[j] = sm.b2[j];
+      o[j] = sm.b2[j] + c[j];  // the residual: o = c + M2 h + b2
     }
     for (int k = 0; k < kMlpHidden; ++k) {
       float a = sm.b1[k];
@@ -492,7 +507,7 @@ __global__ __launch_bounds__(kThreads) void k_mlp_fwd(MlpDev m, int64_t N,
     const float s = row_scale ? row_scale[row] : sc;
     for (int j = 0; j < r; ++j) {
       if (cache_o) cache_o[q * r + j] = o[j];
-      Y[off + q * r + j] = s * softplusf(o[j]);
+      Y[off + q * r + j] = s * fmaxf(o[j], 0.f);
     }
   }
 }
@@ -520,7 +535,7 @@ __global__ __launch_bounds__(kThreads) void k_mlp_loss_parts(int64_t B, int r,
     for (int j = 0; j < 3; ++j) part[(size_t)blockIdx.x * kNumPart + j] = v[j];
 }
 
-// do = dL/dy * sigmoid(o) with dL/dy = 2 (y - t) / N + mu 2 dlt 2 y / N; then
+// do = dL/dy * [o > 0] with dL/dy = 2 (y - t) / N + mu 2 dlt 2 y / N; then
 // da = (M2^T do) * [a > 0].  scal: {sum (y-t)^2, sum y^2, sum t^2} after reduction.
 template <int RP>
 __global__ __launch_bounds__(kThreads) void k_mlp_back_rows(MlpDev m, int64_t B,
@@ -558,9 +573,7 @@ __global__ __launch_bounds__(kThreads) void k_mlp_back_rows(MlpDev m, int64_t B,
     if (j < r) {
       const float yy = y[q * r + j], tt = T[row * r + j];
       const float dy = (float)(2.0 / N) * (yy - tt) + mu * 2.f * dlt * (float)(2.0 / N) * yy;
-      const float o = cache_o[q * r + j];
-      const float sg = 0.5f * (1.f + tanhf(0.5f * o));
-      g = dy * sg;
+      g = cache_o[q * r + j] > 0.f ? dy : 0.f;
       dO[q * r + j] = g;
     }
     dov[j] = g;

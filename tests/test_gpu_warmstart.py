@@ -84,8 +84,11 @@ def test_frame_matches_oracle(S, prec):
         # decisions taken on the device's own sketch
         K = WS.spa(WS.row_normalise(Yb[i], WS.row_sums(a_in[g])), r)
         assert list(anc[i, :r]) == K, i
-        assert nrel(Cb[i], WS.coords(Yb[i], K)) <= ctol, i
-        assert np.allclose(Cb[i][K], np.eye(r), atol=1e-6 if prec == "f64" else 1e-3)
+        Co = WS.coords(Yb[i], K)
+        rms = WS.rms_pos(Co)
+        assert nrel(Cb[i], Co / rms) <= ctol, i
+        assert np.allclose(Cb[i][K] * rms, np.eye(r), atol=1e-6 if prec == "f64" else 1e-3)
+        assert abs(WS.rms_pos(Cb[i]) - 1.0) <= (1e-12 if prec == "f64" else 1e-6)
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
@@ -111,16 +114,16 @@ def test_targets_match_oracle(S, prec):
     for i in range(len(Tb)):
         g = i // 2
         n, r = graphs[g]
-        pi = WS.match_columns(Cb[i], Hb[i])
+        To, pi = WS.targets(Cb[i], Hb[i])
         assert list(perm[i, :r]) == list(pi), i
-        s = WS.scale(np.sqrt(O.norm2_A(a_in[g])), n, r)
-        assert nrel(Tb[i], Hb[i][:, pi] / s) <= (1e-12 if prec == "f64" else 1e-6), i
+        assert nrel(Tb[i], To) <= (1e-12 if prec == "f64" else 1e-6), i
 
 
 def _rand_init(r, seed):
     rng = np.random.default_rng(seed)
     init = gen.mlp_init(r, 128, seed)
     init["b1"] = 0.1 * rng.standard_normal(128)
+    init["M2"] = rng.standard_normal((r, 128)) * (0.5 / np.sqrt(128))
     init["b2"] = 0.3 * rng.standard_normal(r)
     return init
 
@@ -193,7 +196,7 @@ def test_batch_warmstart_end_to_end(S):
         s = WS.scale(np.sqrt(O.norm2_A(a_in[g])), n, r)
         yo, _ = WS.forward(prm, Cb[i])
         assert nrel(Wb[i], s * yo) <= 2e-6, i
-        assert (Wb[i] > 0).all()
+        assert (Wb[i] >= 0).all() and np.array_equal(Wb[i] == 0, yo == 0)
 
 
 def test_warmstart_error_codes(S):
@@ -269,19 +272,28 @@ def test_single_problem_learned_start_matches_oracle(S, kind):
     Wo, _, _ = WS.warm_start(mlp.params(), ref, Om.double().cpu().numpy(),
                              np.sqrt(O.norm2_A(ref)))
     assert nrel(W0, Wo) <= 2e-5, nrel(W0, Wo)
-    assert (W0 > 0).all()
+    assert (W0 >= 0).all()
 
 
 def test_warm_start_gain_on_detectable_graphs(S):
-    """Trained on 48 separately seeded SBM graphs (clusters detectable), the learned start
-    and the frame alone are closer to the end point after the first outer iteration than
-    random starts on 12 held-out graphs (median over graphs of res_1 / best final - 1)."""
+    """Trained on 48 separately seeded SBM graphs (clusters detectable; every tenth held
+    out for validation), the network's held-out loss falls below that of the frame's own
+    start (the network's starting point) on the same targets; on 12 further graphs the
+    learned start and the frame alone are closer to the end point after the first outer
+    iteration than random starts (median over graphs of res_1 / best final - 1), and the
+    learned start needs no more outer iterations to tau_g = (1 + 1e-4) x best final
+    residual than the frame alone (median over graphs)."""
     from paper_2606_02887_amd import train_ws
     mk = lambda num, seed: gen.batched_sbm(num_graphs=num, n_lo=240, n_hi=480, ranks=(8,),
                                            restarts=3, p_in=0.2, p_out=0.01, seed=seed)
     train = mk(48, 30000)
     pools = train_ws.training_pools(S, torch, train, outer=120)
-    models = train_ws.train(S, torch, pools, epochs=6, batch=1024, lr=2e-3)
+    log = []
+    models = train_ws.train(S, torch, pools, epochs=12, batch=1024, lr=2e-3, log=log)
+    for rec in log:
+        print(rec)
+    assert abs(log[0]["held_loss"] - log[0]["frame_held_loss"]) <= 1e-6 * log[0]["frame_held_loss"]
+    assert log[-1]["held_loss"] < log[-1]["frame_held_loss"]
     test = mk(12, 31000)
     As = [S.csr_from_scipy(g["A"], torch.float32) for g in test]
     W0r = torch.from_numpy(np.concatenate([np.stack(g["W0"]).ravel() for g in test])).to(
@@ -296,13 +308,21 @@ def test_warm_start_gain_on_detectable_graphs(S):
     for g in range(len(test)):
         best.append(min(runs[k][3][g * 3 + s, T - 1, 0] for k in runs for s in range(3)
                         if runs[k][2][g * 3 + s]["status"] == 0))
-    gap = {}
-    for it in (1, 2, 4):
-        for k, (_, _, infos, tr) in runs.items():
+    gap, its = {}, {}
+    for k, (_, _, infos, tr) in runs.items():
+        for it in (1, 2, 4):
             per = [min(tr[g * 3 + s, it - 1, 0] for s in range(3)) / best[g] - 1.0
                    for g in range(len(test))]
             gap[(k, it)] = float(np.median(per))
+        per = []
+        for g in range(len(test)):
+            hit = [np.nonzero(tr[g * 3 + s, :, 0] <= (1 + 1e-4) * best[g])[0] for s in range(3)
+                   if infos[g * 3 + s]["status"] == 0]
+            firsts = [h[0] + 1 for h in hit if h.size]
+            per.append(min(firsts) if firsts else T + 1)
+        its[k] = float(np.median(per))
     print("median gap after 1, 2, 4 outer iterations:", gap)
-    gap = {k: gap[(k, 1)] for k in runs}
-    assert gap["learned"] < gap["random"]
-    assert gap["frame"] < gap["random"]
+    print("median outer iterations to tau_g:", its)
+    assert gap[("learned", 1)] < gap[("random", 1)]
+    assert gap[("frame", 1)] < gap[("random", 1)]
+    assert its["learned"] <= its["frame"]
