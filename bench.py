@@ -78,10 +78,22 @@ def _cpu_baseline(A64, W0, lam, outer):
     t0 = time.perf_counter()
     O.snmpbb(A64, W0, O.Params(lam=lam), outer)
     dt = time.perf_counter() - t0
-    return {"value": outer / dt, "unit": "outer iterations/s", "cores": int(threads),
-            "kind": "oracle",
-            "sample": f"{outer} outer iterations of the FP64 numpy reference on the same "
-                      f"n={N}, r={R} workload ({dt:.1f} s)"}
+    out = {"value": outer / dt, "unit": "outer iterations/s", "cores": int(threads),
+           "kind": "oracle",
+           "sample": f"{outer} outer iterations of the FP64 numpy reference on the same "
+                     f"n={N}, r={R} workload ({dt:.1f} s)"}
+    # the same reference on one thread (BLAS limited to one), one outer iteration
+    try:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            O.snmpbb(A64, W0, O.Params(lam=lam), 1)
+            d1 = time.perf_counter() - t0
+        out["single_thread"] = {"value": 1.0 / d1, "unit": "outer iterations/s", "cores": 1,
+                                "sample": f"1 outer iteration on one thread ({d1:.1f} s)"}
+    except Exception as e:  # pragma: no cover
+        out["single_thread"] = {"error": str(e)}
+    return out
 
 
 COPY_BYTES = 256 << 20
