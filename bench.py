@@ -39,14 +39,15 @@ def _args():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-outer", type=int, default=0,
                     help="outer iterations of the CPU-reference sample (0: pick ~15 s)")
-    ap.add_argument("--workload", choices=("c1", "c2", "c3", "c4", "c4ws", "scale"), default="c1",
+    ap.add_argument("--workload", choices=("c1", "c2", "c3", "c4", "c4ws", "scale", "nmf"), default="c1",
                     help="c1: dense n=8192, r=64 (the headline line); c4: 256 SBM graphs, "
                          "8 restarts each, in one batched solve; c4ws: the learned warm start "
                          "(trained here) against random starts and the frame alone on c4; c2: "
                          "Graph-SNMPBB on an SBM graph n=20000, r=20 with its kNN Laplacian; "
                          "c3: LAI-SNMPBB on a rank-64 surrogate of a power-law graph n=200000, "
                          "r=32; scale: the sparse and low-rank A-pass kernels at n=2e6 (past "
-                         "the caches) against the HBM roofline, beside a device copy")
+                         "the caches) against the HBM roofline, beside a device copy; nmf: "
+                         "NMPBB for rectangular NMF on a dense and a sparse V")
     ap.add_argument("--tuning-cache", default=None,
                     help="c4: JSON cache of the batch autotuner (default: the user cache)")
     ap.add_argument("--train-graphs", type=int, default=2048)
@@ -446,6 +447,46 @@ def _bench_c3(a, torch, np, S, gen):
                         "products), 5 shifted/plain Cholesky QR rounds, Q^T A Q, Jacobi"}))
 
 
+def _bench_nmf(a, torch, np, S, gen):
+    """NMPBB for rectangular NMF (eq. (1.1)): a planted dense V (m = 8192, n = 4096,
+    r = 64, FP32, read in place) and a sparse V (m = 100000, n = 20000, 0.1% of the
+    entries, r = 32, FP32, transposed once on the device).  value: dense outer iterations/s
+    (W-step and H-step of 5 inner iterations each)."""
+    dev = torch.device("cuda:0")
+    out = {"metric": "NMF outer iterations/s (dense V 8192 x 4096, r = 64, FP32)",
+           "unit": "outer iterations/s", "n_gpus": 1, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic"}
+    cases = {}
+    for name, prob, r, ncols in (("dense", gen.planted_rect(8192, 4096, 64, 1031), 64, 4096),
+                                 ("csr", gen.random_rect_csr(100000, 20000, 0.001, 32, 1032), 32,
+                                  20000)):
+        if name == "dense":
+            Vt = torch.from_numpy(prob["V"]).to(dev, torch.float32)
+            M = S.dense(Vt)
+        else:
+            M = S.csr_from_scipy(prob["V"], torch.float32)
+        W0 = torch.from_numpy(prob["W0"]).to(dev, torch.float32)
+        H0 = torch.from_numpy(prob["Ht0"]).to(dev, torch.float32)
+        S.nmf_solve(M, ncols, W0, H0, S.params(prec=S.F32, lam=0.0, max_outer=a.warmup))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, info = S.nmf_solve(M, ncols, W0, H0, S.params(prec=S.F32, lam=0.0,
+                                                           max_outer=a.steps,
+                                                           check_every=1 << 30))
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        cases[name] = {"outer_per_s": a.steps / el, "ms_per_outer": 1e3 * el / a.steps,
+                       "res_WH": info["res_WH"], "m": int(M.n), "n": int(ncols), "r": r,
+                       "nnz": int(prob["V"].nnz) if name == "csr" else None}
+    out.update({"value": cases["dense"]["outer_per_s"], "steps": a.steps, "warmup": a.warmup,
+                "ms_per_step": cases["dense"]["ms_per_outer"],
+                "config": {"workload": "planted dense V = max(W* H*^T + E, 0) 8192 x 4096, "
+                                       "seed 1031; sparse V 100000 x 20000, seed 1032",
+                           "parallelism": "single GPU"},
+                "cases": cases})
+    print(json.dumps(out))
+
+
 def _bench_scale(a, torch, np, S, gen):
     """The HBM-bound A-pass kernels at a size past the L2 and the 256 MB last-level cache:
     the CSR SpMM (random symmetric graph, n = 2e6, mean degree 30, r = 20 and 32) and the
@@ -514,7 +555,7 @@ def main():
         from paper_2606_02887_amd import gen
         from paper_2606_02887_amd import snmf as S
         {"c2": _bench_c2, "c3": _bench_c3, "c4": _bench_c4, "c4ws": _bench_c4ws,
-         "scale": _bench_scale}[a.workload](
+         "scale": _bench_scale, "nmf": _bench_nmf}[a.workload](
             a, torch, np, S, gen)
         return
 

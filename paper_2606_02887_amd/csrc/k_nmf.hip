@@ -174,6 +174,131 @@ __global__ __launch_bounds__(kThreads) void k_csr_sort_pairs(const int64_t* __re
   }
 }
 
+// ----------------------------------------------------------------------------- FP32 MFMA
+typedef float f32x16n __attribute__((ext_vector_type(16)));
+
+// Split-K product panel y of B = A^T P: Bpart[y][j][m] = sum over k in chunk y of
+// A[k][j] P[k][m], A K x N row-major (leading dimension lda), P K x r, on
+// v_mfma_f32_32x32x2f32.  Grid x: blocks of 256 output rows (4 waves x 64), y: K chunks of
+// kchunk rows (kchunk even).  Wave w takes output rows j0 .. j0 + 63 (two MFMA N-blocks)
+// and all r <= 64 columns (NMB M-blocks of 32); per k-pair lane (c, h) = (lane % 32,
+// lane / 32) loads A[k + h][j0 + c], A[k + h][j0 + 32 + c] and P[k + h][c], P[k + h][32 + c],
+// eight k-pairs per batch with the next batch in flight during this one's MFMAs.  With
+// A = V (m x n) the panel sums give V^T P (the H-step), with A = V^T (an n x m transposed
+// copy) V P (the W-step).  Skipped when the solve is done.
+template <int NMB>
+__global__ __launch_bounds__(256) void k_rect_f32(const float* __restrict__ A, int64_t lda,
+                                                  const float* __restrict__ P, int64_t K,
+                                                  int64_t N, int r, int64_t kchunk,
+                                                  float* __restrict__ Bpart, int64_t pstride,
+                                                  const State* __restrict__ st) {
+  if (st->done) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int c = lane & 31, h = lane >> 5;
+  const int64_t j0 = ((int64_t)blockIdx.x * 4 + wave) * 64;
+  const int64_t kb = (int64_t)blockIdx.y * kchunk;
+  const int64_t ke = kb + kchunk < K ? kb + kchunk : K;
+  f32x16n acc[NMB][2];
+#pragma unroll
+  for (int mb = 0; mb < NMB; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[mb][nb][v] = 0.0f;
+  const bool jok0 = j0 + c < N, jok1 = j0 + 32 + c < N;
+  const bool mok0 = c < r, mok1 = 32 + c < r;
+  const float* arow = A + j0 + c;
+  constexpr int U = 8;
+  float a0[U], a1[U], p0[U], p1[U];
+  float b0[U], b1[U], q0[U], q1[U];
+  auto load = [&](float (&x0)[U], float (&x1)[U], float (&y0)[U], float (&y1)[U], int64_t kk0) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t kk = kk0 + 2 * u + h;
+      x0[u] = jok0 ? __builtin_nontemporal_load(arow + kk * lda) : 0.0f;
+      x1[u] = jok1 ? __builtin_nontemporal_load(arow + kk * lda + 32) : 0.0f;
+      y0[u] = mok0 ? P[kk * r + c] : 0.0f;
+      if (NMB > 1) y1[u] = mok1 ? P[kk * r + 32 + c] : 0.0f;
+    }
+  };
+  auto mma = [&](const float (&x0)[U], const float (&x1)[U], const float (&y0)[U],
+                 const float (&y1)[U]) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(y0[u], x0[u], acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(y0[u], x1[u], acc[0][1], 0, 0, 0);
+      if (NMB > 1) {
+        acc[NMB - 1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(y1[u], x0[u], acc[NMB - 1][0], 0, 0, 0);
+        acc[NMB - 1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(y1[u], x1[u], acc[NMB - 1][1], 0, 0, 0);
+      }
+    }
+  };
+  int64_t k = kb;
+  if (k + 2 * U <= ke) load(a0, a1, p0, p1, k);
+  while (k + 2 * U <= ke) {
+    if (k + 4 * U <= ke) {
+      load(b0, b1, q0, q1, k + 2 * U);
+      mma(a0, a1, p0, p1);
+      k += 2 * U;
+      if (k + 4 * U <= ke) load(a0, a1, p0, p1, k + 2 * U);
+      mma(b0, b1, q0, q1);
+      k += 2 * U;
+    } else {
+      mma(a0, a1, p0, p1);
+      k += 2 * U;
+    }
+  }
+  for (; k < ke; k += 2) {
+    const int64_t kk = k + h;
+    const bool kin = kk < ke;
+    const float x0 = (kin && jok0) ? arow[kk * lda] : 0.0f;
+    const float x1 = (kin && jok1) ? arow[kk * lda + 32] : 0.0f;
+    const float y0 = (kin && mok0) ? P[kk * r + c] : 0.0f;
+    const float y1 = (NMB > 1 && kin && mok1) ? P[kk * r + 32 + c] : 0.0f;
+    acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(y0, x0, acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(y0, x1, acc[0][1], 0, 0, 0);
+    if (NMB > 1) {
+      acc[NMB - 1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(y1, x0, acc[NMB - 1][0], 0, 0, 0);
+      acc[NMB - 1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(y1, x1, acc[NMB - 1][1], 0, 0, 0);
+    }
+  }
+  // D[m][j] of block (mb, nb): lane (c, h) holds j = j0 + 32 nb + c and
+  // m = 32 mb + 8 (v / 4) + 4 h + v % 4 in register v
+  float* out = Bpart + (int64_t)blockIdx.y * pstride;
+#pragma unroll
+  for (int mb = 0; mb < NMB; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb) {
+      const int64_t j = j0 + 32 * nb + c;
+      if (j < N) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int m = 32 * mb + 8 * (v >> 2) + 4 * h + (v & 3);
+          if (m < r) out[j * r + m] = acc[mb][nb][v];
+        }
+      }
+    }
+}
+
+// AT (cols x rows) = A^T for A rows x cols (leading dimension lda): 64 x 64 tiles through
+// LDS, reads and writes along rows.
+template <typename T>
+__global__ __launch_bounds__(256) void k_transpose(const T* __restrict__ A, int64_t rows,
+                                                   int64_t cols, int64_t lda, T* __restrict__ AT) {
+  __shared__ T t[64][65];
+  const int64_t r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int i = ty; i < 64; i += 4) {
+    const int64_t rr = r0 + i, cc = c0 + tx;
+    t[i][tx] = (rr < rows && cc < cols) ? A[rr * lda + cc] : T(0);
+  }
+  __syncthreads();
+  for (int i = ty; i < 64; i += 4) {
+    const int64_t cc = c0 + i, rr = r0 + tx;
+    if (cc < cols && rr < rows) AT[cc * rows + rr] = t[tx][i];
+  }
+}
+
 static unsigned nblk(int64_t m) {
   int64_t b = (m + kThreads - 1) / kThreads;
   return (unsigned)(b < 1 ? 1 : b);
@@ -208,6 +333,38 @@ void launch_csr_transpose(const int64_t* rowptr, const int32_t* col, const T* va
   hipLaunchKernelGGL(k_csr_sort_pairs<T>, dim3(nblk(ncols)), dim3(kThreads), 0, s,
                      (const int64_t*)rowptrT, ncols, colT, valT);
 }
+
+RectSplit rect_split(int64_t K, int64_t N) {
+  RectSplit sp;
+  sp.gx = (int)((N + 255) / 256);
+  int64_t want = (512 + sp.gx - 1) / sp.gx;          // about two workgroups per CU
+  int64_t most = (K + 63) / 64;                      // chunks of at least 64 rows
+  if (want > most) want = most;
+  if (want < 1) want = 1;
+  sp.kchunk = ((K + want - 1) / want + 15) / 16 * 16;  // whole batches of eight k-pairs
+  sp.ksplit = (int)((K + sp.kchunk - 1) / sp.kchunk);
+  return sp;
+}
+
+void launch_rect_f32(const float* A, int64_t lda, const float* P, int64_t K, int64_t N, int r,
+                     const RectSplit& sp, float* Bpart, const State* st, hipStream_t s) {
+  const dim3 grid((unsigned)sp.gx, (unsigned)sp.ksplit);
+  if (r > 32)
+    hipLaunchKernelGGL(k_rect_f32<2>, grid, dim3(256), 0, s, A, lda, P, K, N, r, sp.kchunk,
+                       Bpart, N * r, st);
+  else
+    hipLaunchKernelGGL(k_rect_f32<1>, grid, dim3(256), 0, s, A, lda, P, K, N, r, sp.kchunk,
+                       Bpart, N * r, st);
+}
+
+template <typename T>
+void launch_transpose(const T* A, int64_t rows, int64_t cols, int64_t lda, T* AT, hipStream_t s) {
+  hipLaunchKernelGGL(k_transpose<T>, dim3((unsigned)((cols + 63) / 64), (unsigned)((rows + 63) / 64)),
+                     dim3(256), 0, s, A, rows, cols, lda, AT);
+}
+template void launch_transpose<float>(const float*, int64_t, int64_t, int64_t, float*, hipStream_t);
+template void launch_transpose<double>(const double*, int64_t, int64_t, int64_t, double*,
+                                       hipStream_t);
 
 template void launch_rect_apass<float>(const float*, int64_t, int64_t, int64_t, int, const float*,
                                        int, float*, const State*, hipStream_t);

@@ -208,6 +208,17 @@ void launch_knn_values(const T* X, int64_t n, int dim, double sigma, int laplaci
 template <typename T>
 void launch_rect_apass(const T* V, int64_t ld, int64_t rows, int64_t K, int trans, const T* P,
                        int r, T* B, const State* st, hipStream_t s);
+// Split-K panels of B = A^T P on FP32 MFMA (A K x N): gx blocks of 256 output rows, ksplit
+// chunks of kchunk rows of K (panel y at Bpart + y N r).
+struct RectSplit {
+  int gx = 1, ksplit = 1;
+  int64_t kchunk = 0;
+};
+RectSplit rect_split(int64_t K, int64_t N);
+void launch_rect_f32(const float* A, int64_t lda, const float* P, int64_t K, int64_t N, int r,
+                     const RectSplit& sp, float* Bpart, const State* st, hipStream_t s);
+template <typename T>
+void launch_transpose(const T* A, int64_t rows, int64_t cols, int64_t lda, T* AT, hipStream_t s);
 void launch_csr_check_rect(const int64_t* rowptr, const int32_t* col, int64_t m, int64_t ncols,
                            int64_t nnz, unsigned* flags, hipStream_t s);
 template <typename T>

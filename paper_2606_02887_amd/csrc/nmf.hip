@@ -33,6 +33,8 @@ struct NmfPlan {
   void* pool = nullptr;
   void *Wb = nullptr, *Hb = nullptr, *C = nullptr, *g = nullptr, *Z = nullptr, *D = nullptr,
        *B = nullptr, *Pz = nullptr, *GT[2] = {nullptr, nullptr};
+  void *VT = nullptr, *Bpart = nullptr;  // dense FP32: V^T and the split-K panels
+  RectSplit spW, spH;
   double* G64[2] = {nullptr, nullptr};
   double *part = nullptr, *gram_part = nullptr, *dots = nullptr;
   double *partsA = nullptr, *partsB = nullptr, *partsC = nullptr, *trace = nullptr;
@@ -73,7 +75,16 @@ void half_step(NmfPlan& pl, T* X, int64_t nX, const T* P, int64_t nP, int is_hst
   launch_gram<T>(P, nP, r, pl.gram_part, gram_blocks(nP), pl.G64[gi], (T*)pl.GT[gi], pl.st, s);
   if (with_rho) launch_rho(pl.G64[gi], r, pl.st, s);
   T* B = (T*)pl.B;
-  if (pl.V.fmt == SNMF_DENSE) {
+  int ksplit = 1;
+  if (pl.V.fmt == SNMF_DENSE && sizeof(T) == 4) {
+    // FP32 MFMA: the H-step's V^T W reads V, the W-step's V Ht its transposed copy
+    const RectSplit& sp = is_hstep ? pl.spH : pl.spW;
+    const float* A = is_hstep ? (const float*)pl.V.dense : (const float*)pl.VT;
+    const int64_t lda = is_hstep ? pl.V.ld : pl.m;
+    launch_rect_f32(A, lda, (const float*)P, nP, nX, r, sp, (float*)pl.Bpart, pl.st, s);
+    B = (T*)pl.Bpart;
+    ksplit = sp.ksplit;
+  } else if (pl.V.fmt == SNMF_DENSE) {
     launch_rect_apass<T>((const T*)pl.V.dense, pl.V.ld, nX, nP, is_hstep, P, r, B, pl.st, s);
   } else if (!is_hstep) {
     launch_spmm<T>(pl.V.rowptr, pl.V.col, (const T*)pl.V.val, P, nX, r, B, nullptr, nullptr,
@@ -87,8 +98,8 @@ void half_step(NmfPlan& pl, T* X, int64_t nX, const T* P, int64_t nP, int is_hst
   // one grid for both half-steps: the first inner kernel of a W-step reduces the partial
   // sums of the previous H-step's last kernel together with its own init's
   const int grid = pl.grid;
-  launch_init<T>(X, Pz, B, 1, nX * r, (T*)pl.C, (T*)pl.g, nullptr, GT, nX, r, is_hstep, pl.kp,
-                 pl.st, pl.partsA, s, BMap{}, grid);
+  launch_init<T>(X, Pz, B, ksplit, nX * r, (T*)pl.C, (T*)pl.g, nullptr, GT, nX, r, is_hstep,
+                 pl.kp, pl.st, pl.partsA, s, BMap{}, grid);
   T* Z = (T*)pl.Z;
   T* D = (T*)pl.D;
   T* g = (T*)pl.g;
@@ -243,6 +254,14 @@ snmf_status nmf_solve(const snmf_matrix* V, int64_t ncols, int32_t r, const void
   add((void**)&pl.st, sizeof(State));
   add((void**)&pl.counters, C_COUNT * sizeof(unsigned));
   add((void**)&pl.flags, 4 * sizeof(unsigned));
+  if (V->fmt == SNMF_DENSE && p->prec == SNMF_F32) {
+    if ((m + 63) / 64 > 65535 || (ncols + 63) / 64 > 65535)
+      return fail(SNMF_E_SHAPE, "V: FP32 dense NMF takes m, n_cols <= 4194240");
+    pl.spW = rect_split(ncols, m);  // W-step: K = n_cols, output rows m
+    pl.spH = rect_split(m, ncols);  // H-step: K = m, output rows n_cols
+    add(&pl.VT, (size_t)m * ncols * 4);
+    add(&pl.Bpart, (size_t)std::max<int64_t>(pl.spW.ksplit * m, pl.spH.ksplit * ncols) * r * 4);
+  }
   if (V->fmt == SNMF_CSR) {
     add((void**)&pl.cnt, (size_t)ncols * sizeof(unsigned));
     add((void**)&pl.cursor, (size_t)ncols * 8);
@@ -295,6 +314,10 @@ snmf_status nmf_solve(const snmf_matrix* V, int64_t ncols, int32_t r, const void
   }
   pl.normV2 = st3[0];
   if (!(pl.normV2 > 0.0)) return fail(SNMF_E_ARG, "V is zero");
+  if (pl.VT) {
+    launch_transpose<float>((const float*)V->dense, m, ncols, V->ld, (float*)pl.VT, s);
+    HIP_TRY(hipGetLastError());
+  }
   if (p->validate) {
     double w3[3], h3[3];
     if (pl.prec == SNMF_F64) {

@@ -31,7 +31,7 @@ def half_step_fp32(hs, X0, prm):
         return f32(L @ V) if L is not None else 0.0
 
     X = f32(X0)
-    C = f32(hs.B + lam * hs.P)
+    C = f32(hs.B + lam * hs.P) if lam else f32(hs.B)   # (NMF: P and X differ in shape)
     g = f32(f32(X @ G32) + f32(lam * X) - C)
     if L is not None:
         g = f32(g + f32(gam * lap(X)))
