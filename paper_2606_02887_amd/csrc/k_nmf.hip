@@ -3,6 +3,7 @@
 // counts, their scan, the scatter and a per-row sort that makes the result deterministic).
 #include "common.hpp"
 #include "kernels.hpp"
+#include "rho.hpp"
 
 namespace snmf {
 
@@ -185,18 +186,28 @@ typedef float f32x16n __attribute__((ext_vector_type(16)));
 // lane / 32) loads A[k + h][j0 + c], A[k + h][j0 + 32 + c] and P[k + h][c], P[k + h][32 + c],
 // eight k-pairs per batch with the next batch in flight during this one's MFMAs.  With
 // A = V (m x n) the panel sums give V^T P (the H-step), with A = V^T (an n x m transposed
-// copy) V P (the W-step).  Skipped when the solve is done.
+// copy) V P (the W-step).  With rj.G set the grid has one more row of workgroups, the
+// first (dispatched before the panels, so that it runs beside them from the start), whose
+// first workgroup computes rho = ||G||_2 (rho.hpp).  Skipped when the solve is done.
 template <int NMB>
 __global__ __launch_bounds__(256) void k_rect_f32(const float* __restrict__ A, int64_t lda,
                                                   const float* __restrict__ P, int64_t K,
                                                   int64_t N, int r, int64_t kchunk,
                                                   float* __restrict__ Bpart, int64_t pstride,
-                                                  const State* __restrict__ st) {
+                                                  const State* __restrict__ st, RhoJob rj) {
   if (st->done) return;
+  int64_t y = blockIdx.y;
+  if (rj.G) {
+    if (y == 0) {
+      if (blockIdx.x == 0) rho_body(rj.G, rj.r, rj.st);  // (issue priority: no gain measured)
+      return;
+    }
+    --y;
+  }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int c = lane & 31, h = lane >> 5;
   const int64_t j0 = ((int64_t)blockIdx.x * 4 + wave) * 64;
-  const int64_t kb = (int64_t)blockIdx.y * kchunk;
+  const int64_t kb = y * kchunk;
   const int64_t ke = kb + kchunk < K ? kb + kchunk : K;
   f32x16n acc[NMB][2];
 #pragma unroll
@@ -264,7 +275,7 @@ __global__ __launch_bounds__(256) void k_rect_f32(const float* __restrict__ A, i
   }
   // D[m][j] of block (mb, nb): lane (c, h) holds j = j0 + 32 nb + c and
   // m = 32 mb + 8 (v / 4) + 4 h + v % 4 in register v
-  float* out = Bpart + (int64_t)blockIdx.y * pstride;
+  float* out = Bpart + y * pstride;
 #pragma unroll
   for (int mb = 0; mb < NMB; ++mb)
 #pragma unroll
@@ -347,14 +358,15 @@ RectSplit rect_split(int64_t K, int64_t N) {
 }
 
 void launch_rect_f32(const float* A, int64_t lda, const float* P, int64_t K, int64_t N, int r,
-                     const RectSplit& sp, float* Bpart, const State* st, hipStream_t s) {
-  const dim3 grid((unsigned)sp.gx, (unsigned)sp.ksplit);
+                     const RectSplit& sp, float* Bpart, const State* st, hipStream_t s,
+                     const RhoJob& rj) {
+  const dim3 grid((unsigned)sp.gx, (unsigned)(sp.ksplit + (rj.G ? 1 : 0)));
   if (r > 32)
     hipLaunchKernelGGL(k_rect_f32<2>, grid, dim3(256), 0, s, A, lda, P, K, N, r, sp.kchunk,
-                       Bpart, N * r, st);
+                       Bpart, N * r, st, rj);
   else
     hipLaunchKernelGGL(k_rect_f32<1>, grid, dim3(256), 0, s, A, lda, P, K, N, r, sp.kchunk,
-                       Bpart, N * r, st);
+                       Bpart, N * r, st, rj);
 }
 
 template <typename T>

@@ -216,7 +216,8 @@ struct RectSplit {
 };
 RectSplit rect_split(int64_t K, int64_t N);
 void launch_rect_f32(const float* A, int64_t lda, const float* P, int64_t K, int64_t N, int r,
-                     const RectSplit& sp, float* Bpart, const State* st, hipStream_t s);
+                     const RectSplit& sp, float* Bpart, const State* st, hipStream_t s,
+                     const RhoJob& rj = RhoJob{});
 template <typename T>
 void launch_transpose(const T* A, int64_t rows, int64_t cols, int64_t lda, T* AT, hipStream_t s);
 void launch_csr_check_rect(const int64_t* rowptr, const int32_t* col, int64_t m, int64_t ncols,

@@ -73,7 +73,14 @@ void half_step(NmfPlan& pl, T* X, int64_t nX, const T* P, int64_t nP, int is_hst
   const int r = pl.r;
   const int gi = is_hstep ? 1 : 0;
   launch_gram<T>(P, nP, r, pl.gram_part, gram_blocks(nP), pl.G64[gi], (T*)pl.GT[gi], pl.st, s);
-  if (with_rho) launch_rho(pl.G64[gi], r, pl.st, s);
+  // rho of this half-step runs in one more workgroup of the product launch (the FP64
+  // dense product: a launch of its own before it)
+  RhoJob rj;
+  if (with_rho) {
+    rj.G = pl.G64[gi];
+    rj.r = r;
+    rj.st = pl.st;
+  }
   T* B = (T*)pl.B;
   int ksplit = 1;
   if (pl.V.fmt == SNMF_DENSE && sizeof(T) == 4) {
@@ -81,17 +88,18 @@ void half_step(NmfPlan& pl, T* X, int64_t nX, const T* P, int64_t nP, int is_hst
     const RectSplit& sp = is_hstep ? pl.spH : pl.spW;
     const float* A = is_hstep ? (const float*)pl.V.dense : (const float*)pl.VT;
     const int64_t lda = is_hstep ? pl.V.ld : pl.m;
-    launch_rect_f32(A, lda, (const float*)P, nP, nX, r, sp, (float*)pl.Bpart, pl.st, s);
+    launch_rect_f32(A, lda, (const float*)P, nP, nX, r, sp, (float*)pl.Bpart, pl.st, s, rj);
     B = (T*)pl.Bpart;
     ksplit = sp.ksplit;
   } else if (pl.V.fmt == SNMF_DENSE) {
+    if (with_rho) launch_rho(pl.G64[gi], r, pl.st, s);
     launch_rect_apass<T>((const T*)pl.V.dense, pl.V.ld, nX, nP, is_hstep, P, r, B, pl.st, s);
   } else if (!is_hstep) {
     launch_spmm<T>(pl.V.rowptr, pl.V.col, (const T*)pl.V.val, P, nX, r, B, nullptr, nullptr,
-                   &pl.st->done, nullptr, s);
+                   &pl.st->done, nullptr, s, rj);
   } else {
     launch_spmm<T>(pl.rowptrT, pl.colT, (const T*)pl.valT, P, nX, r, B, nullptr, nullptr,
-                   &pl.st->done, nullptr, s);
+                   &pl.st->done, nullptr, s, rj);
   }
   const T* Pz = (const T*)pl.Pz;
   const T* GT = (const T*)pl.GT[gi];
