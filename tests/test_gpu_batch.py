@@ -263,21 +263,26 @@ def test_batch_bf16x3_instances_follow_the_oracle(S):
 
 
 def test_batch_bf16x3_rho_beside_the_split(S):
-    """57 restarts of rank 64 at n = 1100 fill every workgroup slot of the stacked product
-    (9 x 57 pairs), so rho runs in the partner split's launch instead: restarts 0 and 56
+    """Enough restarts of rank 64 at n = 1100 that the stacked product (9 row tiles x one
+    column block per restart) and the restarts' rho workgroups exceed the two workgroup
+    slots per CU (the restart count is derived from this device's CU count: 52 on 256
+    CUs), so rho runs in the partner split's launch instead: the first and last restarts
     must follow the oracle's solve from their starts for 5 outer iterations."""
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    R = (2 * cus) // 10 + 1
+    assert 9 * R + R > 2 * cus
     prob = gen.planted_dense(1100, 64, 57)
     At = torch.from_numpy(prob["A"]).to(DEV, torch.float32)
     a_in = At.double().cpu().numpy()
     lam = O.default_lambda(a_in)
     rng = np.random.default_rng(57)
-    w0 = np.stack([gen.start_factor(rng, 1100, 64, float(a_in.mean())) for _ in range(57)])
+    w0 = np.stack([gen.start_factor(rng, 1100, 64, float(a_in.mean())) for _ in range(R)])
     W0 = torch.from_numpy(w0).to(DEV, torch.float32).contiguous()
     w_in = W0.double().cpu().numpy()
     with S.Batch([S.dense(At)], [64], S.params(lam=lam, prec=S.BF16X3, max_outer=5),
-                 restarts=57) as b:
+                 restarts=R) as b:
         _, _, infos, _ = b.solve([W0])
-    for s in (0, 56):
+    for s in (0, R - 1):
         _, _, hist = O.snmpbb(a_in, w_in[s], O.Params(lam=lam), 5)
         assert infos[s]["status"] == 0 and infos[s]["outer"] == 5
         assert abs(infos[s]["res_WH"] - hist[-1]["res_WH"]) <= 1e-3 * hist[-1]["res_WH"], s
