@@ -1,8 +1,10 @@
 // Sparse and low-rank products of the SNMPBB hot path.
 //
 // * CSR SpMM  Y = A X  (A symmetric, both triangles stored).  One wavefront per row:
-//   lane (slot, c) with c = lane % RP walks the nonzeros slot, slot + 64/RP, ... of the row
-//   and accumulates A_ik X[k][c]; the slots are combined with cross-lane adds.  Used for
+//   lane (slot, c) = (lane / r, lane % r), slot < 64 / r, walks the nonzeros slot,
+//   slot + 64 / r, ... of the row and accumulates A_ik X[k][c]; slot 0 adds the other
+//   slots' sums in slot order.  (RP, the rank padded to a power of two, only selects the
+//   instantiation.)  Used for
 //   the A-pass of Graph-SNMPBB and of batched graph problems, and for the Laplacian
 //   products L X, L(Z-X), L S of eq. (2.3).  In "dot" mode the kernel writes FP64 partial
 //   sums of <X2, A X> per workgroup (the curvature <D, L D>, reduced by the next kernel)
@@ -35,16 +37,19 @@ __global__ __launch_bounds__(256) void k_spmm(const int64_t* __restrict__ rowptr
       return;
     }
   }
-  constexpr int NS = kWave / RP;  // nonzero slots per wave
+  // nonzero slots per wave: lanes s r .. s r + r - 1 serve slot s (at r = 20 three slots,
+  // 60 lanes busy, where slots of the padded width RP = 32 would give two)
+  const int ns = kWave / r;
   // gathers in flight per lane (each lane's nonzeros are added in the same order for any
   // SU, so the sums do not depend on it).  Measured at the graph workload (A-pass, n =
-  // 20000, r = 20) and on a random graph of 6e7 nonzeros (n = 2e6, r = 20): SU = 2
-  // 13.8 us / 1.94 ms, 4 12.5 us / 1.59 ms, 8 17.7 us / 2.41 ms (its registers cost
-  // resident waves).
+  // 20000, r = 20) and on a random graph of 6e7 nonzeros (n = 2e6, r = 20), with slots of
+  // the padded width: SU = 2 13.8 us / 1.94 ms, 4 12.5 us / 1.59 ms, 8 17.7 us / 2.41 ms
+  // (its registers cost resident waves).
   constexpr int SU = 4;
   __shared__ double sred[kThreads / kWave * kNumPart];
   const int lane = threadIdx.x & 63;
-  const int c = lane % RP, slot = lane / RP;
+  const int slot = lane / r, c = lane - slot * r;
+  const bool act = slot < ns;
   const int64_t bid = (int64_t)blockIdx.x - b0;
   const int64_t wave_id = (bid * kThreads + threadIdx.x) / kWave;
   const int64_t nwaves = ((int64_t)gridDim.x - b0) * kThreads / kWave;
@@ -58,29 +63,35 @@ __global__ __launch_bounds__(256) void k_spmm(const int64_t* __restrict__ rowptr
       const int cnt = e - zb < kWave ? (int)(e - zb) : kWave;
       const int mc = lane < cnt ? col[zb + lane] : 0;
       const T mv = lane < cnt ? val[zb + lane] : T(0);
-      for (int k0 = 0; k0 < cnt; k0 += SU * NS) {  // uniform trip count: all lanes shuffle
+      for (int k0 = 0; k0 < cnt; k0 += SU * ns) {  // uniform trip count: all lanes shuffle
         int ck[SU];
         T vk[SU], pk[SU];
 #pragma unroll
         for (int u = 0; u < SU; ++u) {
-          const int k = k0 + slot + u * NS;
+          const int k = k0 + slot + u * ns;
           const int src = k < kWave ? k : kWave - 1;
           ck[u] = __shfl(mc, src, kWave);
           vk[u] = __shfl(mv, src, kWave);
         }
 #pragma unroll
         for (int u = 0; u < SU; ++u) {
-          const int k = k0 + slot + u * NS;
-          pk[u] = (c < r && k < cnt) ? X[(int64_t)ck[u] * r + c] : T(0);
+          const int k = k0 + slot + u * ns;
+          pk[u] = (act && k < cnt) ? X[(int64_t)ck[u] * r + c] : T(0);
         }
 #pragma unroll
         for (int u = 0; u < SU; ++u)
-          if (k0 + slot + u * NS < cnt) acc += vk[u] * pk[u];
+          if (act && k0 + slot + u * ns < cnt) acc += vk[u] * pk[u];
       }
     }
-#pragma unroll
-    for (int o = RP; o < kWave; o <<= 1) acc += __shfl_xor(acc, o, kWave);
-    if (slot == 0 && c < r) {
+    // slot 0 adds the other slots' sums in slot order
+    T tot = acc;
+    for (int q = 1; q < ns; ++q) {
+      const int src = lane + q * r;
+      const T o = __shfl(acc, src < kWave ? src : kWave - 1, kWave);
+      tot += o;
+    }
+    acc = tot;
+    if (slot == 0) {
       if (X2)
         dot += (double)X2[row * r + c] * (double)acc;
       else
