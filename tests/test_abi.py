@@ -40,7 +40,9 @@ def test_struct_layout_matches_c(S, tmp_path):
     checks = {
         "snmf_matrix": ["n", "dense", "ld", "rowptr", "val", "nnz", "U", "ell", "lam"],
         "snmf_params": ["gamma", "L", "eta", "beta_shrink", "max_ls", "check_every",
-                        "target_res", "prec", "use_graph"],
+                        "target_res", "prec", "use_graph", "check_symmetry", "naive",
+                        "tuning"],
+        "snmf_batch_tuning": ["tiles_per_wg", "spmm_rows_per_wg", "reserved"],
         "snmf_info": ["inner_total", "ls_exhausted", "res_WH", "seconds_to_target", "normA2"],
         "snmf_mlp": ["hidden", "M1", "b1", "M2", "b2", "M1h", "M2h", "adam_m", "adam_v"],
     }
@@ -55,12 +57,41 @@ def test_struct_layout_matches_c(S, tmp_path):
     subprocess.check_call([gcc, "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)])
     out = dict(l.split() for l in subprocess.check_output([str(exe)]).decode().splitlines())
     py = {"snmf_matrix": S.Matrix, "snmf_params": S.Params, "snmf_info": S.Info,
-          "snmf_mlp": S.MlpC}
+          "snmf_mlp": S.MlpC, "snmf_batch_tuning": S.Tuning}
     for st, cls in py.items():
         assert int(out[st]) == ctypes.sizeof(cls)
         for f in checks[st]:
             pyf = "lambda_" if f == "lambda" else f
             assert int(out[f"{st}.{f}"]) == getattr(cls, pyf).offset, (st, f)
+
+
+def test_abi_version_matches_the_binding(S):
+    assert S.abi_version() == S.ABI_VERSION
+
+
+def test_naive_and_nmf_arguments_are_rejected_before_any_device_work(S):
+    A = S.Matrix(fmt=S.DENSE, n=10, dense=1, ld=10)  # never dereferenced
+    p = S.params(naive=1, lam=0.5)
+    st, h = _create(S, A, 3, p)
+    assert st == 1 and not h.value                     # the naive variant needs lambda = 0
+    info = S.Info()
+    V = S.Matrix(fmt=S.LOWRANK, n=10, U=1, ell=2, lam=None)
+    assert S._lib.snmf_nmf_solve(ctypes.byref(V), 8, 3, 1, 1, ctypes.byref(S.params(lam=0.0)),
+                                 1, 1, ctypes.byref(info), None, None) != 0
+    V = S.Matrix(fmt=S.DENSE, n=10, dense=1, ld=8)
+    assert S._lib.snmf_nmf_solve(ctypes.byref(V), 8, 3, 1, 1, ctypes.byref(S.params(lam=0.3)),
+                                 1, 1, ctypes.byref(info), None, None) == 1   # lambda != 0
+    assert S._lib.snmf_nmf_solve(ctypes.byref(V), 9, 3, 1, 1, ctypes.byref(S.params(lam=0.0)),
+                                 1, 1, ctypes.byref(info), None, None) == 2   # ld < n_cols
+
+
+def test_bad_batch_tuning_is_rejected(S):
+    p = S.params(tuning={"tiles_per_wg": [4, 0, 4, 4], "spmm_rows_per_wg": 16})
+    A = (S.Matrix * 1)(S.Matrix(fmt=S.CSR, n=10, rowptr=1, col=1, val=1, nnz=4))
+    r = (ctypes.c_int32 * 1)(3)
+    h = ctypes.c_void_p()
+    st = S._lib.snmf_batch_create(1, A, r, None, 1, ctypes.byref(p), None, ctypes.byref(h))
+    assert st == 1 and not h.value and "tuning" in S._lib.snmf_last_error().decode()
 
 
 def test_params_default(S):
