@@ -97,6 +97,30 @@ def _cpu_baseline(A64, W0, lam, outer):
     return out
 
 
+def _blas_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        return int(max([i.get("num_threads", 1) for i in threadpool_info()
+                        if i.get("user_api") == "blas"] or [1]))
+    except Exception:  # pragma: no cover
+        return os.cpu_count() or 1
+
+
+def _cpu_sample(run, unit_per_call, what, budget_s=10.0, cap=50):
+    """The oracle timed on a bounded sample: run(k) performs k units of work (outer
+    iterations, or instance outer iterations); one unit first sizes k to about budget_s."""
+    t0 = time.perf_counter()
+    run(1)
+    one = time.perf_counter() - t0
+    k = max(1, min(cap, int(budget_s / max(one, 1e-3))))
+    t0 = time.perf_counter()
+    run(k)
+    dt = time.perf_counter() - t0
+    return {"value": k * unit_per_call / dt, "unit": "outer iterations/s" if unit_per_call == 1
+            else "instance outer iterations/s", "cores": _blas_threads(), "kind": "oracle",
+            "sample": f"{k} x {what} of the FP64 numpy reference ({dt:.1f} s)"}
+
+
 COPY_BYTES = 256 << 20
 
 
@@ -231,7 +255,23 @@ def _bench_c4(a, torch, np, S, gen):
             "fraction_of_restarts_reaching": float(np.mean(frac)),
             "restarts_broken_down": broken, "graphs_without_a_valid_restart": no_valid}
     out["instances_broken_down"] = int(sum(i["status"] != 0 for i in infos))
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = _c4_cpu(np, graphs, lams)
     print(json.dumps(out))
+
+
+def _c4_cpu(np, graphs, lams, count=16):
+    """The oracle on a sample of the batch: the first start of the first `count` graphs,
+    solved one after another (instance outer iterations per second)."""
+    import oracle as O
+    As = [g["A"].astype(np.float32).astype(np.float64) for g in graphs[:count]]
+    W0 = [np.asarray(g["W0"][0], dtype=np.float64) for g in graphs[:count]]
+
+    def run(k):
+        for A, w, lam in zip(As, W0, lams[:count]):
+            O.snmpbb(A, w, O.Params(lam=lam), k)
+    return _cpu_sample(run, count, f"outer iterations of {count} instances (the first start of "
+                       f"the first {count} graphs)")
 
 
 def _arm_stats(np, graphs, restarts, infos, tr, hz, taus, extra_s=0.0):
@@ -399,7 +439,19 @@ def _bench_c2(a, torch, np, S, gen):
         "laplacian_seconds": lap_s,
         "laplacian": "device: brute-force 10-NN over 16-dim features (FP64 distances), union "
                      "pattern, normalised Laplacian",
-        "clustering": {"accuracy": float(acc), "ari": ari}}))
+        "clustering": {"accuracy": float(acc), "ari": ari},
+        **({} if a.no_cpu_baseline else {"cpu_baseline": _c2_cpu(np, p, lam, r, W0n)})}))
+
+
+def _c2_cpu(np, p, lam, r, W0n):
+    """The oracle's Graph-SNMPBB on the same workload (its Laplacian built by the oracle's
+    own preprocessing beforehand, outside the timed sample)."""
+    import oracle as O
+    A64 = p["A"].astype(np.float32).astype(np.float64)
+    L = O.knn_laplacian(p["X"].astype(np.float32).astype(np.float64), p["knn"])
+    prm = O.Params(lam=lam, gamma=0.2)
+    return _cpu_sample(lambda k: O.snmpbb(A64, W0n, prm, k, L=L), 1,
+                       "outer iterations on the n=20000, r=20 graph workload")
 
 
 def _bench_c3(a, torch, np, S, gen):
@@ -444,7 +496,17 @@ def _bench_c3(a, torch, np, S, gen):
         "res_WH_surrogate": info["res_WH"], "pg_norm": info["pg_norm"],
         "range_finder_seconds": sketch_s,
         "range_finder": "device: A Omega (CSR, 74 columns), 2 power iterations (4 more "
-                        "products), 5 shifted/plain Cholesky QR rounds, Q^T A Q, Jacobi"}))
+                        "products), 5 shifted/plain Cholesky QR rounds, Q^T A Q, Jacobi",
+        **({} if a.no_cpu_baseline else {"cpu_baseline": _c3_cpu(np, Ug, lg, lam, W0n)})}))
+
+
+def _c3_cpu(np, Ug, lg, lam, W0n):
+    """The oracle's LAI-SNMPBB on the same surrogate (U, lam from the device sketch)."""
+    import oracle as O
+    lr = O.LowRank(Ug.double().cpu().numpy(), lg.cpu().numpy())
+    prm = O.Params(lam=lam)
+    return _cpu_sample(lambda k: O.snmpbb(lr, W0n, prm, k), 1,
+                       "outer iterations on the n=200000, ell=64, r=32 surrogate")
 
 
 def _bench_nmf(a, torch, np, S, gen):
@@ -489,7 +551,8 @@ def _bench_nmf(a, torch, np, S, gen):
 
 def _bench_scale(a, torch, np, S, gen):
     """The HBM-bound A-pass kernels at a size past the L2 and the 256 MB last-level cache:
-    the CSR SpMM (random symmetric graph, n = 2e6, mean degree 30, r = 20 and 32) and the
+    the CSR SpMM (random symmetric graph, n = 2e6, mean degree 30, r = 20 and 32; the SBM
+    graph workload at 100 times its size, clusters contiguous and permuted, r = 20) and the
     LAI products (n = 2e6, ell = 64, r = 32), each against 8 TB/s and against a measured
     device-to-device copy."""
     dev = torch.device("cuda:0")
@@ -519,6 +582,27 @@ def _bench_scale(a, torch, np, S, gen):
         rows.append({"kernel": "k_spmm (CSR A-pass)", "n": n, "nnz": nnz, "r": r, "ms": ms,
                      "algorithmic_bytes": byts, "gbs": byts / (ms * 1e-3) / 1e9})
     del A, a_host
+    # the graph workload's kind at 100 times its size: SBM n = 2e6, 20 clusters of 1e5
+    # contiguous node ids, the degrees of the n = 20000 workload (p_in 2e-4, p_out 5e-6),
+    # A = D^-1/2 Adj D^-1/2; and the same graph with its node ids randomly permuted (no
+    # locality left in the gathers)
+    adj, _ = gen.sbm_adjacency(n, 20, 2e-4, 5e-6, np.random.default_rng(gen.SEED_BASE + 22))
+    a_sbm = gen.normalized_adjacency(adj)
+    del adj
+    perm = np.random.default_rng(gen.SEED_BASE + 23).permutation(n)
+    for name, a_host in (("SBM, clusters contiguous", a_sbm),
+                         ("SBM, node ids permuted", a_sbm[perm][:, perm].tocsr())):
+        a_host.sort_indices()
+        A = S.csr_from_scipy(a_host, torch.float32)
+        nnz = a_host.nnz
+        P = torch.rand((n, 20), device=dev, dtype=torch.float32)
+        with S.Plan(A, 20, S.params(lam=0.0, prec=S.F32, max_outer=1)) as pl:
+            ms = pl.time_apass(P, 50)
+        byts = 8.0 * (n + 1) + 8.0 * nnz + 2 * 4.0 * n * 20
+        rows.append({"kernel": f"k_spmm (CSR A-pass), {name}", "n": n, "nnz": nnz, "r": 20,
+                     "ms": ms, "algorithmic_bytes": byts, "gbs": byts / (ms * 1e-3) / 1e9})
+        del A
+    del a_sbm
     ell, r = 64, 32
     U, lamv = gen.random_lowrank(n, ell, gen.SEED_BASE + 21)
     Ug = torch.from_numpy(U).to(dev)
@@ -538,8 +622,10 @@ def _bench_scale(a, torch, np, S, gen):
         "value": min(row["frac_of_peak"] for row in rows), "unit": "fraction of 8 TB/s (worst kernel)",
         "n_gpus": 1, "higher_is_better": True, "dtype": "f32", "data": "synthetic",
         "vs_baseline": None,
-        "config": {"workload": "random symmetric CSR n=2e6 mean degree 30 (seed 1020); "
-                               "Gaussian U n=2e6 x 64 (seed 1021)", "parallelism": "single GPU"},
+        "config": {"workload": "random symmetric CSR n=2e6 mean degree 30 (seed 1020); SBM "
+                               "n=2e6, 20 clusters, p_in 2e-4, p_out 5e-6 (seed 1022), ordered "
+                               "and permuted (seed 1023); Gaussian U n=2e6 x 64 (seed 1021)",
+                   "parallelism": "single GPU"},
         "copy_gbs": copy_gbs, "peak_gbs": HBM_PEAK_GBS, "kernels": rows}))
 
 
