@@ -32,7 +32,7 @@ def _t(x, dtype):
 
 
 # ------------------------------------------------------------------ rho = ||G||_2
-@pytest.mark.parametrize("r", [1, 2, 5, 10, 20, 33, 64])
+@pytest.mark.parametrize("r", [1, 2, 5, 10, 20, 31, 32, 33, 64])
 def test_rho_matches_eigvalsh(S, r):
     rng = np.random.default_rng(r)
     P = rng.random((3 * r + 5, r))
