@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define SNMF_ABI_VERSION 3
+#define SNMF_ABI_VERSION 4
 #define SNMF_TRACE_FIELDS 10
 
 typedef enum snmf_status {
@@ -131,6 +131,15 @@ typedef struct snmf_params {
                           the partner held at the current W and no penalty, then sets
                           H <- W^T (an ablation).  Needs lambda = 0 (E_ARG) and no Laplacian
                           (E_UNSUPPORTED); single solves only (batches: E_UNSUPPORTED)     [0] */
+  int32_t fuse_inner;  /* 1: one kernel per inner iteration, 0: two (step 1 and step 2).
+                          The fused kernel forms the next BB step from sums its predecessor
+                          prepared: for the first backtracking trial (beta = 1) the update's
+                          own sums, which give the same bits as 0; after a backtrack the
+                          sums of S = dZ + phi beta D, which the projection leaves unclipped
+                          when phi beta_shrink <= 1 (the same scalars up to rounding).  Used
+                          where phi beta_shrink <= 1, project_update = 0 or max_ls = 0, on
+                          single solves; the H-steps of Graph-SNMPBB and of the naive
+                          variant keep two kernels                                        [1] */
   const snmf_batch_tuning* tuning; /* batched solves: launch shape, or NULL for the
                           defaults (read at snmf_batch_create; values out of range: E_ARG)
                           [NULL] */

@@ -161,6 +161,59 @@ __device__ __forceinline__ void block_sum(double (&v)[K], double* sred) {
   __syncthreads();
 }
 
+// Block sums of K <= 16 doubles per thread for the row-tile kernels, in a fixed order that
+// does not depend on K: the values go to LDS (stage, kStage doubles), thread 16 s + q adds
+// the values of threads 16 u + q of slot s (u = 0..15, even and odd u in two chains), and
+// the 16 threads of slot s -- one DPP row -- add their results with row shifts, so lane
+// q = 15 holds the total.  Three times faster than a wave reduction per value followed by a
+// cross-wave one (0.5 against 1.5 us for 13 values).  slot_sum returns that lane's total
+// (and sets s); the callers below broadcast or store it.
+constexpr int kStage = 16 * kThreads + 16;
+template <int K>
+__device__ __forceinline__ double slot_sum(const double (&v)[K], double* stage, int& s) {
+  static_assert(K >= 1 && K <= 16, "at most 16 slots");
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int j = 0; j < K; ++j) stage[j * kThreads + t] = v[j];
+  __syncthreads();
+  s = t >> 4;
+  const int q = t & 15;
+  double a = 0.0;
+  if (s < K) {
+    double b = 0.0;
+#pragma unroll
+    for (int u = 0; u < 16; u += 2) {
+      a += stage[s * kThreads + u * 16 + q];
+      b += stage[s * kThreads + (u + 1) * 16 + q];
+    }
+    a += b;
+    a += dpp_d<0x111>(a);  // row_shr:1
+    a += dpp_d<0x112>(a);  // row_shr:2
+    a += dpp_d<0x114>(a);  // row_shr:4
+    a += dpp_d<0x118>(a);  // row_shr:8
+  }
+  return a;
+}
+// Totals in every thread.  The stage may alias buffers no wave reads any more.
+template <int K>
+__device__ __forceinline__ void block_sum_wide(double (&v)[K], double* stage) {
+  int s;
+  const double a = slot_sum<K>(v, stage, s);
+  if (s < K && (threadIdx.x & 15) == 15) stage[16 * kThreads + s] = a;
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < K; ++j) v[j] = stage[16 * kThreads + j];
+}
+// Totals handed to emit(slot, total), one thread per slot; starts with a barrier, so the
+// stage may alias tile buffers that other waves were still reading.
+template <int K, typename F>
+__device__ __forceinline__ void block_sum_emit(const double (&v)[K], double* stage, F&& emit) {
+  __syncthreads();
+  int s;
+  const double a = slot_sum<K>(v, stage, s);
+  if (s < K && (threadIdx.x & 15) == 15) emit(s, a);
+}
+
 // Release this block's partials; returns true in every thread of the last block to
 // arrive (which then sees all partials).  The last block resets the counter.
 __device__ __forceinline__ bool arrive_last(unsigned int* counter, unsigned int nblocks) {

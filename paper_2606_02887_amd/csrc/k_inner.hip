@@ -16,6 +16,9 @@
 //             writes partsB = {<grad f(Z),D>, <DG,D>, ||D||^2, f(Z)-f(X)}
 //   step2_k   reads partsB [+ partsD = <D,LD>] (line search -> beta_k);
 //             writes partsC = {||S||^2, <SG,S>, <g,S>, monitor pieces, <S,LS>}
+// Half-steps without the Laplacian term run the fused form instead (k_advance below):
+// init also forms direction 0, and each later kernel runs a line search, the update and,
+// when the first trial was accepted, the next direction.
 //
 // A workgroup (256 threads) works on tiles of TM = 8 * 256 / RP rows, RP being the rank
 // rounded up to a power of 2; each thread owns 8 elements of a tile (see Lay).  Each
@@ -133,12 +136,18 @@ __device__ __forceinline__ void tile_gemm(const T* __restrict__ sY, const T* __r
   }
 }
 
+// The tile buffers share their LDS with the staging area of the block sums (kStage
+// doubles), which run before the first tile product or after the last.
 template <typename T, int RP>
 struct __attribute__((aligned(32))) Smem {
-  T G[RP * Lay<T, RP>::GP];
-  T a[Lay<T, RP>::TM * Lay<T, RP>::YP];
-  T b[Lay<T, RP>::TM * Lay<T, RP>::YP];
-  double red[kThreads / kWave * kNumPart];
+  union {
+    struct {
+      T G[RP * Lay<T, RP>::GP];
+      T a[Lay<T, RP>::TM * Lay<T, RP>::YP];
+      T b[Lay<T, RP>::TM * Lay<T, RP>::YP];
+    };
+    double red[kStage];
+  };
 };
 
 // G (r x r, row-major in global memory) in registers, then into the zero-padded LDS copy.
@@ -158,13 +167,6 @@ __device__ __forceinline__ void store_G(T* __restrict__ sG, const T (&v)[TileCfg
     const int e = threadIdx.x + q * kThreads;
     if (e < RP * RP) sG[(e / RP) * Lay<T, RP>::GP + (e % RP)] = v[q];
   }
-}
-
-template <int K>
-__device__ __forceinline__ void write_parts(double* __restrict__ parts, int bid, const double (&v)[K]) {
-  if (threadIdx.x == 0)
-#pragma unroll
-    for (int j = 0; j < K; ++j) parts[(size_t)bid * kNumPart + j] = v[j];
 }
 
 // This thread's share (workgroups b = tid, tid + 256, ... in increasing b) of K consecutive
@@ -261,15 +263,133 @@ template <typename T>
 __device__ __forceinline__ T second_dir(T z, T gz, T alpha) {  // max(0, Z - alpha gZ) - Z
   return relu(fmaT(-alpha, gz, z)) - z;
 }
+// The update and its sums, written once so that every kernel forming them (step 2, and
+// the fused kernels below, which form the update at beta = 1 one kernel early) produces
+// the same bits: X+ = max(0, Z + phi beta D) (no projection when project = 0) and
+// g+ = g + S G + lam S.
+template <typename T>
+__device__ __forceinline__ T next_point(T z, T d, T step, int project) {
+  const T y = fmaT(step, d, z);
+  return project ? relu(y) : y;
+}
+template <typename T>
+__device__ __forceinline__ T next_grad(T g, T sg, T lam, T s) {
+  return fmaT(lam, s, g + sg);
+}
+// <S,S>, <S G, S>, <g, S> of an update
+template <typename T, int K>
+__device__ __forceinline__ void update_sums(double (&v)[K], T s, T sg, T g) {
+  const double sd = (double)s;
+  v[0] = fmaT(sd, sd, v[0]);
+  v[1] = fmaT((double)sg, sd, v[1]);
+  v[2] = fmaT((double)g, sd, v[2]);
+}
+// <grad f(Z), D>, ||D||^2 and f(Z) - f(X) = <g + grad f(Z), Z - X>/2 of a direction
+template <typename T>
+__device__ __forceinline__ void direction_sums(double (&v)[4], T gz, T d, T g, T dz) {
+  const double dd = (double)d;
+  v[0] = fmaT((double)gz, dd, v[0]);
+  v[2] = fmaT(dd, dd, v[2]);
+  v[3] = fmaT(0.5 * ((double)g + (double)gz), (double)dz, v[3]);
+}
+// Monitor sums of the H-step's final X (x) with its gradient g, C and the partner p:
+// m = {<C, X>, <P, X>, ||X - P||^2, ||min(X, g)||^2}
+template <typename T>
+__device__ __forceinline__ void monitor_sums(double* m, T x, T g, T c, T p) {
+  const double xd = (double)x, pd = (double)p, dxp = xd - pd;
+  const double mn = (double)(x < g ? x : g);
+  m[0] = fmaT((double)c, xd, m[0]);
+  m[1] = fmaT(pd, xd, m[1]);
+  m[2] = fmaT(dxp, dxp, m[2]);
+  m[3] = fmaT(mn, mn, m[3]);
+}
+
+// ----------------------------------------------------------------------------- direction
+// Step 1 of a fused inner iteration on one tile whose X and g are in registers (sm.G
+// holds G; sm.a and sm.b are free): Z, grad f(Z), D with step 1's arithmetic (D stored at
+// Dt), and the sums the next kernel needs to finish the iteration in one pass
+// (kFusedParts of them):
+//   ls  = {<grad f(Z),D>, <DG,D>, ||D||^2, f(Z)-f(X)}: the line search;
+//   sp  = {||S||^2, <SG,S>, <g,S>} of the update of the trial beta = 1,
+//         X+ = max(0, Z + phi D), formed with step 2's arithmetic: the BB step when the
+//         line search accepts that trial, the same bits as step 2 would give;
+//   xp  = {<dZ,dZ>, <dZ,D>, <dZ,dZ G>, <dZ,DG>, <g,dZ>, <g,D>} with dZ = Z - X: the BB
+//         step after a backtrack.  A trial beta <= beta_shrink has t = phi beta <= 1
+//         (the fused path requires phi beta_shrink <= 1), and Z + t D is then a convex
+//         combination of Z >= 0 and Z + D >= 0, so the projection clips nothing and
+//         S = dZ + t D: its sums are polynomials in t of these (G symmetric).
+// The caller synchronises before reusing sm.a and sm.b.
+constexpr int kFusedParts = 13;
+template <typename T, int RP>
+__device__ __forceinline__ void tile_direction(Smem<T, RP>& sm, const int (&lr)[8],
+                                               const int (&cl)[8], const uint32_t (&bo)[8],
+                                               int64_t row0, int64_t n, int r, const T (&x)[8],
+                                               const T (&gv)[8], T rinv, T alpha, T lam,
+                                               T step1, int project, T* __restrict__ Dt,
+                                               double (&ls)[4], double (&sp)[3],
+                                               double (&xp)[6]) {
+  typedef Lay<T, RP> L;
+  T z[8];
+#pragma unroll
+  for (int p = 0; p < 8; ++p) {
+    const bool ok = row0 + lr[p] < n && cl[p] < r;
+    z[p] = first_proj(x[p], gv[p], rinv);
+    sm.a[lr[p] * L::YP + cl[p]] = ok ? z[p] - x[p] : T(0);
+  }
+  __syncthreads();
+  T dzg[8];
+  tile_gemm<T, RP>(sm.a, sm.G, dzg);
+  T d[8];
+#pragma unroll
+  for (int p = 0; p < 8; ++p) {
+    const bool ok = row0 + lr[p] < n && cl[p] < r;
+    const T dz = z[p] - x[p];
+    const T gz = grad_at_z(gv[p], dzg[p], lam, dz);
+    const T dd = ok ? second_dir(z[p], gz, alpha) : T(0);
+    d[p] = dd;
+    if (ok) {
+      sto(Dt, bo[p], dd);
+      direction_sums(ls, gz, dd, gv[p], dz);
+      const double dzd = (double)dz, gd = (double)gv[p];
+      xp[0] = fmaT(dzd, dzd, xp[0]);
+      xp[1] = fmaT(dzd, (double)dd, xp[1]);
+      xp[2] = fmaT(dzd, (double)dzg[p], xp[2]);
+      xp[4] = fmaT(gd, dzd, xp[4]);
+      xp[5] = fmaT(gd, (double)dd, xp[5]);
+    }
+    sm.b[lr[p] * L::YP + cl[p]] = dd;
+  }
+  __syncthreads();
+  T dg[8];
+  tile_gemm<T, RP>(sm.b, sm.G, dg);
+  T xn[8];
+#pragma unroll
+  for (int p = 0; p < 8; ++p) {
+    ls[1] = fmaT((double)dg[p], (double)d[p], ls[1]);
+    const bool ok = row0 + lr[p] < n && cl[p] < r;
+    if (ok) xp[3] = fmaT((double)(z[p] - x[p]), (double)dg[p], xp[3]);
+    xn[p] = ok ? next_point(z[p], d[p], step1, project) : T(0);
+    sm.a[lr[p] * L::YP + cl[p]] = ok ? xn[p] - x[p] : T(0);
+  }
+  __syncthreads();
+  T sg[8];
+  tile_gemm<T, RP>(sm.a, sm.G, sg);
+#pragma unroll
+  for (int p = 0; p < 8; ++p)
+    if (row0 + lr[p] < n && cl[p] < r) update_sums(sp, xn[p] - x[p], sg[p], gv[p]);
+}
 
 // ----------------------------------------------------------------------------- init
 // C = (sum of the A-pass partials) + lam P;  g = X G + lam X - C [+ gam LX].
-template <typename T, int RP>
+// DIR (fused inner iterations): also the direction of inner iteration 0 (alpha_0 = 1/rho)
+// and its sums (tile_direction) into pout; the first fused kernel runs its line search.
+template <typename T, int RP, int DIR>
 __global__ __launch_bounds__(kThreads, (inner_occupancy<T, RP>())) void k_init(
     const T* __restrict__ X, const T* __restrict__ P, const T* __restrict__ Bpart, int ksplit,
     int64_t bstride, T* __restrict__ Cout, T* __restrict__ g, const T* __restrict__ LX,
     const T* __restrict__ GT, int64_t n, int r, int is_hstep, KParams kp, State* __restrict__ st,
-    double* __restrict__ partsA, BMap bm, T* __restrict__ Zn, T* __restrict__ Dn) {
+    double* __restrict__ partsA, BMap bm, T* __restrict__ Zn, T* __restrict__ Dn,
+    T* __restrict__ Dd, double* __restrict__ pout) {
   const Loc lc = locate(bm, n, st, nullptr, kp.lam);
   st = lc.st;
   if (st->done) return;
@@ -303,8 +423,10 @@ __global__ __launch_bounds__(kThreads, (inner_occupancy<T, RP>())) void k_init(
   T gv[TileCfg<RP>::NG];
   load_G<T, RP>(GT, r, gv);
   const T lam = (T)kp.lam, gam = (T)kp.gamma;
-  const T rinv = Zn ? (T)(1.0 / st->rho) : T(0);
-  double v[1] = {0.0};
+  const T rinv = (Zn || DIR) ? (T)(1.0 / st->rho) : T(0);
+  const T step1 = (T)(kp.phi * 1.0);
+  double v[1] = {0.0}, ls[4] = {0.0, 0.0, 0.0, 0.0}, sp[3] = {0.0, 0.0, 0.0};
+  double xp[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   const int64_t ntiles = (n + TM - 1) / TM;
   bool first = true;
   for (int64_t t = lc.bid; t < ntiles; t += lc.nb) {
@@ -353,14 +475,16 @@ __global__ __launch_bounds__(kThreads, (inner_occupancy<T, RP>())) void k_init(
 #pragma unroll
     for (int p = 0; p < 8; ++p) sm.a[lr[p] * L::YP + cl[p]] = x[p];
     __syncthreads();
-    T xg[8];
+    T xg[8], gq[8];
     tile_gemm<T, RP>(sm.a, sm.G, xg);
 #pragma unroll
     for (int p = 0; p < 8; ++p) {
+      gq[p] = T(0);
       if (ok[p]) {
         sto(tile_ptr(Cout, tb), bo[p], cv[p]);
         T gvv = xg[p] + lam * x[p] - cv[p];
         if (LX) gvv += gam * lx[p];
+        gq[p] = gvv;
         sto(tile_ptr(g, tb), bo[p], gvv);
         if (Zn) {  // Laplacian H-step: Z and Z - X of the first inner iteration
           const T zz = first_proj(x[p], gvv, rinv);
@@ -368,23 +492,43 @@ __global__ __launch_bounds__(kThreads, (inner_occupancy<T, RP>())) void k_init(
           sto(tile_ptr(Dn, tb), bo[p], zz - x[p]);
         }
         if (is_hstep) {
-          v[0] += (double)cv[p] * (double)pv[p];
+          v[0] = fmaT((double)cv[p], (double)pv[p], v[0]);
         } else {
           const double mn = (double)(x[p] < gvv ? x[p] : gvv);
-          v[0] += mn * mn;
+          v[0] = fmaT(mn, mn, v[0]);
         }
       }
     }
+    if constexpr (DIR != 0) {
+      __syncthreads();  // every wave is done with the product on sm.a
+      tile_direction<T, RP>(sm, lr, cl, bo, row0, n, r, x, gq, rinv, rinv, lam, step1,
+                            kp.project, tile_ptr(Dd, tb), ls, sp, xp);
+    }
   }
-  block_sum<1>(v, sm.red);
-  write_parts<1>(partsA, lc.bid, v);
+  if constexpr (DIR != 0) {
+    const double o[1 + kFusedParts] = {v[0],  ls[0], ls[1], ls[2], ls[3], sp[0], sp[1],
+                                       sp[2], xp[0], xp[1], xp[2], xp[3], xp[4], xp[5]};
+    double* pa = partsA + (size_t)lc.bid * kNumPart;
+    double* po = pout + (size_t)lc.bid * kNumPart;
+    block_sum_emit<1 + kFusedParts>(o, sm.red, [&](int j, double a) {
+      if (j)
+        po[j - 1] = a;
+      else
+        pa[0] = a;
+    });
+  } else {
+    double* pa = partsA + (size_t)lc.bid * kNumPart;
+    block_sum_emit<1>(v, sm.red, [&](int j, double a) { pa[j] = a; });
+  }
 }
 
 // ----------------------------------------------------------------------------- entry
 // First kernel of inner iteration k: derive e_k and alpha_k (or, at k = 0, complete the
 // monitor record of the previous outer iteration).  `pe` holds this thread's share of
-// the partial sums (loaded at kernel start by entry_loads).  Returns false if this
-// inner iteration must not run (solve done, half-step stopped, breakdown).
+// the partial sums (loaded at kernel start by entry_loads).  Returns kEntryRun, or why
+// this inner iteration must not run: the half-step stopped (X_k = X_{k-1}), or the solve
+// is over (monitor target or max_outer met, breakdown).
+constexpr int kEntryRun = 0, kEntryHalfOver = 1, kEntrySolveOver = 2;
 __device__ __forceinline__ void entry_loads(int k, int is_hstep, const double* __restrict__ partsA,
                                             const double* __restrict__ partsC, int nb,
                                             double (&pe)[6]) {
@@ -413,7 +557,40 @@ __device__ __forceinline__ void entry_loads(int k, int is_hstep, const double* _
   }
 }
 
-__device__ bool inner_entry(int k, int is_hstep, int r, const KParams& kp, State* __restrict__ st,
+// e_k and alpha_k of inner iteration k >= 1 from the reduced sums of the last update,
+// s4 = {<S,S>, <S G, S>, <g, S>, <S, L S>}; the same return codes as inner_entry.
+__device__ int bb_step(int k, const double (&s4)[4], double e_prev, const KParams& kp,
+                       State* __restrict__ st, bool w0, double& alpha_out) {
+  const double ss = s4[0];
+  const double sy = s4[1] + kp.lam * ss + kp.gamma * s4[3];  // <S,Y> = <S(G+lam I),S> [+gam<S,LS>]
+  const double dlt = s4[2] + 0.5 * sy;                        // f(X_k) - f(X_{k-1})
+  const double e_k = kp.eta * (e_prev - dlt);                 // F_k - f(X_k)
+  const double ratio = sy > 0.0 ? ss / sy : 1e308;
+  const double alpha_k = fmin(kp.amax, fmax(kp.amin, ratio));
+  const bool bad = !(sy == sy) || !(dlt == dlt);
+  if (w0) {
+    st->last_ss = ss;
+    st->last_sy = sy;
+    if (bad) {
+      st->status = 9;
+      st->done = 1;
+    }
+  }
+  if (bad) return kEntrySolveOver;
+  if (ss == 0.0) {  // X_k = X_{k-1}: stationary, the half-step is over
+    if (w0) st->stop[k] = 1;
+    return kEntryHalfOver;
+  }
+  if (w0) {
+    st->e[k] = e_k;
+    st->alpha[k] = alpha_k;
+    st->stop[k] = 0;
+  }
+  alpha_out = alpha_k;
+  return kEntryRun;
+}
+
+__device__ int inner_entry(int k, int is_hstep, int r, const KParams& kp, State* __restrict__ st,
                             double (&pe)[6], int stop_prev, double e_prev, double rho,
                             const double* __restrict__ Gcur,
                             const double* __restrict__ Gprev, double* __restrict__ trace,
@@ -423,14 +600,14 @@ __device__ bool inner_entry(int k, int is_hstep, int r, const KParams& kp, State
     if (!is_hstep) {
       if (st->snap_pending) {
         // ||min(W, grad_W)||^2, <C,Ht>, <W,Ht>, ||Ht-W||^2, pgH^2, <Ht,LHt>
-        block_sum<6>(pe, sred);
+        block_sum_wide<6>(pe, sred);
         double gg[3] = {0.0, 0.0, 0.0};
         for (int e = threadIdx.x; e < r * r; e += kThreads) {
           gg[0] += Gprev[e] * Gcur[e];   // <W^T W, Ht^T Ht>
           gg[1] += Gprev[e] * Gprev[e];  // ||W^T W||_F^2
         }
         for (int a = threadIdx.x; a < r; a += kThreads) gg[2] += Gprev[a * r + a];  // ||W||^2
-        block_sum<3>(gg, sred);
+        block_sum_wide<3>(gg, sred);
         const double nA2 = st->normA2;
         const double AWHt = pe[1] - kp.lam * pe[2];     // <A W, Ht>
         const double AWW = st->m_CP - kp.lam * gg[2];   // <A W, W>
@@ -473,11 +650,11 @@ __device__ bool inner_entry(int k, int is_hstep, int r, const KParams& kp, State
           if (bad) st->status = 9;
           if (fin) st->done = 1;
         }
-        if (fin) return false;
+        if (fin) return kEntrySolveOver;
       }
     } else {
       double a1[1] = {pe[0]};
-      block_sum<1>(a1, sred);                        // <C, P> with P = W
+      block_sum_wide<1>(a1, sred);                   // <C, P> with P = W
       if (w0) st->m_CP = a1[0];
     }
     // the partner block vanished (rho = 0) or overflowed: breakdown, reported here so
@@ -487,37 +664,18 @@ __device__ bool inner_entry(int k, int is_hstep, int r, const KParams& kp, State
         st->status = 9;
         st->done = 1;
       }
-      return false;
+      return kEntrySolveOver;
     }
     e_k = 0.0;
     alpha_k = 1.0 / rho;
   } else {
     if (stop_prev) {
       if (w0) st->stop[k] = 1;
-      return false;
+      return kEntryHalfOver;
     }
     double s4[4] = {pe[0], pe[1], pe[2], pe[3]};
-    block_sum<4>(s4, sred);
-    const double ss = s4[0];
-    const double sy = s4[1] + kp.lam * ss + kp.gamma * s4[3];  // <S,Y> = <S(G+lam I),S> [+gam<S,LS>]
-    const double dlt = s4[2] + 0.5 * sy;                        // f(X_k) - f(X_{k-1})
-    e_k = kp.eta * (e_prev - dlt);                        // F_k - f(X_k)
-    const double ratio = sy > 0.0 ? ss / sy : 1e308;
-    alpha_k = fmin(kp.amax, fmax(kp.amin, ratio));
-    const bool bad = !(sy == sy) || !(dlt == dlt);
-    if (w0) {
-      st->last_ss = ss;
-      st->last_sy = sy;
-      if (bad) {
-        st->status = 9;
-        st->done = 1;
-      }
-    }
-    if (bad) return false;
-    if (ss == 0.0) {  // X_k = X_{k-1}: stationary, the half-step is over
-      if (w0) st->stop[k] = 1;
-      return false;
-    }
+    block_sum_wide<4>(s4, sred);
+    return bb_step(k, s4, e_prev, kp, st, w0, alpha_out);
   }
   if (w0) {
     st->e[k] = e_k;
@@ -525,7 +683,7 @@ __device__ bool inner_entry(int k, int is_hstep, int r, const KParams& kp, State
     st->stop[k] = 0;
   }
   alpha_out = alpha_k;
-  return true;
+  return kEntryRun;
 }
 
 // ----------------------------------------------------------------------------- step 1
@@ -599,8 +757,8 @@ __global__ __launch_bounds__(kThreads, (inner_occupancy<T, RP>())) void k_step1(
   // Z and Z - X come from the previous step 2 or from init), phase 1 only as the closing
   // entry of the half-step API
   double alpha_d = 0.0;
-  if (!inner_entry(k, is_hstep, r, kp, st, pe, stop_prev, e_prev, rho, Gcur, Gprev, trace,
-                   sm.red, lc.bid == 0 && threadIdx.x == 0, alpha_d))
+  if (inner_entry(k, is_hstep, r, kp, st, pe, stop_prev, e_prev, rho, Gcur, Gprev, trace,
+                  sm.red, lc.bid == 0 && threadIdx.x == 0, alpha_d) != kEntryRun)
     return;
   const T rinv = (T)(1.0 / rho);
   const T alpha = (T)alpha_d;
@@ -649,9 +807,7 @@ __global__ __launch_bounds__(kThreads, (inner_occupancy<T, RP>())) void k_step1(
         // phase 0 keeps Z in registers only, and D too when rd is set: step 2 recomputes
         // them from X and g
         if (phase != 0 || !rd) sto(tile_ptr(D, tb), bo[p], dd);
-        v[0] += (double)gz * (double)dd;
-        v[2] += (double)dd * (double)dd;
-        v[3] += 0.5 * ((double)gvv[p] + (double)gz) * (double)dz;
+        direction_sums(v, gz, dd, gvv[p], dz);
       }
       sm.b[lr[p] * L::YP + cl[p]] = dd;
     }
@@ -659,10 +815,10 @@ __global__ __launch_bounds__(kThreads, (inner_occupancy<T, RP>())) void k_step1(
     T dg[8];
     tile_gemm<T, RP>(sm.b, sm.G, dg);
 #pragma unroll
-    for (int p = 0; p < 8; ++p) v[1] += (double)dg[p] * (double)d[p];
+    for (int p = 0; p < 8; ++p) v[1] = fmaT((double)dg[p], (double)d[p], v[1]);
   }
-  block_sum<4>(v, sm.red);
-  write_parts<4>(partsB, lc.bid, v);
+  double* pb = partsB + (size_t)lc.bid * kNumPart;
+  block_sum_emit<4>(v, sm.red, [&](int j, double a) { pb[j] = a; });
 }
 
 // ----------------------------------------------------------------------------- line search
@@ -794,18 +950,13 @@ __global__ __launch_bounds__(kThreads, (inner_occupancy<T, RP, V>())) void k_ste
 #pragma unroll
           for (int p = 0; p < 8; ++p) {
             if (t * TM + lr[p] < n && cl[p] < r) {
-              const T xv = ldo(tile_ptr(X, tb), bo[p]), gg = ldo(tile_ptr(g, tb), bo[p]);
-              const double xd = (double)xv, pd2 = (double)ldo(tile_ptr(P, tb), bo[p]);
-              v[3] += (double)ldo(tile_ptr(C, tb), bo[p]) * xd;
-              v[4] += pd2 * xd;
-              v[5] += (xd - pd2) * (xd - pd2);
-              const double mn = (double)(xv < gg ? xv : gg);
-              v[6] += mn * mn;
+              monitor_sums(v + 3, ldo(tile_ptr(X, tb), bo[p]), ldo(tile_ptr(g, tb), bo[p]),
+                           ldo(tile_ptr(C, tb), bo[p]), ldo(tile_ptr(P, tb), bo[p]));
             }
           }
         }
-        block_sum<9>(v, sm.red);
-        write_parts<9>(partsC, lc.bid, v);
+        double* pc = partsC + (size_t)lc.bid * kNumPart;
+        block_sum_emit<9>(v, sm.red, [&](int j, double a) { pc[j] = a; });
         if (w0) {  // (set already when an earlier step 2 of this H-step ran)
           st->pending = 1;
           st->t_hstep = wall_clock64();
@@ -816,10 +967,10 @@ __global__ __launch_bounds__(kThreads, (inner_occupancy<T, RP, V>())) void k_ste
   }
   double beta;
   if (phase != 2) {
-    block_sum<4>(pb, sm.red);
+    block_sum_wide<4>(pb, sm.red);
     double q = pb[1] + kp.lam * pb[2];
     if (partsD) {
-      block_sum<1>(pd, sm.red);
+      block_sum_wide<1>(pd, sm.red);
       q += kp.gamma * pd[0];
     }
     int evals, exh;
@@ -842,8 +993,7 @@ __global__ __launch_bounds__(kThreads, (inner_occupancy<T, RP, V>())) void k_ste
 #pragma unroll
       for (int p = 0; p < 8; ++p) {
         if (t * TM + lr[p] < n && cl[p] < r) {
-          T xn = zz[p] + step * dd[p];
-          if (kp.project) xn = relu(xn);
+          const T xn = next_point(zz[p], dd[p], step, kp.project);
           sto(tile_ptr(Z, tb), bo[p], xn);
           sto(tile_ptr(D, tb), bo[p], xn - x[p]);
         }
@@ -881,9 +1031,7 @@ __global__ __launch_bounds__(kThreads, (inner_occupancy<T, RP, V>())) void k_ste
       if (phase == 2) {
         xn[p] = zz[p];
       } else {
-        T y = zz[p] + step * dd[p];
-        if (kp.project) y = relu(y);
-        xn[p] = ok ? y : T(0);
+        xn[p] = ok ? next_point(zz[p], dd[p], step, kp.project) : T(0);
       }
       sm.b[lr[p] * L::YP + cl[p]] = ok ? xn[p] - x[p] : T(0);
     }
@@ -895,22 +1043,13 @@ __global__ __launch_bounds__(kThreads, (inner_occupancy<T, RP, V>())) void k_ste
     for (int p = 0; p < 8; ++p) {
       if (row0 + lr[p] < n && cl[p] < r) {
         const T s = xn[p] - x[p];
-        T gn = go[p] + sg[p] + lam * s;
+        T gn = next_grad(go[p], sg[p], lam, s);
         if (lap) gn += gam * ls[p];
         sto(tile_ptr(X, tb), bo[p], xn[p]);
         sto(tile_ptr(g, tb), bo[p], gn);
-        v[0] += (double)s * (double)s;
-        v[1] += (double)sg[p] * (double)s;
-        v[2] += (double)go[p] * (double)s;
+        update_sums(v, s, sg[p], go[p]);
         if (lap) v[8] += (double)s * (double)ls[p];
-        if (mon) {
-          const double xv = (double)xn[p];
-          v[3] += (double)cv[p] * xv;
-          v[4] += (double)pv[p] * xv;
-          v[5] += (xv - (double)pv[p]) * (xv - (double)pv[p]);
-          const double mn = (double)(xn[p] < gn ? xn[p] : gn);
-          v[6] += mn * mn;
-        }
+        if (mon) monitor_sums(v + 3, xn[p], gn, cv[p], pv[p]);
         if (lap && LXb) {
           const T lxn = lx[p] + ls[p];
           sto(tile_ptr(LXb, tb), bo[p], lxn);
@@ -924,19 +1063,190 @@ __global__ __launch_bounds__(kThreads, (inner_occupancy<T, RP, V>())) void k_ste
       }
     }
   }
+  double* pc = partsC + (size_t)lc.bid * kNumPart;
   if (mon || lap) {
-    block_sum<9>(v, sm.red);
+    block_sum_emit<9>(v, sm.red, [&](int j, double a) { pc[j] = a; });
   } else {  // a step without monitor sums or Laplacian produces only the first three
-    double v3[3] = {v[0], v[1], v[2]};
-    block_sum<3>(v3, sm.red);
-    v[0] = v3[0];
-    v[1] = v3[1];
-    v[2] = v3[2];
+    const double v3[3] = {v[0], v[1], v[2]};
+    block_sum_emit<3>(v3, sm.red, [&](int j, double a) { pc[j] = a; });
+    if (threadIdx.x == 0)
+      for (int j = 3; j < 9; ++j) pc[j] = 0.0;
   }
-  write_parts<9>(partsC, lc.bid, v);
   if (is_hstep && w0) {
     st->pending = 1;
     st->t_hstep = wall_clock64();
+  }
+}
+
+// ----------------------------------------------------------------------------- fused
+// Inner iterations with one kernel each (half-steps without the Laplacian term).  An inner
+// iteration needs two grid-wide sums: those of its direction (for the line search) and
+// those of its update S_k (for the next BB step).  The kernel that forms D_k also forms
+// the sums from which the next kernel gets the update's without another reduction
+// (tile_direction): for the trial beta = 1 those of the update itself, formed as step 2
+// forms them (the same bits), and for any backtracked trial the polynomial coefficients
+// of S = dZ + t D.  Kernel i of a half-step thus runs the line search of iteration i,
+// derives e_{i+1} and alpha_{i+1}, applies the update and forms direction i + 1 in one
+// pass over its tiles; kernel K - 1 applies the last update and, in an H-step, forms the
+// monitor sums (into partsC, as step 2 does).  Partial sums alternate between two arrays
+// (pin of kernel i = pout of kernel i - 1).  A half-step that stops early (S = 0) marks
+// the remaining iterations stopped; their kernels return at once.
+template <typename T, int RP, int HS>
+__global__ __launch_bounds__(kThreads, (inner_occupancy<T, RP>())) void k_advance(
+    T* __restrict__ X, T* __restrict__ g, T* __restrict__ D, const T* __restrict__ C,
+    const T* __restrict__ P, const T* __restrict__ GT, const double* __restrict__ Gcur,
+    const double* __restrict__ Gprev, int64_t n, int r, int K, int i, KParams kp,
+    State* __restrict__ st, const double* __restrict__ pin, double* __restrict__ pout,
+    const double* __restrict__ partsA, double* __restrict__ partsC, double* __restrict__ trace) {
+  typedef Lay<T, RP> L;
+  constexpr int TM = L::TM;
+  __shared__ Smem<T, RP> sm;
+  const int nb = (int)gridDim.x, bid = (int)blockIdx.x;
+  const bool w0 = bid == 0 && threadIdx.x == 0;
+  int lr[8], cl[8];
+  uint32_t bo[8];
+#pragma unroll
+  for (int p = 0; p < 8; ++p) {
+    L::rc(p, lr[p], cl[p]);
+    bo[p] = (uint32_t)((lr[p] * r + cl[p]) * (int)sizeof(T));
+  }
+  const int64_t ntiles = (n + TM - 1) / TM;
+  // loads first: State scalars, the partial sums (and the k = 0 entry's), G, the first tile
+  const int done = st->done;
+  const int stopped = i > 0 ? st->stop[i] : 0;
+  const double rho = st->rho, e_i = i > 0 ? st->e[i] : 0.0;
+  double pa[kFusedParts];
+  load_slots<kFusedParts>(pin, nb, 0, pa);
+  double pe[6];
+  entry_loads(0, HS, partsA, partsC, nb, pe);
+  T gv[TileCfg<RP>::NG];
+  load_G<T, RP>(GT, r, gv);
+  T x[8], go[8], dd[8];
+  auto load_tile = [&](int64_t row0) {
+    const int64_t tb = row0 * r;
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+      const bool ok = row0 + lr[p] < n && cl[p] < r;
+      x[p] = ok ? ldo(tile_ptr(X, tb), bo[p]) : T(0);
+      go[p] = ok ? ldo(tile_ptr(g, tb), bo[p]) : T(0);
+      dd[p] = ok ? ldo(tile_ptr(D, tb), bo[p]) : T(0);
+    }
+  };
+  if (bid < ntiles) load_tile((int64_t)bid * TM);
+  if (done || stopped) return;
+  if (i == 0) {  // inner iteration 0 opens here: monitor record, <C, P>, rho check
+    double a0;
+    if (inner_entry(0, HS, r, kp, st, pe, 0, 0.0, rho, Gcur, Gprev, trace, sm.red, w0, a0) !=
+        kEntryRun)
+      return;
+  }
+  block_sum_wide<kFusedParts>(pa, sm.red);
+  // line search of iteration i (step 2's)
+  const double q = pa[1] + kp.lam * pa[2];
+  int evals, exh;
+  const double beta = line_search(pa[0], q, pa[3], e_i, kp, evals, exh);
+  if (w0) {
+    st->beta[i] = beta;
+    st->ls_evals += evals;
+    st->ls_exhausted += exh;
+    st->inner_total += 1;
+  }
+  // then the next BB step from the sums of this update
+  bool dir = false, closing = i + 1 >= K;
+  double alpha_d = 0.0;
+  if (!closing) {
+    double s4[4];
+    if (beta == 1.0) {
+      s4[0] = pa[4];
+      s4[1] = pa[5];
+      s4[2] = pa[6];
+    } else {  // S = dZ + t D
+      const double t = kp.phi * beta;
+      s4[0] = pa[7] + t * (2.0 * pa[8] + t * pa[2]);
+      s4[1] = pa[9] + t * (2.0 * pa[10] + t * pa[1]);
+      s4[2] = pa[11] + t * pa[12];
+    }
+    s4[3] = 0.0;
+    const int e = bb_step(i + 1, s4, e_i, kp, st, w0, alpha_d);
+    if (e == kEntrySolveOver) return;
+    dir = e == kEntryRun;
+    closing = e == kEntryHalfOver;
+  }
+  store_G<T, RP>(sm.G, gv);
+  const T rinv = (T)(1.0 / rho);
+  const T lam = (T)kp.lam;
+  const T step = (T)(kp.phi * beta), step1 = (T)(kp.phi * 1.0), alpha = (T)alpha_d;
+  double ex[3] = {0.0, 0.0, 0.0}, ls[4] = {0.0, 0.0, 0.0, 0.0}, sp[3] = {0.0, 0.0, 0.0};
+  double xp[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, mon[4] = {0.0, 0.0, 0.0, 0.0};
+  // step 2's update of one tile (X+ and g+ in xn, gn; X, g stored)
+  auto update_tile = [&](int64_t row0, T (&xn)[8], T (&gn)[8]) {
+    const int64_t tb = row0 * r;
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+      const bool ok = row0 + lr[p] < n && cl[p] < r;
+      const T zz = first_proj(x[p], go[p], rinv);
+      xn[p] = ok ? next_point(zz, dd[p], step, kp.project) : T(0);
+      sm.b[lr[p] * L::YP + cl[p]] = ok ? xn[p] - x[p] : T(0);
+    }
+    __syncthreads();
+    T sg[8];
+    tile_gemm<T, RP>(sm.b, sm.G, sg);
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+      gn[p] = T(0);
+      if (row0 + lr[p] < n && cl[p] < r) {
+        const T s = xn[p] - x[p];
+        gn[p] = next_grad(go[p], sg[p], lam, s);
+        sto(tile_ptr(X, tb), bo[p], xn[p]);
+        sto(tile_ptr(g, tb), bo[p], gn[p]);
+        update_sums(ex, s, sg[p], go[p]);
+      }
+    }
+  };
+  if (closing) {  // the last update, then the H-step's monitor sums of the final X
+    for (int64_t t = bid; t < ntiles; t += nb) {
+      const int64_t row0 = t * TM, tb = row0 * r;
+      if (t != bid) load_tile(row0);
+      T xn[8], gn[8];
+      __syncthreads();
+      update_tile(row0, xn, gn);
+      if (HS) {
+#pragma unroll
+        for (int p = 0; p < 8; ++p)
+          if (row0 + lr[p] < n && cl[p] < r)
+            monitor_sums(mon, xn[p], gn[p], ldo(tile_ptr(C, tb), bo[p]), ldo(tile_ptr(P, tb), bo[p]));
+      }
+    }
+  } else {  // the update and direction i + 1
+    for (int64_t t = bid; t < ntiles; t += nb) {
+      const int64_t row0 = t * TM, tb = row0 * r;
+      if (t != bid) load_tile(row0);
+      T xn[8], gn[8];
+      __syncthreads();
+      update_tile(row0, xn, gn);
+      // sm.a was last read before this tile's first barrier
+      tile_direction<T, RP>(sm, lr, cl, bo, row0, n, r, xn, gn, rinv, alpha, lam, step1,
+                            kp.project, tile_ptr(D, tb), ls, sp, xp);
+    }
+  }
+  if (dir) {
+    const double o[kFusedParts] = {ls[0], ls[1], ls[2], ls[3], sp[0], sp[1], sp[2],
+                                   xp[0], xp[1], xp[2], xp[3], xp[4], xp[5]};
+    double* po = pout + (size_t)bid * kNumPart;
+    block_sum_emit<kFusedParts>(o, sm.red, [&](int j, double a) { po[j] = a; });
+  } else {
+    if (HS) {
+      const double v[9] = {ex[0], ex[1], ex[2], mon[0], mon[1], mon[2], mon[3], 0.0, 0.0};
+      double* pc = partsC + (size_t)bid * kNumPart;
+      block_sum_emit<9>(v, sm.red, [&](int j, double a) { pc[j] = a; });
+    }
+    if (w0) {
+      for (int k = i + 2; k < K; ++k) st->stop[k] = 1;  // (stop[i + 1] set by bb_step)
+      if (HS) {
+        st->pending = 1;
+        st->t_hstep = wall_clock64();
+      }
+    }
   }
 }
 
@@ -947,11 +1257,11 @@ __global__ __launch_bounds__(kThreads, (inner_occupancy<T, RP, V>())) void k_ste
 // 0, so that its one step 2 forms the monitor sums of H = W without moving it.
 __global__ __launch_bounds__(kThreads) void k_naive_hentry(const double* __restrict__ partsA,
                                                            int nb, State* __restrict__ st) {
-  __shared__ double sred[kThreads / kWave];
+  __shared__ double sred[kStage];
   if (st->done) return;
   double a1[1];
   load_slots<1>(partsA, nb, 0, a1);
-  block_sum<1>(a1, sred);
+  block_sum_wide<1>(a1, sred);
   if (threadIdx.x == 0) {
     st->m_CP = a1[0];
     st->stop[0] = 1;
@@ -1013,12 +1323,38 @@ template <typename T>
 void launch_init(const T* X, const T* P, const T* Bpart, int ksplit, int64_t bstride, T* C, T* g,
                  const T* LX, const T* GT, int64_t n, int r, int is_hstep, const KParams& kp,
                  State* st, double* partsA, hipStream_t s, const BMap& bm, int grid, T* Zn,
-                 T* Dn) {
+                 T* Dn, T* Dd, double* pout) {
   if (grid <= 0) grid = inner_grid(n, r, (int)sizeof(T));
-  SNMF_DISPATCH_RP(rank_pad(r),
-                   hipLaunchKernelGGL((k_init<T, RP>), dim3(grid), dim3(kThreads), 0, s, X, P,
-                                      Bpart, ksplit, bstride, C, g, LX, GT, n, r, is_hstep, kp, st,
-                                      partsA, bm, Zn, Dn))
+  if (Dd) {
+    SNMF_DISPATCH_RP(rank_pad(r),
+                     hipLaunchKernelGGL((k_init<T, RP, 1>), dim3(grid), dim3(kThreads), 0, s, X,
+                                        P, Bpart, ksplit, bstride, C, g, LX, GT, n, r, is_hstep,
+                                        kp, st, partsA, bm, Zn, Dn, Dd, pout))
+  } else {
+    SNMF_DISPATCH_RP(rank_pad(r),
+                     hipLaunchKernelGGL((k_init<T, RP, 0>), dim3(grid), dim3(kThreads), 0, s, X,
+                                        P, Bpart, ksplit, bstride, C, g, LX, GT, n, r, is_hstep,
+                                        kp, st, partsA, bm, Zn, Dn, Dd, pout))
+  }
+}
+
+template <typename T>
+void launch_advance(T* X, T* g, T* D, const T* C, const T* P, const T* GT, const double* Gcur,
+                    const double* Gprev, int64_t n, int r, int K, int i, int is_hstep,
+                    const KParams& kp, State* st, const double* pin, double* pout,
+                    const double* partsA, double* partsC, double* trace, hipStream_t s) {
+  const int grid = inner_grid(n, r, (int)sizeof(T));
+  if (is_hstep) {
+    SNMF_DISPATCH_RP(rank_pad(r),
+                     hipLaunchKernelGGL((k_advance<T, RP, 1>), dim3(grid), dim3(kThreads), 0, s,
+                                        X, g, D, C, P, GT, Gcur, Gprev, n, r, K, i, kp, st, pin,
+                                        pout, partsA, partsC, trace))
+  } else {
+    SNMF_DISPATCH_RP(rank_pad(r),
+                     hipLaunchKernelGGL((k_advance<T, RP, 0>), dim3(grid), dim3(kThreads), 0, s,
+                                        X, g, D, C, P, GT, Gcur, Gprev, n, r, K, i, kp, st, pin,
+                                        pout, partsA, partsC, trace))
+  }
 }
 
 template <typename T>
@@ -1068,7 +1404,11 @@ void launch_step2(T* X, T* g, T* Z, T* D, const T* LS, const T* C, const T* P, T
 #define SNMF_INST(T)                                                                            \
   template void launch_init<T>(const T*, const T*, const T*, int, int64_t, T*, T*, const T*,   \
                                const T*, int64_t, int, int, const KParams&, State*, double*,   \
-                               hipStream_t, const BMap&, int, T*, T*);                          \
+                               hipStream_t, const BMap&, int, T*, T*, T*, double*);             \
+  template void launch_advance<T>(T*, T*, T*, const T*, const T*, const T*, const double*,      \
+                                  const double*, int64_t, int, int, int, int, const KParams&,   \
+                                  State*, const double*, double*, const double*, double*,       \
+                                  double*, hipStream_t);                                        \
   template void launch_step1<T>(const T*, const T*, T*, T*, const T*, const T*, const double*, \
                                 const double*, int64_t, int, int, int, int, const KParams&,     \
                                 State*, const double*, double*, const double*, double*,         \

@@ -132,7 +132,16 @@ template <typename T>
 void launch_init(const T* X, const T* P, const T* Bpart, int ksplit, int64_t bstride, T* C, T* g,
                  const T* LX, const T* GT, int64_t n, int r, int is_hstep, const KParams& kp,
                  State* st, double* partsA, hipStream_t s, const BMap& bm = BMap{}, int grid = 0,
-                 T* Zn = nullptr, T* Dn = nullptr);  // Laplacian H-step: Z, Z - X of iteration 0
+                 T* Zn = nullptr, T* Dn = nullptr,  // Laplacian H-step: Z, Z - X of iteration 0
+                 T* Dd = nullptr, double* pout = nullptr);  // fused: direction 0 into Dd
+// Fused inner kernel i (0 <= i < K: line search and update of inner iteration i, direction
+// i + 1) of a half-step without the Laplacian term (single solves); pin / pout alternate
+// between two partial-sum arrays.
+template <typename T>
+void launch_advance(T* X, T* g, T* D, const T* C, const T* P, const T* GT, const double* Gcur,
+                    const double* Gprev, int64_t n, int r, int K, int i, int is_hstep,
+                    const KParams& kp, State* st, const double* pin, double* pout,
+                    const double* partsA, double* partsC, double* trace, hipStream_t s);
 template <typename T>
 void launch_step1(const T* X, const T* g, T* Z, T* D, const T* LdZ, const T* GT,
                   const double* Gcur, const double* Gprev, int64_t n, int r, int k, int phase,

@@ -101,6 +101,7 @@ snmf_status check_params(const snmf_params* p) {
   if (p->max_outer < 1) return fail(SNMF_E_ARG, "max_outer must be >= 1");
   if (!(p->target_res >= 0.0)) return fail(SNMF_E_ARG, "target_res must be >= 0");
   if (p->prec < SNMF_F64 || p->prec > SNMF_BF16X3) return fail(SNMF_E_ARG, "unknown precision");
+  if (p->fuse_inner != 0 && p->fuse_inner != 1) return fail(SNMF_E_ARG, "fuse_inner must be 0 or 1");
   if (p->accept_at_relaxed && p->project_update)
     return fail(SNMF_E_UNSUPPORTED,
                 "accept_at_relaxed needs project_update = 0 (the projected relaxed point has "
@@ -276,9 +277,21 @@ int ksplit_of(const snmf_plan* pl) {
 // Start of a half-step up to and including init: G, rho (in or just before the A-pass,
 // on the same stream: a second stream would cost more in cross-queue waits than rho
 // takes), the A-pass and the gradient.  The first reader of rho is the first inner kernel.
+// Inner iterations of this half-step run as fused kernels, one per inner iteration: every
+// half-step without the Laplacian term, except the H-step of the naive variant, provided a
+// backtracked update is never clipped by the projection (phi beta_shrink <= 1, or no
+// projection, or no backtracking at all), which the fused kernels' BB step after a
+// backtrack relies on.
+bool fused_half(const snmf_plan* pl, int is_hstep) {
+  const snmf_params& p = pl->p;
+  const bool unclipped = !p.project_update || p.max_ls == 0 || p.phi * p.beta_shrink <= 1.0;
+  return p.fuse_inner && unclipped && !(pl->lap && is_hstep) && !(p.naive && is_hstep);
+}
+
+// dir: init also forms the fused path's direction 0 (fused_half).
 template <typename T>
 snmf_status half_start(snmf_plan* pl, T* X, const T* P, int is_hstep, bool with_rho,
-                       hipStream_t s) {
+                       hipStream_t s, bool dir = false) {
   const int64_t n = pl->n;
   const int r = pl->r;
   const int gi = is_hstep ? 1 : 0;
@@ -299,7 +312,8 @@ snmf_status half_start(snmf_plan* pl, T* X, const T* P, int is_hstep, bool with_
   launch_init<T>(X, P, (const T*)pl->Bpart, ksplit_of(pl), n * r, (T*)pl->C, (T*)pl->g,
                  lap ? (const T*)pl->LX : nullptr, (const T*)pl->GT[gi], n, r, is_hstep, pl->kp,
                  pl->st, pl->partsA, s, BMap{}, 0, lap ? (T*)pl->Z : nullptr,
-                 lap ? (T*)pl->D : nullptr);
+                 lap ? (T*)pl->D : nullptr, dir ? (T*)pl->D : nullptr,
+                 dir ? pl->partsB : nullptr);
   HIP_TRY(hipGetLastError());
   return SNMF_OK;
 }
@@ -352,9 +366,24 @@ snmf_status inner_step(snmf_plan* pl, T* X, const T* P, int is_hstep, int k, hip
   return SNMF_OK;
 }
 
+// The inner iterations of a half-step: with `fused` (its init ran with dir set) K fused
+// kernels, partial sums alternating between partsB and partsD (which the fused path does
+// not otherwise use); else K pairs of step 1 and step 2.
 template <typename T>
-snmf_status inner_steps(snmf_plan* pl, T* X, const T* P, int is_hstep, hipStream_t s) {
-  for (int k = 0; k < pl->p.inner_iters; ++k) SNMF_TRY(inner_step<T>(pl, X, P, is_hstep, k, s));
+snmf_status inner_steps(snmf_plan* pl, T* X, const T* P, int is_hstep, hipStream_t s,
+                        bool fused) {
+  const int K = pl->p.inner_iters;
+  if (fused) {
+    for (int i = 0; i < K; ++i) {
+      launch_advance<T>(X, (T*)pl->g, (T*)pl->D, (const T*)pl->C, P,
+                        (const T*)pl->GT[is_hstep ? 1 : 0], pl->G64[0], pl->G64[1], pl->n, pl->r,
+                        K, i, is_hstep, pl->kp, pl->st, (i & 1) ? pl->partsD : pl->partsB,
+                        (i & 1) ? pl->partsB : pl->partsD, pl->partsA, pl->partsC, pl->trace, s);
+    }
+    HIP_TRY(hipGetLastError());
+    return SNMF_OK;
+  }
+  for (int k = 0; k < K; ++k) SNMF_TRY(inner_step<T>(pl, X, P, is_hstep, k, s));
   return SNMF_OK;
 }
 
@@ -362,8 +391,8 @@ template <typename T>
 snmf_status outer_iteration(snmf_plan* pl, hipStream_t s) {
   T* W = (T*)pl->Wb;
   T* H = (T*)pl->Hb;
-  SNMF_TRY(half_start<T>(pl, W, H, 0, true, s));
-  SNMF_TRY(inner_steps<T>(pl, W, H, 0, s));
+  SNMF_TRY(half_start<T>(pl, W, H, 0, true, s, fused_half(pl, 0)));
+  SNMF_TRY(inner_steps<T>(pl, W, H, 0, s, fused_half(pl, 0)));
   if (pl->p.naive) {
     // H <- W^T, then an H-step that stops before its first inner iteration: its init
     // (at H = W) and its one step 2 supply the monitor sums of the pair (W, W)
@@ -376,8 +405,8 @@ snmf_status outer_iteration(snmf_plan* pl, hipStream_t s) {
     HIP_TRY(hipGetLastError());
     return SNMF_OK;
   }
-  SNMF_TRY(half_start<T>(pl, H, W, 1, true, s));
-  SNMF_TRY(inner_steps<T>(pl, H, W, 1, s));
+  SNMF_TRY(half_start<T>(pl, H, W, 1, true, s, fused_half(pl, 1)));
+  SNMF_TRY(inner_steps<T>(pl, H, W, 1, s, fused_half(pl, 1)));
   return SNMF_OK;
 }
 
@@ -747,6 +776,7 @@ snmf_status snmf_params_default(snmf_params* p) {
   p->project_update = 1;
   p->validate = 1;
   p->use_graph = 1;
+  p->fuse_inner = 1;
   return SNMF_OK;
 }
 
@@ -794,14 +824,14 @@ snmf_status snmf_plan_half_step(snmf_plan* pl, void* X, const void* P, int32_t i
   // touches scratch (Z, D), never X.
   if (pl->prec == SNMF_F64) {
     SNMF_TRY(half_start<double>(pl, (double*)X, (const double*)P, is_hstep, true, pl->s));
-    SNMF_TRY(inner_steps<double>(pl, (double*)X, (const double*)P, is_hstep, pl->s));
+    SNMF_TRY(inner_steps<double>(pl, (double*)X, (const double*)P, is_hstep, pl->s, false));
     launch_step1<double>((const double*)X, (const double*)pl->g, (double*)pl->Z, (double*)pl->D,
                          nullptr, (const double*)pl->GT[is_hstep ? 1 : 0], pl->G64[0], pl->G64[1],
                          pl->n, pl->r, K, (pl->lap && is_hstep) ? 1 : 0, is_hstep, pl->kp, pl->st,
                          pl->partsA, pl->partsB, pl->partsC, pl->trace, pl->s, BMap{}, 0, 1);
   } else {
     SNMF_TRY(half_start<float>(pl, (float*)X, (const float*)P, is_hstep, true, pl->s));
-    SNMF_TRY(inner_steps<float>(pl, (float*)X, (const float*)P, is_hstep, pl->s));
+    SNMF_TRY(inner_steps<float>(pl, (float*)X, (const float*)P, is_hstep, pl->s, false));
     launch_step1<float>((const float*)X, (const float*)pl->g, (float*)pl->Z, (float*)pl->D,
                         nullptr, (const float*)pl->GT[is_hstep ? 1 : 0], pl->G64[0], pl->G64[1],
                         pl->n, pl->r, K, (pl->lap && is_hstep) ? 1 : 0, is_hstep, pl->kp, pl->st,

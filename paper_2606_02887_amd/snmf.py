@@ -50,7 +50,7 @@ class Params(ctypes.Structure):
                 ("check_every", c_int32), ("target_res", c_double), ("prec", c_int32),
                 ("accept_at_relaxed", c_int32), ("project_update", c_int32),
                 ("validate", c_int32), ("use_graph", c_int32), ("check_symmetry", c_int32),
-                ("naive", c_int32), ("tuning", POINTER(Tuning))]
+                ("naive", c_int32), ("fuse_inner", c_int32), ("tuning", POINTER(Tuning))]
 
 
 class Info(ctypes.Structure):
@@ -70,7 +70,7 @@ class MlpC(ctypes.Structure):
                 ("adam_m", c_void_p), ("adam_v", c_void_p)]
 
 
-ABI_VERSION = 3
+ABI_VERSION = 4
 EXPORTS = ("snmf_params_default", "snmf_solve", "snmf_solve_noalloc", "snmf_plan_create",
            "snmf_plan_solve",
            "snmf_plan_destroy", "snmf_plan_half_step", "snmf_plan_apass", "snmf_plan_gram",

@@ -95,14 +95,15 @@ def test_batch_instances_follow_the_oracle(S, prec):
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_batch_equal_starts_are_bitwise_equal_and_match_single_solve(S, prec):
     """Instances are isolated: S copies of one start give bitwise identical factors, and
-    (dense A: the same kernels as the single path) bitwise the single solve's factors."""
+    (dense A: the same kernels as the single path's two-kernel inner iterations,
+    fuse_inner = 0) bitwise the single solve's factors."""
     dt = DT[prec]
     prob = gen.planted_dense(240, 6, 77)
     At = torch.from_numpy(prob["A"]).to(DEV, dt)
     W0 = torch.from_numpy(prob["W0"]).to(DEV, dt)
     lam = O.default_lambda(prob["A"])
     p = S.F64 if prec == "f64" else S.F32
-    W1, H1, i1 = S.solve(S.dense(At), W0, S.params(lam=lam, prec=p, max_outer=30))
+    W1, H1, i1 = S.solve(S.dense(At), W0, S.params(lam=lam, prec=p, max_outer=30, fuse_inner=0))
     W0s = [W0.unsqueeze(0).repeat(3, 1, 1).contiguous()]
     with S.Batch([S.dense(At)], [6], S.params(lam=lam, prec=p, max_outer=30), restarts=3) as b:
         Ws, Hs, infos, _ = b.solve(W0s)
