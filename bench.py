@@ -36,6 +36,8 @@ def _args():
                          "FP64 reference after 2000 outer iterations, which the FP32 forms "
                          "reach a few dozen iterations later)")
     ap.add_argument("--no-target", action="store_true")
+    ap.add_argument("--fuse-inner", type=int, choices=(0, 1), default=1,
+                    help="single solves: one kernel per inner iteration (1) or two (0)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-outer", type=int, default=0,
                     help="outer iterations of the CPU-reference sample (0: pick ~15 s)")
@@ -406,7 +408,8 @@ def _bench_c2(a, torch, np, S, gen):
     L_nnz = int(Lg.keep[2].numel())
     Ag = S.csr_from_scipy(A, torch.float32)
     W0 = torch.from_numpy(W0n).to(dev, torch.float32)
-    prm = S.params(lam=lam, gamma=0.2, prec=S.F32, max_outer=a.steps, check_every=1 << 30)
+    prm = S.params(lam=lam, gamma=0.2, prec=S.F32, max_outer=a.steps, check_every=1 << 30,
+                   fuse_inner=a.fuse_inner)
     with S.Plan(Ag, r, prm, Lg) as pl:
         el, Ht, info = _timed_solve(torch, pl, W0, a.steps)
         ms = pl.time_apass(W0, 100)
@@ -474,7 +477,8 @@ def _bench_c3(a, torch, np, S, gen):
     r = W0n.shape[1]
     lam = 0.01 * float(np.sqrt(np.sum(lamv ** 2)))
     W0 = torch.from_numpy(W0n).to(dev, torch.float32)
-    prm = S.params(lam=lam, prec=S.F32, max_outer=a.steps, check_every=1 << 30)
+    prm = S.params(lam=lam, prec=S.F32, max_outer=a.steps, check_every=1 << 30,
+                   fuse_inner=a.fuse_inner)
     with S.Plan(S.lowrank(Ug, lg), r, prm) as pl:
         el, Ht, info = _timed_solve(torch, pl, W0, a.steps)
         ms = pl.time_apass(W0, 100)
@@ -668,9 +672,10 @@ def main():
     plans = {}
     for name, prec in (("fp32", S.F32), ("bf16x3", S.BF16X3)):
         pl = S.Plan(S.dense(A), R, S.params(lam=lam, prec=prec, max_outer=a.steps,
-                                            check_every=1 << 30))
+                                            check_every=1 << 30, fuse_inner=a.fuse_inner))
         plans[name] = pl
-        wp = S.Plan(S.dense(A), R, S.params(lam=lam, prec=prec, max_outer=max(1, a.warmup)))
+        wp = S.Plan(S.dense(A), R, S.params(lam=lam, prec=prec, max_outer=max(1, a.warmup),
+                                            fuse_inner=a.fuse_inner))
         wp.solve(W0, trace=False)                        # warmup (graph capture, clocks)
         wp.close()
         pl.solve(W0, trace=False)                        # first call captures its graph
@@ -735,7 +740,8 @@ def main():
         target = (1 + 1e-4) * ref["res_ref"]
         for name, prec in (("fp32", S.F32), ("bf16x3", S.BF16X3)):
             with S.Plan(S.dense(A), R, S.params(lam=lam, prec=prec, max_outer=a.target_cap,
-                                                target_res=target, check_every=16)) as tp:
+                                                target_res=target, check_every=16,
+                                                fuse_inner=a.fuse_inner)) as tp:
                 _, _, info = tp.solve(W0, trace=True)
             forms[name]["time_to_target_s"] = info["seconds_to_target"] if info["converged_at"] else None
             forms[name]["outer_to_target"] = info["converged_at"] or None

@@ -137,9 +137,11 @@ typedef struct snmf_params {
                           own sums, which give the same bits as 0; after a backtrack the
                           sums of S = dZ + phi beta D, which the projection leaves unclipped
                           when phi beta_shrink <= 1 (the same scalars up to rounding).  Used
-                          where phi beta_shrink <= 1, project_update = 0 or max_ls = 0, on
-                          single solves; the H-steps of Graph-SNMPBB and of the naive
-                          variant keep two kernels                                        [1] */
+                          on single solves whose n x r arrays are below 4 MiB (where the
+                          iteration is bound by latency, not memory traffic) and where
+                          phi beta_shrink <= 1, project_update = 0 or max_ls = 0; the
+                          H-steps of Graph-SNMPBB and of the naive variant keep two
+                          kernels                                                         [1] */
   const snmf_batch_tuning* tuning; /* batched solves: launch shape, or NULL for the
                           defaults (read at snmf_batch_create; values out of range: E_ARG)
                           [NULL] */

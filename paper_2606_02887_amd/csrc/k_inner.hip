@@ -42,6 +42,15 @@ __host__ __device__ constexpr int inner_occupancy() {
   return (sizeof(T) == 4 && RP <= 32 && V != 2) ? 3 : 1;
 }
 
+// The fused kernels (k_init with the direction, k_advance) hold more values per thread:
+// bounded to 168 registers they spill at RP <= 32, so they are built for two workgroups
+// per CU.  They run only on arrays below kRecomputeDBytes (latency-bound sizes, where
+// the grid fits in two workgroups per CU).
+template <typename T, int RP>
+__host__ __device__ constexpr int fused_occupancy() {
+  return (sizeof(T) == 4 && RP <= 32) ? 2 : 1;
+}
+
 template <int RP>
 struct TileCfg {
   static constexpr int RS = kThreads / RP;  // rows per pass (VALU layout)
@@ -384,7 +393,7 @@ __device__ __forceinline__ void tile_direction(Smem<T, RP>& sm, const int (&lr)[
 // DIR (fused inner iterations): also the direction of inner iteration 0 (alpha_0 = 1/rho)
 // and its sums (tile_direction) into pout; the first fused kernel runs its line search.
 template <typename T, int RP, int DIR>
-__global__ __launch_bounds__(kThreads, (inner_occupancy<T, RP>())) void k_init(
+__global__ __launch_bounds__(kThreads, (DIR ? fused_occupancy<T, RP>() : inner_occupancy<T, RP>())) void k_init(
     const T* __restrict__ X, const T* __restrict__ P, const T* __restrict__ Bpart, int ksplit,
     int64_t bstride, T* __restrict__ Cout, T* __restrict__ g, const T* __restrict__ LX,
     const T* __restrict__ GT, int64_t n, int r, int is_hstep, KParams kp, State* __restrict__ st,
@@ -1092,7 +1101,7 @@ __global__ __launch_bounds__(kThreads, (inner_occupancy<T, RP, V>())) void k_ste
 // (pin of kernel i = pout of kernel i - 1).  A half-step that stops early (S = 0) marks
 // the remaining iterations stopped; their kernels return at once.
 template <typename T, int RP, int HS>
-__global__ __launch_bounds__(kThreads, (inner_occupancy<T, RP>())) void k_advance(
+__global__ __launch_bounds__(kThreads, (fused_occupancy<T, RP>())) void k_advance(
     T* __restrict__ X, T* __restrict__ g, T* __restrict__ D, const T* __restrict__ C,
     const T* __restrict__ P, const T* __restrict__ GT, const double* __restrict__ Gcur,
     const double* __restrict__ Gprev, int64_t n, int r, int K, int i, KParams kp,
