@@ -37,7 +37,7 @@ def _args():
                          "reach a few dozen iterations later)")
     ap.add_argument("--no-target", action="store_true")
     ap.add_argument("--fuse-inner", type=int, choices=(0, 1), default=1,
-                    help="single solves: one kernel per inner iteration (1) or two (0)")
+                    help="single and NMF solves: one kernel per inner iteration (1) or two (0)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-outer", type=int, default=0,
                     help="outer iterations of the CPU-reference sample (0: pick ~15 s)")
@@ -533,12 +533,14 @@ def _bench_nmf(a, torch, np, S, gen):
             M = S.csr_from_scipy(prob["V"], torch.float32)
         W0 = torch.from_numpy(prob["W0"]).to(dev, torch.float32)
         H0 = torch.from_numpy(prob["Ht0"]).to(dev, torch.float32)
-        S.nmf_solve(M, ncols, W0, H0, S.params(prec=S.F32, lam=0.0, max_outer=a.warmup))
+        S.nmf_solve(M, ncols, W0, H0, S.params(prec=S.F32, lam=0.0, max_outer=a.warmup,
+                                               fuse_inner=a.fuse_inner))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         _, _, info = S.nmf_solve(M, ncols, W0, H0, S.params(prec=S.F32, lam=0.0,
                                                            max_outer=a.steps,
-                                                           check_every=1 << 30))
+                                                           check_every=1 << 30,
+                                                           fuse_inner=a.fuse_inner))
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         cases[name] = {"outer_per_s": a.steps / el, "ms_per_outer": 1e3 * el / a.steps,

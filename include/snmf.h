@@ -139,7 +139,8 @@ typedef struct snmf_params {
                           when phi beta_shrink <= 1 (the same scalars up to rounding).  Used
                           on single solves whose n x r arrays are below 4 MiB (where the
                           iteration is bound by latency, not memory traffic) and where
-                          phi beta_shrink <= 1, project_update = 0 or max_ls = 0; the
+                          phi beta_shrink <= 1, project_update = 0 or max_ls = 0, and on
+                          the half-steps of snmf_nmf_solve under the same conditions; the
                           H-steps of Graph-SNMPBB and of the naive variant keep two
                           kernels                                                         [1] */
   const snmf_batch_tuning* tuning; /* batched solves: launch shape, or NULL for the

@@ -1351,8 +1351,9 @@ template <typename T>
 void launch_advance(T* X, T* g, T* D, const T* C, const T* P, const T* GT, const double* Gcur,
                     const double* Gprev, int64_t n, int r, int K, int i, int is_hstep,
                     const KParams& kp, State* st, const double* pin, double* pout,
-                    const double* partsA, double* partsC, double* trace, hipStream_t s) {
-  const int grid = inner_grid(n, r, (int)sizeof(T));
+                    const double* partsA, double* partsC, double* trace, hipStream_t s,
+                    int grid) {
+  if (grid <= 0) grid = inner_grid(n, r, (int)sizeof(T));
   if (is_hstep) {
     SNMF_DISPATCH_RP(rank_pad(r),
                      hipLaunchKernelGGL((k_advance<T, RP, 1>), dim3(grid), dim3(kThreads), 0, s,
@@ -1417,7 +1418,7 @@ void launch_step2(T* X, T* g, T* Z, T* D, const T* LS, const T* C, const T* P, T
   template void launch_advance<T>(T*, T*, T*, const T*, const T*, const T*, const double*,      \
                                   const double*, int64_t, int, int, int, int, const KParams&,   \
                                   State*, const double*, double*, const double*, double*,       \
-                                  double*, hipStream_t);                                        \
+                                  double*, hipStream_t, int);                                   \
   template void launch_step1<T>(const T*, const T*, T*, T*, const T*, const T*, const double*, \
                                 const double*, int64_t, int, int, int, int, const KParams&,     \
                                 State*, const double*, double*, const double*, double*,         \

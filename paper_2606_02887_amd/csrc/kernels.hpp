@@ -141,7 +141,8 @@ template <typename T>
 void launch_advance(T* X, T* g, T* D, const T* C, const T* P, const T* GT, const double* Gcur,
                     const double* Gprev, int64_t n, int r, int K, int i, int is_hstep,
                     const KParams& kp, State* st, const double* pin, double* pout,
-                    const double* partsA, double* partsC, double* trace, hipStream_t s);
+                    const double* partsA, double* partsC, double* trace, hipStream_t s,
+                    int grid = 0);
 template <typename T>
 void launch_step1(const T* X, const T* g, T* Z, T* D, const T* LdZ, const T* GT,
                   const double* Gcur, const double* Gprev, int64_t n, int r, int k, int phase,

@@ -37,7 +37,8 @@ struct NmfPlan {
   RectSplit spW, spH;
   double* G64[2] = {nullptr, nullptr};
   double *part = nullptr, *gram_part = nullptr, *dots = nullptr;
-  double *partsA = nullptr, *partsB = nullptr, *partsC = nullptr, *trace = nullptr;
+  double *partsA = nullptr, *partsB = nullptr, *partsC = nullptr, *partsD = nullptr;
+  double* trace = nullptr;
   State* st = nullptr;
   unsigned *counters = nullptr, *flags = nullptr, *cnt = nullptr;
   unsigned long long* cursor = nullptr;
@@ -106,11 +107,24 @@ void half_step(NmfPlan& pl, T* X, int64_t nX, const T* P, int64_t nP, int is_hst
   // one grid for both half-steps: the first inner kernel of a W-step reduces the partial
   // sums of the previous H-step's last kernel together with its own init's
   const int grid = pl.grid;
-  launch_init<T>(X, Pz, B, ksplit, nX * r, (T*)pl.C, (T*)pl.g, nullptr, GT, nX, r, is_hstep,
-                 pl.kp, pl.st, pl.partsA, s, BMap{}, grid);
   T* Z = (T*)pl.Z;
   T* D = (T*)pl.D;
   T* g = (T*)pl.g;
+  // one kernel per inner iteration where the arrays are small (fused_inner_ok), init then
+  // also forming direction 0; partial sums alternate between partsB and partsD
+  const bool fused = run_inner && fused_inner_ok(pl.p, nX, r, sizeof(T));
+  launch_init<T>(X, Pz, B, ksplit, nX * r, (T*)pl.C, g, nullptr, GT, nX, r, is_hstep, pl.kp,
+                 pl.st, pl.partsA, s, BMap{}, grid, nullptr, nullptr, fused ? D : nullptr,
+                 fused ? pl.partsB : nullptr);
+  if (fused) {
+    const int K = pl.p.inner_iters;
+    for (int i = 0; i < K; ++i)
+      launch_advance<T>(X, g, D, (const T*)pl.C, Pz, GT, pl.G64[0], pl.G64[1], nX, r, K, i,
+                        is_hstep, pl.kp, pl.st, (i & 1) ? pl.partsD : pl.partsB,
+                        (i & 1) ? pl.partsB : pl.partsD, pl.partsA, pl.partsC, pl.trace, s,
+                        grid);
+    return;
+  }
   const int rd = (int64_t)nX * r * (int64_t)sizeof(T) >= kRecomputeDBytes;
   if (!run_inner) {  // the closing entry: completes the monitor record of the last outer
     launch_step1<T>(X, g, Z, D, nullptr, GT, pl.G64[0], pl.G64[1], nX, r, 0, 0, 0, pl.kp, pl.st,
@@ -258,6 +272,7 @@ snmf_status nmf_solve(const snmf_matrix* V, int64_t ncols, int32_t r, const void
   add((void**)&pl.partsA, (size_t)kInnerGrid * kNumPart * 8);
   add((void**)&pl.partsB, (size_t)kInnerGrid * kNumPart * 8);
   add((void**)&pl.partsC, (size_t)kInnerGrid * kNumPart * 8);
+  add((void**)&pl.partsD, (size_t)kInnerGrid * kNumPart * 8);
   add((void**)&pl.trace, (size_t)p->max_outer * kTraceFields * 8);
   add((void**)&pl.st, sizeof(State));
   add((void**)&pl.counters, C_COUNT * sizeof(unsigned));

@@ -277,18 +277,12 @@ int ksplit_of(const snmf_plan* pl) {
 // Start of a half-step up to and including init: G, rho (in or just before the A-pass,
 // on the same stream: a second stream would cost more in cross-queue waits than rho
 // takes), the A-pass and the gradient.  The first reader of rho is the first inner kernel.
-// Inner iterations of this half-step run as fused kernels, one per inner iteration: every
-// half-step without the Laplacian term, except the H-step of the naive variant, on n x r
-// arrays below kRecomputeDBytes (latency-bound; above it the two kernels stream fewer
-// bytes, step 2 forming D again), provided a backtracked update is never clipped by the
-// projection (phi beta_shrink <= 1, or no projection, or no backtracking at all), which
-// the fused kernels' BB step after a backtrack relies on.
+// Inner iterations of this half-step run as fused kernels, one per inner iteration
+// (fused_inner_ok), on every half-step without the Laplacian term except the H-step of
+// the naive variant.
 bool fused_half(const snmf_plan* pl, int is_hstep) {
-  const snmf_params& p = pl->p;
-  const bool unclipped = !p.project_update || p.max_ls == 0 || p.phi * p.beta_shrink <= 1.0;
-  const bool small = (int64_t)pl->n * pl->r * (int64_t)pl->esz < kRecomputeDBytes;
-  return p.fuse_inner && unclipped && small && !(pl->lap && is_hstep) &&
-         !(p.naive && is_hstep);
+  return fused_inner_ok(pl->p, pl->n, pl->r, pl->esz) && !(pl->lap && is_hstep) &&
+         !(pl->p.naive && is_hstep);
 }
 
 // dir: init also forms the fused path's direction 0 (fused_half).

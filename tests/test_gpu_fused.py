@@ -156,3 +156,27 @@ def test_fused_graph_and_naive_same_bits(S):
         _same(a, b)
         a, b = _both(S, Ag, _t(W0, dt), lam=0.0, naive=1, prec=prec, max_outer=10)
         _same(a, b)
+
+
+@pytest.mark.parametrize("prec,kind", [("f32", "dense"), ("f64", "dense"), ("f32", "csr")])
+def test_fused_nmf_same_bits(S, prec, kind):
+    """Rectangular NMF (eq. (1.1)) runs the same inner kernels: its W-step and H-step take
+    the fused form too (arrays below 4 MiB) and give the two-kernel form's bits."""
+    dt = torch.float64 if prec == "f64" else torch.float32
+    p = S.F64 if prec == "f64" else S.F32
+    if kind == "dense":
+        m, n = 700, 450
+        prob = gen.planted_rect(m, n, 12, 5)
+        M = S.dense(_t(prob["V"], dt))
+    else:
+        m, n = 3000, 1700
+        prob = gen.random_rect_csr(m, n, 0.02, 16, 6)
+        M = S.csr_from_scipy(prob["V"], dt)
+    W0, H0 = _t(prob["W0"], dt), _t(prob["Ht0"], dt)
+    out = []
+    for fuse in (1, 0):
+        W, Ht, info = S.nmf_solve(M, n, W0, H0, S.params(prec=p, lam=0.0, max_outer=10, max_ls=0,
+                                                         fuse_inner=fuse))
+        torch.cuda.synchronize()
+        out.append((W.cpu().numpy(), Ht.cpu().numpy(), info))
+    _same(out[0], out[1])
