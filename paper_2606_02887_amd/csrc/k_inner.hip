@@ -321,7 +321,9 @@ __device__ __forceinline__ void monitor_sums(double* m, T x, T g, T c, T p) {
 //   ls  = {<grad f(Z),D>, <DG,D>, ||D||^2, f(Z)-f(X)}: the line search;
 //   sp  = {||S||^2, <SG,S>, <g,S>} of the update of the trial beta = 1,
 //         X+ = max(0, Z + phi D), formed with step 2's arithmetic: the BB step when the
-//         line search accepts that trial, the same bits as step 2 would give;
+//         line search accepts that trial, the same bits as step 2 would give; that update
+//         and its gradient g+ = g + S G + lam S are stored (Xt, gt), so the next kernel
+//         has them without forming them again;
 //   xp  = {<dZ,dZ>, <dZ,D>, <dZ,dZ G>, <dZ,DG>, <g,dZ>, <g,D>} with dZ = Z - X: the BB
 //         step after a backtrack.  A trial beta <= beta_shrink has t = phi beta <= 1
 //         (the fused path requires phi beta_shrink <= 1), and Z + t D is then a convex
@@ -335,6 +337,7 @@ __device__ __forceinline__ void tile_direction(Smem<T, RP>& sm, const int (&lr)[
                                                int64_t row0, int64_t n, int r, const T (&x)[8],
                                                const T (&gv)[8], T rinv, T alpha, T lam,
                                                T step1, int project, T* __restrict__ Dt,
+                                               T* __restrict__ Xt, T* __restrict__ gt,
                                                double (&ls)[4], double (&sp)[3],
                                                double (&xp)[6]) {
   typedef Lay<T, RP> L;
@@ -384,21 +387,28 @@ __device__ __forceinline__ void tile_direction(Smem<T, RP>& sm, const int (&lr)[
   T sg[8];
   tile_gemm<T, RP>(sm.a, sm.G, sg);
 #pragma unroll
-  for (int p = 0; p < 8; ++p)
-    if (row0 + lr[p] < n && cl[p] < r) update_sums(sp, xn[p] - x[p], sg[p], gv[p]);
+  for (int p = 0; p < 8; ++p) {
+    if (row0 + lr[p] < n && cl[p] < r) {
+      const T s1 = xn[p] - x[p];
+      update_sums(sp, s1, sg[p], gv[p]);
+      sto(Xt, bo[p], xn[p]);
+      sto(gt, bo[p], next_grad(gv[p], sg[p], lam, s1));
+    }
+  }
 }
 
 // ----------------------------------------------------------------------------- init
 // C = (sum of the A-pass partials) + lam P;  g = X G + lam X - C [+ gam LX].
-// DIR (fused inner iterations): also the direction of inner iteration 0 (alpha_0 = 1/rho)
-// and its sums (tile_direction) into pout; the first fused kernel runs its line search.
+// DIR (fused inner iterations): also the direction of inner iteration 0 (alpha_0 = 1/rho),
+// its sums (tile_direction) into pout and its beta = 1 trial update into (Xs, gs); the
+// first fused kernel runs its line search.
 template <typename T, int RP, int DIR>
 __global__ __launch_bounds__(kThreads, (DIR ? fused_occupancy<T, RP>() : inner_occupancy<T, RP>())) void k_init(
     const T* __restrict__ X, const T* __restrict__ P, const T* __restrict__ Bpart, int ksplit,
     int64_t bstride, T* __restrict__ Cout, T* __restrict__ g, const T* __restrict__ LX,
     const T* __restrict__ GT, int64_t n, int r, int is_hstep, KParams kp, State* __restrict__ st,
     double* __restrict__ partsA, BMap bm, T* __restrict__ Zn, T* __restrict__ Dn,
-    T* __restrict__ Dd, double* __restrict__ pout) {
+    T* __restrict__ Dd, double* __restrict__ pout, T* __restrict__ Xs, T* __restrict__ gs) {
   const Loc lc = locate(bm, n, st, nullptr, kp.lam);
   st = lc.st;
   if (st->done) return;
@@ -511,7 +521,8 @@ __global__ __launch_bounds__(kThreads, (DIR ? fused_occupancy<T, RP>() : inner_o
     if constexpr (DIR != 0) {
       __syncthreads();  // every wave is done with the product on sm.a
       tile_direction<T, RP>(sm, lr, cl, bo, row0, n, r, x, gq, rinv, rinv, lam, step1,
-                            kp.project, tile_ptr(Dd, tb), ls, sp, xp);
+                            kp.project, tile_ptr(Dd, tb), tile_ptr(Xs, tb), tile_ptr(gs, tb), ls,
+                            sp, xp);
     }
   }
   if constexpr (DIR != 0) {
@@ -1094,24 +1105,36 @@ __global__ __launch_bounds__(kThreads, (inner_occupancy<T, RP, V>())) void k_ste
 // the sums from which the next kernel gets the update's without another reduction
 // (tile_direction): for the trial beta = 1 those of the update itself, formed as step 2
 // forms them (the same bits), and for any backtracked trial the polynomial coefficients
-// of S = dZ + t D.  Kernel i of a half-step thus runs the line search of iteration i,
-// derives e_{i+1} and alpha_{i+1}, applies the update and forms direction i + 1 in one
-// pass over its tiles; kernel K - 1 applies the last update and, in an H-step, forms the
-// monitor sums (into partsC, as step 2 does).  Partial sums alternate between two arrays
+// of S = dZ + t D.  It also stores that trial update and its gradient.  Kernel i of a
+// half-step thus runs the line search of iteration i, derives e_{i+1} and alpha_{i+1},
+// takes the stored update when the line search accepted beta = 1 (else it forms the
+// update from X_i, g_i, D_i), and forms direction i + 1 in one pass over its tiles;
+// kernel K - 1 applies the last update and, in an H-step, forms the monitor sums (into
+// partsC, as step 2 does).
+// Two buffer pairs (X0, g0) = the half-step's X and g, (X1, g1) scratch, alternate:
+// before kernel i, pair i % 2 holds the iterate X_i and its gradient, pair (i + 1) % 2 the
+// beta = 1 trial of X_{i+1}.  Kernel i leaves X_{i+1} in pair (i + 1) % 2 (the trial when
+// accepted, else overwritten) and the next trial in pair i % 2; the closing kernel copies
+// the final X into X0 when it sits in pair 1.  Partial sums alternate between two arrays
 // (pin of kernel i = pout of kernel i - 1).  A half-step that stops early (S = 0) marks
 // the remaining iterations stopped; their kernels return at once.
 template <typename T, int RP, int HS>
 __global__ __launch_bounds__(kThreads, (fused_occupancy<T, RP>())) void k_advance(
-    T* __restrict__ X, T* __restrict__ g, T* __restrict__ D, const T* __restrict__ C,
-    const T* __restrict__ P, const T* __restrict__ GT, const double* __restrict__ Gcur,
-    const double* __restrict__ Gprev, int64_t n, int r, int K, int i, KParams kp,
-    State* __restrict__ st, const double* __restrict__ pin, double* __restrict__ pout,
-    const double* __restrict__ partsA, double* __restrict__ partsC, double* __restrict__ trace) {
+    T* __restrict__ X0, T* __restrict__ g0, T* __restrict__ X1, T* __restrict__ g1,
+    T* __restrict__ D, const T* __restrict__ C, const T* __restrict__ P,
+    const T* __restrict__ GT, const double* __restrict__ Gcur, const double* __restrict__ Gprev,
+    int64_t n, int r, int K, int i, KParams kp, State* __restrict__ st,
+    const double* __restrict__ pin, double* __restrict__ pout, const double* __restrict__ partsA,
+    double* __restrict__ partsC, double* __restrict__ trace) {
   typedef Lay<T, RP> L;
   constexpr int TM = L::TM;
   __shared__ Smem<T, RP> sm;
   const int nb = (int)gridDim.x, bid = (int)blockIdx.x;
   const bool w0 = bid == 0 && threadIdx.x == 0;
+  T* const Xc = (i & 1) ? X1 : X0;   // X_i, g_i (then the next trial)
+  T* const gc = (i & 1) ? g1 : g0;
+  T* const Xn = (i & 1) ? X0 : X1;   // the trial of X_{i+1} (then X_{i+1})
+  T* const gn_ = (i & 1) ? g0 : g1;
   int lr[8], cl[8];
   uint32_t bo[8];
 #pragma unroll
@@ -1120,7 +1143,8 @@ __global__ __launch_bounds__(kThreads, (fused_occupancy<T, RP>())) void k_advanc
     bo[p] = (uint32_t)((lr[p] * r + cl[p]) * (int)sizeof(T));
   }
   const int64_t ntiles = (n + TM - 1) / TM;
-  // loads first: State scalars, the partial sums (and the k = 0 entry's), G, the first tile
+  // loads first: State scalars, the partial sums (and the k = 0 entry's), G, the trial
+  // update of the first tile
   const int done = st->done;
   const int stopped = i > 0 ? st->stop[i] : 0;
   const double rho = st->rho, e_i = i > 0 ? st->e[i] : 0.0;
@@ -1130,18 +1154,17 @@ __global__ __launch_bounds__(kThreads, (fused_occupancy<T, RP>())) void k_advanc
   entry_loads(0, HS, partsA, partsC, nb, pe);
   T gv[TileCfg<RP>::NG];
   load_G<T, RP>(GT, r, gv);
-  T x[8], go[8], dd[8];
-  auto load_tile = [&](int64_t row0) {
+  T xt[8], gt[8];
+  auto load_trial = [&](int64_t row0) {
     const int64_t tb = row0 * r;
 #pragma unroll
     for (int p = 0; p < 8; ++p) {
       const bool ok = row0 + lr[p] < n && cl[p] < r;
-      x[p] = ok ? ldo(tile_ptr(X, tb), bo[p]) : T(0);
-      go[p] = ok ? ldo(tile_ptr(g, tb), bo[p]) : T(0);
-      dd[p] = ok ? ldo(tile_ptr(D, tb), bo[p]) : T(0);
+      xt[p] = ok ? ldo(tile_ptr(Xn, tb), bo[p]) : T(0);
+      gt[p] = ok ? ldo(tile_ptr(gn_, tb), bo[p]) : T(0);
     }
   };
-  if (bid < ntiles) load_tile((int64_t)bid * TM);
+  if (bid < ntiles) load_trial((int64_t)bid * TM);
   if (done || stopped) return;
   if (i == 0) {  // inner iteration 0 opens here: monitor record, <C, P>, rho check
     double a0;
@@ -1160,12 +1183,13 @@ __global__ __launch_bounds__(kThreads, (fused_occupancy<T, RP>())) void k_advanc
     st->ls_exhausted += exh;
     st->inner_total += 1;
   }
+  const bool trial = beta == 1.0;  // the stored update is X_{i+1}
   // then the next BB step from the sums of this update
   bool dir = false, closing = i + 1 >= K;
   double alpha_d = 0.0;
   if (!closing) {
     double s4[4];
-    if (beta == 1.0) {
+    if (trial) {
       s4[0] = pa[4];
       s4[1] = pa[5];
       s4[2] = pa[6];
@@ -1185,16 +1209,29 @@ __global__ __launch_bounds__(kThreads, (fused_occupancy<T, RP>())) void k_advanc
   const T rinv = (T)(1.0 / rho);
   const T lam = (T)kp.lam;
   const T step = (T)(kp.phi * beta), step1 = (T)(kp.phi * 1.0), alpha = (T)alpha_d;
-  double ex[3] = {0.0, 0.0, 0.0}, ls[4] = {0.0, 0.0, 0.0, 0.0}, sp[3] = {0.0, 0.0, 0.0};
+  double ls[4] = {0.0, 0.0, 0.0, 0.0}, sp[3] = {0.0, 0.0, 0.0};
   double xp[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, mon[4] = {0.0, 0.0, 0.0, 0.0};
-  // step 2's update of one tile (X+ and g+ in xn, gn; X, g stored)
-  auto update_tile = [&](int64_t row0, T (&xn)[8], T (&gn)[8]) {
+  // X_{i+1} and its gradient of one tile: the trial, or step 2's update formed from X_i,
+  // g_i and D_i (stored over the trial)
+  auto next_tile = [&](int64_t row0, T (&xn)[8], T (&gn)[8]) {
     const int64_t tb = row0 * r;
+    if (trial) {
+#pragma unroll
+      for (int p = 0; p < 8; ++p) {
+        xn[p] = xt[p];
+        gn[p] = gt[p];
+      }
+      return;
+    }
+    T x[8], go[8];
 #pragma unroll
     for (int p = 0; p < 8; ++p) {
       const bool ok = row0 + lr[p] < n && cl[p] < r;
+      x[p] = ok ? ldo(tile_ptr(Xc, tb), bo[p]) : T(0);
+      go[p] = ok ? ldo(tile_ptr(gc, tb), bo[p]) : T(0);
+      const T dd = ok ? ldo(tile_ptr(D, tb), bo[p]) : T(0);
       const T zz = first_proj(x[p], go[p], rinv);
-      xn[p] = ok ? next_point(zz, dd[p], step, kp.project) : T(0);
+      xn[p] = ok ? next_point(zz, dd, step, kp.project) : T(0);
       sm.b[lr[p] * L::YP + cl[p]] = ok ? xn[p] - x[p] : T(0);
     }
     __syncthreads();
@@ -1204,38 +1241,39 @@ __global__ __launch_bounds__(kThreads, (fused_occupancy<T, RP>())) void k_advanc
     for (int p = 0; p < 8; ++p) {
       gn[p] = T(0);
       if (row0 + lr[p] < n && cl[p] < r) {
-        const T s = xn[p] - x[p];
-        gn[p] = next_grad(go[p], sg[p], lam, s);
-        sto(tile_ptr(X, tb), bo[p], xn[p]);
-        sto(tile_ptr(g, tb), bo[p], gn[p]);
-        update_sums(ex, s, sg[p], go[p]);
+        gn[p] = next_grad(go[p], sg[p], lam, xn[p] - x[p]);
+        sto(tile_ptr(Xn, tb), bo[p], xn[p]);
+        sto(tile_ptr(gn_, tb), bo[p], gn[p]);
       }
     }
   };
   if (closing) {  // the last update, then the H-step's monitor sums of the final X
     for (int64_t t = bid; t < ntiles; t += nb) {
       const int64_t row0 = t * TM, tb = row0 * r;
-      if (t != bid) load_tile(row0);
+      if (t != bid && trial) load_trial(row0);
       T xn[8], gn[8];
       __syncthreads();
-      update_tile(row0, xn, gn);
-      if (HS) {
+      next_tile(row0, xn, gn);
 #pragma unroll
-        for (int p = 0; p < 8; ++p)
-          if (row0 + lr[p] < n && cl[p] < r)
+      for (int p = 0; p < 8; ++p) {
+        if (row0 + lr[p] < n && cl[p] < r) {
+          if (Xn != X0) sto(tile_ptr(X0, tb), bo[p], xn[p]);
+          if (HS)
             monitor_sums(mon, xn[p], gn[p], ldo(tile_ptr(C, tb), bo[p]), ldo(tile_ptr(P, tb), bo[p]));
+        }
       }
     }
-  } else {  // the update and direction i + 1
+  } else {  // X_{i+1}, then direction i + 1 and the next trial (into pair i % 2)
     for (int64_t t = bid; t < ntiles; t += nb) {
       const int64_t row0 = t * TM, tb = row0 * r;
-      if (t != bid) load_tile(row0);
+      if (t != bid && trial) load_trial(row0);
       T xn[8], gn[8];
       __syncthreads();
-      update_tile(row0, xn, gn);
+      next_tile(row0, xn, gn);
       // sm.a was last read before this tile's first barrier
       tile_direction<T, RP>(sm, lr, cl, bo, row0, n, r, xn, gn, rinv, alpha, lam, step1,
-                            kp.project, tile_ptr(D, tb), ls, sp, xp);
+                            kp.project, tile_ptr(D, tb), tile_ptr(Xc, tb), tile_ptr(gc, tb), ls,
+                            sp, xp);
     }
   }
   if (dir) {
@@ -1244,8 +1282,8 @@ __global__ __launch_bounds__(kThreads, (fused_occupancy<T, RP>())) void k_advanc
     double* po = pout + (size_t)bid * kNumPart;
     block_sum_emit<kFusedParts>(o, sm.red, [&](int j, double a) { po[j] = a; });
   } else {
-    if (HS) {
-      const double v[9] = {ex[0], ex[1], ex[2], mon[0], mon[1], mon[2], mon[3], 0.0, 0.0};
+    if (HS) {  // slots 0-2 (the last update's sums in step 2) are not read after a half-step
+      const double v[9] = {0.0, 0.0, 0.0, mon[0], mon[1], mon[2], mon[3], 0.0, 0.0};
       double* pc = partsC + (size_t)bid * kNumPart;
       block_sum_emit<9>(v, sm.red, [&](int j, double a) { pc[j] = a; });
     }
@@ -1332,38 +1370,38 @@ template <typename T>
 void launch_init(const T* X, const T* P, const T* Bpart, int ksplit, int64_t bstride, T* C, T* g,
                  const T* LX, const T* GT, int64_t n, int r, int is_hstep, const KParams& kp,
                  State* st, double* partsA, hipStream_t s, const BMap& bm, int grid, T* Zn,
-                 T* Dn, T* Dd, double* pout) {
+                 T* Dn, T* Dd, double* pout, T* Xs, T* gs) {
   if (grid <= 0) grid = inner_grid(n, r, (int)sizeof(T));
   if (Dd) {
     SNMF_DISPATCH_RP(rank_pad(r),
                      hipLaunchKernelGGL((k_init<T, RP, 1>), dim3(grid), dim3(kThreads), 0, s, X,
                                         P, Bpart, ksplit, bstride, C, g, LX, GT, n, r, is_hstep,
-                                        kp, st, partsA, bm, Zn, Dn, Dd, pout))
+                                        kp, st, partsA, bm, Zn, Dn, Dd, pout, Xs, gs))
   } else {
     SNMF_DISPATCH_RP(rank_pad(r),
                      hipLaunchKernelGGL((k_init<T, RP, 0>), dim3(grid), dim3(kThreads), 0, s, X,
                                         P, Bpart, ksplit, bstride, C, g, LX, GT, n, r, is_hstep,
-                                        kp, st, partsA, bm, Zn, Dn, Dd, pout))
+                                        kp, st, partsA, bm, Zn, Dn, Dd, pout, Xs, gs))
   }
 }
 
 template <typename T>
-void launch_advance(T* X, T* g, T* D, const T* C, const T* P, const T* GT, const double* Gcur,
-                    const double* Gprev, int64_t n, int r, int K, int i, int is_hstep,
-                    const KParams& kp, State* st, const double* pin, double* pout,
+void launch_advance(T* X, T* g, T* Xs, T* gs, T* D, const T* C, const T* P, const T* GT,
+                    const double* Gcur, const double* Gprev, int64_t n, int r, int K, int i,
+                    int is_hstep, const KParams& kp, State* st, const double* pin, double* pout,
                     const double* partsA, double* partsC, double* trace, hipStream_t s,
                     int grid) {
   if (grid <= 0) grid = inner_grid(n, r, (int)sizeof(T));
   if (is_hstep) {
     SNMF_DISPATCH_RP(rank_pad(r),
                      hipLaunchKernelGGL((k_advance<T, RP, 1>), dim3(grid), dim3(kThreads), 0, s,
-                                        X, g, D, C, P, GT, Gcur, Gprev, n, r, K, i, kp, st, pin,
-                                        pout, partsA, partsC, trace))
+                                        X, g, Xs, gs, D, C, P, GT, Gcur, Gprev, n, r, K, i, kp,
+                                        st, pin, pout, partsA, partsC, trace))
   } else {
     SNMF_DISPATCH_RP(rank_pad(r),
                      hipLaunchKernelGGL((k_advance<T, RP, 0>), dim3(grid), dim3(kThreads), 0, s,
-                                        X, g, D, C, P, GT, Gcur, Gprev, n, r, K, i, kp, st, pin,
-                                        pout, partsA, partsC, trace))
+                                        X, g, Xs, gs, D, C, P, GT, Gcur, Gprev, n, r, K, i, kp,
+                                        st, pin, pout, partsA, partsC, trace))
   }
 }
 
@@ -1414,11 +1452,11 @@ void launch_step2(T* X, T* g, T* Z, T* D, const T* LS, const T* C, const T* P, T
 #define SNMF_INST(T)                                                                            \
   template void launch_init<T>(const T*, const T*, const T*, int, int64_t, T*, T*, const T*,   \
                                const T*, int64_t, int, int, const KParams&, State*, double*,   \
-                               hipStream_t, const BMap&, int, T*, T*, T*, double*);             \
-  template void launch_advance<T>(T*, T*, T*, const T*, const T*, const T*, const double*,      \
-                                  const double*, int64_t, int, int, int, int, const KParams&,   \
-                                  State*, const double*, double*, const double*, double*,       \
-                                  double*, hipStream_t, int);                                   \
+                               hipStream_t, const BMap&, int, T*, T*, T*, double*, T*, T*);     \
+  template void launch_advance<T>(T*, T*, T*, T*, T*, const T*, const T*, const T*,          \
+                                  const double*, const double*, int64_t, int, int, int, int,   \
+                                  const KParams&, State*, const double*, double*,              \
+                                  const double*, double*, double*, hipStream_t, int);          \
   template void launch_step1<T>(const T*, const T*, T*, T*, const T*, const T*, const double*, \
                                 const double*, int64_t, int, int, int, int, const KParams&,     \
                                 State*, const double*, double*, const double*, double*,         \

@@ -133,14 +133,16 @@ void launch_init(const T* X, const T* P, const T* Bpart, int ksplit, int64_t bst
                  const T* LX, const T* GT, int64_t n, int r, int is_hstep, const KParams& kp,
                  State* st, double* partsA, hipStream_t s, const BMap& bm = BMap{}, int grid = 0,
                  T* Zn = nullptr, T* Dn = nullptr,  // Laplacian H-step: Z, Z - X of iteration 0
-                 T* Dd = nullptr, double* pout = nullptr);  // fused: direction 0 into Dd
+                 T* Dd = nullptr, double* pout = nullptr,   // fused: direction 0 into Dd,
+                 T* Xs = nullptr, T* gs = nullptr);         // its beta = 1 trial into Xs, gs
 // Fused inner kernel i (0 <= i < K: line search and update of inner iteration i, direction
-// i + 1) of a half-step without the Laplacian term (single solves); pin / pout alternate
-// between two partial-sum arrays.
+// i + 1) of a half-step without the Laplacian term; (X, g) and the scratch pair (Xs, gs)
+// alternate as iterate and trial update; pin / pout alternate between two partial-sum
+// arrays.
 template <typename T>
-void launch_advance(T* X, T* g, T* D, const T* C, const T* P, const T* GT, const double* Gcur,
-                    const double* Gprev, int64_t n, int r, int K, int i, int is_hstep,
-                    const KParams& kp, State* st, const double* pin, double* pout,
+void launch_advance(T* X, T* g, T* Xs, T* gs, T* D, const T* C, const T* P, const T* GT,
+                    const double* Gcur, const double* Gprev, int64_t n, int r, int K, int i,
+                    int is_hstep, const KParams& kp, State* st, const double* pin, double* pout,
                     const double* partsA, double* partsC, double* trace, hipStream_t s,
                     int grid = 0);
 template <typename T>

@@ -32,7 +32,7 @@ struct NmfPlan {
   hipStream_t s = nullptr;
   void* pool = nullptr;
   void *Wb = nullptr, *Hb = nullptr, *C = nullptr, *g = nullptr, *Z = nullptr, *D = nullptr,
-       *B = nullptr, *Pz = nullptr, *GT[2] = {nullptr, nullptr};
+       *B = nullptr, *Pz = nullptr, *GT[2] = {nullptr, nullptr}, *gs = nullptr;
   void *VT = nullptr, *Bpart = nullptr;  // dense FP32: V^T and the split-K panels
   RectSplit spW, spH;
   double* G64[2] = {nullptr, nullptr};
@@ -115,11 +115,12 @@ void half_step(NmfPlan& pl, T* X, int64_t nX, const T* P, int64_t nP, int is_hst
   const bool fused = run_inner && fused_inner_ok(pl.p, nX, r, sizeof(T));
   launch_init<T>(X, Pz, B, ksplit, nX * r, (T*)pl.C, g, nullptr, GT, nX, r, is_hstep, pl.kp,
                  pl.st, pl.partsA, s, BMap{}, grid, nullptr, nullptr, fused ? D : nullptr,
-                 fused ? pl.partsB : nullptr);
+                 fused ? pl.partsB : nullptr, fused ? Z : nullptr, fused ? (T*)pl.gs : nullptr);
   if (fused) {
     const int K = pl.p.inner_iters;
     for (int i = 0; i < K; ++i)
-      launch_advance<T>(X, g, D, (const T*)pl.C, Pz, GT, pl.G64[0], pl.G64[1], nX, r, K, i,
+      launch_advance<T>(X, g, Z, (T*)pl.gs, D, (const T*)pl.C, Pz, GT, pl.G64[0], pl.G64[1], nX,
+                        r, K, i,
                         is_hstep, pl.kp, pl.st, (i & 1) ? pl.partsD : pl.partsB,
                         (i & 1) ? pl.partsB : pl.partsD, pl.partsA, pl.partsC, pl.trace, s,
                         grid);
@@ -259,6 +260,7 @@ snmf_status nmf_solve(const snmf_matrix* V, int64_t ncols, int32_t r, const void
   add(&pl.C, xr);
   add(&pl.g, xr);
   add(&pl.Z, xr);
+  add(&pl.gs, xr);  // the fused inner kernels' trial gradient (the trial update goes to Z)
   add(&pl.D, xr);
   add(&pl.B, xr);
   add(&pl.Pz, xr);

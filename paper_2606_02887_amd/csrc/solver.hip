@@ -47,6 +47,7 @@ struct snmf_plan {
   // device memory (one allocation, carved)
   void* pool = nullptr;
   void *Wb = nullptr, *Hb = nullptr, *C = nullptr, *g = nullptr, *Z = nullptr, *D = nullptr;
+  void* gs = nullptr;
   void *Bpart = nullptr, *LT = nullptr, *LX = nullptr, *GT[2] = {nullptr, nullptr}, *TT = nullptr;
   double* G64[2] = {nullptr, nullptr};
   double *part = nullptr, *gram_part = nullptr, *lai_part = nullptr, *dots = nullptr;
@@ -310,7 +311,8 @@ snmf_status half_start(snmf_plan* pl, T* X, const T* P, int is_hstep, bool with_
                  lap ? (const T*)pl->LX : nullptr, (const T*)pl->GT[gi], n, r, is_hstep, pl->kp,
                  pl->st, pl->partsA, s, BMap{}, 0, lap ? (T*)pl->Z : nullptr,
                  lap ? (T*)pl->D : nullptr, dir ? (T*)pl->D : nullptr,
-                 dir ? pl->partsB : nullptr);
+                 dir ? pl->partsB : nullptr, dir ? (T*)pl->Z : nullptr,
+                 dir ? (T*)pl->gs : nullptr);
   HIP_TRY(hipGetLastError());
   return SNMF_OK;
 }
@@ -364,15 +366,16 @@ snmf_status inner_step(snmf_plan* pl, T* X, const T* P, int is_hstep, int k, hip
 }
 
 // The inner iterations of a half-step: with `fused` (its init ran with dir set) K fused
-// kernels, partial sums alternating between partsB and partsD (which the fused path does
-// not otherwise use); else K pairs of step 1 and step 2.
+// kernels, the iterate and the trial update alternating between (X, g) and (Z, gs) and
+// the partial sums between partsB and partsD (which the fused path does not otherwise
+// use); else K pairs of step 1 and step 2.
 template <typename T>
 snmf_status inner_steps(snmf_plan* pl, T* X, const T* P, int is_hstep, hipStream_t s,
                         bool fused) {
   const int K = pl->p.inner_iters;
   if (fused) {
     for (int i = 0; i < K; ++i) {
-      launch_advance<T>(X, (T*)pl->g, (T*)pl->D, (const T*)pl->C, P,
+      launch_advance<T>(X, (T*)pl->g, (T*)pl->Z, (T*)pl->gs, (T*)pl->D, (const T*)pl->C, P,
                         (const T*)pl->GT[is_hstep ? 1 : 0], pl->G64[0], pl->G64[1], pl->n, pl->r,
                         K, i, is_hstep, pl->kp, pl->st, (i & 1) ? pl->partsD : pl->partsB,
                         (i & 1) ? pl->partsB : pl->partsD, pl->partsA, pl->partsC, pl->trace, s);
@@ -497,6 +500,8 @@ snmf_status plan_init(snmf_plan* pl, const snmf_matrix* A, int32_t r, const snmf
   add(&pl->C, nr);
   add(&pl->g, nr);
   add(&pl->Z, nr);
+  // the fused inner kernels' trial gradient (the trial update itself goes to Z)
+  if (fused_inner_ok(*p, n, r, pl->esz)) add(&pl->gs, nr);
   add(&pl->D, nr);
   add(&pl->Bpart, nr * ksplit);
   if (lap) {
