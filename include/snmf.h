@@ -134,13 +134,11 @@ typedef struct snmf_params {
   int32_t fuse_inner;  /* 1: one kernel per inner iteration, 0: two (step 1 and step 2).
                           The fused kernel forms the next BB step from sums its predecessor
                           prepared: for the first backtracking trial (beta = 1) the update's
-                          own sums, which give the same bits as 0; after a backtrack the
-                          sums of S = dZ + phi beta D, which the projection leaves unclipped
-                          when phi beta_shrink <= 1 (the same scalars up to rounding).  Used
-                          on single solves whose n x r arrays are below 4 MiB (where the
-                          iteration is bound by latency, not memory traffic) and where
-                          phi beta_shrink <= 1, project_update = 0 or max_ls = 0, and on
-                          the half-steps of snmf_nmf_solve under the same conditions; the
+                          own sums (that update is kept, not formed again), which give the
+                          same bits as 0; after a backtrack the sums of S = dZ + phi beta D,
+                          which the projection leaves unclipped when phi beta_shrink <= 1
+                          (the same scalars up to rounding).  Used on single and NMF solves
+                          where phi beta_shrink <= 1, project_update = 0 or max_ls = 0; the
                           H-steps of Graph-SNMPBB and of the naive variant keep two
                           kernels                                                         [1] */
   const snmf_batch_tuning* tuning; /* batched solves: launch shape, or NULL for the

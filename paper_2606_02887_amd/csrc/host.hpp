@@ -35,14 +35,15 @@ inline snmf_status fail(snmf_status s, const std::string& msg) {
 
 inline size_t elt_size(int prec) { return prec == SNMF_F64 ? 8 : 4; }
 
-// The fused inner kernels (one per inner iteration) serve a half-step whose n x r arrays
-// are below kRecomputeDBytes (latency-bound; above it the two-kernel form streams fewer
-// bytes, step 2 forming D again), when fuse_inner is set and a backtracked update is never
-// clipped by the projection (phi beta_shrink <= 1, no projection, or no backtracking),
-// which their BB step after a backtrack relies on.
-inline bool fused_inner_ok(const snmf_params& p, int64_t n, int r, size_t esz) {
+// The fused inner kernels (one per inner iteration) serve the half-steps of a solve when
+// fuse_inner is set and a backtracked update is never clipped by the projection
+// (phi beta_shrink <= 1, no projection, or no backtracking), which their BB step after a
+// backtrack relies on.  They beat the two-kernel form at every size measured: where the
+// iteration is latency-bound (fewer kernels) and where it streams the n x r arrays (five
+// array transfers per inner iteration against six).
+inline bool fused_inner_ok(const snmf_params& p) {
   const bool unclipped = !p.project_update || p.max_ls == 0 || p.phi * p.beta_shrink <= 1.0;
-  return p.fuse_inner && unclipped && n * r * (int64_t)esz < kRecomputeDBytes;
+  return p.fuse_inner && unclipped;
 }
 
 struct DevBuf {

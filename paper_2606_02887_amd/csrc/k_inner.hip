@@ -44,8 +44,7 @@ __host__ __device__ constexpr int inner_occupancy() {
 
 // The fused kernels (k_init with the direction, k_advance) hold more values per thread:
 // bounded to 168 registers they spill at RP <= 32, so they are built for two workgroups
-// per CU.  They run only on arrays below kRecomputeDBytes (latency-bound sizes, where
-// the grid fits in two workgroups per CU).
+// per CU, and a plan that uses them caps its grid there (inner_grid).
 template <typename T, int RP>
 __host__ __device__ constexpr int fused_occupancy() {
   return (sizeof(T) == 4 && RP <= 32) ? 2 : 1;
@@ -1341,17 +1340,18 @@ static int64_t inner_cus() {
 }
 
 // One workgroup per tile up to what stays resident at once (FP32 up to rank 32: three per
-// CU), at most kInnerGrid (the partial-sum rows).  A grid larger than the resident
-// workgroups runs in two rounds, and the second round's workgroups start only when
-// first-round ones end.
-int inner_grid(int64_t n, int r, int esz) {
+// CU, two where the grid also serves the fused kernels), at most kInnerGrid (the
+// partial-sum rows).  A grid larger than the resident workgroups runs in two rounds, and
+// the second round's workgroups start only when first-round ones end.
+int inner_grid(int64_t n, int r, int esz, bool fused) {
   const int rp = rank_pad(r);
   const int tm = 8 * kThreads / rp;
   int64_t nt = (n + tm - 1) / tm;
   if (nt < 1) nt = 1;
   int64_t cap = kInnerGrid;
   if (esz == 4 && rp <= 32) {
-    const int64_t res = inner_occupancy<float, 32>() * inner_cus();
+    const int per_cu = fused ? fused_occupancy<float, 32>() : inner_occupancy<float, 32>();
+    const int64_t res = per_cu * inner_cus();
     if (res < cap) cap = res;
   }
   return (int)(nt < cap ? nt : cap);

@@ -61,7 +61,8 @@ void launch_ws_spa_only(const BInst* inst, int ninst, const T* C, T* W, hipStrea
 template <typename T>
 void launch_ws_match(const BInst* inst, int ninst, const T* C, const T* H, T* Tout, int32_t* perm,
                      hipStream_t s);
-int inner_grid(int64_t n, int r, int esz);  // esz: bytes per element (4 or 8)
+// esz: bytes per element (4 or 8); fused: the grid also serves the fused inner kernels
+int inner_grid(int64_t n, int r, int esz, bool fused = false);
 int lai_blocks(int64_t n);
 
 template <typename T>

@@ -110,9 +110,9 @@ void half_step(NmfPlan& pl, T* X, int64_t nX, const T* P, int64_t nP, int is_hst
   T* Z = (T*)pl.Z;
   T* D = (T*)pl.D;
   T* g = (T*)pl.g;
-  // one kernel per inner iteration where the arrays are small (fused_inner_ok), init then
-  // also forming direction 0; partial sums alternate between partsB and partsD
-  const bool fused = run_inner && fused_inner_ok(pl.p, nX, r, sizeof(T));
+  // one kernel per inner iteration (fused_inner_ok), init then also forming direction 0;
+  // partial sums alternate between partsB and partsD
+  const bool fused = run_inner && fused_inner_ok(pl.p);
   launch_init<T>(X, Pz, B, ksplit, nX * r, (T*)pl.C, g, nullptr, GT, nX, r, is_hstep, pl.kp,
                  pl.st, pl.partsA, s, BMap{}, grid, nullptr, nullptr, fused ? D : nullptr,
                  fused ? pl.partsB : nullptr, fused ? Z : nullptr, fused ? (T*)pl.gs : nullptr);
@@ -248,7 +248,7 @@ snmf_status nmf_solve(const snmf_matrix* V, int64_t ncols, int32_t r, const void
   pl.p = *p;
   pl.kp = kparams_of(*p, false);
   pl.s = s;
-  pl.grid = inner_grid(pl.mx, r, (int)pl.esz);
+  pl.grid = inner_grid(pl.mx, r, (int)pl.esz, fused_inner_ok(pl.p));
   const size_t xr = (size_t)pl.mx * r * pl.esz;
   std::pair<void**, size_t> req[40];
   int nreq = 0;

@@ -60,6 +60,7 @@ struct snmf_plan {
   unsigned* flags = nullptr;
   DenseSplit ds{};
   int gram_blocks = 1;
+  int grid = 1;  // workgroups of every row-tile kernel of the plan (one partial-sum layout)
   double normA2 = 0.0;
   KParams kp{};
   // captured outer iterations: one, and kGraphRun of them back to back (one launch per
@@ -282,8 +283,7 @@ int ksplit_of(const snmf_plan* pl) {
 // (fused_inner_ok), on every half-step without the Laplacian term except the H-step of
 // the naive variant.
 bool fused_half(const snmf_plan* pl, int is_hstep) {
-  return fused_inner_ok(pl->p, pl->n, pl->r, pl->esz) && !(pl->lap && is_hstep) &&
-         !(pl->p.naive && is_hstep);
+  return fused_inner_ok(pl->p) && !(pl->lap && is_hstep) && !(pl->p.naive && is_hstep);
 }
 
 // dir: init also forms the fused path's direction 0 (fused_half).
@@ -309,7 +309,7 @@ snmf_status half_start(snmf_plan* pl, T* X, const T* P, int is_hstep, bool with_
   }
   launch_init<T>(X, P, (const T*)pl->Bpart, ksplit_of(pl), n * r, (T*)pl->C, (T*)pl->g,
                  lap ? (const T*)pl->LX : nullptr, (const T*)pl->GT[gi], n, r, is_hstep, pl->kp,
-                 pl->st, pl->partsA, s, BMap{}, 0, lap ? (T*)pl->Z : nullptr,
+                 pl->st, pl->partsA, s, BMap{}, pl->grid, lap ? (T*)pl->Z : nullptr,
                  lap ? (T*)pl->D : nullptr, dir ? (T*)pl->D : nullptr,
                  dir ? pl->partsB : nullptr, dir ? (T*)pl->Z : nullptr,
                  dir ? (T*)pl->gs : nullptr);
@@ -336,9 +336,10 @@ snmf_status inner_step(snmf_plan* pl, T* X, const T* P, int is_hstep, int k, hip
     // n = 20000, r = 20) storing it measured faster (1.6% and 0.5%)
     const int rd = (int64_t)n * r * (int64_t)sizeof(T) >= kRecomputeDBytes;
     launch_step1<T>(X, g, Z, D, nullptr, GT, pl->G64[0], pl->G64[1], n, r, k, 0, is_hstep, pl->kp,
-                    pl->st, pl->partsA, pl->partsB, pl->partsC, pl->trace, s, BMap{}, 0, rd);
+                    pl->st, pl->partsA, pl->partsB, pl->partsC, pl->trace, s, BMap{}, pl->grid,
+                    rd);
     launch_step2<T>(X, g, Z, D, nullptr, (const T*)pl->C, P, nullptr, GT, n, r, k, 0, is_hstep,
-                    pl->kp, pl->st, pl->partsB, nullptr, 0, pl->partsC, s, BMap{}, 0,
+                    pl->kp, pl->st, pl->partsB, nullptr, 0, pl->partsC, s, BMap{}, pl->grid,
                     pl->p.inner_iters - 1, rd);
   } else {
     const int64_t* rp = pl->L.rowptr;
@@ -353,13 +354,14 @@ snmf_status inner_step(snmf_plan* pl, T* X, const T* P, int is_hstep, int k, hip
     // previous half-step's flag, and a stopped iteration's product is never read
     launch_spmm<T>(rp, ci, lv, D, n, r, LT, nullptr, nullptr, g1, nullptr, s);
     launch_step1<T>(X, g, Z, D, LT, GT, pl->G64[0], pl->G64[1], n, r, k, 2, is_hstep, pl->kp,
-                    pl->st, pl->partsA, pl->partsB, pl->partsC, pl->trace, s);
+                    pl->st, pl->partsA, pl->partsB, pl->partsC, pl->trace, s, BMap{}, pl->grid);
     launch_spmm<T>(rp, ci, lv, D, n, r, nullptr, D, pl->partsD, g1, g2, s);
     launch_step2<T>(X, g, Z, D, nullptr, (const T*)pl->C, P, nullptr, GT, n, r, k, 1, is_hstep,
-                    pl->kp, pl->st, pl->partsB, pl->partsD, spmm_dot_grid(n), pl->partsC, s);
+                    pl->kp, pl->st, pl->partsB, pl->partsD, spmm_dot_grid(n), pl->partsC, s,
+                    BMap{}, pl->grid);
     launch_spmm<T>(rp, ci, lv, D, n, r, LT, nullptr, nullptr, g1, g2, s);
     launch_step2<T>(X, g, Z, D, LT, (const T*)pl->C, P, (T*)pl->LX, GT, n, r, k, 2, is_hstep,
-                    pl->kp, pl->st, pl->partsB, nullptr, 0, pl->partsC, s);
+                    pl->kp, pl->st, pl->partsB, nullptr, 0, pl->partsC, s, BMap{}, pl->grid);
   }
   HIP_TRY(hipGetLastError());
   return SNMF_OK;
@@ -378,7 +380,8 @@ snmf_status inner_steps(snmf_plan* pl, T* X, const T* P, int is_hstep, hipStream
       launch_advance<T>(X, (T*)pl->g, (T*)pl->Z, (T*)pl->gs, (T*)pl->D, (const T*)pl->C, P,
                         (const T*)pl->GT[is_hstep ? 1 : 0], pl->G64[0], pl->G64[1], pl->n, pl->r,
                         K, i, is_hstep, pl->kp, pl->st, (i & 1) ? pl->partsD : pl->partsB,
-                        (i & 1) ? pl->partsB : pl->partsD, pl->partsA, pl->partsC, pl->trace, s);
+                        (i & 1) ? pl->partsB : pl->partsD, pl->partsA, pl->partsC, pl->trace, s,
+                        pl->grid);
     }
     HIP_TRY(hipGetLastError());
     return SNMF_OK;
@@ -398,10 +401,10 @@ snmf_status outer_iteration(snmf_plan* pl, hipStream_t s) {
     // (at H = W) and its one step 2 supply the monitor sums of the pair (W, W)
     HIP_TRY(hipMemcpyAsync(H, W, (size_t)pl->n * pl->r * sizeof(T), hipMemcpyDeviceToDevice, s));
     SNMF_TRY(half_start<T>(pl, H, W, 1, false, s));
-    launch_naive_hentry(pl->partsA, inner_grid(pl->n, pl->r, (int)sizeof(T)), pl->st, s);
+    launch_naive_hentry(pl->partsA, pl->grid, pl->st, s);
     launch_step2<T>(H, (T*)pl->g, (T*)pl->Z, (T*)pl->D, nullptr, (const T*)pl->C, W, nullptr,
                     (const T*)pl->GT[1], pl->n, pl->r, 0, 0, 1, pl->kp, pl->st, pl->partsB,
-                    nullptr, 0, pl->partsC, s, BMap{}, 0, 0, 0);
+                    nullptr, 0, pl->partsC, s, BMap{}, pl->grid, 0, 0);
     HIP_TRY(hipGetLastError());
     return SNMF_OK;
   }
@@ -424,7 +427,7 @@ snmf_status finalize(snmf_plan* pl, hipStream_t s) {
   const int64_t n = pl->n;
   launch_step1<T>(W, (const T*)pl->g, (T*)pl->Z, (T*)pl->D, nullptr, (const T*)pl->GT[0],
                   pl->G64[0], pl->G64[1], n, pl->r, 0, 0, 0, pl->kp, pl->st,
-                  pl->partsA, pl->partsB, pl->partsC, pl->trace, s, BMap{}, 0,
+                  pl->partsA, pl->partsB, pl->partsC, pl->trace, s, BMap{}, pl->grid,
                   1);  // D is never read after it
   HIP_TRY(hipGetLastError());
   return SNMF_OK;
@@ -501,7 +504,9 @@ snmf_status plan_init(snmf_plan* pl, const snmf_matrix* A, int32_t r, const snmf
   add(&pl->g, nr);
   add(&pl->Z, nr);
   // the fused inner kernels' trial gradient (the trial update itself goes to Z)
-  if (fused_inner_ok(*p, n, r, pl->esz)) add(&pl->gs, nr);
+  const bool fused = fused_inner_ok(*p);
+  if (fused) add(&pl->gs, nr);
+  pl->grid = inner_grid(n, r, (int)pl->esz, fused);
   add(&pl->D, nr);
   add(&pl->Bpart, nr * ksplit);
   if (lap) {
@@ -830,14 +835,16 @@ snmf_status snmf_plan_half_step(snmf_plan* pl, void* X, const void* P, int32_t i
     launch_step1<double>((const double*)X, (const double*)pl->g, (double*)pl->Z, (double*)pl->D,
                          nullptr, (const double*)pl->GT[is_hstep ? 1 : 0], pl->G64[0], pl->G64[1],
                          pl->n, pl->r, K, (pl->lap && is_hstep) ? 1 : 0, is_hstep, pl->kp, pl->st,
-                         pl->partsA, pl->partsB, pl->partsC, pl->trace, pl->s, BMap{}, 0, 1);
+                         pl->partsA, pl->partsB, pl->partsC, pl->trace, pl->s, BMap{},
+                         pl->grid, 1);
   } else {
     SNMF_TRY(half_start<float>(pl, (float*)X, (const float*)P, is_hstep, true, pl->s));
     SNMF_TRY(inner_steps<float>(pl, (float*)X, (const float*)P, is_hstep, pl->s, false));
     launch_step1<float>((const float*)X, (const float*)pl->g, (float*)pl->Z, (float*)pl->D,
                         nullptr, (const float*)pl->GT[is_hstep ? 1 : 0], pl->G64[0], pl->G64[1],
                         pl->n, pl->r, K, (pl->lap && is_hstep) ? 1 : 0, is_hstep, pl->kp, pl->st,
-                        pl->partsA, pl->partsB, pl->partsC, pl->trace, pl->s, BMap{}, 0, 1);
+                        pl->partsA, pl->partsB, pl->partsC, pl->trace, pl->s, BMap{},
+                        pl->grid, 1);
   }
   HIP_TRY(hipGetLastError());
   State hs;

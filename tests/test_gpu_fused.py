@@ -11,7 +11,7 @@ same numbers up to rounding: the FP64 solves then match the oracle as closely as
 two-kernel path does (1e-9), and the two paths agree to 1e-10 in FP64.  Cases: dense FP32,
 split BF16 and FP64, CSR, low rank; a strict monotone line search (theta = 0.5, eta = 0)
 that backtracks often; one, three and five inner iterations; workgroups owning several row
-tiles (n = 50000, r = 20); Graph-SNMPBB and the naive variant, whose W-steps take the fused
+tiles (n = 40000, r = 64); Graph-SNMPBB and the naive variant, whose W-steps take the fused
 path and H-steps the two-kernel one.
 """
 import numpy as np
@@ -115,9 +115,10 @@ def test_fused_inner_counts_same_bits(S, inner):
 
 
 def test_fused_csr_several_tiles_per_workgroup(S):
-    """n = 50000, r = 20: 782 row tiles of 64 rows on 768 workgroups (the largest n x r
-    FP32 arrays the fused path takes are below 4 MiB)."""
-    n, r = 50000, 20
+    """n = 40000, r = 64: 1250 row tiles of 32 rows on 1024 workgroups.  (At r <= 32 in
+    FP32 a fused plan keeps two workgroups per CU and a two-kernel plan three, so their
+    partial sums are grouped differently there.)"""
+    n, r = 40000, 64
     a_ = gen.random_symmetric_csr(n, 6.0, 3)
     rng = np.random.default_rng(2)
     W0 = gen.start_factor(rng, n, r, gen.mean_of_sparse(a_))
