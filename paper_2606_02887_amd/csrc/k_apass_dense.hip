@@ -186,19 +186,23 @@ __global__ __launch_bounds__(256) void k_apass_f32(const float* __restrict__ A, 
 //    part of t to panel nband + w - first(t), and last(t) writes zeros to the panels
 //    above its own up to nslot - 1.
 // So every tile has exactly nslot panels, added in panel order by the consumer.
-// With rj.G set, the grid has one more workgroup (the last): it computes rho = ||G||_2
-// (rho.hpp) beside the tiles.  The register bound of two waves per SIMD and the 64 KB of
-// LDS leave room on a CU for it next to a tile workgroup (the tiles take one slot fewer
-// than two per CU), so rho (56 us alone at r = 64) adds only the slowdown of the tile
-// workgroup that shares its CU: about 6 us at n = 8192.
+// With rj.G set, the grid has one more workgroup (number rho_wg): it computes
+// rho = ||G||_2 (rho.hpp) beside the tiles.  The register bound of two waves per SIMD and
+// the 64 KB of LDS leave room on a CU for it next to a tile workgroup (the tiles take one
+// slot fewer than two per CU), so rho (56 us alone at r = 64) adds only the slowdown of
+// the tile workgroup that shares its CU.  With two workgroups per CU, workgroups i and
+// i + CUs are dispatched to the same CU, so the host places rho at the last index minus
+// the CU count, beside the last workgroup: a chunk of the rows after the bands, which
+// carries fewer rows than a band.
 __global__ __launch_bounds__(256, 2) void k_apass_f32w(const float* __restrict__ A, int64_t lda,
                                                        const float* __restrict__ P, int64_t n,
                                                        int r, int64_t band, int nband,
                                                        int64_t rchunk, int nslot,
                                                        float* __restrict__ Bpart, int64_t pstride,
-                                                       const State* __restrict__ st, RhoJob rj) {
+                                                       const State* __restrict__ st, RhoJob rj,
+                                                       int rho_wg) {
   if (st->done) return;
-  if (rj.G && blockIdx.x == gridDim.x - 1) {
+  if (rj.G && (int)blockIdx.x == rho_wg) {
     rho_body(rj.G, rj.r, rj.st);
     return;
   }
@@ -206,7 +210,7 @@ __global__ __launch_bounds__(256, 2) void k_apass_f32w(const float* __restrict__
   // the wave index is uniform: K ranges, batch counts and loop control stay scalar
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int c = lane & 31, h = lane >> 5;
-  const int64_t w = blockIdx.x;
+  const int64_t w = (rj.G && (int)blockIdx.x > rho_wg) ? blockIdx.x - 1 : blockIdx.x;
   const int64_t gx = (n + 127) / 128;
   const int64_t nfull = (int64_t)nband * gx;
   const int64_t r0 = (int64_t)nband * band;  // first row of K after the full bands
@@ -646,9 +650,17 @@ void launch_apass_f32(const float* A, int64_t lda, const float* P, int64_t n, in
                       hipStream_t s, const RhoJob& rj) {
   dim3 grid((unsigned)d.gx, (unsigned)d.ksplit);
   if (d.wide) {
-    const dim3 gw((unsigned)(d.nwg + (rj.G ? 1 : 0)));
-    hipLaunchKernelGGL(k_apass_f32w, gw, dim3(256), 0, s, A, lda, P, n, r, d.kchunk, d.nband,
-                       d.rchunk, d.ksplit, Bpart, pstride, st, rj);
+    const int64_t total = d.nwg + (rj.G ? 1 : 0);
+    int rho_wg = (int)total - 1;
+    if (rj.G) {
+      int dev = 0, cus = 0;
+      if (hipGetDevice(&dev) == hipSuccess &&
+          hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+          cus > 0 && total - 1 - cus >= 0)
+        rho_wg = (int)(total - 1 - cus);
+    }
+    hipLaunchKernelGGL(k_apass_f32w, dim3((unsigned)total), dim3(256), 0, s, A, lda, P, n, r,
+                       d.kchunk, d.nband, d.rchunk, d.ksplit, Bpart, pstride, st, rj, rho_wg);
     return;
   }
   if (rj.G) launch_rho(rj.G, rj.r, rj.st, s);
