@@ -179,15 +179,43 @@ __device__ __forceinline__ void store_G(T* __restrict__ sG, const T (&v)[TileCfg
 
 // This thread's share (workgroups b = tid, tid + 256, ... in increasing b) of K consecutive
 // partial-sum slots starting at `first`; block_sum then adds the shares in a fixed order.
+// Thread t adds the rows t, t + 256, ... in that order; each pass loads two rows before it
+// adds either, so up to 512 workgroups cost one memory round trip, not one per row.
+template <int K, typename F>
+__device__ __forceinline__ void load_rows(int nb, double (&out)[K], F&& at) {
+#pragma unroll
+  for (int j = 0; j < K; ++j) out[j] = 0.0;
+  for (int b = threadIdx.x; b < nb; b += 2 * kThreads) {
+    const bool two = b + kThreads < nb;
+    const int b1 = min(b + kThreads, nb - 1);  // (an in-bounds row, added only if two)
+    double u0[K], u1[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) u0[j] = at(b, j);
+#pragma unroll
+    for (int j = 0; j < K; ++j) u1[j] = at(b1, j);
+    __builtin_amdgcn_sched_barrier(0);  // every load issued before the first add waits
+#pragma unroll
+    for (int j = 0; j < K; ++j) out[j] += u0[j];
+    // adding +0.0 leaves a sum that started at +0.0 unchanged, so this is "if (two) add"
+#pragma unroll
+    for (int j = 0; j < K; ++j) out[j] += two ? u1[j] : 0.0;
+  }
+}
 template <int K>
 __device__ __forceinline__ void load_slots(const double* __restrict__ part, int nb, int first,
                                            double (&out)[K]) {
-#pragma unroll
-  for (int j = 0; j < K; ++j) out[j] = 0.0;
-  for (int b = threadIdx.x; b < nb; b += kThreads) {
-#pragma unroll
-    for (int j = 0; j < K; ++j) out[j] += part[(size_t)b * kNumPart + first + j];
-  }
+  load_rows<K>(nb, out, [&](int b, int j) { return part[(size_t)b * kNumPart + first + j]; });
+}
+
+// The partial sums of the fused kernels (kFusedParts slots, below) are slot-major: slot j of
+// workgroup b at part[j * kInnerGrid + b].  Every workgroup re-reads all of them, and with
+// this layout a wave's load of one slot covers 64 consecutive workgroups (4 cache lines;
+// row-major rows would put its 64 lanes on 64 lines).  Each thread adds the same rows in
+// the same order as load_slots.
+template <int K>
+__device__ __forceinline__ void load_cols(const double* __restrict__ part, int nb,
+                                          double (&out)[K]) {
+  load_rows<K>(nb, out, [&](int b, int j) { return part[(size_t)j * kInnerGrid + b]; });
 }
 
 // ----------------------------------------------------------------------------- instances
@@ -397,7 +425,8 @@ __device__ __forceinline__ void tile_direction(Smem<T, RP>& sm, const int (&lr)[
 }
 
 // ----------------------------------------------------------------------------- init
-// C = (sum of the A-pass partials) + lam P;  g = X G + lam X - C [+ gam LX].
+// C = (sum of the A-pass partials) + lam P;  g = X G + lam X - C [+ gam LX].  C is stored in
+// H-steps only: the outer iteration's monitor sum <C, X> at the final X reads it there.
 // DIR (fused inner iterations): also the direction of inner iteration 0 (alpha_0 = 1/rho),
 // its sums (tile_direction) into pout and its beta = 1 trial update into (Xs, gs); the
 // first fused kernel runs its line search.
@@ -499,7 +528,7 @@ __global__ __launch_bounds__(kThreads, (DIR ? fused_occupancy<T, RP>() : inner_o
     for (int p = 0; p < 8; ++p) {
       gq[p] = T(0);
       if (ok[p]) {
-        sto(tile_ptr(Cout, tb), bo[p], cv[p]);
+        if (is_hstep) sto(tile_ptr(Cout, tb), bo[p], cv[p]);  // only H-step monitors read C
         T gvv = xg[p] + lam * x[p] - cv[p];
         if (LX) gvv += gam * lx[p];
         gq[p] = gvv;
@@ -528,10 +557,9 @@ __global__ __launch_bounds__(kThreads, (DIR ? fused_occupancy<T, RP>() : inner_o
     const double o[1 + kFusedParts] = {v[0],  ls[0], ls[1], ls[2], ls[3], sp[0], sp[1],
                                        sp[2], xp[0], xp[1], xp[2], xp[3], xp[4], xp[5]};
     double* pa = partsA + (size_t)lc.bid * kNumPart;
-    double* po = pout + (size_t)lc.bid * kNumPart;
     block_sum_emit<1 + kFusedParts>(o, sm.red, [&](int j, double a) {
       if (j)
-        po[j - 1] = a;
+        pout[(size_t)(j - 1) * kInnerGrid + lc.bid] = a;
       else
         pa[0] = a;
     });
@@ -1148,9 +1176,9 @@ __global__ __launch_bounds__(kThreads, (fused_occupancy<T, RP>())) void k_advanc
   const int stopped = i > 0 ? st->stop[i] : 0;
   const double rho = st->rho, e_i = i > 0 ? st->e[i] : 0.0;
   double pa[kFusedParts];
-  load_slots<kFusedParts>(pin, nb, 0, pa);
-  double pe[6];
-  entry_loads(0, HS, partsA, partsC, nb, pe);
+  load_cols<kFusedParts>(pin, nb, pa);
+  double pe[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (i == 0) entry_loads(0, HS, partsA, partsC, nb, pe);
   T gv[TileCfg<RP>::NG];
   load_G<T, RP>(GT, r, gv);
   T xt[8], gt[8];
@@ -1249,10 +1277,10 @@ __global__ __launch_bounds__(kThreads, (fused_occupancy<T, RP>())) void k_advanc
   if (closing) {  // the last update, then the H-step's monitor sums of the final X
     for (int64_t t = bid; t < ntiles; t += nb) {
       const int64_t row0 = t * TM, tb = row0 * r;
-      if (t != bid && trial) load_trial(row0);
       T xn[8], gn[8];
       __syncthreads();
       next_tile(row0, xn, gn);
+      if (trial && t + nb < ntiles) load_trial(row0 + (int64_t)nb * TM);
 #pragma unroll
       for (int p = 0; p < 8; ++p) {
         if (row0 + lr[p] < n && cl[p] < r) {
@@ -1265,10 +1293,11 @@ __global__ __launch_bounds__(kThreads, (fused_occupancy<T, RP>())) void k_advanc
   } else {  // X_{i+1}, then direction i + 1 and the next trial (into pair i % 2)
     for (int64_t t = bid; t < ntiles; t += nb) {
       const int64_t row0 = t * TM, tb = row0 * r;
-      if (t != bid && trial) load_trial(row0);
       T xn[8], gn[8];
       __syncthreads();
       next_tile(row0, xn, gn);
+      // the trial of this workgroup's next tile loads while this one is worked on
+      if (trial && t + nb < ntiles) load_trial(row0 + (int64_t)nb * TM);
       // sm.a was last read before this tile's first barrier
       tile_direction<T, RP>(sm, lr, cl, bo, row0, n, r, xn, gn, rinv, alpha, lam, step1,
                             kp.project, tile_ptr(D, tb), tile_ptr(Xc, tb), tile_ptr(gc, tb), ls,
@@ -1278,8 +1307,8 @@ __global__ __launch_bounds__(kThreads, (fused_occupancy<T, RP>())) void k_advanc
   if (dir) {
     const double o[kFusedParts] = {ls[0], ls[1], ls[2], ls[3], sp[0], sp[1], sp[2],
                                    xp[0], xp[1], xp[2], xp[3], xp[4], xp[5]};
-    double* po = pout + (size_t)bid * kNumPart;
-    block_sum_emit<kFusedParts>(o, sm.red, [&](int j, double a) { po[j] = a; });
+    block_sum_emit<kFusedParts>(o, sm.red,
+                                [&](int j, double a) { pout[(size_t)j * kInnerGrid + bid] = a; });
   } else {
     if (HS) {  // slots 0-2 (the last update's sums in step 2) are not read after a half-step
       const double v[9] = {0.0, 0.0, 0.0, mon[0], mon[1], mon[2], mon[3], 0.0, 0.0};
