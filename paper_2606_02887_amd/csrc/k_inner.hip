@@ -648,12 +648,27 @@ __device__ int inner_entry(int k, int is_hstep, int r, const KParams& kp, State*
       if (st->snap_pending) {
         // ||min(W, grad_W)||^2, <C,Ht>, <W,Ht>, ||Ht-W||^2, pgH^2, <Ht,LHt>
         block_sum_wide<6>(pe, sred);
-        double gg[3] = {0.0, 0.0, 0.0};
-        for (int e = threadIdx.x; e < r * r; e += kThreads) {
-          gg[0] += Gprev[e] * Gcur[e];   // <W^T W, Ht^T Ht>
-          gg[1] += Gprev[e] * Gprev[e];  // ||W^T W||_F^2
+        // <W^T W, Ht^T Ht>, ||W^T W||_F^2, ||W||^2 = tr(W^T W); thread t adds the entries
+        // t, t + 256, ... in that order, all loaded before the first add
+        constexpr int kGE = kMaxRank * kMaxRank / kThreads;
+        const int rr = r * r;
+        double gp[kGE], gc[kGE];
+#pragma unroll
+        for (int u = 0; u < kGE; ++u) {
+          const int e = min((int)threadIdx.x + u * kThreads, rr - 1);
+          gp[u] = Gprev[e];
+          gc[u] = Gcur[e];
         }
-        for (int a = threadIdx.x; a < r; a += kThreads) gg[2] += Gprev[a * r + a];  // ||W||^2
+        const double dg = (int)threadIdx.x < r ? Gprev[threadIdx.x * r + threadIdx.x] : 0.0;
+        __builtin_amdgcn_sched_barrier(0);
+        double gg[3] = {0.0, 0.0, dg};
+#pragma unroll
+        for (int u = 0; u < kGE; ++u) {
+          if ((int)threadIdx.x + u * kThreads < rr) {
+            gg[0] = fma(gp[u], gc[u], gg[0]);
+            gg[1] = fma(gp[u], gp[u], gg[1]);
+          }
+        }
         block_sum_wide<3>(gg, sred);
         const double nA2 = st->normA2;
         const double AWHt = pe[1] - kp.lam * pe[2];     // <A W, Ht>
