@@ -179,27 +179,30 @@ __device__ __forceinline__ void store_G(T* __restrict__ sG, const T (&v)[TileCfg
 
 // This thread's share (workgroups b = tid, tid + 256, ... in increasing b) of K consecutive
 // partial-sum slots starting at `first`; block_sum then adds the shares in a fixed order.
-// Thread t adds the rows t, t + 256, ... in that order; each pass loads two rows before it
-// adds either, so up to 512 workgroups cost one memory round trip, not one per row.
+// Thread t adds the rows t, t + 256, ... in that order.  Each pass loads two rows before it
+// adds either, so up to 512 workgroups cost one memory round trip, not one per row; the
+// first pass is straight-line code (no loop guard between the kernel arguments and the
+// loads, so nothing waits for other scalar loads first).  Rows past nb are loaded from an
+// in-bounds row and add +0.0, which leaves a sum that started at +0.0 unchanged.
 template <int K, typename F>
 __device__ __forceinline__ void load_rows(int nb, double (&out)[K], F&& at) {
-#pragma unroll
-  for (int j = 0; j < K; ++j) out[j] = 0.0;
-  for (int b = threadIdx.x; b < nb; b += 2 * kThreads) {
-    const bool two = b + kThreads < nb;
-    const int b1 = min(b + kThreads, nb - 1);  // (an in-bounds row, added only if two)
+  auto pass = [&](int b) {
+    const int b0 = min(b, nb - 1), b1 = min(b + kThreads, nb - 1);
     double u0[K], u1[K];
 #pragma unroll
-    for (int j = 0; j < K; ++j) u0[j] = at(b, j);
+    for (int j = 0; j < K; ++j) u0[j] = at(b0, j);
 #pragma unroll
     for (int j = 0; j < K; ++j) u1[j] = at(b1, j);
     __builtin_amdgcn_sched_barrier(0);  // every load issued before the first add waits
 #pragma unroll
-    for (int j = 0; j < K; ++j) out[j] += u0[j];
-    // adding +0.0 leaves a sum that started at +0.0 unchanged, so this is "if (two) add"
+    for (int j = 0; j < K; ++j) out[j] += b < nb ? u0[j] : 0.0;
 #pragma unroll
-    for (int j = 0; j < K; ++j) out[j] += two ? u1[j] : 0.0;
-  }
+    for (int j = 0; j < K; ++j) out[j] += b + kThreads < nb ? u1[j] : 0.0;
+  };
+#pragma unroll
+  for (int j = 0; j < K; ++j) out[j] = 0.0;
+  pass(threadIdx.x);
+  for (int b = threadIdx.x + 2 * kThreads; b < nb; b += 2 * kThreads) pass(b);
 }
 template <int K>
 __device__ __forceinline__ void load_slots(const double* __restrict__ part, int nb, int first,
@@ -1187,9 +1190,12 @@ __global__ __launch_bounds__(kThreads, (fused_occupancy<T, RP>())) void k_advanc
   const int64_t ntiles = (n + TM - 1) / TM;
   // loads first: State scalars, the partial sums (and the k = 0 entry's), G, the trial
   // update of the first tile
-  const int done = st->done;
-  const int stopped = i > 0 ? st->stop[i] : 0;
-  const double rho = st->rho, e_i = i > 0 ? st->e[i] : 0.0;
+  // (unconditional loads, selected afterwards: a load under "i > 0" became a branch that
+  // waited for it before any other load was issued)
+  const int done = st->done, stop_i = st->stop[i];
+  const double rho = st->rho, e_raw = st->e[i];
+  const int stopped = i > 0 ? stop_i : 0;
+  const double e_i = i > 0 ? e_raw : 0.0;
   double pa[kFusedParts];
   load_cols<kFusedParts>(pin, nb, pa);
   double pe[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
