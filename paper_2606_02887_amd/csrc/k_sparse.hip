@@ -18,6 +18,10 @@
 
 namespace snmf {
 
+// Stands in for an absent gate, so that both gate flags load without a condition (a load
+// under a null test waited for its pointer argument and its flag in turn).
+__device__ int32_t g_no_gate = 0;
+
 template <typename T, int RP, bool RHO>
 __global__ __launch_bounds__(256) void k_spmm(const int64_t* __restrict__ rowptr,
                                               const int32_t* __restrict__ col,
@@ -26,13 +30,16 @@ __global__ __launch_bounds__(256) void k_spmm(const int64_t* __restrict__ rowptr
                                               const T* __restrict__ X2, double* __restrict__ part,
                                               const int32_t* __restrict__ gate,
                                               const int32_t* __restrict__ gate2, RhoJob rj) {
-  if ((gate && gate[0]) || (gate2 && gate2[0])) return;
+  // gate, gate2: the product is skipped when either flag is set (nullptr: none)
+  const int32_t* __restrict__ g1 = gate ? gate : &g_no_gate;
+  const int32_t* __restrict__ g2 = gate2 ? gate2 : g1;
   // RHO: workgroup 0 computes rho = ||G||_2 (dispatched first, so it runs beside the
   // product) and the product uses the workgroups after it.  A template flag, so the plain
   // product keeps its lower register count.
   constexpr int64_t b0 = RHO ? 1 : 0;
   if constexpr (RHO) {
     if (blockIdx.x == 0) {
+      if (g1[0] | g2[0]) return;
       rho_body(rj.G, rj.r, rj.st);
       return;
     }
@@ -53,9 +60,14 @@ __global__ __launch_bounds__(256) void k_spmm(const int64_t* __restrict__ rowptr
   const int64_t bid = (int64_t)blockIdx.x - b0;
   const int64_t wave_id = (bid * kThreads + threadIdx.x) / kWave;
   const int64_t nwaves = ((int64_t)gridDim.x - b0) * kThreads / kWave;
+  // the first row's extent is loaded before the gates are tested: both round trips overlap
+  const int64_t b_first = wave_id < n ? rowptr[wave_id] : 0;
+  const int64_t e_first = wave_id < n ? rowptr[wave_id + 1] : 0;
+  if (g1[0] | g2[0]) return;
   double dot = 0.0;
   for (int64_t row = wave_id; row < n; row += nwaves) {
-    const int64_t b = rowptr[row], e = rowptr[row + 1];
+    const int64_t b = row == wave_id ? b_first : rowptr[row];
+    const int64_t e = row == wave_id ? e_first : rowptr[row + 1];
     T acc = T(0);
     // up to 64 (column, value) pairs per load, broadcast by cross-lane shuffles so that
     // the gathers of four nonzeros per lane group are in flight together
