@@ -51,10 +51,11 @@ def _t(x, dtype):
 
 
 def _half_step(S, Aop_gpu, Aop_oracle, X, P, prec, is_hstep, lam, gamma=0.0, L_gpu=None,
-               L_or=None):
+               L_or=None, fuse=1):
     Xt, Pt = _t(X, torch.float32), _t(P, torch.float32)
     X_in, P_in = Xt.double().cpu().numpy(), Pt.double().cpu().numpy()
-    prm = S.params(lam=lam, gamma=gamma, prec=prec, inner_iters=5, max_outer=1, validate=0)
+    prm = S.params(lam=lam, gamma=gamma, prec=prec, inner_iters=5, max_outer=1, validate=0,
+                   fuse_inner=fuse)
     pl = S.Plan(Aop_gpu, X.shape[1], prm, L_gpu)
     sc = pl.half_step(Xt, Pt, bool(is_hstep))
     pl.close()
@@ -122,7 +123,11 @@ def test_graph_n20000_r20_hstep(S):
     _scalars(sc, log, 1e-3)
 
 
-def test_lowrank_n200000_r32_half_step(S):
+@pytest.mark.parametrize("fuse", [1, 0])
+def test_lowrank_n200000_r32_half_step(S, fuse):
+    """fuse = 1: one kernel per inner iteration, two workgroups per CU (512).  fuse = 0:
+    two kernels, three workgroups per CU (768), so every kernel re-reduces more than 512
+    rows of partial sums, the loader's second pass."""
     q = gen.config(3)                                   # LAI n = 200000, ell = 64
     U, lamv = O.range_finder(q["A"], q["rank"], q["power_iters"], q["Omega"])
     r = 32
@@ -132,10 +137,10 @@ def test_lowrank_n200000_r32_half_step(S):
     X = q["W0"]
     P = np.random.default_rng(5).random(X.shape) * float(X.mean())
     Xg, Xo, sc, log = _half_step(S, S.lowrank(Ut, _t(lamv, torch.float64)), lr_in, X, P,
-                                 S.F32, 0, lam)
+                                 S.F32, 0, lam, fuse=fuse)
     err = nrel(Xg, Xo)
     ee = elem_rel(Xg, Xo)
-    print(f"low rank n=200000 r=32: nrel {err:.3e} entrywise {ee:.3e}")
+    print(f"low rank n=200000 r=32 fuse={fuse}: nrel {err:.3e} entrywise {ee:.3e}")
     assert ee <= _etol(), (ee, _half_step.model)
     assert err <= 3e-5
     _scalars(sc, log, 1e-3)
