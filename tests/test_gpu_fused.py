@@ -128,6 +128,23 @@ def test_fused_csr_several_tiles_per_workgroup(S):
     _same(a, b)
 
 
+@pytest.mark.parametrize("ntiles", [257, 513])
+def test_fused_partial_grid_edges_same_bits(S, ntiles):
+    """FP32 at r = 64: both forms launch one workgroup per 32-row tile (up to 1024), and
+    every kernel re-reduces one row of partial sums per workgroup, thread t adding the rows
+    t, t + 256, ... (two per pass).  257 rows: one thread has a second row; 513: one pass
+    more.  The fused kernels' slot-major sums and the two-kernel form's row-major ones must
+    add the same rows in the same order."""
+    n, r = 32 * ntiles, 64
+    a_ = gen.random_symmetric_csr(n, 6.0, 40 + ntiles)
+    rng = np.random.default_rng(ntiles)
+    W0 = gen.start_factor(rng, n, r, gen.mean_of_sparse(a_))
+    M = S.csr_from_scipy(a_, torch.float32)
+    lam = 0.01 * float(np.sqrt(np.sum(a_.data.astype(np.float32).astype(np.float64) ** 2)))
+    a, b = _both(S, M, _t(W0, torch.float32), lam=lam, prec=S.F32, max_outer=4)
+    _same(a, b)
+
+
 @pytest.mark.parametrize("prec", ["f32", "f64"])
 def test_fused_lowrank_same_bits(S, prec):
     n, ell, r = 4000, 24, 16
