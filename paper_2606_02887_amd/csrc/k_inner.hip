@@ -183,7 +183,10 @@ __device__ __forceinline__ void store_G(T* __restrict__ sG, const T (&v)[TileCfg
 // adds either, so up to 512 workgroups cost one memory round trip, not one per row; the
 // first pass is straight-line code (no loop guard between the kernel arguments and the
 // loads, so nothing waits for other scalar loads first).  Rows past nb are loaded from an
-// in-bounds row and add +0.0, which leaves a sum that started at +0.0 unchanged.
+// in-bounds row and add +0.0, which leaves a sum that started at +0.0 unchanged.  Every
+// thread loads, so this suits the fused kernels' plan-wide grids (256 or 512 workgroups);
+// load_slots below keeps the plain loop, in which threads past nb load nothing (batches
+// re-reduce grids of a few dozen workgroups per instance).
 template <int K, typename F>
 __device__ __forceinline__ void load_rows(int nb, double (&out)[K], F&& at) {
   auto pass = [&](int b) {
@@ -207,7 +210,12 @@ __device__ __forceinline__ void load_rows(int nb, double (&out)[K], F&& at) {
 template <int K>
 __device__ __forceinline__ void load_slots(const double* __restrict__ part, int nb, int first,
                                            double (&out)[K]) {
-  load_rows<K>(nb, out, [&](int b, int j) { return part[(size_t)b * kNumPart + first + j]; });
+#pragma unroll
+  for (int j = 0; j < K; ++j) out[j] = 0.0;
+  for (int b = threadIdx.x; b < nb; b += kThreads) {
+#pragma unroll
+    for (int j = 0; j < K; ++j) out[j] += part[(size_t)b * kNumPart + first + j];
+  }
 }
 
 // The partial sums of the fused kernels (kFusedParts slots, below) are slot-major: slot j of
@@ -640,6 +648,7 @@ __device__ int bb_step(int k, const double (&s4)[4], double e_prev, const KParam
   return kEntryRun;
 }
 
+template <int RP>
 __device__ int inner_entry(int k, int is_hstep, int r, const KParams& kp, State* __restrict__ st,
                             double (&pe)[6], int stop_prev, double e_prev, double rho,
                             const double* __restrict__ Gcur,
@@ -652,8 +661,9 @@ __device__ int inner_entry(int k, int is_hstep, int r, const KParams& kp, State*
         // ||min(W, grad_W)||^2, <C,Ht>, <W,Ht>, ||Ht-W||^2, pgH^2, <Ht,LHt>
         block_sum_wide<6>(pe, sred);
         // <W^T W, Ht^T Ht>, ||W^T W||_F^2, ||W||^2 = tr(W^T W); thread t adds the entries
-        // t, t + 256, ... in that order, all loaded before the first add
-        constexpr int kGE = kMaxRank * kMaxRank / kThreads;
+        // t, t + 256, ... in that order, all loaded before the first add (as many per
+        // thread as the padded rank needs: one below rank 17)
+        constexpr int kGE = (RP * RP + kThreads - 1) / kThreads;
         const int rr = r * r;
         double gp[kGE], gc[kGE];
 #pragma unroll
@@ -822,7 +832,7 @@ __global__ __launch_bounds__(kThreads, (inner_occupancy<T, RP>())) void k_step1(
   // Z and Z - X come from the previous step 2 or from init), phase 1 only as the closing
   // entry of the half-step API
   double alpha_d = 0.0;
-  if (inner_entry(k, is_hstep, r, kp, st, pe, stop_prev, e_prev, rho, Gcur, Gprev, trace,
+  if (inner_entry<RP>(k, is_hstep, r, kp, st, pe, stop_prev, e_prev, rho, Gcur, Gprev, trace,
                   sm.red, lc.bid == 0 && threadIdx.x == 0, alpha_d) != kEntryRun)
     return;
   const T rinv = (T)(1.0 / rho);
@@ -1216,7 +1226,7 @@ __global__ __launch_bounds__(kThreads, (fused_occupancy<T, RP>())) void k_advanc
   if (done || stopped) return;
   if (i == 0) {  // inner iteration 0 opens here: monitor record, <C, P>, rho check
     double a0;
-    if (inner_entry(0, HS, r, kp, st, pe, 0, 0.0, rho, Gcur, Gprev, trace, sm.red, w0, a0) !=
+    if (inner_entry<RP>(0, HS, r, kp, st, pe, 0, 0.0, rho, Gcur, Gprev, trace, sm.red, w0, a0) !=
         kEntryRun)
       return;
   }
