@@ -177,8 +177,6 @@ __device__ __forceinline__ void store_G(T* __restrict__ sG, const T (&v)[TileCfg
   }
 }
 
-// This thread's share (workgroups b = tid, tid + 256, ... in increasing b) of K consecutive
-// partial-sum slots starting at `first`; block_sum then adds the shares in a fixed order.
 // Thread t adds the rows t, t + 256, ... in that order.  Each pass loads two rows before it
 // adds either, so up to 512 workgroups cost one memory round trip, not one per row; the
 // first pass is straight-line code (no loop guard between the kernel arguments and the
@@ -207,6 +205,9 @@ __device__ __forceinline__ void load_rows(int nb, double (&out)[K], F&& at) {
   pass(threadIdx.x);
   for (int b = threadIdx.x + 2 * kThreads; b < nb; b += 2 * kThreads) pass(b);
 }
+
+// This thread's share (workgroups b = tid, tid + 256, ... in increasing b) of K consecutive
+// partial-sum slots starting at `first`; block_sum then adds the shares in a fixed order.
 template <int K>
 __device__ __forceinline__ void load_slots(const double* __restrict__ part, int nb, int first,
                                            double (&out)[K]) {
