@@ -367,8 +367,8 @@ snmf_status batch_create(int32_t nprob, const snmf_matrix* A, const int32_t* r, 
     b->Ahi.assign(nprob, nullptr);
     b->Alo.assign(nprob, nullptr);
     // rho runs inside the product launch when its S workgroups find free slots beside the
-    // product's (two per CU): a rho workgroup that waits for a slot, or holds one a tile
-    // workgroup waits for, lengthens the launch by a whole rho (about 55 us at r = 64).
+    // product's (stack_per_cu() per CU): a rho workgroup that waits for a slot, or holds one
+    // a tile workgroup waits for, lengthens the launch by a whole rho (about 55 us at r = 64).
     // Otherwise it runs inside the partner split's launch, whose tiles are short.
     int dev = 0, cus = 0;
     HIP_TRY(hipGetDevice(&dev));
@@ -377,7 +377,7 @@ snmf_status batch_create(int32_t nprob, const snmf_matrix* A, const int32_t* r, 
     for (int g = 0; g < nprob; ++g) {
       const int64_t R = (int64_t)restarts * b->r[g];
       b->ds[g] = plan_dense_bf16_stack(b->n[g], R);
-      if (b->ds[g].nwg + restarts > 2 * (int64_t)cus) b->rho_in_apass = false;
+      if (b->ds[g].nwg + restarts > stack_per_cu() * (int64_t)cus) b->rho_in_apass = false;
       b->ldb[g] = (b->n[g] + 63) / 64 * 64;
       pt_max = std::max(pt_max, R * b->ldb[g]);
       if (b->ds[g].ksplit > 1)

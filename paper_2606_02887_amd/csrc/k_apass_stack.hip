@@ -7,8 +7,8 @@
 //
 // Operands: A_hi, A_lo (n x ldb BF16, columns n.. zero); Pt_hi, Pt_lo ((S r) x ldb BF16,
 // row s r + m holds column m of P_s, columns n.. zero; k_split_pt_stack writes them).
-// The S r stacked columns are cut into blocks of 64.  A workgroup (4 waves x 32 output
-// rows) computes 128 rows x one column block over one K slice; with one slice it writes
+// The S r stacked columns are cut into blocks of kStackCols (128).  A workgroup (4 waves x
+// 32 output rows) computes 128 rows x one column block over one K slice; with one slice it writes
 // B directly, else split-K partials that k_sum_parts adds in slice order.  The spectral
 // norms rho_s of the restarts' Grams can run in the same launch.
 #include <type_traits>
@@ -18,6 +18,14 @@
 #include "rho.hpp"
 
 namespace snmf {
+
+// Stacked columns per workgroup, in units of 32: 4 gives 128-column blocks, so each row
+// tile's A is requested by half as many workgroups as with 64 (the product is bound by
+// those requests through L2); the LDS of such a workgroup leaves one per CU.
+constexpr int kStackNNB = 4;
+constexpr int kStackCols = 32 * kStackNNB;
+constexpr int kStackPerCU = kStackNNB == 2 ? 2 : 1;
+int stack_per_cu() { return kStackPerCU; }
 
 typedef float f32x4s __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -76,7 +84,7 @@ using IC = std::integral_constant<int, V>;
 //
 // Workgroups past the first ntile (one per restart, launched when Grho is set) compute
 // rho = ||G_s||_2 of restart s (r x r FP64 Grams r^2 apart) beside the products.
-__global__ __launch_bounds__(256, 2) void k_apass_bf16x3s(
+__global__ __launch_bounds__(256, kStackPerCU) void k_apass_bf16x3s(
     const uint16_t* __restrict__ Ahi, const uint16_t* __restrict__ Alo, int64_t ldb,
     const uint16_t* __restrict__ Pthi, const uint16_t* __restrict__ Ptlo, int64_t n, int r,
     int S, int64_t gx, int ncb, int64_t kchunk, int64_t ntile, float* __restrict__ Bout,
@@ -87,7 +95,8 @@ __global__ __launch_bounds__(256, 2) void k_apass_bf16x3s(
     return;
   }
   if (stack_done(st, S)) return;
-  constexpr int NNB = 2;                    // the workgroup's 64 stacked columns, in units of 32
+  constexpr int NNB = kStackNNB;            // the workgroup's stacked columns, in units of 32
+  constexpr int CB = 2 * NNB;               // its 16-column blocks
   constexpr int KS = 64;                    // k per slab
   constexpr int PROW = KS + 8;              // LDS row pitch (bf16), keeps 16-byte alignment
   __shared__ __attribute__((aligned(16))) uint16_t sP[2][2][32 * NNB * PROW];  // [buf][hi/lo]
@@ -95,7 +104,7 @@ __global__ __launch_bounds__(256, 2) void k_apass_bf16x3s(
   // FP32 accumulation drifts low by a small fraction of an ulp per instruction (measured
   // mean relative error -1.65e-7 over one chain of 8192 k), so short chains whose sums
   // are added with ordinary FP32 adds keep the product unbiased; [rb * 4 + cb][thread]
-  __shared__ f32x4s sAcc[8][256];
+  __shared__ f32x4s sAcc[2 * CB][256];
   const StackMap sm = stack_map((int64_t)blockIdx.x, ntile, ncb);
   const int64_t tile = sm.unit % gx, ksl = sm.unit / gx;
   const int64_t R = (int64_t)S * r;
@@ -109,21 +118,21 @@ __global__ __launch_bounds__(256, 2) void k_apass_bf16x3s(
   if (ke > ldb) ke = ldb;
   const int64_t nk = (ke - kb) / KS;        // slabs, >= 1
   const int64_t klast = kb + (nk - 1) * KS;
-  f32x4s acc[2][4];                         // [row block][16-column block]
+  f32x4s acc[2][CB];                        // [row block][16-column block]
 #pragma unroll
   for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb) {
+    for (int cb = 0; cb < CB; ++cb) {
       acc[rb][cb] = f32x4s{0.0f, 0.0f, 0.0f, 0.0f};
-      sAcc[rb * 4 + cb][tid] = f32x4s{0.0f, 0.0f, 0.0f, 0.0f};
+      sAcc[rb * CB + cb][tid] = f32x4s{0.0f, 0.0f, 0.0f, 0.0f};
     }
   // each thread adds its own accumulators into its own LDS slots: no barrier needed
   auto flush = [&]() {
 #pragma unroll
     for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-      for (int cb = 0; cb < 4; ++cb) {
-        sAcc[rb * 4 + cb][tid] += acc[rb][cb];
+      for (int cb = 0; cb < CB; ++cb) {
+        sAcc[rb * CB + cb][tid] += acc[rb][cb];
         acc[rb][cb] = f32x4s{0.0f, 0.0f, 0.0f, 0.0f};
       }
   };
@@ -178,7 +187,7 @@ __global__ __launch_bounds__(256, 2) void k_apass_bf16x3s(
 #pragma unroll
     for (int kh = 0; kh < 2; ++kh) {
 #pragma unroll
-      for (int cb = 0; cb < 4; ++cb) {
+      for (int cb = 0; cb < CB; ++cb) {
         const int m = 16 * cb + ri;
         const u16x8 bh = *(const u16x8*)&sP[b][0][m * PROW + 32 * kh + 8 * g];
         const u16x8 bl = *(const u16x8*)&sP[b][1][m * PROW + 32 * kh + 8 * g];
@@ -235,7 +244,7 @@ __global__ __launch_bounds__(256, 2) void k_apass_bf16x3s(
   // M / r, whose n x r block starts at (M / r) n r.
   float* out = Bout + ksl * pstride;
 #pragma unroll
-  for (int cb = 0; cb < 4; ++cb) {
+  for (int cb = 0; cb < CB; ++cb) {
     const int64_t M = mb + 16 * cb + ri;
     if (M < R) {
       const int64_t s = M / r, m = M - s * r;
@@ -245,7 +254,7 @@ __global__ __launch_bounds__(256, 2) void k_apass_bf16x3s(
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int64_t jj = j0 + 16 * rb + 4 * g + v;
-          if (jj < n) o[jj * r] = sAcc[rb * 4 + cb][tid][v];
+          if (jj < n) o[jj * r] = sAcc[rb * CB + cb][tid][v];
         }
     }
   }
@@ -261,16 +270,16 @@ static int64_t stack_cus() {
   return cus;
 }
 
-// Two workgroups per CU: the (row tile, column block) pairs, times K slices of whole
+// kStackPerCU workgroups per CU: the (row tile, column block) pairs, times K slices of whole
 // 64-column slabs while there are fewer pairs than that (at most kMaxKSplit slices).
-// n = 8192, S r = 512: 64 x 8 pairs, one slice.
+// n = 8192, S r = 512: 64 x 4 pairs, one slice.
 DenseSplit plan_dense_bf16_stack(int64_t n, int64_t R) {
   DenseSplit d;
   const int64_t ldb = (n + 63) / 64 * 64;
   d.gx = (n + 127) / 128;
-  const int64_t ncb = (R + 63) / 64;
+  const int64_t ncb = (R + kStackCols - 1) / kStackCols;
   const int64_t pairs = d.gx * ncb;
-  int64_t ks = (2 * stack_cus() + pairs - 1) / pairs;
+  int64_t ks = (kStackPerCU * stack_cus() + pairs - 1) / pairs;
   const int64_t kmax = ldb / 64;
   if (ks > kmax) ks = kmax;
   if (ks > kMaxKSplit) ks = kMaxKSplit;
@@ -287,7 +296,7 @@ void launch_apass_bf16x3_stack(const uint16_t* Ahi, const uint16_t* Alo, int64_t
                                const uint16_t* Pthi, const uint16_t* Ptlo, int64_t n, int r,
                                int S, const DenseSplit& d, float* Bout, int64_t pstride,
                                State* st, const double* Grho, hipStream_t s) {
-  const int ncb = (int)(((int64_t)S * r + 63) / 64);
+  const int ncb = (int)(((int64_t)S * r + kStackCols - 1) / kStackCols);
   const int64_t nrho = Grho ? S : 0;
   hipLaunchKernelGGL(k_apass_bf16x3s, dim3((unsigned)(d.nwg + nrho)), dim3(256), 0, s, Ahi, Alo,
                      ldb, Pthi, Ptlo, n, r, S, d.gx, ncb, d.kchunk, d.nwg, Bout, pstride, st,

@@ -109,6 +109,7 @@ void launch_apass_bf16x3(const uint16_t* Ahi, const uint16_t* Alo, int64_t ldb,
 // written to Bout + s n r (one K slice) or as d.ksplit partials pstride apart.  With Grho
 // set, rho of restart s (st[s].rho) from the FP64 Gram at Grho + s r^2 in the same launch.
 DenseSplit plan_dense_bf16_stack(int64_t n, int64_t R);
+int stack_per_cu();  // workgroups of the stacked split-BF16 product per CU
 void launch_apass_bf16x3_stack(const uint16_t* Ahi, const uint16_t* Alo, int64_t ldb,
                                const uint16_t* Pthi, const uint16_t* Ptlo, int64_t n, int r,
                                int S, const DenseSplit& d, float* Bout, int64_t pstride,
